@@ -1,0 +1,176 @@
+/*
+ * sfk.h -- C ABI of the sketched flexible LSQR / LSMR library (gfx950, FP64).
+ *
+ * Method (Bucci, Gazzola, Robol, "Randomized flexible LSQR and LSMR with
+ * applications to inverse problems"):
+ *   solve min ||A x - b||_2 (eq. (LS)) for b = A x_true + e (eq. (inverseproblem))
+ *   with the partially orthogonalised flexible Golub-Kahan process (eq. (FGK)):
+ *     A^T W_k = P_k T_k (here B W_k = P_k T_k, B = A^T or an unmatched
+ *     back-projector), A Z_k = W_{k+1} H_{k+1,k}, Z_k = tau(P_k),
+ *   and a sketched projected least-squares problem per step:
+ *     sFLSQR (eq. (sFLSQR), Algorithm 1): y_k = argmin || S (A Z_k y - b) ||
+ *     sFLSMR (eq. (sFLSMR), Algorithm 2): y_k = argmin || S (B A Z_k y - B b) ||
+ *   with x_k = Z_k y_k and discrepancy-principle stopping (eq. (discrP)).
+ *
+ * Conventions
+ *   - Every pointer argument is a DEVICE pointer unless its name ends in _host.
+ *   - Matrices, vectors and workspaces passed in are BORROWED: they stay owned
+ *     by the caller and must outlive the context.  The library never frees them.
+ *   - All device work of a context is enqueued on the stream given to
+ *     sfk_init (a hipStream_t passed as void*; NULL is the default stream).
+ *   - Functions return sfk_status; on failure sfk_last_error(ctx) (or
+ *     sfk_last_error(NULL) for failures before a context exists) describes it.
+ *     Failures never leave work running on the device.
+ *   - A context is not thread-safe: one thread at a time per context.
+ *   - Index base is 0; CSR row pointers and column indices are int32, values
+ *     float64; column indices of a row need not be sorted; rows may be empty.
+ */
+#ifndef SFK_H
+#define SFK_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct sfk_ctx sfk_ctx;
+
+typedef enum {
+  SFK_OK = 0,
+  SFK_EINVAL = 1,     /* invalid argument: dims, params, CSR structure, b zero or non-finite */
+  SFK_ENOMEM = 2,     /* device allocation failed, or caller workspace too small */
+  SFK_EDEVICE = 3,    /* HIP runtime error or no suitable device */
+  SFK_BREAKDOWN = 4,  /* basis could not be extended (Q10 reading); results stay valid */
+  SFK_ESTATE = 5      /* call not allowed in the context's state (e.g. k out of range) */
+} sfk_status;
+
+typedef enum { SFK_SFLSQR = 0, SFK_SFLSMR = 1 } sfk_method;
+
+/* Sketch families (paper Sec. 2.7 names them; the concrete definitions and the
+ * seeding are the library's, identical to the test oracle's):
+ *   SPARSE_SIGN: zeta distinct rows per column with values +-1/sqrt(zeta); zeta = 1
+ *                is CountSketch, the family of the paper's imaging experiments;
+ *   SRHT:        sqrt(N/s) R H_N D pad(v), N = 2^ceil(log2 d), Sylvester-ordered H_N;
+ *   IDENTITY:    S = I (requires s = d), which turns sFLSQR into FLSQR-type solves.
+ * Randomness: Philox4x64-10 keyed (seed, stream + (instance << 32)). */
+typedef enum { SFK_SK_SPARSE_SIGN = 0, SFK_SK_SRHT = 1, SFK_SK_IDENTITY = 2 } sfk_sketch_kind;
+
+/* Flexible operator tau (paper eq. (modbasis); the l1 reweighting follows the
+ * IRLS interpretation of Sec. 1.2): IDENTITY, or
+ * REWEIGHT_L1: z_k = (x_{k-1}^2 + eps^2)^(1/4) * p_k elementwise, x_0 = 0. */
+typedef enum { SFK_TAU_IDENTITY = 0, SFK_TAU_REWEIGHT_L1 = 1 } sfk_tau;
+
+/* Iteration driver: AUTO picks PERSISTENT when the device supports cooperative
+ * launch, else MULTI (one kernel per pipeline stage). */
+typedef enum { SFK_DRIVER_AUTO = 0, SFK_DRIVER_MULTI = 1, SFK_DRIVER_PERSISTENT = 2 } sfk_driver;
+
+/* CSR matrix, device arrays: rowptr[rows + 1], colind[nnz], val[nnz]. */
+typedef struct {
+  int64_t rows, cols, nnz;
+  const int32_t *rowptr;
+  const int32_t *colind;
+  const double *val;
+} sfk_csr;
+
+typedef struct {
+  int32_t method;      /* sfk_method */
+  int32_t ell;         /* orthogonalisation window, 0..8; the paper uses 2 (Sec. 3) */
+  int32_t maxit;       /* capacity: maximum number of iterations, 1..s-1 */
+  int32_t sketch;      /* sfk_sketch_kind */
+  int32_t s;           /* sketch rows: 1..2048, s > maxit, s <= d (SRHT: s <= N) */
+  int32_t zeta;        /* SPARSE_SIGN nonzeros per column, 1..min(s, 64) */
+  uint64_t seed;       /* Philox key word 0 */
+  int32_t instance;    /* Philox stream offset (distinct instances of a batch) */
+  int32_t tau;         /* sfk_tau */
+  double eps;          /* reweighting parameter, > 0 for REWEIGHT_L1 */
+  double eta;          /* discrepancy safety factor (eq. (discrP)), e.g. 1.01 */
+  double noise_norm;   /* delta_e = ||e||; > 0 enables the discrepancy stop (sFLSQR) */
+  double tol;          /* relative tolerance of the sketched stop test when the
+                          discrepancy stop is off; 0 runs to maxit */
+  int32_t driver;      /* sfk_driver */
+  int32_t vw;          /* SpMV lanes per row (8, 16, 32, 64); 0 = automatic */
+  int32_t wg_per_cu;   /* data-parallel workgroups per CU; 0 = automatic */
+  int32_t reserved[5];
+} sfk_params;
+
+/* Fills *p with defaults: sFLSQR, ell = 2, maxit = 50, sparse-sign s = 101, zeta = 8,
+ * seed 0, tau identity, eps 1e-3, eta 1.01, no discrepancy stop, tol 0, AUTO. */
+void sfk_params_default(sfk_params *p);
+
+/* Host-only check of dimensions and parameters (no device access).  A and B
+ * may have NULL arrays here; B NULL means B = A^T.  Returns SFK_OK or
+ * SFK_EINVAL with sfk_last_error(NULL) set. */
+sfk_status sfk_validate(const sfk_csr *A, const sfk_csr *B, const sfk_params *p);
+
+/* Device workspace the context needs for these sizes (bytes, 256-aligned
+ * sub-buffers included).  Returns 0 when the arguments are invalid. */
+size_t sfk_workspace_bytes(const sfk_csr *A, const sfk_csr *B, const sfk_params *p);
+
+/* Creates a context (Algorithm 1 / 2 initialisation: beta = ||b||, w_1 = b / beta,
+ * z = B w_1, S b or S B w_1, and the first basis vector).
+ *   A: m x n CSR (forward projector).  B: n x m CSR, or NULL for B = A^T (built
+ *   on the device).  b: m-vector.  workspace: device buffer of at least
+ *   sfk_workspace_bytes(...) bytes, or NULL to let the library allocate (and
+ *   free in sfk_destroy).  stream: hipStream_t or NULL.
+ * Validates the CSR structures on the device (SFK_EINVAL on a bad row pointer
+ * or column index) and b (SFK_EINVAL if zero or non-finite).  Synchronises the
+ * stream before returning. */
+sfk_status sfk_init(sfk_ctx **out, const sfk_csr *A, const sfk_csr *B, const double *b,
+                    const sfk_params *p, void *workspace, size_t workspace_bytes, void *stream);
+
+/* Runs up to k more iterations (Algorithm 1 / 2 loop body), stopping early on
+ * the stop test or a breakdown.  Synchronous: returns after the device
+ * finished.  *iters_done_host = total iterations completed so far (index of the
+ * current iterate), *stopped_host = 1 if the stop test fired.  Returns
+ * SFK_BREAKDOWN if the basis could not be extended (iterates up to
+ * *iters_done_host stay valid), SFK_ESTATE if the capacity maxit is exhausted
+ * or the run has already stopped. */
+sfk_status sfk_iterate(sfk_ctx *ctx, int32_t k, int32_t *iters_done_host, int32_t *stopped_host);
+
+/* x_k = Z_k y_k for the current k, written to the device n-vector x. */
+sfk_status sfk_solution(sfk_ctx *ctx, double *x);
+
+/* x_j = Z_j y_j for 1 <= j <= current k (y_j from the stored factorisation). */
+sfk_status sfk_solution_at(sfk_ctx *ctx, int32_t j, double *x);
+
+/* Per-iteration minimised sketched objective rho_j = min_y ||S(A Z_j y - b)||
+ * (sFLSQR) or ||S(B A Z_j y - B b)|| (sFLSMR), j = 1..k: copies min(k, cap)
+ * values to out_host, *count_host = k.  *rhs_norm_host (may be NULL) receives
+ * ||S b|| (resp. ||S B b||), the scale of the stop test. */
+sfk_status sfk_residual_norms(sfk_ctx *ctx, double *out_host, int32_t cap, int32_t *count_host,
+                              double *rhs_norm_host);
+
+/* Explicit true residual ||b - A x_k|| of the current iterate (one extra SpMV). */
+sfk_status sfk_true_residual(sfk_ctx *ctx, double *out_host);
+
+/* Frees the context and the workspace it allocated.  NULL is a no-op. */
+sfk_status sfk_destroy(sfk_ctx *ctx);
+
+/* Error description of the last failing call on ctx (NULL: of the calling
+ * thread's last failure outside a context).  Never NULL. */
+const char *sfk_last_error(const sfk_ctx *ctx);
+
+/* ---- introspection, for parity tests ------------------------------------ */
+
+/* Sparse-sign sketch as generated on the device: rows_host[d * zeta] and
+ * neg_host[d * zeta] (1 = negative), column-major in draw order, d = m
+ * (sFLSQR) or n (sFLSMR).  SFK_ESTATE for other sketch kinds. */
+sfk_status sfk_sketch_sparse_sign(sfk_ctx *ctx, int32_t *rows_host, int8_t *neg_host);
+
+/* SRHT sketch: rows_host[s] and neg_host[N] (D signs), *N_host = N. */
+sfk_status sfk_sketch_srht(sfk_ctx *ctx, int32_t *rows_host, int8_t *neg_host, int64_t *N_host);
+
+/* Recurrence coefficients of eq. (FGK) for the first k steps: H_host
+ * ((k+1) x k, column-major) and T_host (k x k, column-major). */
+sfk_status sfk_coefficients(sfk_ctx *ctx, double *H_host, double *T_host, int32_t k);
+
+/* Library and device description (static string). */
+const char *sfk_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SFK_H */

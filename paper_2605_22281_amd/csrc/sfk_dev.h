@@ -1,0 +1,97 @@
+// Internal device-side layout of one solver instance.  Everything here is
+// FP64 except indices; all arrays live in one device workspace carved by the
+// host (sfk_capi.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace sfk {
+
+constexpr int kMaxEll = 8;                 // orthogonalisation window limit
+constexpr int kMaxS = 2048;                // sketch rows limit (LS kept in one wave)
+constexpr int kWG = 256;                   // threads per data-parallel workgroup
+constexpr int kMaxQ = kMaxEll + 2;         // partial sums per workgroup and stage
+constexpr int kSrhtL = 2048;               // SRHT block length staged in LDS
+constexpr double kBreakdownTol = 1e-14;    // relative breakdown threshold
+
+// Scalar state shared by the stages (device memory).  Slots: w_j lives in
+// W ring slot j % (ell + 2), p_j in P ring slot j % (ell + 1).
+struct Scal {
+  double beta;        // ||b||
+  double rhsnorm;     // ||S b|| (sFLSQR) or ||S B b|| (sFLSMR)
+  double tol;         // relative tolerance of the stop test (0: none)
+  double wpre;        // ||A z_k|| before orthogonalisation
+  double zpre;        // ||B w_{k+1}|| before orthogonalisation
+  double wcoef[kMaxEll + 1];   // w~_j multipliers of the current w update
+  double pcoef[kMaxEll + 1];   // p~_j multipliers of the current p update
+  double Gw[(kMaxEll + 2) * (kMaxEll + 2)];  // <w_i, w_j> by slot
+  double Gp[(kMaxEll + 1) * (kMaxEll + 1)];  // <p_i, p_j> by slot
+  int halt;           // 1: no further stage may run
+  int stopped;        // stop test fired
+  int breakdown;      // 1: t breakdown, 2: h breakdown
+  int k_done;         // iterations whose LS has completed
+  int happy;          // h_{k+1,k} == 0 at the current step
+  int err;            // device-detected error code (CSR check)
+  int pad[2];
+};
+
+struct Dev {
+  // sizes and parameters
+  int m, n, s, ell, maxit, method, tau, sketch, zeta;
+  int d_sk;           // length of sketched vectors (m or n)
+  int N;              // SRHT padded length
+  int log2L;          // SRHT block length log2
+  int nblk;           // SRHT blocks
+  int nw;             // data-parallel workgroups
+  int vwA, vwB;       // SpMV lanes per row
+  double eps;
+  double sk_scale;    // 1/sqrt(zeta) or 1/sqrt(s)
+  // operators
+  const int *Arp, *Aci; const double *Ava;
+  const int *Brp, *Bci; const double *Bva;
+  const double *b;
+  const int *Apart, *Bpart;    // nnz-balanced row ranges, nw + 1 entries each
+  // vectors
+  double *W;          // (ell + 2) * m, unnormalised w~_j
+  double *P;          // (ell + 1) * n, unnormalised p~_j (unused when tau = I)
+  double *Z;          // (maxit + 1) * n, z~_j (column j-1)
+  double *wraw;       // m, A z_k
+  double *zraw;       // n, B w_{k+1}
+  double *x;          // n, current iterate (reweighting) / scratch
+  // sketch
+  int *sk_rp;         // s + 1   (sparse-sign, transposed: entries per sketch row)
+  int *sk_ent;        // zeta * d: column | (negative << 31)
+  int *sk_code;       // zeta * d: (row << 1) | negative, per column in draw order
+  int *srht_rows;     // s
+  unsigned long long *srht_d;  // N / 64 sign words
+  double *srht_part;  // nblk * s
+  double *SK;         // s * (maxit + 1), sketched columns
+  double *skrhs;      // s
+  // stage reductions
+  double *part;       // kMaxQ * nw
+  unsigned *ticket;   // 1
+  Scal *sc;
+  double *sigw;       // maxit + 2: 1 / ||w~_j||
+  double *sigp;       // maxit + 2: 1 / ||p~_j||
+  double *H;          // (maxit + 1) * maxit, column-major
+  double *T;          // (maxit + 1) * (maxit + 1), column-major
+  double *rho;        // maxit
+  // small least-squares state (Householder QR of the sketched matrix)
+  double *V;          // s * maxit reflectors (v_j[j] = 1, zeros above)
+  double *tauv;       // maxit
+  double *R;          // maxit * maxit, column-major
+  double *Rinv;       // maxit * maxit, column-major
+  double *c;          // s: Q^T rhs
+  double *y;          // maxit: y_k
+};
+
+__device__ __forceinline__ int wslot(const Dev &D, int j) { return j % (D.ell + 2); }
+__device__ __forceinline__ int pslot(const Dev &D, int j) { return j % (D.ell + 1); }
+__device__ __forceinline__ double *wvec(const Dev &D, int j) { return D.W + (size_t)wslot(D, j) * D.m; }
+__device__ __forceinline__ double *pvec(const Dev &D, int j) {
+  // with tau = I the stored basis column z~_j is p~_j itself
+  return D.tau == 0 ? D.Z + (size_t)(j - 1) * D.n : D.P + (size_t)pslot(D, j) * D.n;
+}
+
+}  // namespace sfk

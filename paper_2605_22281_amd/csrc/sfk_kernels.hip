@@ -1,0 +1,996 @@
+// HIP kernels (gfx950, wave64, FP64) of the sketched flexible LSQR / LSMR
+// iteration.  One instance, stage per kernel; the host driver (sfk_capi.hip)
+// sequences them on one stream.
+//
+// Stages of iteration k (paper Algorithm 1 / Algorithm 2, eq. (FGK)):
+//   A(k)  w = A z_k                       + dots <w_j, w> of the window, ||w||
+//   B(k)  w~_{k+1} = w - sum h_jk w_j     + ||w~_{k+1}||, Gram entries
+//   S     sketch of w (sFLSQR) or of z (sFLSMR) -> one new sketched column
+//   LS(k) Householder update of the small sketched least-squares problem
+//   C(k)  z = B w_{k+1}                   + dots <p_j, z> of the window, ||z||
+//   D(k)  p~_{k+1} = z - sum t_j p_j, z~_{k+1} = tau(p~_{k+1}) + norms, Gram
+// Vectors are kept unnormalised (w~, p~) with their inverse norms in sigw /
+// sigp; the normalisation is folded into the next consumer.  The modified
+// Gram-Schmidt coefficients of the paper's loops are obtained from one pass of
+// dot products corrected with the Gram matrix of the window (equal in exact
+// arithmetic; see the design notes).
+//
+// Every reduction is deterministic: per-workgroup partial sums are written to
+// a buffer and the last workgroup to finish (atomic ticket) sums them in a
+// fixed order.
+
+#include "sfk_dev.h"
+
+namespace sfk {
+
+// ---------------------------------------------------------------------------
+// Philox4x64-10 (Salmon et al., SC'11), from the published definition.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void philox4x64_10(uint64_t c[4], uint64_t k0, uint64_t k1) {
+  const uint64_t M0 = 0xD2E7470EE14C6C93ull, M1 = 0xCA5A826395121157ull;
+  const uint64_t W0 = 0x9E3779B97F4A7C15ull, W1 = 0xBB67AE8584CAA73Bull;
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    if (r) { k0 += W0; k1 += W1; }
+    const uint64_t hi0 = __umul64hi(M0, c[0]), lo0 = M0 * c[0];
+    const uint64_t hi1 = __umul64hi(M1, c[2]), lo1 = M1 * c[2];
+    const uint64_t n0 = hi1 ^ c[1] ^ k0;
+    const uint64_t n2 = hi0 ^ c[3] ^ k1;
+    c[0] = n0; c[1] = lo1; c[2] = n2; c[3] = lo0;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// reductions
+// ---------------------------------------------------------------------------
+template <int W>
+__device__ __forceinline__ double group_sum(double v) {
+#pragma unroll
+  for (int o = W / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, W);
+  return v;
+}
+
+// Sum of Q per-thread values over the workgroup; result in out[0..Q) (LDS).
+__device__ __forceinline__ void block_sum(const double (&v)[kMaxQ], int Q, double *lds_w,
+                                          double *out) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+  for (int q = 0; q < kMaxQ; ++q) {
+    if (q < Q) {
+      const double t = group_sum<64>(v[q]);
+      if (lane == 0) lds_w[q * (kWG / 64) + wv] = t;
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x < Q) {
+    double t = 0.0;
+    for (int w = 0; w < kWG / 64; ++w) t += lds_w[threadIdx.x * (kWG / 64) + w];
+    out[threadIdx.x] = t;
+  }
+  __syncthreads();
+}
+
+// Publishes this workgroup's Q partials; returns true in the last workgroup,
+// which then holds the fixed-order totals in tot[0..Q).
+__device__ bool stage_reduce(const Dev &D, int Q, const double *blk, double *lds_w,
+                             double *tot) {
+  __shared__ int s_last;
+  const int wid = blockIdx.x;
+  if (threadIdx.x == 0) {
+    for (int q = 0; q < Q; ++q) D.part[(size_t)q * D.nw + wid] = blk[q];
+    __threadfence();
+    const unsigned t = atomicAdd(D.ticket, 1u);
+    s_last = (t == (unsigned)D.nw - 1u);
+  }
+  __syncthreads();
+  if (!s_last) return false;
+  __threadfence();
+  double acc[kMaxQ];
+#pragma unroll
+  for (int q = 0; q < kMaxQ; ++q) acc[q] = 0.0;
+  for (int i = threadIdx.x; i < D.nw; i += kWG) {
+#pragma unroll
+    for (int q = 0; q < kMaxQ; ++q)
+      if (q < Q) acc[q] += __hip_atomic_load(D.part + (size_t)q * D.nw + i, __ATOMIC_RELAXED,
+                                             __HIP_MEMORY_SCOPE_AGENT);
+  }
+  block_sum(acc, Q, lds_w, tot);
+  if (threadIdx.x == 0) *D.ticket = 0u;
+  return true;
+}
+
+__device__ __forceinline__ bool halted(const Dev &D) {
+  return __hip_atomic_load(&D.sc->halt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0;
+}
+
+__device__ __forceinline__ void chunk_range(int d, int nw, int wid, int &i0, int &i1) {
+  const int per = (d + nw - 1) / nw;
+  i0 = min(d, wid * per);
+  i1 = min(d, i0 + per);
+}
+
+// ---------------------------------------------------------------------------
+// A(k) / C(k): CSR SpMV with the window dot products fused in the epilogue.
+//   ISA = true : w = sigp_k * A z~_k, dots with w~_j, j = max(1,k-ell)..k
+//   ISA = false: z = sigw_{k+1} * B w~_{k+1}, dots with p~_j, j = max(1,k+1-ell)..k
+// VW lanes cooperate on a row; rows of the workgroup's nnz-balanced range are
+// dealt round-robin to the kWG / VW lane groups.
+// ---------------------------------------------------------------------------
+template <int VW, bool ISA>
+__global__ void __launch_bounds__(kWG) k_spmv(Dev D, int k) {
+  if (halted(D)) return;
+  __shared__ double lds_w[kMaxQ * (kWG / 64)];
+  __shared__ double tot[kMaxQ];
+  const int wid = blockIdx.x;
+  const int *rp = ISA ? D.Arp : D.Brp;
+  const int *ci = ISA ? D.Aci : D.Bci;
+  const double *va = ISA ? D.Ava : D.Bva;
+  const int *part = ISA ? D.Apart : D.Bpart;
+  const double *xin;
+  double scale;
+  double *yout;
+  int j0, nwin;
+  if (ISA) {
+    xin = D.Z + (size_t)(k - 1) * D.n;
+    scale = D.sigp[k];
+    yout = D.wraw;
+    j0 = max(1, k - D.ell);
+    nwin = k - j0 + 1;
+  } else {
+    xin = wvec(D, k + 1);
+    scale = D.sigw[k + 1];
+    yout = D.zraw;
+    j0 = max(1, k + 1 - D.ell);
+    nwin = k >= j0 ? k - j0 + 1 : 0;
+  }
+  const double *win[kMaxEll + 1];
+#pragma unroll
+  for (int q = 0; q < kMaxEll + 1; ++q)
+    win[q] = (q < nwin) ? (ISA ? wvec(D, j0 + q) : pvec(D, j0 + q)) : nullptr;
+
+  double acc[kMaxQ];
+#pragma unroll
+  for (int q = 0; q < kMaxQ; ++q) acc[q] = 0.0;
+
+  const int r0 = part[wid], r1 = part[wid + 1];
+  const int grp = threadIdx.x / VW, lane = threadIdx.x % VW;
+  constexpr int NG = kWG / VW;
+  for (int r = r0 + grp; r < r1; r += NG) {
+    const int e0 = rp[r], e1 = rp[r + 1];
+    double s0 = 0.0, s1 = 0.0;
+    int e = e0 + lane;
+    for (; e + VW < e1; e += 2 * VW) {
+      const double v0 = __builtin_nontemporal_load(va + e);
+      const int c0 = __builtin_nontemporal_load(ci + e);
+      const double v1 = __builtin_nontemporal_load(va + e + VW);
+      const int c1 = __builtin_nontemporal_load(ci + e + VW);
+      s0 += v0 * xin[c0];
+      s1 += v1 * xin[c1];
+    }
+    if (e < e1) s0 += __builtin_nontemporal_load(va + e) * xin[__builtin_nontemporal_load(ci + e)];
+    const double yr = group_sum<VW>(s0 + s1) * scale;
+    if (lane == 0) {
+      yout[r] = yr;
+#pragma unroll
+      for (int q = 0; q < kMaxEll + 1; ++q)
+        if (q < nwin) acc[q] += win[q][r] * yr;
+      acc[kMaxEll + 1] += yr * yr;
+    }
+  }
+  // compact: window dots then the norm
+  double v[kMaxQ];
+#pragma unroll
+  for (int q = 0; q < kMaxQ; ++q) v[q] = 0.0;
+#pragma unroll
+  for (int q = 0; q < kMaxEll + 1; ++q)
+    if (q < nwin) v[q] = acc[q];
+#pragma unroll
+  for (int q = 0; q < kMaxQ; ++q)
+    if (q == nwin) v[q] = acc[kMaxEll + 1];
+  const int Q = nwin + 1;
+  __shared__ double blk[kMaxQ];
+  block_sum(v, Q, lds_w, blk);
+  if (!stage_reduce(D, Q, blk, lds_w, tot)) return;
+  if (threadIdx.x != 0) return;
+
+  // scalar step: modified Gram-Schmidt coefficients from the dots and the Gram
+  // matrix of the (normalised) window vectors
+  Scal *sc = D.sc;
+  const int ld = D.maxit + 1;
+  double h[kMaxEll + 1];
+  if (ISA) {
+    sc->wpre = sqrt(tot[nwin]);
+    const int ns = D.ell + 2;
+    for (int q = 0; q < nwin; ++q) {
+      const int jq = j0 + q;
+      double t = D.sigw[jq] * tot[q];
+      for (int i = 0; i < q; ++i) t -= h[i] * sc->Gw[wslot(D, jq) * ns + wslot(D, j0 + i)];
+      h[q] = t;
+      D.H[(size_t)(k - 1) * ld + (jq - 1)] = t;
+      sc->wcoef[q] = t * D.sigw[jq];
+    }
+  } else {
+    sc->zpre = sqrt(tot[nwin]);
+    const int ns = D.ell + 1;
+    for (int q = 0; q < nwin; ++q) {
+      const int jq = j0 + q;
+      double t = D.sigp[jq] * tot[q];
+      for (int i = 0; i < q; ++i) t -= h[i] * sc->Gp[pslot(D, jq) * ns + pslot(D, j0 + i)];
+      h[q] = t;
+      D.T[(size_t)k * ld + (jq - 1)] = t;
+      sc->pcoef[q] = t * D.sigp[jq];
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// B(k): w~_{k+1} = w - sum_q wcoef_q w~_{j0+q}; ||w~_{k+1}||, <w~_{k+1}, w~_j>
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(kWG) k_wupdate(Dev D, int k) {
+  if (halted(D)) return;
+  __shared__ double lds_w[kMaxQ * (kWG / 64)];
+  __shared__ double tot[kMaxQ];
+  __shared__ double blk[kMaxQ];
+  const int j0 = max(1, k - D.ell), nwin = k - j0 + 1;
+  const int g0 = max(1, k + 1 - D.ell), ng = k - g0 + 1;  // Gram targets (suffix of window)
+  const int goff = g0 - j0;
+  const double *win[kMaxEll + 1];
+  double cf[kMaxEll + 1];
+#pragma unroll
+  for (int q = 0; q < kMaxEll + 1; ++q) {
+    win[q] = (q < nwin) ? wvec(D, j0 + q) : nullptr;
+    cf[q] = (q < nwin) ? D.sc->wcoef[q] : 0.0;
+  }
+  double *out = wvec(D, k + 1);
+  int i0, i1;
+  chunk_range(D.m, D.nw, blockIdx.x, i0, i1);
+  double acc[kMaxQ];
+#pragma unroll
+  for (int q = 0; q < kMaxQ; ++q) acc[q] = 0.0;
+  for (int i = i0 + threadIdx.x; i < i1; i += kWG) {
+    double v = D.wraw[i];
+    double wj[kMaxEll + 1];
+#pragma unroll
+    for (int q = 0; q < kMaxEll + 1; ++q)
+      if (q < nwin) { wj[q] = win[q][i]; v -= cf[q] * wj[q]; }
+    out[i] = v;
+    acc[0] += v * v;
+#pragma unroll
+    for (int q = 0; q < kMaxEll + 1; ++q)
+      if (q < nwin) acc[1 + q] += v * wj[q];
+  }
+  const int Q = nwin + 1;  // norm, then <w~_{k+1}, w~_j> for the whole window
+  block_sum(acc, Q, lds_w, blk);
+  if (!stage_reduce(D, Q, blk, lds_w, tot)) return;
+  if (threadIdx.x != 0) return;
+  Scal *sc = D.sc;
+  const int ld = D.maxit + 1;
+  const double hk = sqrt(tot[0]);
+  D.H[(size_t)(k - 1) * ld + k] = hk;
+  const int ns = D.ell + 2;
+  const int sk = wslot(D, k + 1);
+  if (hk <= kBreakdownTol * sc->wpre || hk == 0.0) {
+    sc->happy = 1;
+    D.H[(size_t)(k - 1) * ld + k] = 0.0;
+    D.sigw[k + 1] = 0.0;
+  } else {
+    const double sg = 1.0 / hk;
+    D.sigw[k + 1] = sg;
+    sc->Gw[sk * ns + sk] = 1.0;
+    for (int q = 0; q < ng; ++q) {
+      const int j = g0 + q;
+      const double g = sg * D.sigw[j] * tot[1 + goff + q];
+      sc->Gw[sk * ns + wslot(D, j)] = g;
+      sc->Gw[wslot(D, j) * ns + sk] = g;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// D(k): p~_{k+1} = z - sum_q pcoef_q p~_{j0+q}; z~_{k+1} = tau(p~_{k+1}).
+// k = 0 is the initial step (empty window, x_0 = 0).
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(kWG) k_pupdate(Dev D, int k) {
+  if (halted(D)) return;
+  __shared__ double lds_w[kMaxQ * (kWG / 64)];
+  __shared__ double tot[kMaxQ];
+  __shared__ double blk[kMaxQ];
+  extern __shared__ double coefx[];  // k coefficients of x_k (reweighting)
+  const int j0 = max(1, k + 1 - D.ell);
+  const int nwin = k >= j0 ? k - j0 + 1 : 0;
+  const int g0 = max(1, k + 2 - D.ell);
+  const int ng = k >= g0 ? k - g0 + 1 : 0;
+  const int goff = g0 - j0;
+  const bool rew = D.tau == 1;
+  const double *win[kMaxEll + 1];
+  double cf[kMaxEll + 1];
+#pragma unroll
+  for (int q = 0; q < kMaxEll + 1; ++q) {
+    win[q] = (q < nwin) ? pvec(D, j0 + q) : nullptr;
+    cf[q] = (q < nwin) ? D.sc->pcoef[q] : 0.0;
+  }
+  if (rew) {
+    for (int j = threadIdx.x; j < k; j += kWG) coefx[j] = D.sigp[j + 1] * D.y[j];
+    __syncthreads();
+  }
+  double *zcol = D.Z + (size_t)k * D.n;
+  double *pout = rew ? D.P + (size_t)pslot(D, k + 1) * D.n : zcol;
+  const double eps2 = D.eps * D.eps;
+  int i0, i1;
+  chunk_range(D.n, D.nw, blockIdx.x, i0, i1);
+  double acc[kMaxQ];
+#pragma unroll
+  for (int q = 0; q < kMaxQ; ++q) acc[q] = 0.0;
+  for (int i = i0 + threadIdx.x; i < i1; i += kWG) {
+    double v = D.zraw[i];
+    double pj[kMaxEll + 1];
+#pragma unroll
+    for (int q = 0; q < kMaxEll + 1; ++q)
+      if (q < nwin) { pj[q] = win[q][i]; v -= cf[q] * pj[q]; }
+    pout[i] = v;
+    if (rew) {
+      double xi = 0.0;
+      for (int j = 0; j < k; ++j) xi += coefx[j] * D.Z[(size_t)j * D.n + i];
+      D.x[i] = xi;
+      zcol[i] = sqrt(sqrt(xi * xi + eps2)) * v;
+    }
+    acc[0] += v * v;
+#pragma unroll
+    for (int q = 0; q < kMaxEll + 1; ++q)
+      if (q < nwin) acc[1 + q] += v * pj[q];
+  }
+  const int Q = nwin + 1;
+  block_sum(acc, Q, lds_w, blk);
+  if (!stage_reduce(D, Q, blk, lds_w, tot)) return;
+  if (threadIdx.x != 0) return;
+  Scal *sc = D.sc;
+  const int ld = D.maxit + 1;
+  const double t = sqrt(tot[0]);
+  D.T[(size_t)k * ld + k] = t;
+  if (t <= kBreakdownTol * sc->zpre || t == 0.0) {
+    sc->breakdown = 1;
+    sc->halt = 1;
+    return;
+  }
+  const double sg = 1.0 / t;
+  D.sigp[k + 1] = sg;
+  const int ns = D.ell + 1;
+  const int sk = pslot(D, k + 1);
+  sc->Gp[sk * ns + sk] = 1.0;
+  for (int q = 0; q < ng; ++q) {
+    const int j = g0 + q;
+    const double g = sg * D.sigp[j] * tot[1 + goff + q];
+    sc->Gp[sk * ns + pslot(D, j)] = g;
+    sc->Gp[pslot(D, j) * ns + sk] = g;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Sketch application.
+// ---------------------------------------------------------------------------
+// sparse-sign: one wave per sketch row, over the row's (column, sign) entries
+// in increasing column order; identity: copy.
+__global__ void __launch_bounds__(kWG) k_sketch_gather(Dev D, const double *v, double *dst) {
+  if (halted(D)) return;
+  const int wave = (blockIdx.x * kWG + threadIdx.x) >> 6;
+  const int lane = threadIdx.x & 63;
+  if (D.sketch == 2) {
+    const int i = blockIdx.x * kWG + threadIdx.x;
+    if (i < D.s) dst[i] = v[i];
+    return;
+  }
+  const int nwaves = (gridDim.x * kWG) >> 6;
+  for (int r = wave; r < D.s; r += nwaves) {
+    const int e0 = D.sk_rp[r], e1 = D.sk_rp[r + 1];
+    double acc = 0.0;
+    for (int e = e0 + lane; e < e1; e += 64) {
+      const int code = D.sk_ent[e];
+      const double val = v[code & 0x7fffffff];
+      acc += code < 0 ? -val : val;
+    }
+    acc = group_sum<64>(acc);
+    if (lane == 0) dst[r] = acc * D.sk_scale;
+  }
+}
+
+// SRHT, stage 1: per block of L = 2^log2L entries, u = D pad(v) staged in LDS and
+// transformed by the Sylvester-ordered Walsh-Hadamard butterflies; the entries
+// that the s selected rows need are kept: part[b][i] = (H_L u_b)[rows_i mod L].
+__global__ void __launch_bounds__(kWG) k_srht_blocks(Dev D, const double *v) {
+  if (halted(D)) return;
+  __shared__ double u[kSrhtL];
+  const int L = 1 << D.log2L;
+  const int b = blockIdx.x;
+  const int base = b * L;
+  for (int i = threadIdx.x; i < L; i += kWG) {
+    const int g = base + i;
+    double val = 0.0;
+    if (g < D.d_sk) {
+      const unsigned long long w = D.srht_d[g >> 6];
+      val = ((w >> (g & 63)) & 1ull) ? -v[g] : v[g];
+    }
+    u[i] = val;
+  }
+  __syncthreads();
+  for (int h = 1; h < L; h <<= 1) {
+    for (int p = threadIdx.x; p < (L >> 1); p += kWG) {
+      const int i = (p / h) * 2 * h + (p % h);
+      const double a = u[i], c = u[i + h];
+      u[i] = a + c;
+      u[i + h] = a - c;
+    }
+    __syncthreads();
+  }
+  for (int i = threadIdx.x; i < D.s; i += kWG)
+    D.srht_part[(size_t)b * D.s + i] = u[D.srht_rows[i] & (L - 1)];
+}
+
+// SRHT, stage 2: dst_i = (1/sqrt(s)) sum_b (-1)^popcount((rows_i >> log2L) & b) part[b][i]
+__global__ void __launch_bounds__(kWG) k_srht_combine(Dev D, double *dst) {
+  if (halted(D)) return;
+  const int i = blockIdx.x * kWG + threadIdx.x;
+  if (i >= D.s) return;
+  const int hi = D.srht_rows[i] >> D.log2L;
+  double acc = 0.0;
+  for (int b = 0; b < D.nblk; ++b) {
+    const double p = D.srht_part[(size_t)b * D.s + i];
+    acc += (__popc(hi & b) & 1) ? -p : p;
+  }
+  dst[i] = acc * D.sk_scale;
+}
+
+// ---------------------------------------------------------------------------
+// LS(k): one wave.  Householder QR of the sketched matrix, grown by one column:
+//   sFLSQR column k = S A z_k;  sFLSMR column k = [S B W_{k+1}] H[:, k].
+// Keeps c = Q^T rhs, R, R^{-1} and y_k = R^{-1} c[0:k] (y_k = y_{k-1} + c_k R^{-1} e_k,
+// since the first k-1 entries of c no longer change).  rho_k = ||c[k:s]||.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double wave_sum(double v) { return group_sum<64>(v); }
+
+template <int E, int PF>
+__global__ void __launch_bounds__(64) k_ls(Dev D, int k) {
+  if (halted(D)) return;
+  __shared__ double s_tau[kMaxS];
+  __shared__ double s_r[kMaxS];
+  const int lane = threadIdx.x;
+  const int s = D.s;
+  const int ldr = D.maxit;
+  const int ldh = D.maxit + 1;
+  const int nsel = k - 1;
+  Scal *sc = D.sc;
+
+  double a[E];
+#pragma unroll
+  for (int e = 0; e < E; ++e) a[e] = 0.0;
+  if (D.method == 0) {
+    const double *col = D.SK + (size_t)(k - 1) * s;
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const int i = lane + 64 * e;
+      if (i < s) a[e] = col[i];
+    }
+  } else {
+    const int j0 = max(1, k - D.ell);
+    for (int j = j0; j <= k + 1; ++j) {
+      const double hj = D.H[(size_t)(k - 1) * ldh + (j - 1)];
+      const double *col = D.SK + (size_t)(j - 1) * s;
+#pragma unroll
+      for (int e = 0; e < E; ++e) {
+        const int i = lane + 64 * e;
+        if (i < s) a[e] += hj * col[i];
+      }
+    }
+  }
+  for (int t = lane; t < nsel; t += 64) s_tau[t] = D.tauv[t];
+  __syncthreads();
+
+  // apply H_1 ... H_{k-1} (register ring prefetch of the reflectors)
+  double vb[PF][E];
+#pragma unroll
+  for (int p = 0; p < PF; ++p) {
+    if (p < nsel) {
+      const double *vp = D.V + (size_t)p * s;
+#pragma unroll
+      for (int e = 0; e < E; ++e) {
+        const int i = lane + 64 * e;
+        vb[p][e] = i < s ? vp[i] : 0.0;
+      }
+    }
+  }
+  for (int j = 0; j < nsel; j += PF) {
+#pragma unroll
+    for (int p = 0; p < PF; ++p) {
+      const int jj = j + p;
+      if (jj < nsel) {
+        double d = 0.0;
+#pragma unroll
+        for (int e = 0; e < E; ++e) d += vb[p][e] * a[e];
+        const double g = s_tau[jj] * wave_sum(d);
+#pragma unroll
+        for (int e = 0; e < E; ++e) a[e] -= g * vb[p][e];
+        if (jj + PF < nsel) {
+          const double *vp = D.V + (size_t)(jj + PF) * s;
+#pragma unroll
+          for (int e = 0; e < E; ++e) {
+            const int i = lane + 64 * e;
+            vb[p][e] = i < s ? vp[i] : 0.0;
+          }
+        }
+      }
+    }
+  }
+
+  // new reflector from a[nsel:s]
+  double alpha_l = 0.0, x2 = 0.0;
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    const int i = lane + 64 * e;
+    if (i == nsel) alpha_l = a[e];
+    if (i > nsel && i < s) x2 += a[e] * a[e];
+  }
+  const double alpha = __shfl(alpha_l, nsel & 63, 64);
+  x2 = wave_sum(x2);
+  double beta, tau, scl;
+  if (x2 == 0.0) {
+    beta = alpha; tau = 0.0; scl = 0.0;
+  } else {
+    beta = -copysign(sqrt(alpha * alpha + x2), alpha);
+    tau = (beta - alpha) / beta;
+    scl = 1.0 / (alpha - beta);
+  }
+  double v[E];
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    const int i = lane + 64 * e;
+    v[e] = (i == nsel) ? 1.0 : ((i > nsel && i < s) ? a[e] * scl : 0.0);
+  }
+  {
+    double *vp = D.V + (size_t)nsel * s;
+    double *rc = D.R + (size_t)nsel * ldr;
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const int i = lane + 64 * e;
+      if (i < s) vp[i] = v[e];
+      if (i < nsel) { rc[i] = a[e]; s_r[i] = a[e]; }
+    }
+    if (lane == 0) { rc[nsel] = beta; D.tauv[nsel] = tau; }
+  }
+  // c <- H_k c
+  double cv[E];
+  double d = 0.0;
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    const int i = lane + 64 * e;
+    cv[e] = i < s ? D.c[i] : 0.0;
+    d += v[e] * cv[e];
+  }
+  d = tau * wave_sum(d);
+  double ck_l = 0.0, r2 = 0.0;
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    const int i = lane + 64 * e;
+    cv[e] -= d * v[e];
+    if (i < s) D.c[i] = cv[e];
+    if (i == nsel) ck_l = cv[e];
+    if (i > nsel && i < s) r2 += cv[e] * cv[e];
+  }
+  const double ck = __shfl(ck_l, nsel & 63, 64);
+  const double rho = sqrt(wave_sum(r2));
+  __syncthreads();
+
+  if (beta == 0.0) {  // the new sketched column is zero: cannot extend the basis
+    if (lane == 0) { sc->breakdown = 3; sc->halt = 1; }
+    return;
+  }
+  // R^{-1} column and y update
+  const double ib = 1.0 / beta;
+  for (int t = lane; t < nsel; t += 64) {
+    double g = 0.0;
+#pragma unroll 8
+    for (int j = t; j < nsel; ++j) g += D.Rinv[(size_t)j * ldr + t] * s_r[j];
+    g = -g * ib;
+    D.Rinv[(size_t)nsel * ldr + t] = g;
+    D.y[t] += ck * g;
+  }
+  if (lane == 0) {
+    D.Rinv[(size_t)nsel * ldr + nsel] = ib;
+    D.y[nsel] = ck * ib;
+    D.rho[k - 1] = rho;
+    sc->k_done = k;
+    if (sc->happy) { sc->breakdown = 2; sc->halt = 1; }
+    if (sc->tol > 0.0 && rho < sc->tol * sc->rhsnorm) { sc->stopped = 1; sc->halt = 1; }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// solution and residual helpers
+// ---------------------------------------------------------------------------
+// y_j = R_j^{-1} c[0:j] for an earlier j (t-th entry per thread)
+__global__ void k_y_at(Dev D, int j, double *yout) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= j) return;
+  double g = 0.0;
+  for (int i = t; i < j; ++i) g += D.Rinv[(size_t)i * D.maxit + t] * D.c[i];
+  yout[t] = g;
+}
+
+// x = sum_{j<kk} sigp_{j+1} y_j z~_{j+1}
+__global__ void __launch_bounds__(kWG) k_solution(Dev D, int kk, const double *yv, double *x) {
+  extern __shared__ double cf[];
+  for (int j = threadIdx.x; j < kk; j += kWG) cf[j] = D.sigp[j + 1] * yv[j];
+  __syncthreads();
+  const int i = blockIdx.x * kWG + threadIdx.x;
+  if (i >= D.n) return;
+  double xi = 0.0;
+  for (int j = 0; j < kk; ++j) xi += cf[j] * D.Z[(size_t)j * D.n + i];
+  x[i] = xi;
+}
+
+// ||b - A x||^2 partials -> out (plain SpMV, wave per row)
+__global__ void __launch_bounds__(kWG) k_true_residual(Dev D, const double *x, double *out) {
+  __shared__ double lds_w[kMaxQ * (kWG / 64)];
+  __shared__ double tot[kMaxQ];
+  __shared__ double blk[kMaxQ];
+  double acc[kMaxQ];
+#pragma unroll
+  for (int q = 0; q < kMaxQ; ++q) acc[q] = 0.0;
+  const int r0 = D.Apart[blockIdx.x], r1 = D.Apart[blockIdx.x + 1];
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  for (int r = r0 + wv; r < r1; r += kWG / 64) {
+    double s = 0.0;
+    for (int e = D.Arp[r] + lane; e < D.Arp[r + 1]; e += 64) s += D.Ava[e] * x[D.Aci[e]];
+    s = group_sum<64>(s);
+    if (lane == 0) { const double rr = D.b[r] - s; acc[0] += rr * rr; }
+  }
+  block_sum(acc, 1, lds_w, blk);
+  if (!stage_reduce(D, 1, blk, lds_w, tot)) return;
+  if (threadIdx.x == 0) *out = sqrt(tot[0]);
+}
+
+// ---------------------------------------------------------------------------
+// initialisation kernels
+// ---------------------------------------------------------------------------
+// CSR structure check: row pointers monotone from 0 to nnz, columns in range.
+__global__ void k_csr_check(const int *rp, const int *ci, int rows, int cols, long long nnz,
+                            int *err) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r > rows) return;
+  if (r == 0 && rp[0] != 0) atomicOr(err, 1);
+  if (r == rows) { if ((long long)rp[rows] != nnz) atomicOr(err, 1); return; }
+  const int e0 = rp[r], e1 = rp[r + 1];
+  if (e1 < e0 || e0 < 0 || (long long)e1 > nnz) { atomicOr(err, 1); return; }
+  for (int e = e0; e < e1; ++e)
+    if (ci[e] < 0 || ci[e] >= cols) { atomicOr(err, 2); return; }
+}
+
+// nnz-balanced row ranges: part[w] = first row r with rp[r] >= w * nnz / nw
+__global__ void k_partition(const int *rp, int rows, long long nnz, int nw, int *part) {
+  const int w = blockIdx.x * blockDim.x + threadIdx.x;
+  if (w > nw) return;
+  if (w == nw) { part[w] = rows; return; }
+  const long long target = (long long)w * nnz / nw;
+  int lo = 0, hi = rows;
+  while (lo < hi) {
+    const int mid = (lo + hi) >> 1;
+    if ((long long)rp[mid] < target) lo = mid + 1; else hi = mid;
+  }
+  part[w] = lo;
+}
+
+// device transpose of A (m x n) into B (n x m): counts, then atomic fill, then
+// a per-row sort by column so that the row order does not depend on timing.
+__global__ void k_tr_count(const int *rp, const int *ci, int rows, int *cnt) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= rows) return;
+  for (int e = rp[r]; e < rp[r + 1]; ++e) atomicAdd(cnt + ci[e], 1);
+}
+
+// exclusive scan of cnt[0..len] in place by one workgroup (len up to a few 1e6)
+__global__ void __launch_bounds__(1024) k_scan_single(int *a, int len) {
+  __shared__ int sums[1024];
+  const int t = threadIdx.x;
+  const int per = (len + 1023) / 1024;
+  const int b0 = min(len, t * per), b1 = min(len, b0 + per);
+  int s = 0;
+  for (int i = b0; i < b1; ++i) s += a[i];
+  sums[t] = s;
+  __syncthreads();
+  for (int o = 1; o < 1024; o <<= 1) {
+    const int v = t >= o ? sums[t - o] : 0;
+    __syncthreads();
+    sums[t] += v;
+    __syncthreads();
+  }
+  int run = t ? sums[t - 1] : 0;
+  for (int i = b0; i < b1; ++i) { const int v = a[i]; a[i] = run; run += v; }
+}
+
+__global__ void k_tr_fill(const int *rp, const int *ci, const double *va, int rows, int *cursor,
+                          int *bci, double *bva) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= rows) return;
+  for (int e = rp[r]; e < rp[r + 1]; ++e) {
+    const int pos = atomicAdd(cursor + ci[e], 1);
+    bci[pos] = r;
+    bva[pos] = va[e];
+  }
+}
+
+// sort each row segment by column (odd-even transposition in LDS, len <= 4096)
+__global__ void __launch_bounds__(256) k_tr_sort(const int *brp, int *bci, double *bva, int rows,
+                                                 int *err) {
+  __shared__ int kc[4096];
+  __shared__ double kv[4096];
+  const int r = blockIdx.x;
+  if (r >= rows) return;
+  const int e0 = brp[r], len = brp[r + 1] - e0;
+  if (len > 4096) { if (threadIdx.x == 0) atomicOr(err, 4); return; }
+  for (int i = threadIdx.x; i < len; i += 256) { kc[i] = bci[e0 + i]; kv[i] = bva[e0 + i]; }
+  __syncthreads();
+  for (int phase = 0; phase < len; ++phase) {
+    for (int i = 2 * threadIdx.x + (phase & 1); i + 1 < len; i += 512) {
+      if (kc[i] > kc[i + 1]) {
+        const int tc = kc[i]; kc[i] = kc[i + 1]; kc[i + 1] = tc;
+        const double tv = kv[i]; kv[i] = kv[i + 1]; kv[i + 1] = tv;
+      }
+    }
+    __syncthreads();
+  }
+  for (int i = threadIdx.x; i < len; i += 256) { bci[e0 + i] = kc[i]; bva[e0 + i] = kv[i]; }
+}
+
+// sparse-sign generation: column j takes zeta distinct rows from Philox blocks
+// (j, t, 0, 0); code = (row << 1) | negative.
+__global__ void k_ss_gen(Dev D, uint64_t key0, uint64_t key1, int *err) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= D.d_sk) return;
+  const int zeta = D.zeta;
+  const uint64_t s = (uint64_t)D.s;
+  int rows[64];
+  int cnt = 0;
+  for (uint64_t t = 0; cnt < zeta; ++t) {
+    if (t > 100000) { atomicOr(err, 8); return; }
+    uint64_t c[4] = {(uint64_t)j, t, 0ull, 0ull};
+    philox4x64_10(c, key0, key1);
+    for (int w = 0; w < 4 && cnt < zeta; ++w) {
+      const uint64_t u = c[w];
+      const int row = (int)(((u >> 32) * s) >> 32);
+      bool dup = false;
+      for (int q = 0; q < cnt; ++q) dup |= (rows[q] == row);
+      if (dup) continue;
+      rows[cnt] = row;
+      D.sk_code[(size_t)j * zeta + cnt] = (row << 1) | (int)(u & 1ull);
+      ++cnt;
+    }
+  }
+}
+
+// per chunk of 256 columns: entries per sketch row
+__global__ void __launch_bounds__(256) k_ss_count(Dev D, int *chunk_cnt) {
+  extern __shared__ int cnt[];
+  for (int r = threadIdx.x; r < D.s; r += 256) cnt[r] = 0;
+  __syncthreads();
+  const int j = blockIdx.x * 256 + threadIdx.x;
+  if (j < D.d_sk)
+    for (int t = 0; t < D.zeta; ++t) atomicAdd(&cnt[D.sk_code[(size_t)j * D.zeta + t] >> 1], 1);
+  __syncthreads();
+  for (int r = threadIdx.x; r < D.s; r += 256) chunk_cnt[(size_t)blockIdx.x * D.s + r] = cnt[r];
+}
+
+// per sketch row: offsets of each chunk within the row; totals into sk_rp[r]
+__global__ void k_ss_rowscan(Dev D, int *chunk_cnt, int nchunk) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= D.s) return;
+  int run = 0;
+  for (int c = 0; c < nchunk; ++c) {
+    const int v = chunk_cnt[(size_t)c * D.s + r];
+    chunk_cnt[(size_t)c * D.s + r] = run;
+    run += v;
+  }
+  D.sk_rp[r] = run;
+}
+
+// place entries of each chunk in column order (one thread per chunk)
+__global__ void __launch_bounds__(64) k_ss_fill(Dev D, const int *chunk_off) {
+  extern __shared__ int cur[];
+  for (int r = threadIdx.x; r < D.s; r += 64) cur[r] = D.sk_rp[r] + chunk_off[(size_t)blockIdx.x * D.s + r];
+  __syncthreads();
+  if (threadIdx.x != 0) return;
+  const int j0 = blockIdx.x * 256, j1 = min(D.d_sk, j0 + 256);
+  for (int j = j0; j < j1; ++j)
+    for (int t = 0; t < D.zeta; ++t) {
+      const int code = D.sk_code[(size_t)j * D.zeta + t];
+      const int pos = cur[code >> 1]++;
+      D.sk_ent[pos] = (int)((unsigned)j | ((unsigned)(code & 1) << 31));
+    }
+}
+
+// SRHT signs: word w of D is word (w & 3) of the block with counter (w >> 2, 0, 0, 0)
+__global__ void k_srht_dbits(Dev D, uint64_t key0, uint64_t key1) {
+  const int w = blockIdx.x * blockDim.x + threadIdx.x;
+  if (w >= D.N / 64 + (D.N < 64 ? 1 : 0)) return;
+  uint64_t c[4] = {(uint64_t)(w >> 2), 0ull, 0ull, 0ull};
+  philox4x64_10(c, key0, key1);
+  D.srht_d[w] = c[w & 3];
+}
+
+// SRHT rows: partial Fisher-Yates over [0, N) with a permutation in scratch
+__global__ void k_srht_rows(Dev D, uint64_t key0, uint64_t key1, int *perm) {
+  if (blockIdx.x != 0 || threadIdx.x != 0) return;
+  const uint64_t N = (uint64_t)D.N;
+  uint64_t c[4] = {0, 0, 0, 0};
+  for (int t = 0; t < D.s; ++t) {
+    if ((t & 3) == 0) { c[0] = (uint64_t)(t >> 2); c[1] = c[2] = c[3] = 0; philox4x64_10(c, key0, key1); }
+    const uint64_t u = c[t & 3];
+    const int j = t + (int)__umul64hi(u, N - (uint64_t)t);
+    const int a = perm[t], b = perm[j];
+    perm[t] = b; perm[j] = a;
+    D.srht_rows[t] = b;
+  }
+}
+
+__global__ void k_iota(int *a, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) a[i] = i;
+}
+
+// beta = ||b||, w~_1 = b, sigw_1 = 1 / beta; discrepancy tolerance
+__global__ void __launch_bounds__(kWG) k_init_b(Dev D, double eta, double noise, double tol_user,
+                                               int use_disc) {
+  __shared__ double lds_w[kMaxQ * (kWG / 64)];
+  __shared__ double tot[kMaxQ];
+  __shared__ double blk[kMaxQ];
+  int i0, i1;
+  chunk_range(D.m, D.nw, blockIdx.x, i0, i1);
+  double acc[kMaxQ];
+#pragma unroll
+  for (int q = 0; q < kMaxQ; ++q) acc[q] = 0.0;
+  double *w1 = wvec(D, 1);
+  for (int i = i0 + threadIdx.x; i < i1; i += kWG) {
+    const double v = D.b[i];
+    w1[i] = v;
+    acc[0] += v * v;
+  }
+  block_sum(acc, 1, lds_w, blk);
+  if (!stage_reduce(D, 1, blk, lds_w, tot)) return;
+  if (threadIdx.x != 0) return;
+  Scal *sc = D.sc;
+  const double beta = sqrt(tot[0]);
+  sc->beta = beta;
+  if (!(beta > 0.0) || !isfinite(beta)) { sc->err |= 16; sc->halt = 1; return; }
+  D.sigw[1] = 1.0 / beta;
+  sc->tol = use_disc ? eta * noise / beta : tol_user;
+}
+
+// sFLSMR initial sketch: rhs = beta * S B w_1 (already in SK column 0);
+// both methods: c = rhs, rhsnorm = ||rhs||
+__global__ void __launch_bounds__(64) k_init_rhs(Dev D) {
+  Scal *sc = D.sc;
+  if (sc->halt) return;
+  const int lane = threadIdx.x;
+  double r2 = 0.0;
+  for (int i = lane; i < D.s; i += 64) {
+    double v = D.method == 0 ? D.skrhs[i] : sc->beta * D.SK[i];
+    D.skrhs[i] = v;
+    D.c[i] = v;
+    r2 += v * v;
+  }
+  r2 = wave_sum(r2);
+  if (lane == 0) sc->rhsnorm = sqrt(r2);
+}
+
+// ---------------------------------------------------------------------------
+// launch helpers (host side)
+// ---------------------------------------------------------------------------
+template <bool ISA>
+static void launch_spmv_vw(const Dev &D, int k, int vw, hipStream_t st) {
+  switch (vw) {
+    case 8: hipLaunchKernelGGL((k_spmv<8, ISA>), dim3(D.nw), dim3(kWG), 0, st, D, k); break;
+    case 16: hipLaunchKernelGGL((k_spmv<16, ISA>), dim3(D.nw), dim3(kWG), 0, st, D, k); break;
+    case 32: hipLaunchKernelGGL((k_spmv<32, ISA>), dim3(D.nw), dim3(kWG), 0, st, D, k); break;
+    default: hipLaunchKernelGGL((k_spmv<64, ISA>), dim3(D.nw), dim3(kWG), 0, st, D, k); break;
+  }
+}
+
+void launch_stage_A(const Dev &D, int k, hipStream_t st) { launch_spmv_vw<true>(D, k, D.vwA, st); }
+void launch_stage_C(const Dev &D, int k, hipStream_t st) { launch_spmv_vw<false>(D, k, D.vwB, st); }
+void launch_stage_B(const Dev &D, int k, hipStream_t st) {
+  hipLaunchKernelGGL(k_wupdate, dim3(D.nw), dim3(kWG), 0, st, D, k);
+}
+void launch_stage_D(const Dev &D, int k, hipStream_t st) {
+  const size_t sh = D.tau == 1 ? sizeof(double) * (size_t)max(1, k) : 0;
+  hipLaunchKernelGGL(k_pupdate, dim3(D.nw), dim3(kWG), sh, st, D, k);
+}
+
+void launch_sketch(const Dev &D, const double *v, double *dst, hipStream_t st) {
+  if (D.sketch == 1) {
+    hipLaunchKernelGGL(k_srht_blocks, dim3(D.nblk), dim3(kWG), 0, st, D, v);
+    hipLaunchKernelGGL(k_srht_combine, dim3((D.s + kWG - 1) / kWG), dim3(kWG), 0, st, D, dst);
+  } else if (D.sketch == 2) {
+    hipLaunchKernelGGL(k_sketch_gather, dim3((D.s + kWG - 1) / kWG), dim3(kWG), 0, st, D, v, dst);
+  } else {
+    const int blocks = (D.s * 64 + kWG - 1) / kWG;
+    hipLaunchKernelGGL(k_sketch_gather, dim3(blocks), dim3(kWG), 0, st, D, v, dst);
+  }
+}
+
+void launch_ls(const Dev &D, int k, hipStream_t st) {
+  const int s = D.s;
+  if (s <= 128) hipLaunchKernelGGL((k_ls<2, 4>), dim3(1), dim3(64), 0, st, D, k);
+  else if (s <= 256) hipLaunchKernelGGL((k_ls<4, 4>), dim3(1), dim3(64), 0, st, D, k);
+  else if (s <= 512) hipLaunchKernelGGL((k_ls<8, 4>), dim3(1), dim3(64), 0, st, D, k);
+  else if (s <= 1024) hipLaunchKernelGGL((k_ls<16, 2>), dim3(1), dim3(64), 0, st, D, k);
+  else hipLaunchKernelGGL((k_ls<32, 2>), dim3(1), dim3(64), 0, st, D, k);
+}
+
+void launch_iteration(const Dev &D, int k, hipStream_t st) {
+  launch_stage_A(D, k, st);
+  launch_stage_B(D, k, st);
+  if (D.method == 0) {
+    launch_sketch(D, D.wraw, D.SK + (size_t)(k - 1) * D.s, st);
+    launch_ls(D, k, st);
+    launch_stage_C(D, k, st);
+  } else {
+    launch_stage_C(D, k, st);
+    launch_sketch(D, D.zraw, D.SK + (size_t)k * D.s, st);
+    launch_ls(D, k, st);
+  }
+  launch_stage_D(D, k, st);
+}
+
+void launch_init_b(const Dev &D, double eta, double noise, double tol_user, int use_disc,
+                   hipStream_t st) {
+  hipLaunchKernelGGL(k_init_b, dim3(D.nw), dim3(kWG), 0, st, D, eta, noise, tol_user, use_disc);
+}
+void launch_init_rhs(const Dev &D, hipStream_t st) {
+  hipLaunchKernelGGL(k_init_rhs, dim3(1), dim3(64), 0, st, D);
+}
+void launch_csr_check(const int *rp, const int *ci, int rows, int cols, long long nnz, int *err,
+                      hipStream_t st) {
+  hipLaunchKernelGGL(k_csr_check, dim3((rows + 1 + 255) / 256), dim3(256), 0, st, rp, ci, rows,
+                     cols, nnz, err);
+}
+void launch_partition(const int *rp, int rows, long long nnz, int nw, int *part, hipStream_t st) {
+  hipLaunchKernelGGL(k_partition, dim3((nw + 1 + 255) / 256), dim3(256), 0, st, rp, rows, nnz, nw,
+                     part);
+}
+void launch_transpose(const int *rp, const int *ci, const double *va, int rows, int cols,
+                      int *brp, int *bci, double *bva, int *cursor, int *err, hipStream_t st) {
+  hipMemsetAsync(brp, 0, sizeof(int) * (cols + 1), st);
+  hipLaunchKernelGGL(k_tr_count, dim3((rows + 255) / 256), dim3(256), 0, st, rp, ci, rows, brp);
+  hipLaunchKernelGGL(k_scan_single, dim3(1), dim3(1024), 0, st, brp, cols + 1);
+  // exclusive scan of [cnt_0, ..., cnt_{n-1}, 0]: entry c is the start of row c,
+  // entry n the total
+  hipMemcpyAsync(cursor, brp, sizeof(int) * cols, hipMemcpyDeviceToDevice, st);
+  hipLaunchKernelGGL(k_tr_fill, dim3((rows + 255) / 256), dim3(256), 0, st, rp, ci, va, rows,
+                     cursor, bci, bva);
+  hipLaunchKernelGGL(k_tr_sort, dim3(cols), dim3(256), 0, st, brp, bci, bva, cols, err);
+}
+void launch_sketch_build(const Dev &D, uint64_t key0, uint64_t key1, uint64_t key1_rows,
+                         int *scratch, int *err, hipStream_t st) {
+  if (D.sketch == 0) {
+    hipLaunchKernelGGL(k_ss_gen, dim3((D.d_sk + 255) / 256), dim3(256), 0, st, D, key0, key1, err);
+    const int nchunk = (D.d_sk + 255) / 256;
+    hipLaunchKernelGGL(k_ss_count, dim3(nchunk), dim3(256), sizeof(int) * D.s, st, D, scratch);
+    hipLaunchKernelGGL(k_ss_rowscan, dim3((D.s + 255) / 256), dim3(256), 0, st, D, scratch, nchunk);
+    hipLaunchKernelGGL(k_scan_single, dim3(1), dim3(1024), 0, st, D.sk_rp, D.s + 1);
+    hipLaunchKernelGGL(k_ss_fill, dim3(nchunk), dim3(64), sizeof(int) * D.s, st, D, scratch);
+  } else if (D.sketch == 1) {
+    const int nw = D.N / 64 + (D.N < 64 ? 1 : 0);
+    hipLaunchKernelGGL(k_srht_dbits, dim3((nw + 255) / 256), dim3(256), 0, st, D, key0, key1);
+    hipLaunchKernelGGL(k_iota, dim3((D.N + 255) / 256), dim3(256), 0, st, scratch, D.N);
+    hipLaunchKernelGGL(k_srht_rows, dim3(1), dim3(1), 0, st, D, key0, key1_rows, scratch);
+  }
+}
+void launch_y_at(const Dev &D, int j, double *yout, hipStream_t st) {
+  hipLaunchKernelGGL(k_y_at, dim3((j + 255) / 256), dim3(256), 0, st, D, j, yout);
+}
+void launch_solution(const Dev &D, int kk, const double *yv, double *x, hipStream_t st) {
+  hipLaunchKernelGGL(k_solution, dim3((D.n + kWG - 1) / kWG), dim3(kWG),
+                     sizeof(double) * (size_t)max(1, kk), st, D, kk, yv, x);
+}
+void launch_true_residual(const Dev &D, const double *x, double *out, hipStream_t st) {
+  hipLaunchKernelGGL(k_true_residual, dim3(D.nw), dim3(kWG), 0, st, D, x, out);
+}
+
+}  // namespace sfk

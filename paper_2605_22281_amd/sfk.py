@@ -1,0 +1,334 @@
+"""Python binding of the C ABI in include/sfk.h (argument marshalling only).
+
+Every step of the method runs in the HIP library libsfk.so; PyTorch only
+provides device memory and the stream.  If the library is not built, or no GPU
+is present, the calls raise: there is no CPU fallback.
+
+Names follow the C entry points without the ``sfk_`` prefix:
+    init, iterate, solution, solution_at, residual_norms, true_residual,
+    destroy, validate, workspace_bytes, sketch_sparse_sign, sketch_srht,
+    coefficients.
+"""
+from __future__ import annotations
+
+import ctypes
+import dataclasses
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libsfk.so")
+
+OK, EINVAL, ENOMEM, EDEVICE, BREAKDOWN, ESTATE = range(6)
+SFLSQR, SFLSMR = 0, 1
+SK_SPARSE_SIGN, SK_SRHT, SK_IDENTITY = 0, 1, 2
+TAU_IDENTITY, TAU_REWEIGHT_L1 = 0, 1
+DRIVER_AUTO, DRIVER_MULTI, DRIVER_PERSISTENT = 0, 1, 2
+
+_METHODS = {"sflsqr": SFLSQR, "sflsmr": SFLSMR}
+_SKETCHES = {"sparse_sign": SK_SPARSE_SIGN, "countsketch": SK_SPARSE_SIGN, "srht": SK_SRHT,
+             "identity": SK_IDENTITY}
+_TAUS = {"identity": TAU_IDENTITY, "reweight_l1": TAU_REWEIGHT_L1}
+_DRIVERS = {"auto": DRIVER_AUTO, "multi": DRIVER_MULTI, "persistent": DRIVER_PERSISTENT}
+
+
+class SfkError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"sfk status {status}: {msg}")
+        self.status = status
+
+
+class CSR(ctypes.Structure):
+    _fields_ = [("rows", ctypes.c_int64), ("cols", ctypes.c_int64), ("nnz", ctypes.c_int64),
+                ("rowptr", ctypes.c_void_p), ("colind", ctypes.c_void_p), ("val", ctypes.c_void_p)]
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("method", ctypes.c_int32), ("ell", ctypes.c_int32), ("maxit", ctypes.c_int32),
+                ("sketch", ctypes.c_int32), ("s", ctypes.c_int32), ("zeta", ctypes.c_int32),
+                ("seed", ctypes.c_uint64), ("instance", ctypes.c_int32), ("tau", ctypes.c_int32),
+                ("eps", ctypes.c_double), ("eta", ctypes.c_double), ("noise_norm", ctypes.c_double),
+                ("tol", ctypes.c_double), ("driver", ctypes.c_int32), ("vw", ctypes.c_int32),
+                ("wg_per_cu", ctypes.c_int32), ("reserved", ctypes.c_int32 * 5)]
+
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    """Loads libsfk.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with paper_2605_22281_amd/build.py")
+    L = ctypes.CDLL(LIB_PATH)
+    P, I32, I64, PI32, PI8, PD = (ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64,
+                                  ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int8),
+                                  ctypes.POINTER(ctypes.c_double))
+    PCSR, PPAR = ctypes.POINTER(CSR), ctypes.POINTER(Params)
+    sig = {
+        "sfk_params_default": (None, [PPAR]),
+        "sfk_validate": (I32, [PCSR, PCSR, PPAR]),
+        "sfk_workspace_bytes": (ctypes.c_size_t, [PCSR, PCSR, PPAR]),
+        "sfk_init": (I32, [ctypes.POINTER(P), PCSR, PCSR, P, PPAR, P, ctypes.c_size_t, P]),
+        "sfk_iterate": (I32, [P, I32, PI32, PI32]),
+        "sfk_solution": (I32, [P, P]),
+        "sfk_solution_at": (I32, [P, I32, P]),
+        "sfk_residual_norms": (I32, [P, PD, I32, PI32, PD]),
+        "sfk_true_residual": (I32, [P, PD]),
+        "sfk_destroy": (I32, [P]),
+        "sfk_last_error": (ctypes.c_char_p, [P]),
+        "sfk_sketch_sparse_sign": (I32, [P, PI32, PI8]),
+        "sfk_sketch_srht": (I32, [P, PI32, PI8, ctypes.POINTER(I64)]),
+        "sfk_coefficients": (I32, [P, PD, PD, I32]),
+        "sfk_version": (ctypes.c_char_p, []),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(L, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = L
+    return L
+
+
+def exported_symbols() -> list[str]:
+    return ["sfk_params_default", "sfk_validate", "sfk_workspace_bytes", "sfk_init", "sfk_iterate",
+            "sfk_solution", "sfk_solution_at", "sfk_residual_norms", "sfk_true_residual",
+            "sfk_destroy", "sfk_last_error", "sfk_sketch_sparse_sign", "sfk_sketch_srht",
+            "sfk_coefficients", "sfk_version"]
+
+
+def _check(status: int, ctx=None):
+    if status != OK:
+        msg = lib().sfk_last_error(ctx)
+        raise SfkError(status, msg.decode() if msg else "")
+
+
+def params(method="sflsqr", *, ell=2, maxit=50, sketch="sparse_sign", s=101, zeta=8, seed=0,
+           instance=0, tau="identity", eps=1e-3, eta=1.01, noise_norm=0.0, tol=0.0,
+           driver="auto", vw=0, wg_per_cu=0) -> Params:
+    p = Params()
+    lib().sfk_params_default(ctypes.byref(p))
+    p.method = _METHODS[method] if isinstance(method, str) else int(method)
+    p.ell, p.maxit = ell, maxit
+    p.sketch = _SKETCHES[sketch] if isinstance(sketch, str) else int(sketch)
+    if sketch == "countsketch":
+        zeta = 1
+    p.s, p.zeta, p.seed, p.instance = s, zeta, seed, instance
+    p.tau = _TAUS[tau] if isinstance(tau, str) else int(tau)
+    p.eps, p.eta, p.noise_norm, p.tol = eps, eta, noise_norm, tol
+    p.driver = _DRIVERS[driver] if isinstance(driver, str) else int(driver)
+    p.vw, p.wg_per_cu = vw, wg_per_cu
+    return p
+
+
+# ----------------------------------------------------------------------------
+# device matrices
+# ----------------------------------------------------------------------------
+
+@dataclasses.dataclass
+class DeviceCSR:
+    """CSR arrays resident on the GPU (torch tensors keep the memory alive)."""
+    rows: int
+    cols: int
+    rowptr: object
+    colind: object
+    val: object
+
+    @property
+    def nnz(self) -> int:
+        return int(self.colind.numel())
+
+    def c(self) -> CSR:
+        return CSR(self.rows, self.cols, self.nnz, self.rowptr.data_ptr(),
+                   self.colind.data_ptr() if self.nnz else self.rowptr.data_ptr(),
+                   self.val.data_ptr() if self.nnz else self.rowptr.data_ptr())
+
+
+def to_device_csr(M, device="cuda") -> DeviceCSR:
+    """scipy CSR -> DeviceCSR (int32 indices, float64 values)."""
+    import torch
+    M = M.tocsr()
+    return DeviceCSR(M.shape[0], M.shape[1],
+                     torch.from_numpy(np.ascontiguousarray(M.indptr, dtype=np.int32)).to(device),
+                     torch.from_numpy(np.ascontiguousarray(M.indices, dtype=np.int32)).to(device),
+                     torch.from_numpy(np.ascontiguousarray(M.data, dtype=np.float64)).to(device))
+
+
+def host_csr_descriptor(rows: int, cols: int, nnz: int) -> CSR:
+    """A descriptor with NULL arrays, for host-only validation."""
+    return CSR(rows, cols, nnz, None, None, None)
+
+
+def validate(A: CSR, B: CSR | None, p: Params) -> tuple[int, str]:
+    st = lib().sfk_validate(ctypes.byref(A), ctypes.byref(B) if B is not None else None,
+                            ctypes.byref(p))
+    msg = lib().sfk_last_error(None).decode() if st != OK else ""
+    return st, msg
+
+
+def workspace_bytes(A: CSR, B: CSR | None, p: Params) -> int:
+    return int(lib().sfk_workspace_bytes(ctypes.byref(A),
+                                         ctypes.byref(B) if B is not None else None, ctypes.byref(p)))
+
+
+# ----------------------------------------------------------------------------
+# context
+# ----------------------------------------------------------------------------
+
+class Context:
+    """Owns an sfk_ctx; keeps the borrowed device buffers alive."""
+
+    def __init__(self, handle, A: DeviceCSR, B: DeviceCSR | None, b, p: Params, ws, stream):
+        self.handle = handle
+        self.A, self.B, self.b, self.p, self.ws, self.stream = A, B, b, p, ws, stream
+        self.m, self.n = A.rows, A.cols
+        self.k = 0
+        self.stopped = False
+
+    def __del__(self):
+        try:
+            destroy(self)
+        except Exception:
+            pass
+
+
+def init(A: DeviceCSR, B: DeviceCSR | None, b, p: Params, *, stream=None,
+         library_workspace: bool = False) -> Context:
+    """sfk_init: A (m x n), B (n x m) or None for A^T, b (m) float64 on the GPU."""
+    import torch
+    if not (b.is_cuda and b.dtype == torch.float64 and b.is_contiguous()):
+        raise ValueError("b must be a contiguous float64 CUDA tensor")
+    Ac = A.c()
+    Bc = B.c() if B is not None else None
+    ws = None
+    ws_ptr, ws_len = None, 0
+    if not library_workspace:
+        nbytes = workspace_bytes(Ac, Bc, p)
+        if nbytes == 0:
+            _check(validate(Ac, Bc, p)[0])
+        ws = torch.empty(nbytes, dtype=torch.uint8, device=b.device)
+        ws_ptr, ws_len = ws.data_ptr(), nbytes
+    st_obj = stream if stream is not None else torch.cuda.current_stream(b.device)
+    h = ctypes.c_void_p()
+    st = lib().sfk_init(ctypes.byref(h), ctypes.byref(Ac), ctypes.byref(Bc) if Bc is not None else None,
+                        b.data_ptr(), ctypes.byref(p), ws_ptr, ws_len, st_obj.cuda_stream)
+    _check(st)
+    return Context(h, A, B, b, p, ws, st_obj)
+
+
+def iterate(ctx: Context, k: int) -> tuple[int, bool, int]:
+    """sfk_iterate: returns (iterations done, stopped, status); BREAKDOWN is not raised."""
+    done, stopped = ctypes.c_int32(), ctypes.c_int32()
+    st = lib().sfk_iterate(ctx.handle, int(k), ctypes.byref(done), ctypes.byref(stopped))
+    if st not in (OK, BREAKDOWN):
+        _check(st, ctx.handle)
+    ctx.k, ctx.stopped = done.value, bool(stopped.value)
+    return done.value, bool(stopped.value), st
+
+
+def solution(ctx: Context, out=None):
+    import torch
+    x = out if out is not None else torch.empty(ctx.n, dtype=torch.float64, device=ctx.b.device)
+    _check(lib().sfk_solution(ctx.handle, x.data_ptr()), ctx.handle)
+    return x
+
+
+def solution_at(ctx: Context, j: int, out=None):
+    import torch
+    x = out if out is not None else torch.empty(ctx.n, dtype=torch.float64, device=ctx.b.device)
+    _check(lib().sfk_solution_at(ctx.handle, int(j), x.data_ptr()), ctx.handle)
+    return x
+
+
+def residual_norms(ctx: Context) -> tuple[np.ndarray, float]:
+    """Per-iteration minimised sketched objective rho_1..rho_k and the rhs norm."""
+    cap = max(1, ctx.p.maxit)
+    buf = (ctypes.c_double * cap)()
+    cnt = ctypes.c_int32()
+    rn = ctypes.c_double()
+    _check(lib().sfk_residual_norms(ctx.handle, buf, cap, ctypes.byref(cnt), ctypes.byref(rn)),
+           ctx.handle)
+    return np.array(buf[: cnt.value]), rn.value
+
+
+def true_residual(ctx: Context) -> float:
+    out = ctypes.c_double()
+    _check(lib().sfk_true_residual(ctx.handle, ctypes.byref(out)), ctx.handle)
+    return out.value
+
+
+def destroy(ctx: Context):
+    if ctx.handle is not None and _lib is not None:
+        lib().sfk_destroy(ctx.handle)
+        ctx.handle = None
+
+
+def sketch_sparse_sign(ctx: Context) -> tuple[np.ndarray, np.ndarray]:
+    d = ctx.m if ctx.p.method == SFLSQR else ctx.n
+    z = ctx.p.zeta
+    rows = np.zeros(d * z, dtype=np.int32)
+    neg = np.zeros(d * z, dtype=np.int8)
+    _check(lib().sfk_sketch_sparse_sign(ctx.handle, rows.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                                        neg.ctypes.data_as(ctypes.POINTER(ctypes.c_int8))), ctx.handle)
+    return rows.reshape(d, z), neg.reshape(d, z)
+
+
+def sketch_srht(ctx: Context) -> tuple[np.ndarray, np.ndarray]:
+    d = ctx.m if ctx.p.method == SFLSQR else ctx.n
+    N = 1
+    while N < d:
+        N *= 2
+    rows = np.zeros(ctx.p.s, dtype=np.int32)
+    neg = np.zeros(N, dtype=np.int8)
+    Nout = ctypes.c_int64()
+    _check(lib().sfk_sketch_srht(ctx.handle, rows.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                                 neg.ctypes.data_as(ctypes.POINTER(ctypes.c_int8)),
+                                 ctypes.byref(Nout)), ctx.handle)
+    return rows, neg
+
+
+def coefficients(ctx: Context, k: int) -> tuple[np.ndarray, np.ndarray]:
+    H = np.zeros((k, k + 1))
+    T = np.zeros((k, k))
+    _check(lib().sfk_coefficients(ctx.handle, H.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                  T.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), int(k)),
+           ctx.handle)
+    return H.T.copy(), T.T.copy()
+
+
+def version() -> str:
+    return lib().sfk_version().decode()
+
+
+# ----------------------------------------------------------------------------
+# convenience
+# ----------------------------------------------------------------------------
+
+class Solver:
+    """Owns device copies of a problem and one context."""
+
+    def __init__(self, A, b, *, B=None, device="cuda", **kw):
+        import torch
+        self.dA = A if isinstance(A, DeviceCSR) else to_device_csr(A, device)
+        self.dB = None if B is None else (B if isinstance(B, DeviceCSR) else to_device_csr(B, device))
+        self.b = b if hasattr(b, "is_cuda") else torch.from_numpy(np.ascontiguousarray(b, np.float64)).to(device)
+        self.p = params(**kw)
+        self.ctx = init(self.dA, self.dB, self.b, self.p)
+
+    def iterate(self, k: int):
+        return iterate(self.ctx, k)
+
+    def solution(self):
+        return solution(self.ctx)
+
+    def solution_at(self, j: int):
+        return solution_at(self.ctx, j)
+
+    def residual_norms(self):
+        return residual_norms(self.ctx)
+
+    def true_residual(self):
+        return true_residual(self.ctx)

@@ -1,0 +1,101 @@
+"""C-ABI library: it loads, exports every declared symbol, and its host-side
+validation rejects invalid arguments without touching a device."""
+import ctypes
+import os
+import re
+import subprocess
+
+import pytest
+
+from paper_2605_22281_amd import sfk
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "sfk.h")
+
+pytestmark = pytest.mark.skipif(not os.path.exists(sfk.LIB_PATH), reason="libsfk.so not built")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(sfk_[a-z_]+)\s*\(", text)))
+
+
+def test_every_declared_symbol_is_exported():
+    out = subprocess.run(["nm", "-D", "--defined-only", sfk.LIB_PATH], capture_output=True,
+                         text=True, check=True).stdout
+    exported = set(re.findall(r"\bT (sfk_\w+)", out))
+    decl = declared_functions()
+    assert decl, "no declarations parsed"
+    missing = [d for d in decl if d not in exported]
+    assert not missing, missing
+    assert set(sfk.exported_symbols()) <= exported
+    L = sfk.lib()
+    for d in decl:
+        assert hasattr(L, d)
+
+
+def test_params_layout_matches_header():
+    # sfk_params: 6 int32, uint64 seed, 2 int32, 4 double, 3 int32, 5 int32 reserved
+    assert ctypes.sizeof(sfk.Params) == 104
+    assert sfk.Params.seed.offset == 24 and sfk.Params.eps.offset == 40
+    assert ctypes.sizeof(sfk.CSR) == 48
+
+
+def test_defaults():
+    p = sfk.params()
+    assert (p.method, p.ell, p.maxit, p.sketch, p.s, p.zeta) == (0, 2, 50, 0, 101, 8)
+    assert p.eta == pytest.approx(1.01)
+
+
+def _A(m=200, n=80, nnz=500):
+    return sfk.host_csr_descriptor(m, n, nnz)
+
+
+@pytest.mark.parametrize("kw,frag", [
+    (dict(ell=-1), "ell"),
+    (dict(ell=9), "ell"),
+    (dict(s=50, maxit=50), "maxit"),
+    (dict(maxit=0), "maxit"),
+    (dict(s=3000, maxit=10), "s "),
+    (dict(zeta=0), "zeta"),
+    (dict(zeta=70, s=90), "zeta"),
+    (dict(s=101, maxit=50, sketch="identity"), "identity"),
+    (dict(tau="reweight_l1", eps=0.0), "eps"),
+    (dict(tol=-1.0), "tol"),
+    (dict(noise_norm=float("nan")), "noise"),
+    (dict(vw=12), "vw"),
+])
+def test_validation_rejects(kw, frag):
+    p = sfk.params(**kw)
+    st, msg = sfk.validate(_A(), None, p)
+    assert st == sfk.EINVAL
+    assert frag in msg
+
+
+def test_validation_dimensions():
+    p = sfk.params(s=60, maxit=20)
+    assert sfk.validate(_A(0, 10, 0), None, p)[0] == sfk.EINVAL
+    assert sfk.validate(_A(100, 80, -1), None, p)[0] == sfk.EINVAL
+    B_bad = sfk.host_csr_descriptor(200, 80, 10)          # should be 80 x 200
+    st, msg = sfk.validate(_A(), B_bad, p)
+    assert st == sfk.EINVAL and "B must be" in msg
+    # sparse-sign on m-vectors needs s <= m (sFLSQR); SRHT may pad
+    st, _ = sfk.validate(_A(40, 80, 10), None, sfk.params(s=60, maxit=20))
+    assert st == sfk.EINVAL
+    assert sfk.validate(_A(40, 80, 10), None, sfk.params(s=60, maxit=20, sketch="srht"))[0] == sfk.OK
+    assert sfk.validate(_A(), sfk.host_csr_descriptor(80, 200, 10), p)[0] == sfk.OK
+    assert sfk.validate(_A(100, 80, 5), None,
+                        sfk.params(method="sflsmr", s=80, maxit=20, sketch="identity"))[0] == sfk.OK
+
+
+def test_workspace_bytes_is_zero_for_invalid_and_grows_with_maxit():
+    assert sfk.workspace_bytes(_A(), None, sfk.params(ell=-3)) == 0
+    a = sfk.workspace_bytes(_A(), None, sfk.params(s=60, maxit=10))
+    b = sfk.workspace_bytes(_A(), None, sfk.params(s=60, maxit=40))
+    assert 0 < a < b and a % 256 == 0
+
+
+def test_last_error_never_null():
+    assert isinstance(sfk.lib().sfk_last_error(None), bytes)
+    assert "gfx950" in sfk.version()
