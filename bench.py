@@ -1,0 +1,224 @@
+#!/usr/bin/env python3
+"""Throughput of the sketched flexible Golub-Kahan iteration on one MI355X.
+
+Workload (default): 256 x 256 image (n = 65536), 180 angles x 363 bins
+(m = 65340), exact ray/pixel intersection lengths A, unmatched pixel-driven
+back-projector B, ellipse phantom, 2% noise; sFLSMR with an SRHT sketch of
+s = 400 rows, 200 iterations, FP64.  One step = one iteration of the method
+(forward projection, truncated Gram-Schmidt, sketch, small sketched least
+squares, back-projection, flexible preconditioner).  Inputs are resident in HBM
+before the timed region; the context set-up (init) is outside it.
+
+Prints one JSON line.  --gpus N with N > 1 is refused: this build runs on one
+GPU.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "sFLSQR iterations/sec + HBM GB/s (% peak); batched/plain speedup at 1e-8 rel"
+HBM_PEAK_GBS = 8000.0
+
+WORKLOADS = {
+    "ct256_unmatched": dict(method="sflsmr", sketch="srht", s=400, zeta=8, iters=200, tau="identity",
+                            desc="256^2 CT (180 angles x 363 bins), unmatched pixel-driven B, "
+                                 "sFLSMR, SRHT s=400, 200 iterations"),
+    "ct64": dict(method="sflsqr", sketch="sparse_sign", s=200, zeta=8, iters=50, tau="identity",
+                 desc="64^2 CT (90 angles x 91 bins), B = A^T, sFLSQR, sparse-sign s=200 zeta=8, "
+                      "50 iterations"),
+    "ct512_sparse": dict(method="sflsqr", sketch="sparse_sign", s=600, zeta=8, iters=300,
+                         tau="reweight_l1",
+                         desc="512^2 CT (360 angles x 725 bins), B = A^T, sFLSQR with l1 "
+                              "reweighting eps=1e-3, sparse-sign s=600 zeta=8, 300 iterations"),
+}
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def source_hash() -> str:
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2605_22281_amd", "csrc")
+    for f in sorted(os.listdir(csrc)):
+        with open(os.path.join(csrc, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def spmv_bytes(nnz: int, rows: int, cols: int, out_len: int, window: int) -> int:
+    """Algorithmic bytes of one CSR SpMV launch with the fused window dots:
+    12 B per nonzero (value + column), 4 B per row pointer, the gathered vector
+    once, the output once, and the window vectors once."""
+    return 12 * nnz + 4 * (rows + 1) + 8 * cols + 8 * out_len + 8 * out_len * window
+
+
+def copy_calibration(nbytes: int = 1 << 30):
+    """A plain device copy of known size, for scaling rocprofv3 byte counters."""
+    import torch
+    x = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
+    y = torch.empty_like(x)
+    for _ in range(3):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_read": nbytes, "copy_bytes_written": nbytes, "launches": 3}))
+
+
+def cpu_baseline(P, cfg, sample_iters: int):
+    from oracle import fgk, sketches
+    try:
+        from threadpoolctl import threadpool_info
+        blas_threads = max([d.get("num_threads", 1) for d in threadpool_info()] or [1])
+    except Exception:
+        blas_threads = os.cpu_count() or 1
+    d = P.m if cfg["method"] == "sflsqr" else P.n
+    S = sketches.make(cfg["sketch"], d, cfg["s"], 3000 + 2, zeta=cfg["zeta"])
+    B = P.B
+    t0 = time.perf_counter()
+    fgk.sketched_flexible(P.A, P.b, S, method=cfg["method"], B=B, maxit=sample_iters, ell=2,
+                          tau=cfg["tau"], eps=1e-3)
+    dt = time.perf_counter() - t0
+    model = ""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return {"value": sample_iters / dt, "unit": "iterations/s", "cores": blas_threads,
+            "kind": "oracle",
+            "sample": f"first {sample_iters} iterations of the same run "
+                      f"({dt:.1f} s; scipy CSR products single-threaded, numpy BLAS "
+                      f"{blas_threads} threads; {model}, {os.cpu_count()} logical CPUs)"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=None)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--workload", default="ct256_unmatched", choices=sorted(WORKLOADS))
+    ap.add_argument("--driver", default="auto", choices=["auto", "multi", "persistent"])
+    ap.add_argument("--vw", type=int, default=0, help="SpMV variant (0 = CSR-stream)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sample-iters", type=int, default=40)
+    ap.add_argument("--copy-calibration", action="store_true")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(f"bench.py: --gpus {args.gpus} is not supported: this build measures one GPU "
+              f"(a single MI355X); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+    if args.copy_calibration:
+        copy_calibration()
+        return
+
+    import numpy as np
+    import torch
+    from paper_2605_22281_amd import inputs, sfk
+
+    cfg = WORKLOADS[args.workload]
+    K = args.steps if args.steps is not None else cfg["iters"]
+    if K < 1 or K >= cfg["s"]:
+        raise SystemExit(f"--steps must be in [1, {cfg['s'] - 1}] for this workload")
+    W = args.warmup
+    log(f"bench: generating {args.workload}")
+    t = time.perf_counter()
+    P = inputs.workload(args.workload)
+    log(f"bench: m={P.m} n={P.n} nnzA={P.A.nnz} nnzB={(P.B.nnz if P.B is not None else P.A.nnz)} "
+        f"({time.perf_counter() - t:.1f} s)")
+    dev = torch.device("cuda:0")
+    A = sfk.to_device_csr(P.A, dev)
+    B = sfk.to_device_csr(P.B, dev) if P.B is not None else None
+    b = torch.from_numpy(P.b).to(dev)
+    maxit = max(K, W, 1)
+    p = sfk.params(cfg["method"], ell=2, maxit=maxit, sketch=cfg["sketch"], s=cfg["s"],
+                   zeta=cfg["zeta"], seed=3000 + 2, tau=cfg["tau"], eps=1e-3, driver=args.driver,
+                   vw=args.vw)
+
+    if W > 0:
+        log(f"bench: warmup {W} iterations")
+        ctx = sfk.init(A, B, b, p)
+        sfk.iterate(ctx, W)
+        sfk.destroy(ctx)
+
+    # timed region: K iterations of a fresh context (init outside)
+    ctx = sfk.init(A, B, b, p)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    done, stopped, st = sfk.iterate(ctx, K)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    log(f"bench: timed {done} iterations in {elapsed * 1e3:.2f} ms")
+    if done != K:
+        raise SystemExit(f"run ended after {done} of {K} iterations (status {st})")
+    sfk.destroy(ctx)
+
+    # same work again with HIP events around every stage kernel (library stream)
+    ctx = sfk.init(A, B, b, p)
+    sfk.set_timing(ctx, True)
+    sfk.iterate(ctx, K)
+    times = sfk.stage_times(ctx)
+    sfk.destroy(ctx)
+
+    nnzA = P.A.nnz
+    nnzB = P.B.nnz if P.B is not None else P.A.nnz
+    ell = 2
+    per_launch = {
+        "spmv_A": spmv_bytes(nnzA, P.m, P.n, P.m, ell + 1),
+        "spmv_B": spmv_bytes(nnzB, P.n, P.m, P.n, ell),
+    }
+    stage_avg = {k: (v[0] / v[1] if v[1] else 0.0) for k, v in times.items()}
+    dom = max(("spmv_A", "spmv_B"), key=lambda s: times[s][0])
+    achieved = per_launch[dom] / (stage_avg[dom] * 1e-3) / 1e9
+    traffic = None
+    tr_file = os.path.join(ROOT, "profiles", "traffic.json")
+    if os.path.exists(tr_file):
+        try:
+            tr = json.load(open(tr_file))
+            if tr.get("source_hash") == source_hash() and tr.get("workload") == args.workload:
+                traffic = tr.get("bytes_per_launch", {}).get(dom)
+        except (OSError, ValueError):
+            traffic = None
+
+    ms_per_step = elapsed * 1e3 / K
+    iter_bytes = per_launch["spmv_A"] + per_launch["spmv_B"] + 8 * (P.m * (ell + 3) + P.n * (ell + 3))
+    out = {
+        "metric": METRIC,
+        "value": K / elapsed,
+        "unit": "iterations/s",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": W,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": cfg["desc"], "m": P.m, "n": P.n, "nnz_A": nnzA, "nnz_B": nnzB,
+                   "method": cfg["method"], "sketch": cfg["sketch"], "s": cfg["s"], "ell": ell,
+                   "driver": args.driver, "spmv_variant": args.vw},
+        "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "bytes_per_launch": per_launch[dom], "avg_launch_ms": stage_avg[dom]},
+        "iteration_GBps": iter_bytes / (ms_per_step * 1e-3) / 1e9,
+        "stage_avg_ms": stage_avg,
+    }
+    if not args.no_cpu_baseline:
+        log(f"bench: oracle baseline, {args.cpu_sample_iters} iterations")
+        out["cpu_baseline"] = cpu_baseline(P, cfg, args.cpu_sample_iters)
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -42,7 +42,7 @@ typedef enum {
   SFK_EINVAL = 1,     /* invalid argument: dims, params, CSR structure, b zero or non-finite */
   SFK_ENOMEM = 2,     /* device allocation failed, or caller workspace too small */
   SFK_EDEVICE = 3,    /* HIP runtime error or no suitable device */
-  SFK_BREAKDOWN = 4,  /* basis could not be extended (Q10 reading); results stay valid */
+  SFK_BREAKDOWN = 4,  /* basis cannot grow (t_kk or h_{k+1,k} zero); results stay valid */
   SFK_ESTATE = 5      /* call not allowed in the context's state (e.g. k out of range) */
 } sfk_status;
 
@@ -90,7 +90,8 @@ typedef struct {
   double tol;          /* relative tolerance of the sketched stop test when the
                           discrepancy stop is off; 0 runs to maxit */
   int32_t driver;      /* sfk_driver */
-  int32_t vw;          /* SpMV lanes per row (8, 16, 32, 64); 0 = automatic */
+  int32_t vw;          /* SpMV variant: 0 = CSR-stream chunks, 8/16/32/64 = lanes per
+                          row, -1 = lanes per row chosen from the mean row length */
   int32_t wg_per_cu;   /* data-parallel workgroups per CU; 0 = automatic */
   int32_t reserved[5];
 } sfk_params;
@@ -165,6 +166,28 @@ sfk_status sfk_sketch_srht(sfk_ctx *ctx, int32_t *rows_host, int8_t *neg_host, i
 /* Recurrence coefficients of eq. (FGK) for the first k steps: H_host
  * ((k+1) x k, column-major) and T_host (k x k, column-major). */
 sfk_status sfk_coefficients(sfk_ctx *ctx, double *H_host, double *T_host, int32_t k);
+
+/* ---- timing ---------------------------------------------------------------- */
+
+/* Stages of one iteration, in the order the multi-kernel driver runs them. */
+typedef enum {
+  SFK_STAGE_SPMV_A = 0,    /* w = A z_k with the window dot products   (paper Alg. 1/2) */
+  SFK_STAGE_W_UPDATE = 1,  /* truncated Gram-Schmidt of w, ||w||                  */
+  SFK_STAGE_SKETCH = 2,    /* one new sketched column                            */
+  SFK_STAGE_LS = 3,        /* Householder update of the sketched least squares    */
+  SFK_STAGE_SPMV_B = 4,    /* z = B w_{k+1} with the window dot products          */
+  SFK_STAGE_P_UPDATE = 5,  /* truncated Gram-Schmidt of z, tau, ||p||             */
+  SFK_NUM_STAGES = 6
+} sfk_stage;
+
+/* Enables (on != 0) or disables timing of every stage kernel with HIP events
+ * recorded on the context's stream, and clears the accumulated times.  Timing
+ * adds event records between the kernels. */
+sfk_status sfk_set_timing(sfk_ctx *ctx, int32_t on);
+
+/* Accumulated kernel time per stage (ms_host[SFK_NUM_STAGES]) and number of
+ * timed launches (count_host[SFK_NUM_STAGES]) since sfk_set_timing. */
+sfk_status sfk_stage_times(sfk_ctx *ctx, double *ms_host, int32_t *count_host);
 
 /* Library and device description (static string). */
 const char *sfk_version(void);

@@ -8,15 +8,22 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <utility>
+#include <vector>
 
 #include "sfk.h"
 #include "sfk_dev.h"
 
 namespace sfk {
-void launch_iteration(const Dev &D, int k, hipStream_t st);
+void launch_stage_A(const Dev &D, int k, hipStream_t st);
+void launch_stage_B(const Dev &D, int k, hipStream_t st);
 void launch_stage_C(const Dev &D, int k, hipStream_t st);
+void launch_ls(const Dev &D, int k, hipStream_t st);
+int spmv_blocks_per_cu();
 void launch_stage_D(const Dev &D, int k, hipStream_t st);
-void launch_sketch(const Dev &D, const double *v, double *dst, hipStream_t st);
+void launch_sketch(const Dev &D, int k, const double *v, double *dst, hipStream_t st);
+const double *sketch_src(const Dev &D, int k);
+double *sketch_dst(const Dev &D, int k);
 void launch_init_b(const Dev &D, double eta, double noise, double tol_user, int use_disc,
                    hipStream_t st);
 void launch_init_rhs(const Dev &D, hipStream_t st);
@@ -38,6 +45,9 @@ struct sfk_ctx {
   sfk_params p;
   Dev D;
   hipStream_t stream = nullptr;
+  hipStream_t side = nullptr;       // sketch + least-squares stream (default priority)
+  static constexpr int kRing = 4;   // iterations of synchronisation events kept
+  hipEvent_t ev_main[kRing] = {}, ev_sk[kRing] = {}, ev_ls[kRing] = {};
   void *ws = nullptr;
   size_t ws_bytes = 0;
   bool owns_ws = false;
@@ -50,7 +60,82 @@ struct sfk_ctx {
   double *d_ytmp = nullptr;       // maxit
   Scal *h_scal = nullptr;         // pinned copy of the device scalars
   std::string err;
+  // optional per-stage timing with HIP events on the context's stream
+  bool timing = false;
+  std::vector<hipEvent_t> ev_pool;
+  std::vector<std::pair<int, int>> ev_used;   // (stage, index of the start event)
+  double stage_ms[SFK_NUM_STAGES] = {};
+  int stage_count[SFK_NUM_STAGES] = {};
 };
+
+// records the start event of a timed stage; returns its pool index or -1
+static int stage_begin(sfk_ctx *c, int stage, hipStream_t st) {
+  if (!c->timing) return -1;
+  const size_t need = c->ev_used.size() * 2 + 2;
+  while (c->ev_pool.size() < need) {
+    hipEvent_t e;
+    if (hipEventCreate(&e) != hipSuccess) return -1;
+    c->ev_pool.push_back(e);
+  }
+  const int idx = (int)c->ev_used.size() * 2;
+  hipEventRecord(c->ev_pool[idx], st);
+  c->ev_used.push_back({stage, idx});
+  return idx;
+}
+
+static void stage_end(sfk_ctx *c, int idx, hipStream_t st) {
+  if (idx >= 0) hipEventRecord(c->ev_pool[idx + 1], st);
+}
+
+static void collect_stage_times(sfk_ctx *c) {
+  for (auto &u : c->ev_used) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, c->ev_pool[u.second], c->ev_pool[u.second + 1]) == hipSuccess) {
+      c->stage_ms[u.first] += ms;
+      c->stage_count[u.first] += 1;
+    }
+  }
+  c->ev_used.clear();
+}
+
+// One iteration k of Algorithm 1 (sFLSQR) or Algorithm 2 (sFLSMR).  The
+// data-parallel stages A, B, C, D run on the context's stream; the sketch of
+// the new vector and the least-squares update run on the side stream as soon
+// as their input exists.  The raw vectors are double-buffered by iteration
+// parity, so iteration k + 2 waits for the sketch of iteration k only.  The
+// reweighting needs y_k before D(k), so it waits for LS(k).
+static void enqueue_iteration(sfk_ctx *c, int k) {
+  const Dev &D = c->D;
+  hipStream_t st = c->stream, sd = c->side;
+  const int r = k % sfk_ctx::kRing;
+  if (k >= 3) hipStreamWaitEvent(st, c->ev_sk[(k - 2) % sfk_ctx::kRing], 0);
+  int t = stage_begin(c, SFK_STAGE_SPMV_A, st);
+  launch_stage_A(D, k, st);
+  stage_end(c, t, st);
+  t = stage_begin(c, SFK_STAGE_W_UPDATE, st);
+  launch_stage_B(D, k, st);
+  stage_end(c, t, st);
+  if (D.method == 0) hipEventRecord(c->ev_main[r], st);
+  t = stage_begin(c, SFK_STAGE_SPMV_B, st);
+  launch_stage_C(D, k, st);
+  stage_end(c, t, st);
+  if (D.method == 1) hipEventRecord(c->ev_main[r], st);
+
+  hipStreamWaitEvent(sd, c->ev_main[r], 0);
+  t = stage_begin(c, SFK_STAGE_SKETCH, sd);
+  launch_sketch(D, k, sketch_src(D, k), sketch_dst(D, k), sd);
+  stage_end(c, t, sd);
+  hipEventRecord(c->ev_sk[r], sd);
+  t = stage_begin(c, SFK_STAGE_LS, sd);
+  launch_ls(D, k, sd);
+  stage_end(c, t, sd);
+  hipEventRecord(c->ev_ls[r], sd);
+
+  if (D.tau == 1) hipStreamWaitEvent(st, c->ev_ls[r], 0);
+  t = stage_begin(c, SFK_STAGE_P_UPDATE, st);
+  launch_stage_D(D, k, st);
+  stage_end(c, t, st);
+}
 
 static thread_local std::string g_err;
 
@@ -145,8 +230,8 @@ static sfk_status validate(sfk_ctx *c, const sfk_csr *A, const sfk_csr *B, const
     return fail(c, SFK_EINVAL, "noise_norm must be finite >= 0");
   if (!(p->tol >= 0.0) || !std::isfinite(p->tol)) return fail(c, SFK_EINVAL, "tol must be finite >= 0");
   if (p->driver < 0 || p->driver > 2) return fail(c, SFK_EINVAL, "unknown driver %d", p->driver);
-  if (p->vw != 0 && p->vw != 8 && p->vw != 16 && p->vw != 32 && p->vw != 64)
-    return fail(c, SFK_EINVAL, "vw must be 0, 8, 16, 32 or 64");
+  if (p->vw != 0 && p->vw != -1 && p->vw != 8 && p->vw != 16 && p->vw != 32 && p->vw != 64)
+    return fail(c, SFK_EINVAL, "vw must be -1, 0, 8, 16, 32 or 64");
   if (p->wg_per_cu < 0 || p->wg_per_cu > 64) return fail(c, SFK_EINVAL, "wg_per_cu out of range");
   return SFK_OK;
 }
@@ -173,7 +258,7 @@ struct Plan {
   int nw, vwA, vwB, d, N, log2L, nblk, nchunk;
   bool transpose;
   // offsets
-  size_t o_sc, o_ticket, o_err, o_scalar, o_part, o_sigw, o_sigp, o_H, o_T, o_rho;
+  size_t o_sc, o_err, o_scalar, o_part, o_sigw, o_sigp, o_H, o_T, o_rho;
   size_t o_W, o_P, o_Z, o_wraw, o_zraw, o_x, o_Apart, o_Bpart;
   size_t o_skcode, o_skent, o_skrp, o_chunk, o_srows, o_sd, o_spart, o_SK, o_skrhs;
   size_t o_V, o_tauv, o_R, o_Rinv, o_c, o_y, o_ytmp;
@@ -182,7 +267,9 @@ struct Plan {
 };
 
 static int pick_vw(int64_t nnz, int64_t rows, int user) {
-  if (user) return user;
+  if (user > 0) return user;
+  if (user == 0) return 0;     // CSR-stream
+  // user < 0: row-parallel with a width from the mean row length
   const double avg = rows > 0 ? (double)nnz / (double)rows : 0.0;
   if (avg >= 96) return 64;
   if (avg >= 40) return 32;
@@ -190,7 +277,8 @@ static int pick_vw(int64_t nnz, int64_t rows, int user) {
   return 8;
 }
 
-static Plan make_plan(const sfk_csr *A, const sfk_csr *B, const sfk_params *p, int cus) {
+static Plan make_plan(const sfk_csr *A, const sfk_csr *B, const sfk_params *p, int cus,
+                      int blocks_per_cu) {
   Plan P{};
   P.m = A->rows;
   P.n = A->cols;
@@ -198,9 +286,9 @@ static Plan make_plan(const sfk_csr *A, const sfk_csr *B, const sfk_params *p, i
   P.transpose = (B == nullptr);
   P.nnzB = B ? B->nnz : A->nnz;
   const int64_t nnzmax = std::max(P.nnzA, P.nnzB);
-  const int cap = cus * (p->wg_per_cu ? p->wg_per_cu : 8);
+  const int cap = cus * (p->wg_per_cu ? p->wg_per_cu : std::max(1, blocks_per_cu));
   int64_t nw = (nnzmax + 8191) / 8192;
-  nw = std::max<int64_t>(nw, (std::max(P.m, P.n) + 4095) / 4096);
+  nw = std::max<int64_t>(nw, (std::max(P.m, P.n) + 2047) / 2048);
   nw = std::min<int64_t>(std::max<int64_t>(nw, 1), cap);
   P.nw = (int)nw;
   P.vwA = pick_vw(P.nnzA, P.m, p->vw);
@@ -215,10 +303,12 @@ static Plan make_plan(const sfk_csr *A, const sfk_csr *B, const sfk_params *p, i
   const int64_t m = P.m, n = P.n, s = p->s, mi = p->maxit, ell = p->ell, zeta = p->zeta;
   Layout L_;
   P.o_sc = L_.take<Scal>(1);
-  P.o_ticket = L_.take<unsigned>(1);
   P.o_err = L_.take<int>(1);
   P.o_scalar = L_.take<double>(1);
-  P.o_part = L_.take<double>((size_t)kMaxQ * P.nw);
+  // sized for the largest grid any occupancy could give, so that the workspace size
+  // does not depend on the device's register allocation
+  const int nw_alloc = std::max(P.nw, cus * 8);
+  P.o_part = L_.take<double>((size_t)kNumPart * kMaxQ * nw_alloc);
   P.o_sigw = L_.take<double>(mi + 2);
   P.o_sigp = L_.take<double>(mi + 2);
   P.o_H = L_.take<double>((mi + 1) * mi);
@@ -227,11 +317,11 @@ static Plan make_plan(const sfk_csr *A, const sfk_csr *B, const sfk_params *p, i
   P.o_W = L_.take<double>((ell + 2) * m);
   P.o_P = L_.take<double>(p->tau == SFK_TAU_REWEIGHT_L1 ? (ell + 1) * n : 1);
   P.o_Z = L_.take<double>((mi + 1) * n);      // z~_1 .. z~_{maxit+1}
-  P.o_wraw = L_.take<double>(m);
-  P.o_zraw = L_.take<double>(std::max<int64_t>(n, (P.N + 1) / 2 + 1));
+  P.o_wraw = L_.take<double>(2 * m);
+  P.o_zraw = L_.take<double>(2 * std::max<int64_t>(n, (P.N + 1) / 2 + 1));
   P.o_x = L_.take<double>(n);
-  P.o_Apart = L_.take<int>(P.nw + 1);
-  P.o_Bpart = L_.take<int>(P.nw + 1);
+  P.o_Apart = L_.take<int>(nw_alloc + 1);
+  P.o_Bpart = L_.take<int>(nw_alloc + 1);
   const bool ss = p->sketch == SFK_SK_SPARSE_SIGN;
   const bool sr = p->sketch == SFK_SK_SRHT;
   P.o_skcode = L_.take<int>(ss ? zeta * P.d : 1);
@@ -271,7 +361,7 @@ extern "C" size_t sfk_workspace_bytes(const sfk_csr *A, const sfk_csr *B, const 
   if (validate(nullptr, A, B, p) != SFK_OK) return 0;
   int cus = device_cus();
   if (cus <= 0) cus = 256;
-  return make_plan(A, B, p, cus).total;
+  return make_plan(A, B, p, cus, 2).total;
 }
 
 // --------------------------------------------------------------------------
@@ -301,7 +391,7 @@ static sfk_status init_impl(sfk_ctx *c, const sfk_csr *A, const sfk_csr *B, cons
     return fail(c, SFK_EINVAL, "A arrays and b must be device pointers");
   if (B && ((B->nnz > 0 && (!B->colind || !B->val)) || !B->rowptr))
     return fail(c, SFK_EINVAL, "B arrays must be device pointers");
-  const Plan P = make_plan(A, B, &p, cus);
+  const Plan P = make_plan(A, B, &p, cus, spmv_blocks_per_cu());
   if (workspace) {
     if (ws_bytes < P.total)
       return fail(c, SFK_ENOMEM, "workspace of %zu bytes is smaller than the %zu required",
@@ -318,6 +408,12 @@ static sfk_status init_impl(sfk_ctx *c, const sfk_csr *A, const sfk_csr *B, cons
   }
   c->ws_bytes = P.total;
   HIPCHK(c, hipHostMalloc((void **)&c->h_scal, sizeof(Scal), hipHostMallocDefault));
+  HIPCHK(c, hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking));
+  for (int i = 0; i < sfk_ctx::kRing; ++i) {
+    HIPCHK(c, hipEventCreateWithFlags(&c->ev_main[i], hipEventDisableTiming));
+    HIPCHK(c, hipEventCreateWithFlags(&c->ev_sk[i], hipEventDisableTiming));
+    HIPCHK(c, hipEventCreateWithFlags(&c->ev_ls[i], hipEventDisableTiming));
+  }
   void *w = c->ws;
   hipStream_t st = c->stream;
   HIPCHK(c, hipMemsetAsync(w, 0, P.total, st));
@@ -351,7 +447,7 @@ static sfk_status init_impl(sfk_ctx *c, const sfk_csr *A, const sfk_csr *B, cons
   D.P = at<double>(w, P.o_P);
   D.Z = at<double>(w, P.o_Z);
   D.wraw = at<double>(w, P.o_wraw);
-  D.zraw = at<double>(w, P.o_zraw);
+  D.zraw = at<double>(w, P.o_zraw);   // slot 1 starts at zraw + n
   D.x = at<double>(w, P.o_x);
   D.sk_rp = at<int>(w, P.o_skrp);
   D.sk_ent = at<int>(w, P.o_skent);
@@ -362,7 +458,6 @@ static sfk_status init_impl(sfk_ctx *c, const sfk_csr *A, const sfk_csr *B, cons
   D.SK = at<double>(w, P.o_SK);
   D.skrhs = at<double>(w, P.o_skrhs);
   D.part = at<double>(w, P.o_part);
-  D.ticket = at<unsigned>(w, P.o_ticket);
   D.sc = at<Scal>(w, P.o_sc);
   D.sigw = at<double>(w, P.o_sigw);
   D.sigp = at<double>(w, P.o_sigp);
@@ -416,9 +511,9 @@ static sfk_status init_impl(sfk_ctx *c, const sfk_csr *A, const sfk_csr *B, cons
   // Algorithm 1 / 2 initial lines
   const int use_disc = (p.method == SFK_SFLSQR && p.noise_norm > 0.0) ? 1 : 0;
   launch_init_b(D, p.eta, p.noise_norm, p.tol, use_disc, st);
-  if (p.method == SFK_SFLSQR) launch_sketch(D, b, D.skrhs, st);
+  if (p.method == SFK_SFLSQR) launch_sketch(D, 0, b, D.skrhs, st);
   launch_stage_C(D, 0, st);
-  if (p.method == SFK_SFLSMR) launch_sketch(D, D.zraw, D.SK, st);
+  if (p.method == SFK_SFLSMR) launch_sketch(D, 0, D.zraw, D.SK, st);
   launch_init_rhs(D, st);
   launch_stage_D(D, 0, st);
   HIPCHK(c, hipGetLastError());
@@ -429,6 +524,21 @@ static sfk_status init_impl(sfk_ctx *c, const sfk_csr *A, const sfk_csr *B, cons
   if (c->h_scal->breakdown)
     return fail(c, SFK_BREAKDOWN, "B b is zero: the first basis vector does not exist");
   return SFK_OK;
+}
+
+static void release(sfk_ctx *c) {
+  hipStreamSynchronize(c->stream);
+  if (c->side) hipStreamSynchronize(c->side);
+  for (int i = 0; i < sfk_ctx::kRing; ++i) {
+    if (c->ev_main[i]) hipEventDestroy(c->ev_main[i]);
+    if (c->ev_sk[i]) hipEventDestroy(c->ev_sk[i]);
+    if (c->ev_ls[i]) hipEventDestroy(c->ev_ls[i]);
+  }
+  for (hipEvent_t e : c->ev_pool) hipEventDestroy(e);
+  if (c->side) hipStreamDestroy(c->side);
+  if (c->owns_ws && c->ws) hipFree(c->ws);
+  if (c->h_scal) hipHostFree(c->h_scal);
+  delete c;
 }
 
 extern "C" sfk_status sfk_init(sfk_ctx **out, const sfk_csr *A, const sfk_csr *B, const double *b,
@@ -444,10 +554,7 @@ extern "C" sfk_status sfk_init(sfk_ctx **out, const sfk_csr *A, const sfk_csr *B
   s = init_impl(c, A, B, b, workspace, workspace_bytes);
   if (s != SFK_OK) {
     g_err = c->err;
-    hipStreamSynchronize(c->stream);
-    if (c->owns_ws && c->ws) hipFree(c->ws);
-    if (c->h_scal) hipHostFree(c->h_scal);
-    delete c;
+    release(c);
     return s;
   }
   *out = c;
@@ -473,10 +580,13 @@ extern "C" sfk_status sfk_iterate(sfk_ctx *c, int32_t k, int32_t *iters_done_hos
   const int room = c->p.maxit - c->k_done;
   if (k > room) return fail(c, SFK_ESTATE, "capacity maxit = %d exhausted (done %d, asked %d)",
                             c->p.maxit, c->k_done, k);
-  for (int i = 1; i <= k; ++i) launch_iteration(c->D, c->k_done + i, c->stream);
+  const int k0 = c->k_done;
+  for (int i = 1; i <= k; ++i) enqueue_iteration(c, k0 + i);
+  if (k > 0) HIPCHK(c, hipStreamWaitEvent(c->stream, c->ev_ls[(k0 + k) % sfk_ctx::kRing], 0));
   HIPCHK(c, hipGetLastError());
   sfk_status s = read_scal(c);
   if (s != SFK_OK) return s;
+  collect_stage_times(c);
   report();
   if (c->breakdown) return fail(c, SFK_BREAKDOWN, "the basis broke down after iteration %d", c->k_done);
   return SFK_OK;
@@ -536,12 +646,25 @@ extern "C" sfk_status sfk_true_residual(sfk_ctx *c, double *out_host) {
   return SFK_OK;
 }
 
+extern "C" sfk_status sfk_set_timing(sfk_ctx *c, int32_t on) {
+  if (!c) return fail(nullptr, SFK_EINVAL, "NULL context");
+  c->timing = on != 0;
+  for (int i = 0; i < SFK_NUM_STAGES; ++i) { c->stage_ms[i] = 0.0; c->stage_count[i] = 0; }
+  return SFK_OK;
+}
+
+extern "C" sfk_status sfk_stage_times(sfk_ctx *c, double *ms_host, int32_t *count_host) {
+  if (!c) return fail(nullptr, SFK_EINVAL, "NULL context");
+  for (int i = 0; i < SFK_NUM_STAGES; ++i) {
+    if (ms_host) ms_host[i] = c->stage_ms[i];
+    if (count_host) count_host[i] = c->stage_count[i];
+  }
+  return SFK_OK;
+}
+
 extern "C" sfk_status sfk_destroy(sfk_ctx *c) {
   if (!c) return SFK_OK;
-  hipStreamSynchronize(c->stream);
-  if (c->owns_ws && c->ws) hipFree(c->ws);
-  if (c->h_scal) hipHostFree(c->h_scal);
-  delete c;
+  release(c);
   return SFK_OK;
 }
 

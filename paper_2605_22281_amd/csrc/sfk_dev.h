@@ -10,10 +10,15 @@ namespace sfk {
 
 constexpr int kMaxEll = 8;                 // orthogonalisation window limit
 constexpr int kMaxS = 2048;                // sketch rows limit (LS kept in one wave)
-constexpr int kWG = 256;                   // threads per data-parallel workgroup
+constexpr int kWG = 256;                   // threads per vector-stage workgroup
+constexpr int kSpmvWG = 1024;              // threads per SpMV workgroup
+constexpr int kRowsLDS = 2048;             // SpMV results kept in LDS for the epilogue
 constexpr int kMaxQ = kMaxEll + 2;         // partial sums per workgroup and stage
 constexpr int kSrhtL = 2048;               // SRHT block length staged in LDS
 constexpr double kBreakdownTol = 1e-14;    // relative breakdown threshold
+
+// Partial-sum buffers, one per producing stage.
+enum Stage { kStageA = 0, kStageB = 1, kStageC = 2, kStageD = 3, kStageMisc = 4, kNumPart = 5 };
 
 // Scalar state shared by the stages (device memory).  Slots: w_j lives in
 // W ring slot j % (ell + 2), p_j in P ring slot j % (ell + 1).
@@ -23,17 +28,16 @@ struct Scal {
   double tol;         // relative tolerance of the stop test (0: none)
   double wpre;        // ||A z_k|| before orthogonalisation
   double zpre;        // ||B w_{k+1}|| before orthogonalisation
-  double wcoef[kMaxEll + 1];   // w~_j multipliers of the current w update
-  double pcoef[kMaxEll + 1];   // p~_j multipliers of the current p update
   double Gw[(kMaxEll + 2) * (kMaxEll + 2)];  // <w_i, w_j> by slot
   double Gp[(kMaxEll + 1) * (kMaxEll + 1)];  // <p_i, p_j> by slot
-  int halt;           // 1: no further stage may run
+  int halt;           // 1: no further stage may run (stop test, or after a breakdown's LS)
+  int klimit;         // last iteration whose basis vector exists (t breakdown)
   int stopped;        // stop test fired
-  int breakdown;      // 1: t breakdown, 2: h breakdown
+  int breakdown;      // bits: 1 t_{k+1,k+1} = 0, 2 h_{k+1,k} = 0, 4 zero sketched column
   int k_done;         // iterations whose LS has completed
-  int happy;          // h_{k+1,k} == 0 at the current step
-  int err;            // device-detected error code (CSR check)
-  int pad[2];
+  int happy;          // iteration k with h_{k+1,k} = 0 (0: none)
+  int err;            // device-detected error code
+  int pad;
 };
 
 struct Dev {
@@ -43,7 +47,7 @@ struct Dev {
   int N;              // SRHT padded length
   int log2L;          // SRHT block length log2
   int nblk;           // SRHT blocks
-  int nw;             // data-parallel workgroups
+  int nw;             // data-parallel workgroups of every stage
   int vwA, vwB;       // SpMV lanes per row
   double eps;
   double sk_scale;    // 1/sqrt(zeta) or 1/sqrt(s)
@@ -56,8 +60,8 @@ struct Dev {
   double *W;          // (ell + 2) * m, unnormalised w~_j
   double *P;          // (ell + 1) * n, unnormalised p~_j (unused when tau = I)
   double *Z;          // (maxit + 1) * n, z~_j (column j-1)
-  double *wraw;       // m, A z_k
-  double *zraw;       // n, B w_{k+1}
+  double *wraw;       // 2 * m, A z_k in slot k & 1
+  double *zraw;       // 2 * n, B w_{k+1} in slot k & 1
   double *x;          // n, current iterate (reweighting) / scratch
   // sketch
   int *sk_rp;         // s + 1   (sparse-sign, transposed: entries per sketch row)
@@ -69,8 +73,7 @@ struct Dev {
   double *SK;         // s * (maxit + 1), sketched columns
   double *skrhs;      // s
   // stage reductions
-  double *part;       // kMaxQ * nw
-  unsigned *ticket;   // 1
+  double *part;       // kNumPart * kMaxQ * nw
   Scal *sc;
   double *sigw;       // maxit + 2: 1 / ||w~_j||
   double *sigp;       // maxit + 2: 1 / ||p~_j||
@@ -88,6 +91,8 @@ struct Dev {
 
 __device__ __forceinline__ int wslot(const Dev &D, int j) { return j % (D.ell + 2); }
 __device__ __forceinline__ int pslot(const Dev &D, int j) { return j % (D.ell + 1); }
+__device__ __forceinline__ double *wrawk(const Dev &D, int k) { return D.wraw + (size_t)(k & 1) * D.m; }
+__device__ __forceinline__ double *zrawk(const Dev &D, int k) { return D.zraw + (size_t)(k & 1) * D.n; }
 __device__ __forceinline__ double *wvec(const Dev &D, int j) { return D.W + (size_t)wslot(D, j) * D.m; }
 __device__ __forceinline__ double *pvec(const Dev &D, int j) {
   // with tau = I the stored basis column z~_j is p~_j itself

@@ -1,23 +1,22 @@
 // HIP kernels (gfx950, wave64, FP64) of the sketched flexible LSQR / LSMR
-// iteration.  One instance, stage per kernel; the host driver (sfk_capi.hip)
-// sequences them on one stream.
+// iteration.  The host driver (sfk_capi.hip) runs the data-parallel stages on
+// the context's stream and the sketch + small least-squares update on a second
+// stream, so that the latency-bound LS overlaps the bandwidth-bound products.
 //
 // Stages of iteration k (paper Algorithm 1 / Algorithm 2, eq. (FGK)):
-//   A(k)  w = A z_k                       + dots <w_j, w> of the window, ||w||
-//   B(k)  w~_{k+1} = w - sum h_jk w_j     + ||w~_{k+1}||, Gram entries
-//   S     sketch of w (sFLSQR) or of z (sFLSMR) -> one new sketched column
+//   A(k)  w = A z_k                       + partials <w_j, w> (window), ||w||^2
+//   B(k)  w~_{k+1} = w - sum h_jk w_j     + partials ||w~_{k+1}||^2, <w~_{k+1}, w~_j>
+//   C(k)  z = B w_{k+1}                   + partials <p_j, z> (window), ||z||^2
+//   D(k)  p~_{k+1} = z - sum t_j p_j, z~_{k+1} = tau(p~_{k+1})  + partials
+//   S(k)  sketch of w (sFLSQR, after B) or of z (sFLSMR, after C)
 //   LS(k) Householder update of the small sketched least-squares problem
-//   C(k)  z = B w_{k+1}                   + dots <p_j, z> of the window, ||z||
-//   D(k)  p~_{k+1} = z - sum t_j p_j, z~_{k+1} = tau(p~_{k+1}) + norms, Gram
-// Vectors are kept unnormalised (w~, p~) with their inverse norms in sigw /
-// sigp; the normalisation is folded into the next consumer.  The modified
-// Gram-Schmidt coefficients of the paper's loops are obtained from one pass of
-// dot products corrected with the Gram matrix of the window (equal in exact
-// arithmetic; see the design notes).
-//
-// Every reduction is deterministic: per-workgroup partial sums are written to
-// a buffer and the last workgroup to finish (atomic ticket) sums them in a
-// fixed order.
+// Each stage starts by reducing the partial sums of the stage before it, in a
+// fixed order, identically in every workgroup (no atomics): that yields the
+// modified Gram-Schmidt coefficients of the paper's loops (one pass of dot
+// products corrected with the Gram matrix of the window, equal in exact
+// arithmetic), the norms, and the breakdown tests.  Workgroup 0 stores the
+// recurrence coefficients.  Vectors stay unnormalised (w~, p~); their inverse
+// norms (sigw, sigp) are folded into the consumers.
 
 #include "sfk_dev.h"
 
@@ -50,57 +49,65 @@ __device__ __forceinline__ double group_sum(double v) {
   return v;
 }
 
-// Sum of Q per-thread values over the workgroup; result in out[0..Q) (LDS).
+__device__ __forceinline__ double wave_sum(double v) { return group_sum<64>(v); }
+
+// Sum of Q per-thread values over a workgroup of NT threads, result in out[0..Q)
+// (LDS, visible to all threads on return).  lds_w holds kMaxQ * NT / 64 doubles.
+template <int NT>
 __device__ __forceinline__ void block_sum(const double (&v)[kMaxQ], int Q, double *lds_w,
                                           double *out) {
+  constexpr int NWV = NT / 64;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
 #pragma unroll
   for (int q = 0; q < kMaxQ; ++q) {
     if (q < Q) {
-      const double t = group_sum<64>(v[q]);
-      if (lane == 0) lds_w[q * (kWG / 64) + wv] = t;
+      const double t = wave_sum(v[q]);
+      if (lane == 0) lds_w[q * NWV + wv] = t;
     }
   }
   __syncthreads();
   if (threadIdx.x < Q) {
     double t = 0.0;
-    for (int w = 0; w < kWG / 64; ++w) t += lds_w[threadIdx.x * (kWG / 64) + w];
+    for (int w = 0; w < NWV; ++w) t += lds_w[threadIdx.x * NWV + w];
     out[threadIdx.x] = t;
   }
   __syncthreads();
 }
 
-// Publishes this workgroup's Q partials; returns true in the last workgroup,
-// which then holds the fixed-order totals in tot[0..Q).
-__device__ bool stage_reduce(const Dev &D, int Q, const double *blk, double *lds_w,
-                             double *tot) {
-  __shared__ int s_last;
-  const int wid = blockIdx.x;
-  if (threadIdx.x == 0) {
-    for (int q = 0; q < Q; ++q) D.part[(size_t)q * D.nw + wid] = blk[q];
-    __threadfence();
-    const unsigned t = atomicAdd(D.ticket, 1u);
-    s_last = (t == (unsigned)D.nw - 1u);
-  }
-  __syncthreads();
-  if (!s_last) return false;
-  __threadfence();
+__device__ __forceinline__ double *part_of(const Dev &D, int stage) {
+  return D.part + (size_t)stage * kMaxQ * D.nw;
+}
+
+// Totals of the Q partial sums that the previous stage left, in a fixed order
+// (every workgroup obtains identical values).
+template <int NT>
+__device__ void consume(const Dev &D, int stage, int Q, double *lds_w, double *tot) {
+  const double *p = part_of(D, stage);
   double acc[kMaxQ];
 #pragma unroll
   for (int q = 0; q < kMaxQ; ++q) acc[q] = 0.0;
-  for (int i = threadIdx.x; i < D.nw; i += kWG) {
+  for (int i = threadIdx.x; i < D.nw; i += NT) {
 #pragma unroll
     for (int q = 0; q < kMaxQ; ++q)
-      if (q < Q) acc[q] += __hip_atomic_load(D.part + (size_t)q * D.nw + i, __ATOMIC_RELAXED,
-                                             __HIP_MEMORY_SCOPE_AGENT);
+      if (q < Q) acc[q] += p[(size_t)q * D.nw + i];
   }
-  block_sum(acc, Q, lds_w, tot);
-  if (threadIdx.x == 0) *D.ticket = 0u;
-  return true;
+  block_sum<NT>(acc, Q, lds_w, tot);
 }
 
-__device__ __forceinline__ bool halted(const Dev &D) {
-  return __hip_atomic_load(&D.sc->halt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0;
+template <int NT>
+__device__ void produce(const Dev &D, int stage, int Q, const double (&acc)[kMaxQ],
+                        double *lds_w, double *blk) {
+  block_sum<NT>(acc, Q, lds_w, blk);
+  if (threadIdx.x < Q) part_of(D, stage)[(size_t)threadIdx.x * D.nw + blockIdx.x] = blk[threadIdx.x];
+}
+
+__device__ __forceinline__ int ld_flag(const int *p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// stages of iteration k run only while the run is live and the basis reaches k
+__device__ __forceinline__ bool skip_iter(const Dev &D, int k) {
+  return ld_flag(&D.sc->halt) != 0 || k > ld_flag(&D.sc->klimit);
 }
 
 __device__ __forceinline__ void chunk_range(int d, int nw, int wid, int &i0, int &i1) {
@@ -109,138 +116,288 @@ __device__ __forceinline__ void chunk_range(int d, int nw, int wid, int &i0, int
   i1 = min(d, i0 + per);
 }
 
+// windows (1-based basis indices)
+__device__ __forceinline__ int wwin0(const Dev &D, int k) { return max(1, k - D.ell); }      // A(k), B(k)
+__device__ __forceinline__ int pwin0(const Dev &D, int k) { return max(1, k + 1 - D.ell); }  // C(k), D(k)
+
 // ---------------------------------------------------------------------------
-// A(k) / C(k): CSR SpMV with the window dot products fused in the epilogue.
-//   ISA = true : w = sigp_k * A z~_k, dots with w~_j, j = max(1,k-ell)..k
-//   ISA = false: z = sigw_{k+1} * B w~_{k+1}, dots with p~_j, j = max(1,k+1-ell)..k
-// VW lanes cooperate on a row; rows of the workgroup's nnz-balanced range are
-// dealt round-robin to the kWG / VW lane groups.
+// CSR-stream product of one workgroup's rows [r0, r1) (whole rows, contiguous
+// nonzeros).  The nonzeros are streamed in chunks of kChunk: every thread loads
+// kPerThread (value, column) pairs at once, gathers x, and leaves the products
+// in LDS; then one wave per row sums the row's segment of the chunk.  A row
+// that continues into the next chunk carries its partial sum.  The next
+// chunk's values and columns are loaded while the current one is reduced.
+// y[r] = scale * sum_e val[e] x[col[e]]; also kept in ybuf for rows < kRowsLDS.
+// ---------------------------------------------------------------------------
+constexpr int kPerThread = 4;
+constexpr int kChunk = kSpmvWG * kPerThread;
+constexpr int kRowWin = 1024;   // row pointers staged per pass
+
+__device__ void spmv_stream(const int *rp, const int *ci, const double *va, const double *xin,
+                            double *yout, double *ybuf, int r0, int r1, double scale) {
+  constexpr int NT = kSpmvWG;
+  __shared__ double prod[kChunk];
+  __shared__ int rps[kRowWin + 1];
+  __shared__ double s_carry;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  if (r0 >= r1) return;
+  const int E0 = rp[r0], E1 = rp[r1];
+  int rcur = r0;
+  double carry = 0.0;
+  double vv[kPerThread];
+  int cc[kPerThread];
+#pragma unroll
+  for (int j = 0; j < kPerThread; ++j) {
+    const int e = E0 + j * NT + tid;
+    if (e < E1) { vv[j] = __builtin_nontemporal_load(va + e); cc[j] = __builtin_nontemporal_load(ci + e); }
+    else { vv[j] = 0.0; cc[j] = -1; }
+  }
+  for (int cs = E0; cs < E1; cs += kChunk) {
+    const int ce = min(cs + kChunk, E1);
+#pragma unroll
+    for (int j = 0; j < kPerThread; ++j) prod[j * NT + tid] = cc[j] >= 0 ? vv[j] * xin[cc[j]] : 0.0;
+    // prefetch the next chunk while this one is reduced
+#pragma unroll
+    for (int j = 0; j < kPerThread; ++j) {
+      const int e = cs + kChunk + j * NT + tid;
+      if (e < E1) { vv[j] = __builtin_nontemporal_load(va + e); cc[j] = __builtin_nontemporal_load(ci + e); }
+      else { vv[j] = 0.0; cc[j] = -1; }
+    }
+    for (;;) {
+      __syncthreads();
+      rps[tid] = (rcur + tid <= r1) ? rp[rcur + tid] : 0x7fffffff;
+      if (tid == 0) rps[kRowWin] = (rcur + kRowWin <= r1) ? rp[rcur + kRowWin] : 0x7fffffff;
+      __syncthreads();
+      const int nr = __syncthreads_count(rcur + tid < r1 && rps[tid] < ce);
+      if (nr == 0) break;
+      for (int i = wv; i < nr; i += NT / 64) {
+        const int a = max(rps[i], cs) - cs, b = min(rps[i + 1], ce) - cs;
+        double sum = 0.0;
+        for (int q = a + lane; q < b; q += 64) sum += prod[q];
+        sum = wave_sum(sum);
+        if (lane == 0) {
+          if (i == 0) sum += carry;
+          if (rps[i + 1] <= ce) {
+            const int r = rcur + i;
+            const double yr = sum * scale;
+            yout[r] = yr;
+            if (r - r0 < kRowsLDS) ybuf[r - r0] = yr;
+          } else {
+            s_carry = sum;
+          }
+        }
+      }
+      __syncthreads();
+      if (rps[nr] > ce) {             // the last row continues into the next chunk
+        carry = s_carry;
+        rcur += nr - 1;
+        break;
+      }
+      carry = 0.0;
+      rcur += nr;
+      if (nr < kRowWin) break;
+    }
+  }
+  // rows after the last nonzero are empty
+  for (int r = rcur + tid; r < r1; r += NT) {
+    yout[r] = 0.0;
+    if (r - r0 < kRowsLDS) ybuf[r - r0] = 0.0;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// A(k) / C(k): CSR SpMV; the window dot products run as a coalesced epilogue
+// over the workgroup's rows (results staged in LDS).
+//   ISA = true : consumes D(k-1) (||p~_k||, Gram), w = sigp_k * A z~_k
+//   ISA = false: consumes B(k) (||w~_{k+1}||, Gram), z = sigw_{k+1} * B w~_{k+1}
+// VW = 0: CSR-stream (spmv_stream); VW > 0: VW lanes cooperate on a row, four
+// independent loads per lane in flight.
 // ---------------------------------------------------------------------------
 template <int VW, bool ISA>
-__global__ void __launch_bounds__(kWG) k_spmv(Dev D, int k) {
-  if (halted(D)) return;
-  __shared__ double lds_w[kMaxQ * (kWG / 64)];
+__global__ void __launch_bounds__(kSpmvWG, 8) k_spmv(Dev D, int k) {
+  constexpr int NT = kSpmvWG;
+  if (skip_iter(D, k)) return;
+  __shared__ double lds_w[kMaxQ * (NT / 64)];
   __shared__ double tot[kMaxQ];
+  __shared__ double s_scale;
+  __shared__ int s_quit;
+  __shared__ double ybuf[kRowsLDS];
+  Scal *sc = D.sc;
   const int wid = blockIdx.x;
+  const int ldh = D.maxit + 1;
+
+  if (ISA) {
+    // ---- finish D(k-1): t_kk = ||p~_k||, Gram entries of p_k
+    const int j0 = wwin0(D, k);              // D(k-1) window: [max(1,k-ell), k-1]
+    const int nwin = k - j0;
+    consume<NT>(D, kStageD, nwin + 1, lds_w, tot);
+    if (threadIdx.x == 0) {
+      const double t = sqrt(tot[0]);
+      const int quit = (t <= kBreakdownTol * sc->zpre || t == 0.0) ? 1 : 0;
+      s_quit = quit;
+      s_scale = quit ? 0.0 : 1.0 / t;
+      if (wid == 0) {
+        D.T[(size_t)(k - 1) * ldh + (k - 1)] = t;
+        if (quit) {
+          atomicOr(&sc->breakdown, 1);
+          atomicMin(&sc->klimit, k - 1);
+        } else {
+          const double sg = 1.0 / t;
+          D.sigp[k] = sg;
+          const int ns = D.ell + 1, sk = pslot(D, k);
+          sc->Gp[sk * ns + sk] = 1.0;
+          for (int q = 0; q < nwin; ++q) {
+            const int j = j0 + q;
+            if (j < k + 1 - D.ell) continue;
+            const double g = sg * D.sigp[j] * tot[1 + q];
+            sc->Gp[sk * ns + pslot(D, j)] = g;
+            sc->Gp[pslot(D, j) * ns + sk] = g;
+          }
+        }
+      }
+    }
+    __syncthreads();
+    if (s_quit) return;
+  } else {
+    if (k >= 1) {
+      // ---- finish B(k): h_{k+1,k} = ||w~_{k+1}||, Gram entries of w_{k+1}
+      const int j0 = wwin0(D, k);
+      const int nwin = k - j0 + 1;
+      consume<NT>(D, kStageB, nwin + 1, lds_w, tot);
+      if (threadIdx.x == 0) {
+        const double h = sqrt(tot[0]);
+        const bool happy = (h <= kBreakdownTol * sc->wpre || h == 0.0);
+        s_scale = happy ? 0.0 : 1.0 / h;
+        if (wid == 0) {
+          D.H[(size_t)(k - 1) * ldh + k] = happy ? 0.0 : h;
+          D.sigw[k + 1] = s_scale;
+          if (happy) {
+            sc->happy = k;
+          } else {
+            const double sg = 1.0 / h;
+            const int ns = D.ell + 2, sk = wslot(D, k + 1);
+            sc->Gw[sk * ns + sk] = 1.0;
+            for (int q = 0; q < nwin; ++q) {
+              const int j = j0 + q;
+              if (j < k + 1 - D.ell) continue;
+              const double g = sg * D.sigw[j] * tot[1 + q];
+              sc->Gw[sk * ns + wslot(D, j)] = g;
+              sc->Gw[wslot(D, j) * ns + sk] = g;
+            }
+          }
+        }
+      }
+    } else if (threadIdx.x == 0) {
+      s_scale = D.sigw[1];
+    }
+    __syncthreads();
+  }
+
   const int *rp = ISA ? D.Arp : D.Brp;
   const int *ci = ISA ? D.Aci : D.Bci;
   const double *va = ISA ? D.Ava : D.Bva;
   const int *part = ISA ? D.Apart : D.Bpart;
-  const double *xin;
-  double scale;
-  double *yout;
-  int j0, nwin;
-  if (ISA) {
-    xin = D.Z + (size_t)(k - 1) * D.n;
-    scale = D.sigp[k];
-    yout = D.wraw;
-    j0 = max(1, k - D.ell);
-    nwin = k - j0 + 1;
+  const double *xin = ISA ? D.Z + (size_t)(k - 1) * D.n : wvec(D, k + 1);
+  double *yout = ISA ? wrawk(D, k) : zrawk(D, k);
+  const double scale = s_scale;
+
+  const int r0 = part[wid], r1 = part[wid + 1];
+  if (VW == 0) {
+    spmv_stream(rp, ci, va, xin, yout, ybuf, r0, r1, scale);
   } else {
-    xin = wvec(D, k + 1);
-    scale = D.sigw[k + 1];
-    yout = D.zraw;
-    j0 = max(1, k + 1 - D.ell);
-    nwin = k >= j0 ? k - j0 + 1 : 0;
+    constexpr int VWL = VW == 0 ? 64 : VW;
+    const int grp = threadIdx.x / VWL, lane = threadIdx.x % VWL;
+    constexpr int NG = NT / VWL;
+    for (int r = r0 + grp; r < r1; r += NG) {
+      const int e0 = rp[r], e1 = rp[r + 1];
+      double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+      int e = e0 + lane;
+      for (; e + 3 * VWL < e1; e += 4 * VWL) {
+        const double v0 = __builtin_nontemporal_load(va + e);
+        const double v1 = __builtin_nontemporal_load(va + e + VWL);
+        const double v2 = __builtin_nontemporal_load(va + e + 2 * VWL);
+        const double v3 = __builtin_nontemporal_load(va + e + 3 * VWL);
+        const int c0 = __builtin_nontemporal_load(ci + e);
+        const int c1 = __builtin_nontemporal_load(ci + e + VWL);
+        const int c2 = __builtin_nontemporal_load(ci + e + 2 * VWL);
+        const int c3 = __builtin_nontemporal_load(ci + e + 3 * VWL);
+        s0 += v0 * xin[c0];
+        s1 += v1 * xin[c1];
+        s2 += v2 * xin[c2];
+        s3 += v3 * xin[c3];
+      }
+      for (; e < e1; e += VWL)
+        s0 += __builtin_nontemporal_load(va + e) * xin[__builtin_nontemporal_load(ci + e)];
+      const double yr = group_sum<VWL>((s0 + s1) + (s2 + s3)) * scale;
+      if (lane == 0) {
+        yout[r] = yr;
+        if (r - r0 < kRowsLDS) ybuf[r - r0] = yr;
+      }
+    }
   }
+  __threadfence_block();
+  __syncthreads();
+
+  // epilogue: window dots and the norm over this workgroup's rows
+  int j0, nwin;
+  if (ISA) { j0 = wwin0(D, k); nwin = k - j0 + 1; }
+  else { j0 = pwin0(D, k); nwin = k >= j0 ? k - j0 + 1 : 0; }
   const double *win[kMaxEll + 1];
 #pragma unroll
   for (int q = 0; q < kMaxEll + 1; ++q)
     win[q] = (q < nwin) ? (ISA ? wvec(D, j0 + q) : pvec(D, j0 + q)) : nullptr;
-
   double acc[kMaxQ];
 #pragma unroll
   for (int q = 0; q < kMaxQ; ++q) acc[q] = 0.0;
-
-  const int r0 = part[wid], r1 = part[wid + 1];
-  const int grp = threadIdx.x / VW, lane = threadIdx.x % VW;
-  constexpr int NG = kWG / VW;
-  for (int r = r0 + grp; r < r1; r += NG) {
-    const int e0 = rp[r], e1 = rp[r + 1];
-    double s0 = 0.0, s1 = 0.0;
-    int e = e0 + lane;
-    for (; e + VW < e1; e += 2 * VW) {
-      const double v0 = __builtin_nontemporal_load(va + e);
-      const int c0 = __builtin_nontemporal_load(ci + e);
-      const double v1 = __builtin_nontemporal_load(va + e + VW);
-      const int c1 = __builtin_nontemporal_load(ci + e + VW);
-      s0 += v0 * xin[c0];
-      s1 += v1 * xin[c1];
-    }
-    if (e < e1) s0 += __builtin_nontemporal_load(va + e) * xin[__builtin_nontemporal_load(ci + e)];
-    const double yr = group_sum<VW>(s0 + s1) * scale;
-    if (lane == 0) {
-      yout[r] = yr;
+  for (int r = r0 + threadIdx.x; r < r1; r += NT) {
+    const double yr = (r - r0 < kRowsLDS) ? ybuf[r - r0] : yout[r];
 #pragma unroll
-      for (int q = 0; q < kMaxEll + 1; ++q)
-        if (q < nwin) acc[q] += win[q][r] * yr;
-      acc[kMaxEll + 1] += yr * yr;
-    }
+    for (int q = 0; q < kMaxEll + 1; ++q)
+      if (q < nwin) acc[q] += win[q][r] * yr;
+    acc[kMaxEll + 1] += yr * yr;
   }
-  // compact: window dots then the norm
   double v[kMaxQ];
 #pragma unroll
-  for (int q = 0; q < kMaxQ; ++q) v[q] = 0.0;
-#pragma unroll
-  for (int q = 0; q < kMaxEll + 1; ++q)
-    if (q < nwin) v[q] = acc[q];
-#pragma unroll
-  for (int q = 0; q < kMaxQ; ++q)
-    if (q == nwin) v[q] = acc[kMaxEll + 1];
-  const int Q = nwin + 1;
+  for (int q = 0; q < kMaxQ; ++q) v[q] = (q < nwin) ? acc[q] : (q == nwin ? acc[kMaxEll + 1] : 0.0);
   __shared__ double blk[kMaxQ];
-  block_sum(v, Q, lds_w, blk);
-  if (!stage_reduce(D, Q, blk, lds_w, tot)) return;
-  if (threadIdx.x != 0) return;
+  produce<NT>(D, ISA ? kStageA : kStageC, nwin + 1, v, lds_w, blk);
+}
 
-  // scalar step: modified Gram-Schmidt coefficients from the dots and the Gram
-  // matrix of the (normalised) window vectors
+// ---------------------------------------------------------------------------
+// B(k): consumes A(k) (dots, ||w||) -> h_jk; w~_{k+1} = w - sum h_jk w_j
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(kWG) k_wupdate(Dev D, int k) {
+  if (skip_iter(D, k)) return;
+  __shared__ double lds_w[kMaxQ * (kWG / 64)];
+  __shared__ double tot[kMaxQ];
+  __shared__ double blk[kMaxQ];
+  __shared__ double s_cf[kMaxEll + 1];
   Scal *sc = D.sc;
-  const int ld = D.maxit + 1;
-  double h[kMaxEll + 1];
-  if (ISA) {
-    sc->wpre = sqrt(tot[nwin]);
-    const int ns = D.ell + 2;
+  const int j0 = wwin0(D, k), nwin = k - j0 + 1;
+  consume<kWG>(D, kStageA, nwin + 1, lds_w, tot);
+  if (threadIdx.x == 0) {
+    // modified Gram-Schmidt coefficients: h_q = <w_jq, w> - sum_{i<q} h_i <w_jq, w_ji>
+    const int ns = D.ell + 2, ldh = D.maxit + 1;
+    double h[kMaxEll + 1];
     for (int q = 0; q < nwin; ++q) {
       const int jq = j0 + q;
       double t = D.sigw[jq] * tot[q];
       for (int i = 0; i < q; ++i) t -= h[i] * sc->Gw[wslot(D, jq) * ns + wslot(D, j0 + i)];
       h[q] = t;
-      D.H[(size_t)(k - 1) * ld + (jq - 1)] = t;
-      sc->wcoef[q] = t * D.sigw[jq];
+      s_cf[q] = t * D.sigw[jq];
+      if (blockIdx.x == 0) D.H[(size_t)(k - 1) * ldh + (jq - 1)] = t;
     }
-  } else {
-    sc->zpre = sqrt(tot[nwin]);
-    const int ns = D.ell + 1;
-    for (int q = 0; q < nwin; ++q) {
-      const int jq = j0 + q;
-      double t = D.sigp[jq] * tot[q];
-      for (int i = 0; i < q; ++i) t -= h[i] * sc->Gp[pslot(D, jq) * ns + pslot(D, j0 + i)];
-      h[q] = t;
-      D.T[(size_t)k * ld + (jq - 1)] = t;
-      sc->pcoef[q] = t * D.sigp[jq];
-    }
+    if (blockIdx.x == 0) sc->wpre = sqrt(tot[nwin]);
   }
-}
-
-// ---------------------------------------------------------------------------
-// B(k): w~_{k+1} = w - sum_q wcoef_q w~_{j0+q}; ||w~_{k+1}||, <w~_{k+1}, w~_j>
-// ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(kWG) k_wupdate(Dev D, int k) {
-  if (halted(D)) return;
-  __shared__ double lds_w[kMaxQ * (kWG / 64)];
-  __shared__ double tot[kMaxQ];
-  __shared__ double blk[kMaxQ];
-  const int j0 = max(1, k - D.ell), nwin = k - j0 + 1;
-  const int g0 = max(1, k + 1 - D.ell), ng = k - g0 + 1;  // Gram targets (suffix of window)
-  const int goff = g0 - j0;
+  __syncthreads();
   const double *win[kMaxEll + 1];
   double cf[kMaxEll + 1];
 #pragma unroll
   for (int q = 0; q < kMaxEll + 1; ++q) {
     win[q] = (q < nwin) ? wvec(D, j0 + q) : nullptr;
-    cf[q] = (q < nwin) ? D.sc->wcoef[q] : 0.0;
+    cf[q] = (q < nwin) ? s_cf[q] : 0.0;
   }
+  const double *wr = wrawk(D, k);
   double *out = wvec(D, k + 1);
   int i0, i1;
   chunk_range(D.m, D.nw, blockIdx.x, i0, i1);
@@ -248,7 +405,7 @@ __global__ void __launch_bounds__(kWG) k_wupdate(Dev D, int k) {
 #pragma unroll
   for (int q = 0; q < kMaxQ; ++q) acc[q] = 0.0;
   for (int i = i0 + threadIdx.x; i < i1; i += kWG) {
-    double v = D.wraw[i];
+    double v = wr[i];
     double wj[kMaxEll + 1];
 #pragma unroll
     for (int q = 0; q < kMaxEll + 1; ++q)
@@ -259,60 +416,50 @@ __global__ void __launch_bounds__(kWG) k_wupdate(Dev D, int k) {
     for (int q = 0; q < kMaxEll + 1; ++q)
       if (q < nwin) acc[1 + q] += v * wj[q];
   }
-  const int Q = nwin + 1;  // norm, then <w~_{k+1}, w~_j> for the whole window
-  block_sum(acc, Q, lds_w, blk);
-  if (!stage_reduce(D, Q, blk, lds_w, tot)) return;
-  if (threadIdx.x != 0) return;
-  Scal *sc = D.sc;
-  const int ld = D.maxit + 1;
-  const double hk = sqrt(tot[0]);
-  D.H[(size_t)(k - 1) * ld + k] = hk;
-  const int ns = D.ell + 2;
-  const int sk = wslot(D, k + 1);
-  if (hk <= kBreakdownTol * sc->wpre || hk == 0.0) {
-    sc->happy = 1;
-    D.H[(size_t)(k - 1) * ld + k] = 0.0;
-    D.sigw[k + 1] = 0.0;
-  } else {
-    const double sg = 1.0 / hk;
-    D.sigw[k + 1] = sg;
-    sc->Gw[sk * ns + sk] = 1.0;
-    for (int q = 0; q < ng; ++q) {
-      const int j = g0 + q;
-      const double g = sg * D.sigw[j] * tot[1 + goff + q];
-      sc->Gw[sk * ns + wslot(D, j)] = g;
-      sc->Gw[wslot(D, j) * ns + sk] = g;
-    }
-  }
+  produce<kWG>(D, kStageB, nwin + 1, acc, lds_w, blk);
 }
 
 // ---------------------------------------------------------------------------
-// D(k): p~_{k+1} = z - sum_q pcoef_q p~_{j0+q}; z~_{k+1} = tau(p~_{k+1}).
-// k = 0 is the initial step (empty window, x_0 = 0).
+// D(k): consumes C(k) (dots, ||z||) -> t_j,k+1; p~_{k+1} = z - sum t_j p_j;
+// z~_{k+1} = tau(p~_{k+1}).  k = 0 is the initial step (empty window, x_0 = 0).
+// The reweighting assembles x_k = Z_k y_k on the fly (y_k from LS(k)).
 // ---------------------------------------------------------------------------
 __global__ void __launch_bounds__(kWG) k_pupdate(Dev D, int k) {
-  if (halted(D)) return;
+  if (skip_iter(D, k)) return;
   __shared__ double lds_w[kMaxQ * (kWG / 64)];
   __shared__ double tot[kMaxQ];
   __shared__ double blk[kMaxQ];
+  __shared__ double s_cf[kMaxEll + 1];
   extern __shared__ double coefx[];  // k coefficients of x_k (reweighting)
-  const int j0 = max(1, k + 1 - D.ell);
+  Scal *sc = D.sc;
+  const int j0 = pwin0(D, k);
   const int nwin = k >= j0 ? k - j0 + 1 : 0;
-  const int g0 = max(1, k + 2 - D.ell);
-  const int ng = k >= g0 ? k - g0 + 1 : 0;
-  const int goff = g0 - j0;
+  consume<kWG>(D, kStageC, nwin + 1, lds_w, tot);
+  if (threadIdx.x == 0) {
+    const int ns = D.ell + 1, ldh = D.maxit + 1;
+    double t[kMaxEll + 1];
+    for (int q = 0; q < nwin; ++q) {
+      const int jq = j0 + q;
+      double v = D.sigp[jq] * tot[q];
+      for (int i = 0; i < q; ++i) v -= t[i] * sc->Gp[pslot(D, jq) * ns + pslot(D, j0 + i)];
+      t[q] = v;
+      s_cf[q] = v * D.sigp[jq];
+      if (blockIdx.x == 0) D.T[(size_t)k * ldh + (jq - 1)] = v;
+    }
+    if (blockIdx.x == 0) sc->zpre = sqrt(tot[nwin]);
+  }
   const bool rew = D.tau == 1;
+  if (rew)
+    for (int j = threadIdx.x; j < k; j += kWG) coefx[j] = D.sigp[j + 1] * D.y[j];
+  __syncthreads();
   const double *win[kMaxEll + 1];
   double cf[kMaxEll + 1];
 #pragma unroll
   for (int q = 0; q < kMaxEll + 1; ++q) {
     win[q] = (q < nwin) ? pvec(D, j0 + q) : nullptr;
-    cf[q] = (q < nwin) ? D.sc->pcoef[q] : 0.0;
+    cf[q] = (q < nwin) ? s_cf[q] : 0.0;
   }
-  if (rew) {
-    for (int j = threadIdx.x; j < k; j += kWG) coefx[j] = D.sigp[j + 1] * D.y[j];
-    __syncthreads();
-  }
+  const double *zr = zrawk(D, k);
   double *zcol = D.Z + (size_t)k * D.n;
   double *pout = rew ? D.P + (size_t)pslot(D, k + 1) * D.n : zcol;
   const double eps2 = D.eps * D.eps;
@@ -322,7 +469,7 @@ __global__ void __launch_bounds__(kWG) k_pupdate(Dev D, int k) {
 #pragma unroll
   for (int q = 0; q < kMaxQ; ++q) acc[q] = 0.0;
   for (int i = i0 + threadIdx.x; i < i1; i += kWG) {
-    double v = D.zraw[i];
+    double v = zr[i];
     double pj[kMaxEll + 1];
 #pragma unroll
     for (int q = 0; q < kMaxEll + 1; ++q)
@@ -339,46 +486,24 @@ __global__ void __launch_bounds__(kWG) k_pupdate(Dev D, int k) {
     for (int q = 0; q < kMaxEll + 1; ++q)
       if (q < nwin) acc[1 + q] += v * pj[q];
   }
-  const int Q = nwin + 1;
-  block_sum(acc, Q, lds_w, blk);
-  if (!stage_reduce(D, Q, blk, lds_w, tot)) return;
-  if (threadIdx.x != 0) return;
-  Scal *sc = D.sc;
-  const int ld = D.maxit + 1;
-  const double t = sqrt(tot[0]);
-  D.T[(size_t)k * ld + k] = t;
-  if (t <= kBreakdownTol * sc->zpre || t == 0.0) {
-    sc->breakdown = 1;
-    sc->halt = 1;
-    return;
-  }
-  const double sg = 1.0 / t;
-  D.sigp[k + 1] = sg;
-  const int ns = D.ell + 1;
-  const int sk = pslot(D, k + 1);
-  sc->Gp[sk * ns + sk] = 1.0;
-  for (int q = 0; q < ng; ++q) {
-    const int j = g0 + q;
-    const double g = sg * D.sigp[j] * tot[1 + goff + q];
-    sc->Gp[sk * ns + pslot(D, j)] = g;
-    sc->Gp[pslot(D, j) * ns + sk] = g;
-  }
+  produce<kWG>(D, kStageD, nwin + 1, acc, lds_w, blk);
 }
 
 // ---------------------------------------------------------------------------
-// Sketch application.
+// Sketch application (side stream).  k > 0 marks the sketch of iteration k
+// (skipped once the run has halted); k = 0 is used at initialisation.
 // ---------------------------------------------------------------------------
 // sparse-sign: one wave per sketch row, over the row's (column, sign) entries
 // in increasing column order; identity: copy.
-__global__ void __launch_bounds__(kWG) k_sketch_gather(Dev D, const double *v, double *dst) {
-  if (halted(D)) return;
-  const int wave = (blockIdx.x * kWG + threadIdx.x) >> 6;
-  const int lane = threadIdx.x & 63;
+__global__ void __launch_bounds__(kWG) k_sketch_gather(Dev D, int k, const double *v, double *dst) {
+  if (k > 0 && skip_iter(D, k)) return;
   if (D.sketch == 2) {
     const int i = blockIdx.x * kWG + threadIdx.x;
     if (i < D.s) dst[i] = v[i];
     return;
   }
+  const int wave = (blockIdx.x * kWG + threadIdx.x) >> 6;
+  const int lane = threadIdx.x & 63;
   const int nwaves = (gridDim.x * kWG) >> 6;
   for (int r = wave; r < D.s; r += nwaves) {
     const int e0 = D.sk_rp[r], e1 = D.sk_rp[r + 1];
@@ -388,7 +513,7 @@ __global__ void __launch_bounds__(kWG) k_sketch_gather(Dev D, const double *v, d
       const double val = v[code & 0x7fffffff];
       acc += code < 0 ? -val : val;
     }
-    acc = group_sum<64>(acc);
+    acc = wave_sum(acc);
     if (lane == 0) dst[r] = acc * D.sk_scale;
   }
 }
@@ -396,8 +521,8 @@ __global__ void __launch_bounds__(kWG) k_sketch_gather(Dev D, const double *v, d
 // SRHT, stage 1: per block of L = 2^log2L entries, u = D pad(v) staged in LDS and
 // transformed by the Sylvester-ordered Walsh-Hadamard butterflies; the entries
 // that the s selected rows need are kept: part[b][i] = (H_L u_b)[rows_i mod L].
-__global__ void __launch_bounds__(kWG) k_srht_blocks(Dev D, const double *v) {
-  if (halted(D)) return;
+__global__ void __launch_bounds__(kWG) k_srht_blocks(Dev D, int k, const double *v) {
+  if (k > 0 && skip_iter(D, k)) return;
   __shared__ double u[kSrhtL];
   const int L = 1 << D.log2L;
   const int b = blockIdx.x;
@@ -426,8 +551,8 @@ __global__ void __launch_bounds__(kWG) k_srht_blocks(Dev D, const double *v) {
 }
 
 // SRHT, stage 2: dst_i = (1/sqrt(s)) sum_b (-1)^popcount((rows_i >> log2L) & b) part[b][i]
-__global__ void __launch_bounds__(kWG) k_srht_combine(Dev D, double *dst) {
-  if (halted(D)) return;
+__global__ void __launch_bounds__(kWG) k_srht_combine(Dev D, int k, double *dst) {
+  if (k > 0 && skip_iter(D, k)) return;
   const int i = blockIdx.x * kWG + threadIdx.x;
   if (i >= D.s) return;
   const int hi = D.srht_rows[i] >> D.log2L;
@@ -445,11 +570,9 @@ __global__ void __launch_bounds__(kWG) k_srht_combine(Dev D, double *dst) {
 // Keeps c = Q^T rhs, R, R^{-1} and y_k = R^{-1} c[0:k] (y_k = y_{k-1} + c_k R^{-1} e_k,
 // since the first k-1 entries of c no longer change).  rho_k = ||c[k:s]||.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ double wave_sum(double v) { return group_sum<64>(v); }
-
 template <int E, int PF>
 __global__ void __launch_bounds__(64) k_ls(Dev D, int k) {
-  if (halted(D)) return;
+  if (skip_iter(D, k)) return;
   __shared__ double s_tau[kMaxS];
   __shared__ double s_r[kMaxS];
   const int lane = threadIdx.x;
@@ -578,8 +701,8 @@ __global__ void __launch_bounds__(64) k_ls(Dev D, int k) {
   const double rho = sqrt(wave_sum(r2));
   __syncthreads();
 
-  if (beta == 0.0) {  // the new sketched column is zero: cannot extend the basis
-    if (lane == 0) { sc->breakdown = 3; sc->halt = 1; }
+  if (beta == 0.0) {  // the new sketched column is zero: the basis cannot grow
+    if (lane == 0) { atomicOr(&sc->breakdown, 4); sc->halt = 1; }
     return;
   }
   // R^{-1} column and y update
@@ -597,7 +720,7 @@ __global__ void __launch_bounds__(64) k_ls(Dev D, int k) {
     D.y[nsel] = ck * ib;
     D.rho[k - 1] = rho;
     sc->k_done = k;
-    if (sc->happy) { sc->breakdown = 2; sc->halt = 1; }
+    if (ld_flag(&sc->happy) == k) { atomicOr(&sc->breakdown, 2); sc->halt = 1; }
     if (sc->tol > 0.0 && rho < sc->tol * sc->rhsnorm) { sc->stopped = 1; sc->halt = 1; }
   }
 }
@@ -626,10 +749,9 @@ __global__ void __launch_bounds__(kWG) k_solution(Dev D, int kk, const double *y
   x[i] = xi;
 }
 
-// ||b - A x||^2 partials -> out (plain SpMV, wave per row)
-__global__ void __launch_bounds__(kWG) k_true_residual(Dev D, const double *x, double *out) {
+// ||b - A x||^2: partials over the nnz-balanced row ranges, then one workgroup
+__global__ void __launch_bounds__(kWG) k_true_residual(Dev D, const double *x) {
   __shared__ double lds_w[kMaxQ * (kWG / 64)];
-  __shared__ double tot[kMaxQ];
   __shared__ double blk[kMaxQ];
   double acc[kMaxQ];
 #pragma unroll
@@ -639,11 +761,16 @@ __global__ void __launch_bounds__(kWG) k_true_residual(Dev D, const double *x, d
   for (int r = r0 + wv; r < r1; r += kWG / 64) {
     double s = 0.0;
     for (int e = D.Arp[r] + lane; e < D.Arp[r + 1]; e += 64) s += D.Ava[e] * x[D.Aci[e]];
-    s = group_sum<64>(s);
+    s = wave_sum(s);
     if (lane == 0) { const double rr = D.b[r] - s; acc[0] += rr * rr; }
   }
-  block_sum(acc, 1, lds_w, blk);
-  if (!stage_reduce(D, 1, blk, lds_w, tot)) return;
+  produce<kWG>(D, kStageMisc, 1, acc, lds_w, blk);
+}
+
+__global__ void __launch_bounds__(kWG) k_finish_misc(Dev D, double *out) {
+  __shared__ double lds_w[kMaxQ * (kWG / 64)];
+  __shared__ double tot[kMaxQ];
+  consume<kWG>(D, kStageMisc, 1, lds_w, tot);
   if (threadIdx.x == 0) *out = sqrt(tot[0]);
 }
 
@@ -685,7 +812,7 @@ __global__ void k_tr_count(const int *rp, const int *ci, int rows, int *cnt) {
   for (int e = rp[r]; e < rp[r + 1]; ++e) atomicAdd(cnt + ci[e], 1);
 }
 
-// exclusive scan of cnt[0..len] in place by one workgroup (len up to a few 1e6)
+// exclusive scan of a[0..len) in place by one workgroup
 __global__ void __launch_bounds__(1024) k_scan_single(int *a, int len) {
   __shared__ int sums[1024];
   const int t = threadIdx.x;
@@ -834,36 +961,32 @@ __global__ void k_iota(int *a, int n) {
   if (i < n) a[i] = i;
 }
 
-// beta = ||b||, w~_1 = b, sigw_1 = 1 / beta; discrepancy tolerance
-__global__ void __launch_bounds__(kWG) k_init_b(Dev D, double eta, double noise, double tol_user,
-                                               int use_disc) {
-  __shared__ double lds_w[kMaxQ * (kWG / 64)];
+// beta = ||b||, w~_1 = b, sigw_1 = 1 / beta, stop tolerance (one workgroup)
+__global__ void __launch_bounds__(1024) k_init_b(Dev D, double eta, double noise, double tol_user,
+                                                int use_disc) {
+  __shared__ double lds_w[kMaxQ * 16];
   __shared__ double tot[kMaxQ];
-  __shared__ double blk[kMaxQ];
-  int i0, i1;
-  chunk_range(D.m, D.nw, blockIdx.x, i0, i1);
   double acc[kMaxQ];
 #pragma unroll
   for (int q = 0; q < kMaxQ; ++q) acc[q] = 0.0;
   double *w1 = wvec(D, 1);
-  for (int i = i0 + threadIdx.x; i < i1; i += kWG) {
+  for (int i = threadIdx.x; i < D.m; i += 1024) {
     const double v = D.b[i];
     w1[i] = v;
     acc[0] += v * v;
   }
-  block_sum(acc, 1, lds_w, blk);
-  if (!stage_reduce(D, 1, blk, lds_w, tot)) return;
+  block_sum<1024>(acc, 1, lds_w, tot);
   if (threadIdx.x != 0) return;
   Scal *sc = D.sc;
   const double beta = sqrt(tot[0]);
   sc->beta = beta;
+  sc->klimit = 0x7fffffff;
   if (!(beta > 0.0) || !isfinite(beta)) { sc->err |= 16; sc->halt = 1; return; }
   D.sigw[1] = 1.0 / beta;
   sc->tol = use_disc ? eta * noise / beta : tol_user;
 }
 
-// sFLSMR initial sketch: rhs = beta * S B w_1 (already in SK column 0);
-// both methods: c = rhs, rhsnorm = ||rhs||
+// rhs = S b (sFLSQR) or beta * S B w_1 (sFLSMR, in SK column 0); c = rhs
 __global__ void __launch_bounds__(64) k_init_rhs(Dev D) {
   Scal *sc = D.sc;
   if (sc->halt) return;
@@ -884,12 +1007,22 @@ __global__ void __launch_bounds__(64) k_init_rhs(Dev D) {
 // ---------------------------------------------------------------------------
 template <bool ISA>
 static void launch_spmv_vw(const Dev &D, int k, int vw, hipStream_t st) {
+  const dim3 g(D.nw), b(kSpmvWG);
   switch (vw) {
-    case 8: hipLaunchKernelGGL((k_spmv<8, ISA>), dim3(D.nw), dim3(kWG), 0, st, D, k); break;
-    case 16: hipLaunchKernelGGL((k_spmv<16, ISA>), dim3(D.nw), dim3(kWG), 0, st, D, k); break;
-    case 32: hipLaunchKernelGGL((k_spmv<32, ISA>), dim3(D.nw), dim3(kWG), 0, st, D, k); break;
-    default: hipLaunchKernelGGL((k_spmv<64, ISA>), dim3(D.nw), dim3(kWG), 0, st, D, k); break;
+    case 8: hipLaunchKernelGGL((k_spmv<8, ISA>), g, b, 0, st, D, k); break;
+    case 16: hipLaunchKernelGGL((k_spmv<16, ISA>), g, b, 0, st, D, k); break;
+    case 32: hipLaunchKernelGGL((k_spmv<32, ISA>), g, b, 0, st, D, k); break;
+    case 64: hipLaunchKernelGGL((k_spmv<64, ISA>), g, b, 0, st, D, k); break;
+    default: hipLaunchKernelGGL((k_spmv<0, ISA>), g, b, 0, st, D, k); break;
   }
+}
+
+// resident SpMV workgroups per CU (the grid is sized to one wave of workgroups)
+int spmv_blocks_per_cu() {
+  int nb = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_spmv<0, true>, kSpmvWG, 0) != hipSuccess)
+    return 1;
+  return nb > 0 ? nb : 1;
 }
 
 void launch_stage_A(const Dev &D, int k, hipStream_t st) { launch_spmv_vw<true>(D, k, D.vwA, st); }
@@ -902,16 +1035,25 @@ void launch_stage_D(const Dev &D, int k, hipStream_t st) {
   hipLaunchKernelGGL(k_pupdate, dim3(D.nw), dim3(kWG), sh, st, D, k);
 }
 
-void launch_sketch(const Dev &D, const double *v, double *dst, hipStream_t st) {
+// sketch of v into dst; k > 0 marks an iteration stage (skipped once halted)
+void launch_sketch(const Dev &D, int k, const double *v, double *dst, hipStream_t st) {
   if (D.sketch == 1) {
-    hipLaunchKernelGGL(k_srht_blocks, dim3(D.nblk), dim3(kWG), 0, st, D, v);
-    hipLaunchKernelGGL(k_srht_combine, dim3((D.s + kWG - 1) / kWG), dim3(kWG), 0, st, D, dst);
+    hipLaunchKernelGGL(k_srht_blocks, dim3(D.nblk), dim3(kWG), 0, st, D, k, v);
+    hipLaunchKernelGGL(k_srht_combine, dim3((D.s + kWG - 1) / kWG), dim3(kWG), 0, st, D, k, dst);
   } else if (D.sketch == 2) {
-    hipLaunchKernelGGL(k_sketch_gather, dim3((D.s + kWG - 1) / kWG), dim3(kWG), 0, st, D, v, dst);
+    hipLaunchKernelGGL(k_sketch_gather, dim3((D.s + kWG - 1) / kWG), dim3(kWG), 0, st, D, k, v, dst);
   } else {
     const int blocks = (D.s * 64 + kWG - 1) / kWG;
-    hipLaunchKernelGGL(k_sketch_gather, dim3(blocks), dim3(kWG), 0, st, D, v, dst);
+    hipLaunchKernelGGL(k_sketch_gather, dim3(blocks), dim3(kWG), 0, st, D, k, v, dst);
   }
+}
+
+// the raw vector the sketch of iteration k reads, and its destination column
+const double *sketch_src(const Dev &D, int k) {
+  return D.method == 0 ? D.wraw + (size_t)(k & 1) * D.m : D.zraw + (size_t)(k & 1) * D.n;
+}
+double *sketch_dst(const Dev &D, int k) {
+  return D.method == 0 ? D.SK + (size_t)(k - 1) * D.s : D.SK + (size_t)k * D.s;
 }
 
 void launch_ls(const Dev &D, int k, hipStream_t st) {
@@ -923,24 +1065,9 @@ void launch_ls(const Dev &D, int k, hipStream_t st) {
   else hipLaunchKernelGGL((k_ls<32, 2>), dim3(1), dim3(64), 0, st, D, k);
 }
 
-void launch_iteration(const Dev &D, int k, hipStream_t st) {
-  launch_stage_A(D, k, st);
-  launch_stage_B(D, k, st);
-  if (D.method == 0) {
-    launch_sketch(D, D.wraw, D.SK + (size_t)(k - 1) * D.s, st);
-    launch_ls(D, k, st);
-    launch_stage_C(D, k, st);
-  } else {
-    launch_stage_C(D, k, st);
-    launch_sketch(D, D.zraw, D.SK + (size_t)k * D.s, st);
-    launch_ls(D, k, st);
-  }
-  launch_stage_D(D, k, st);
-}
-
 void launch_init_b(const Dev &D, double eta, double noise, double tol_user, int use_disc,
                    hipStream_t st) {
-  hipLaunchKernelGGL(k_init_b, dim3(D.nw), dim3(kWG), 0, st, D, eta, noise, tol_user, use_disc);
+  hipLaunchKernelGGL(k_init_b, dim3(1), dim3(1024), 0, st, D, eta, noise, tol_user, use_disc);
 }
 void launch_init_rhs(const Dev &D, hipStream_t st) {
   hipLaunchKernelGGL(k_init_rhs, dim3(1), dim3(64), 0, st, D);
@@ -958,9 +1085,9 @@ void launch_transpose(const int *rp, const int *ci, const double *va, int rows, 
                       int *brp, int *bci, double *bva, int *cursor, int *err, hipStream_t st) {
   hipMemsetAsync(brp, 0, sizeof(int) * (cols + 1), st);
   hipLaunchKernelGGL(k_tr_count, dim3((rows + 255) / 256), dim3(256), 0, st, rp, ci, rows, brp);
-  hipLaunchKernelGGL(k_scan_single, dim3(1), dim3(1024), 0, st, brp, cols + 1);
   // exclusive scan of [cnt_0, ..., cnt_{n-1}, 0]: entry c is the start of row c,
   // entry n the total
+  hipLaunchKernelGGL(k_scan_single, dim3(1), dim3(1024), 0, st, brp, cols + 1);
   hipMemcpyAsync(cursor, brp, sizeof(int) * cols, hipMemcpyDeviceToDevice, st);
   hipLaunchKernelGGL(k_tr_fill, dim3((rows + 255) / 256), dim3(256), 0, st, rp, ci, va, rows,
                      cursor, bci, bva);
@@ -990,7 +1117,8 @@ void launch_solution(const Dev &D, int kk, const double *yv, double *x, hipStrea
                      sizeof(double) * (size_t)max(1, kk), st, D, kk, yv, x);
 }
 void launch_true_residual(const Dev &D, const double *x, double *out, hipStream_t st) {
-  hipLaunchKernelGGL(k_true_residual, dim3(D.nw), dim3(kWG), 0, st, D, x, out);
+  hipLaunchKernelGGL(k_true_residual, dim3(D.nw), dim3(kWG), 0, st, D, x);
+  hipLaunchKernelGGL(k_finish_misc, dim3(1), dim3(kWG), 0, st, D, out);
 }
 
 }  // namespace sfk

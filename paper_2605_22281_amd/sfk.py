@@ -84,6 +84,8 @@ def lib() -> ctypes.CDLL:
         "sfk_sketch_srht": (I32, [P, PI32, PI8, ctypes.POINTER(I64)]),
         "sfk_coefficients": (I32, [P, PD, PD, I32]),
         "sfk_version": (ctypes.c_char_p, []),
+        "sfk_set_timing": (I32, [P, I32]),
+        "sfk_stage_times": (I32, [P, PD, PI32]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -97,7 +99,7 @@ def exported_symbols() -> list[str]:
     return ["sfk_params_default", "sfk_validate", "sfk_workspace_bytes", "sfk_init", "sfk_iterate",
             "sfk_solution", "sfk_solution_at", "sfk_residual_norms", "sfk_true_residual",
             "sfk_destroy", "sfk_last_error", "sfk_sketch_sparse_sign", "sfk_sketch_srht",
-            "sfk_coefficients", "sfk_version"]
+            "sfk_coefficients", "sfk_version", "sfk_set_timing", "sfk_stage_times"]
 
 
 def _check(status: int, ctx=None):
@@ -297,6 +299,21 @@ def coefficients(ctx: Context, k: int) -> tuple[np.ndarray, np.ndarray]:
                                   T.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), int(k)),
            ctx.handle)
     return H.T.copy(), T.T.copy()
+
+
+STAGES = ("spmv_A", "w_update", "sketch", "ls", "spmv_B", "p_update")
+
+
+def set_timing(ctx: Context, on: bool = True):
+    _check(lib().sfk_set_timing(ctx.handle, 1 if on else 0), ctx.handle)
+
+
+def stage_times(ctx: Context) -> dict:
+    """{stage: (total ms, launches)} accumulated since set_timing."""
+    ms = (ctypes.c_double * len(STAGES))()
+    cnt = (ctypes.c_int32 * len(STAGES))()
+    _check(lib().sfk_stage_times(ctx.handle, ms, cnt), ctx.handle)
+    return {name: (ms[i], cnt[i]) for i, name in enumerate(STAGES)}
 
 
 def version() -> str:

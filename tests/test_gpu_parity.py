@@ -107,7 +107,7 @@ def test_parity_ragged_random(method):
     compare(X, rho, orc, 10, label=f"ragged/{method}")
 
 
-@pytest.mark.parametrize("vw", [8, 16, 32, 64])
+@pytest.mark.parametrize("vw", [0, -1, 8, 16, 32, 64])
 def test_parity_all_row_widths(ct24_sparse, vw):
     say(f"case: ct24 sparse vw={vw}")
     _, X, rho, _, _ = gpu_run(ct24_sparse, "sflsqr", "sparse_sign", 60, 8, tau="reweight_l1",
