@@ -34,7 +34,7 @@ void launch_transpose(const int *rp, const int *ci, const double *va, int rows, 
                       int *bci, double *bva, int *cursor, int *err, hipStream_t st);
 void launch_sketch_build(const Dev &D, uint64_t key0, uint64_t key1, uint64_t key1_rows,
                          int *scratch, int *err, hipStream_t st);
-void launch_y_at(const Dev &D, int j, double *yout, hipStream_t st);
+void launch_backsub(const Dev &D, int j, double *yout, hipStream_t st);
 void launch_solution(const Dev &D, int kk, const double *yv, double *x, hipStream_t st);
 void launch_true_residual(const Dev &D, const double *x, double *out, hipStream_t st);
 }  // namespace sfk
@@ -261,7 +261,7 @@ struct Plan {
   size_t o_sc, o_err, o_scalar, o_part, o_sigw, o_sigp, o_H, o_T, o_rho;
   size_t o_W, o_P, o_Z, o_wraw, o_zraw, o_x, o_Apart, o_Bpart;
   size_t o_skcode, o_skent, o_skrp, o_chunk, o_srows, o_sd, o_spart, o_SK, o_skrhs;
-  size_t o_V, o_tauv, o_R, o_Rinv, o_c, o_y, o_ytmp;
+  size_t o_V, o_tauv, o_R, o_c, o_y, o_ytmp;
   size_t o_brp, o_bci, o_bva, o_cursor;
   size_t total;
 };
@@ -336,7 +336,6 @@ static Plan make_plan(const sfk_csr *A, const sfk_csr *B, const sfk_params *p, i
   P.o_V = L_.take<double>(s * mi);
   P.o_tauv = L_.take<double>(mi);
   P.o_R = L_.take<double>(mi * mi);
-  P.o_Rinv = L_.take<double>(mi * mi);
   P.o_c = L_.take<double>(s);
   P.o_y = L_.take<double>(mi);
   P.o_ytmp = L_.take<double>(mi);
@@ -467,7 +466,6 @@ static sfk_status init_impl(sfk_ctx *c, const sfk_csr *A, const sfk_csr *B, cons
   D.V = at<double>(w, P.o_V);
   D.tauv = at<double>(w, P.o_tauv);
   D.R = at<double>(w, P.o_R);
-  D.Rinv = at<double>(w, P.o_Rinv);
   D.c = at<double>(w, P.o_c);
   D.y = at<double>(w, P.o_y);
   c->d_err = at<int>(w, P.o_err);
@@ -599,7 +597,7 @@ extern "C" sfk_status sfk_solution_at(sfk_ctx *c, int32_t j, double *x) {
   if (j == 0) {
     HIPCHK(c, hipMemsetAsync(x, 0, sizeof(double) * c->D.n, c->stream));
   } else {
-    launch_y_at(c->D, j, c->d_ytmp, c->stream);
+    launch_backsub(c->D, j, c->d_ytmp, c->stream);
     launch_solution(c->D, j, c->d_ytmp, x, c->stream);
   }
   HIPCHK(c, hipGetLastError());
@@ -613,7 +611,8 @@ extern "C" sfk_status sfk_solution(sfk_ctx *c, double *x) {
   if (c->k_done == 0) {
     HIPCHK(c, hipMemsetAsync(x, 0, sizeof(double) * c->D.n, c->stream));
   } else {
-    launch_solution(c->D, c->k_done, c->D.y, x, c->stream);
+    launch_backsub(c->D, c->k_done, c->d_ytmp, c->stream);
+    launch_solution(c->D, c->k_done, c->d_ytmp, x, c->stream);
   }
   HIPCHK(c, hipGetLastError());
   HIPCHK(c, hipStreamSynchronize(c->stream));

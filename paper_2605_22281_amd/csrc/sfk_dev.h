@@ -84,9 +84,8 @@ struct Dev {
   double *V;          // s * maxit reflectors (v_j[j] = 1, zeros above)
   double *tauv;       // maxit
   double *R;          // maxit * maxit, column-major
-  double *Rinv;       // maxit * maxit, column-major
   double *c;          // s: Q^T rhs
-  double *y;          // maxit: y_k
+  double *y;          // maxit: y_k (kept current for the reweighting)
 };
 
 __device__ __forceinline__ int wslot(const Dev &D, int j) { return j % (D.ell + 2); }

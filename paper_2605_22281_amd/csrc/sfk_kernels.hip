@@ -565,12 +565,73 @@ __global__ void __launch_bounds__(kWG) k_srht_combine(Dev D, int k, double *dst)
 }
 
 // ---------------------------------------------------------------------------
+// y = R_j^{-1} c[0:j] by column-oriented back-substitution in one wave (R upper
+// triangular, column-major, leading dimension maxit).  Columns are prefetched
+// kBsPF steps ahead; the running right-hand side lives in LDS (cbuf, j doubles).
+// ---------------------------------------------------------------------------
+constexpr int kBsPF = 4;
+
+template <int ER>
+__device__ void backsub_wave(const Dev &D, int j, double *yout, double *cbuf) {
+  const int lane = threadIdx.x;
+  const int ld = D.maxit;
+  const double *R = D.R;
+  for (int t = lane; t < j; t += 64) cbuf[t] = D.c[t];
+  __syncthreads();
+  double col[kBsPF][ER];
+#pragma unroll
+  for (int p = 0; p < kBsPF; ++p) {
+    const int i = j - 1 - p;
+#pragma unroll
+    for (int e = 0; e < ER; ++e) {
+      const int t = lane + 64 * e;
+      col[p][e] = (i >= 0 && t <= i) ? R[(size_t)i * ld + t] : 0.0;
+    }
+  }
+  for (int i0 = j - 1; i0 >= 0; i0 -= kBsPF) {
+#pragma unroll
+    for (int p = 0; p < kBsPF; ++p) {
+      const int i = i0 - p;
+      if (i >= 0) {
+        double dl = 0.0;
+#pragma unroll
+        for (int e = 0; e < ER; ++e)
+          if (lane + 64 * e == i) dl = col[p][e];
+        const double rii = __shfl(dl, i & 63, 64);
+        const double yi = cbuf[i] / rii;
+        if (lane == 0) yout[i] = yi;
+#pragma unroll
+        for (int e = 0; e < ER; ++e) {
+          const int t = lane + 64 * e;
+          if (t < i) cbuf[t] -= col[p][e] * yi;
+        }
+        const int in = i - kBsPF;
+#pragma unroll
+        for (int e = 0; e < ER; ++e) {
+          const int t = lane + 64 * e;
+          col[p][e] = (in >= 0 && t <= in) ? R[(size_t)in * ld + t] : 0.0;
+        }
+        __syncthreads();
+      }
+    }
+  }
+}
+
+// y_j for 1 <= j <= k_done (solution_at, or y_k when it is not kept up to date)
+template <int ER>
+__global__ void __launch_bounds__(64) k_backsub(Dev D, int j, double *yout) {
+  __shared__ double cbuf[kMaxS];
+  backsub_wave<ER>(D, j, yout, cbuf);
+}
+
+// ---------------------------------------------------------------------------
 // LS(k): one wave.  Householder QR of the sketched matrix, grown by one column:
 //   sFLSQR column k = S A z_k;  sFLSMR column k = [S B W_{k+1}] H[:, k].
-// Keeps c = Q^T rhs, R, R^{-1} and y_k = R^{-1} c[0:k] (y_k = y_{k-1} + c_k R^{-1} e_k,
-// since the first k-1 entries of c no longer change).  rho_k = ||c[k:s]||.
+// Keeps c = Q^T rhs and R; rho_k = ||c[k:s]||.  y_k = R^{-1} c[0:k] is formed by
+// back-substitution when the flexible operator needs x_k (reweighting), else on
+// demand (the leading entries of c never change, so any earlier y_j is available).
 // ---------------------------------------------------------------------------
-template <int E, int PF>
+template <int E, int PF, int ER>
 __global__ void __launch_bounds__(64) k_ls(Dev D, int k) {
   if (skip_iter(D, k)) return;
   __shared__ double s_tau[kMaxS];
@@ -705,38 +766,20 @@ __global__ void __launch_bounds__(64) k_ls(Dev D, int k) {
     if (lane == 0) { atomicOr(&sc->breakdown, 4); sc->halt = 1; }
     return;
   }
-  // R^{-1} column and y update
-  const double ib = 1.0 / beta;
-  for (int t = lane; t < nsel; t += 64) {
-    double g = 0.0;
-#pragma unroll 8
-    for (int j = t; j < nsel; ++j) g += D.Rinv[(size_t)j * ldr + t] * s_r[j];
-    g = -g * ib;
-    D.Rinv[(size_t)nsel * ldr + t] = g;
-    D.y[t] += ck * g;
-  }
+  // the reweighting needs y_k = R_k^{-1} c[0:k] before the next basis vector
+  if (D.tau == 1) backsub_wave<ER>(D, k, D.y, s_r);
   if (lane == 0) {
-    D.Rinv[(size_t)nsel * ldr + nsel] = ib;
-    D.y[nsel] = ck * ib;
     D.rho[k - 1] = rho;
     sc->k_done = k;
     if (ld_flag(&sc->happy) == k) { atomicOr(&sc->breakdown, 2); sc->halt = 1; }
     if (sc->tol > 0.0 && rho < sc->tol * sc->rhsnorm) { sc->stopped = 1; sc->halt = 1; }
   }
+  (void)ck;
 }
 
 // ---------------------------------------------------------------------------
 // solution and residual helpers
 // ---------------------------------------------------------------------------
-// y_j = R_j^{-1} c[0:j] for an earlier j (t-th entry per thread)
-__global__ void k_y_at(Dev D, int j, double *yout) {
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= j) return;
-  double g = 0.0;
-  for (int i = t; i < j; ++i) g += D.Rinv[(size_t)i * D.maxit + t] * D.c[i];
-  yout[t] = g;
-}
-
 // x = sum_{j<kk} sigp_{j+1} y_j z~_{j+1}
 __global__ void __launch_bounds__(kWG) k_solution(Dev D, int kk, const double *yv, double *x) {
   extern __shared__ double cf[];
@@ -1056,13 +1099,31 @@ double *sketch_dst(const Dev &D, int k) {
   return D.method == 0 ? D.SK + (size_t)(k - 1) * D.s : D.SK + (size_t)k * D.s;
 }
 
-void launch_ls(const Dev &D, int k, hipStream_t st) {
+template <int ER>
+static void launch_ls_er(const Dev &D, int k, hipStream_t st) {
   const int s = D.s;
-  if (s <= 128) hipLaunchKernelGGL((k_ls<2, 4>), dim3(1), dim3(64), 0, st, D, k);
-  else if (s <= 256) hipLaunchKernelGGL((k_ls<4, 4>), dim3(1), dim3(64), 0, st, D, k);
-  else if (s <= 512) hipLaunchKernelGGL((k_ls<8, 4>), dim3(1), dim3(64), 0, st, D, k);
-  else if (s <= 1024) hipLaunchKernelGGL((k_ls<16, 2>), dim3(1), dim3(64), 0, st, D, k);
-  else hipLaunchKernelGGL((k_ls<32, 2>), dim3(1), dim3(64), 0, st, D, k);
+  if (s <= 128) hipLaunchKernelGGL((k_ls<2, 4, ER>), dim3(1), dim3(64), 0, st, D, k);
+  else if (s <= 256) hipLaunchKernelGGL((k_ls<4, 4, ER>), dim3(1), dim3(64), 0, st, D, k);
+  else if (s <= 512) hipLaunchKernelGGL((k_ls<8, 4, ER>), dim3(1), dim3(64), 0, st, D, k);
+  else if (s <= 1024) hipLaunchKernelGGL((k_ls<16, 2, ER>), dim3(1), dim3(64), 0, st, D, k);
+  else hipLaunchKernelGGL((k_ls<32, 2, ER>), dim3(1), dim3(64), 0, st, D, k);
+}
+
+// ER = elements per lane of an R column (maxit <= 64 * ER)
+void launch_ls(const Dev &D, int k, hipStream_t st) {
+  if (D.maxit <= 128) launch_ls_er<2>(D, k, st);
+  else if (D.maxit <= 256) launch_ls_er<4>(D, k, st);
+  else if (D.maxit <= 512) launch_ls_er<8>(D, k, st);
+  else if (D.maxit <= 1024) launch_ls_er<16>(D, k, st);
+  else launch_ls_er<32>(D, k, st);
+}
+
+void launch_backsub(const Dev &D, int j, double *yout, hipStream_t st) {
+  if (D.maxit <= 128) hipLaunchKernelGGL((k_backsub<2>), dim3(1), dim3(64), 0, st, D, j, yout);
+  else if (D.maxit <= 256) hipLaunchKernelGGL((k_backsub<4>), dim3(1), dim3(64), 0, st, D, j, yout);
+  else if (D.maxit <= 512) hipLaunchKernelGGL((k_backsub<8>), dim3(1), dim3(64), 0, st, D, j, yout);
+  else if (D.maxit <= 1024) hipLaunchKernelGGL((k_backsub<16>), dim3(1), dim3(64), 0, st, D, j, yout);
+  else hipLaunchKernelGGL((k_backsub<32>), dim3(1), dim3(64), 0, st, D, j, yout);
 }
 
 void launch_init_b(const Dev &D, double eta, double noise, double tol_user, int use_disc,
@@ -1108,9 +1169,6 @@ void launch_sketch_build(const Dev &D, uint64_t key0, uint64_t key1, uint64_t ke
     hipLaunchKernelGGL(k_iota, dim3((D.N + 255) / 256), dim3(256), 0, st, scratch, D.N);
     hipLaunchKernelGGL(k_srht_rows, dim3(1), dim3(1), 0, st, D, key0, key1_rows, scratch);
   }
-}
-void launch_y_at(const Dev &D, int j, double *yout, hipStream_t st) {
-  hipLaunchKernelGGL(k_y_at, dim3((j + 255) / 256), dim3(256), 0, st, D, j, yout);
 }
 void launch_solution(const Dev &D, int kk, const double *yv, double *x, hipStream_t st) {
   hipLaunchKernelGGL(k_solution, dim3((D.n + kWG - 1) / kWG), dim3(kWG),
