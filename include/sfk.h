@@ -127,7 +127,9 @@ sfk_status sfk_init(sfk_ctx **out, const sfk_csr *A, const sfk_csr *B, const dou
  * current iterate), *stopped_host = 1 if the stop test fired.  Returns
  * SFK_BREAKDOWN if the basis could not be extended (iterates up to
  * *iters_done_host stay valid), SFK_ESTATE if the capacity maxit is exhausted
- * or the run has already stopped. */
+ * or the run has already stopped.  For a batch: runs k lockstep iterations,
+ * *iters_done_host = lockstep iterations so far, *stopped_host = 1 once every
+ * instance has stopped; per-instance results via sfk_instance_status. */
 sfk_status sfk_iterate(sfk_ctx *ctx, int32_t k, int32_t *iters_done_host, int32_t *stopped_host);
 
 /* x_k = Z_k y_k for the current k, written to the device n-vector x. */
@@ -152,6 +154,37 @@ sfk_status sfk_destroy(sfk_ctx *ctx);
 /* Error description of the last failing call on ctx (NULL: of the calling
  * thread's last failure outside a context).  Never NULL. */
 const char *sfk_last_error(const sfk_ctx *ctx);
+
+/* ---- batches of independent instances ------------------------------------ */
+
+/* Creates a context holding nb independent instances (uneven sizes allowed),
+ * e.g. several tomography problems solved together.  Instance i has its own
+ * A[i] (m_i x n_i), B (B == NULL, or B[i].rows == 0: A[i]^T built on the
+ * device; else B[i], n_i x m_i), right-hand side b[i] (device, m_i) and
+ * parameters p[i] (its own method, sketch, seed, tolerance and stop test).
+ * All instances advance in lockstep: each stage kernel serves every live
+ * instance in one launch, workgroups shared by nonzero count.  An instance
+ * that stops (discrepancy principle, tolerance, breakdown) is skipped from then
+ * on; the others continue.  Workspaces are allocated by the library.  The
+ * plain entry points (sfk_iterate, sfk_solution, ...) act on instance 0 or on
+ * the whole batch as documented there. */
+sfk_status sfk_init_batch(sfk_ctx **out, int32_t nb, const sfk_csr *A, const sfk_csr *B,
+                          const double *const *b, const sfk_params *p, void *stream);
+
+/* Number of instances of a context (1 for sfk_init). */
+int32_t sfk_batch_size(const sfk_ctx *ctx);
+
+/* Iterations completed, stop flag and breakdown bits (1: t_{k+1,k+1} = 0,
+ * 2: h_{k+1,k} = 0, 4: zero sketched column) of instance i. */
+sfk_status sfk_instance_status(sfk_ctx *ctx, int32_t i, int32_t *iters_done_host,
+                               int32_t *stopped_host, int32_t *breakdown_host);
+
+/* x_k of instance i at its own k (device n_i-vector x). */
+sfk_status sfk_instance_solution(sfk_ctx *ctx, int32_t i, double *x);
+
+/* rho_1..rho_k of instance i (see sfk_residual_norms). */
+sfk_status sfk_instance_residual_norms(sfk_ctx *ctx, int32_t i, double *out_host, int32_t cap,
+                                       int32_t *count_host, double *rhs_norm_host);
 
 /* ---- introspection, for parity tests ------------------------------------ */
 

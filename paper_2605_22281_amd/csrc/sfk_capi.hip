@@ -1,5 +1,8 @@
 // Host side of the C ABI declared in include/sfk.h: validation, workspace
-// layout, initialisation and the per-iteration stage sequence.
+// layout, initialisation and the per-iteration stage sequence.  A context holds
+// one instance (sfk_init) or a batch of independent instances (sfk_init_batch)
+// that advance in lockstep: every stage kernel serves all instances of the
+// context in one launch through a block -> (instance, workgroup) map.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -15,15 +18,14 @@
 #include "sfk_dev.h"
 
 namespace sfk {
-void launch_stage_A(const Dev &D, int k, hipStream_t st);
-void launch_stage_B(const Dev &D, int k, hipStream_t st);
-void launch_stage_C(const Dev &D, int k, hipStream_t st);
-void launch_ls(const Dev &D, int k, hipStream_t st);
+void launch_stage_A(const Launch &L, int k, hipStream_t st);
+void launch_stage_B(const Launch &L, int k, hipStream_t st);
+void launch_stage_C(const Launch &L, int k, hipStream_t st);
+void launch_stage_D(const Launch &L, int k, hipStream_t st);
+void launch_sketch(const Launch &L, int k, hipStream_t st);
+void launch_ls(const Launch &L, int k, hipStream_t st);
 int spmv_blocks_per_cu();
-void launch_stage_D(const Dev &D, int k, hipStream_t st);
-void launch_sketch(const Dev &D, int k, const double *v, double *dst, hipStream_t st);
-const double *sketch_src(const Dev &D, int k);
-double *sketch_dst(const Dev &D, int k);
+void launch_backsub(const Dev &D, int j, double *yout, hipStream_t st);
 void launch_init_b(const Dev &D, double eta, double noise, double tol_user, int use_disc,
                    hipStream_t st);
 void launch_init_rhs(const Dev &D, hipStream_t st);
@@ -34,33 +36,42 @@ void launch_transpose(const int *rp, const int *ci, const double *va, int rows, 
                       int *bci, double *bva, int *cursor, int *err, hipStream_t st);
 void launch_sketch_build(const Dev &D, uint64_t key0, uint64_t key1, uint64_t key1_rows,
                          int *scratch, int *err, hipStream_t st);
-void launch_backsub(const Dev &D, int j, double *yout, hipStream_t st);
 void launch_solution(const Dev &D, int kk, const double *yv, double *x, hipStream_t st);
 void launch_true_residual(const Dev &D, const double *x, double *out, hipStream_t st);
 }  // namespace sfk
 
 using namespace sfk;
 
+struct Plan;
+
+struct Inst {
+  sfk_params p{};
+  Dev D{};                        // host copy of the instance descriptor
+  void *ws = nullptr;
+  size_t ws_bytes = 0;
+  bool owns_ws = false;
+  int *d_err = nullptr;
+  double *d_scalar = nullptr;     // one double of scratch (true residual)
+  double *d_ytmp = nullptr;       // maxit
+  int k_done = 0, stopped = 0, breakdown = 0, halted = 0;
+  double rhsnorm = 0.0;
+};
+
 struct sfk_ctx {
-  sfk_params p;
-  Dev D;
+  std::vector<Inst> inst;
   hipStream_t stream = nullptr;
   hipStream_t side = nullptr;       // sketch + least-squares stream (default priority)
   static constexpr int kRing = 4;   // iterations of synchronisation events kept
   hipEvent_t ev_main[kRing] = {}, ev_sk[kRing] = {}, ev_ls[kRing] = {};
-  void *ws = nullptr;
-  size_t ws_bytes = 0;
-  bool owns_ws = false;
-  int k_done = 0;
-  int stopped = 0;
-  int breakdown = 0;
-  int halted = 0;
-  int *d_err = nullptr;
-  double *d_scalar = nullptr;     // one double of scratch (true residual)
-  double *d_ytmp = nullptr;       // maxit
-  Scal *h_scal = nullptr;         // pinned copy of the device scalars
+  void *hdr = nullptr;              // device: instance descriptors and block maps
+  Launch L{};
+  Scal *h_scal = nullptr;           // pinned copies of the device scalars
+  int k_iter = 0;                   // lockstep iterations launched
+  int maxitmax = 0;
+  bool sketch_after_C = false;      // an sFLSMR instance sketches B w_{k+1}
+  bool any_rew = false;
   std::string err;
-  // optional per-stage timing with HIP events on the context's stream
+  // optional per-stage timing with HIP events
   bool timing = false;
   std::vector<hipEvent_t> ev_pool;
   std::vector<std::pair<int, int>> ev_used;   // (stage, index of the start event)
@@ -98,42 +109,43 @@ static void collect_stage_times(sfk_ctx *c) {
   c->ev_used.clear();
 }
 
-// One iteration k of Algorithm 1 (sFLSQR) or Algorithm 2 (sFLSMR).  The
-// data-parallel stages A, B, C, D run on the context's stream; the sketch of
-// the new vector and the least-squares update run on the side stream as soon
-// as their input exists.  The raw vectors are double-buffered by iteration
-// parity, so iteration k + 2 waits for the sketch of iteration k only.  The
-// reweighting needs y_k before D(k), so it waits for LS(k).
+// One lockstep iteration k of Algorithm 1 (sFLSQR) / Algorithm 2 (sFLSMR) for
+// every instance.  The data-parallel stages A, B, C, D run on the context's
+// stream; the sketch of the new vector and the least-squares update run on the
+// side stream as soon as their input exists.  The raw products are
+// double-buffered by iteration parity, so iteration k + 2 waits for the sketch
+// of iteration k only.  The reweighting needs y_k before D(k), so it waits for
+// LS(k).
 static void enqueue_iteration(sfk_ctx *c, int k) {
-  const Dev &D = c->D;
+  const Launch &L = c->L;
   hipStream_t st = c->stream, sd = c->side;
   const int r = k % sfk_ctx::kRing;
   if (k >= 3) hipStreamWaitEvent(st, c->ev_sk[(k - 2) % sfk_ctx::kRing], 0);
   int t = stage_begin(c, SFK_STAGE_SPMV_A, st);
-  launch_stage_A(D, k, st);
+  launch_stage_A(L, k, st);
   stage_end(c, t, st);
   t = stage_begin(c, SFK_STAGE_W_UPDATE, st);
-  launch_stage_B(D, k, st);
+  launch_stage_B(L, k, st);
   stage_end(c, t, st);
-  if (D.method == 0) hipEventRecord(c->ev_main[r], st);
+  if (!c->sketch_after_C) hipEventRecord(c->ev_main[r], st);
   t = stage_begin(c, SFK_STAGE_SPMV_B, st);
-  launch_stage_C(D, k, st);
+  launch_stage_C(L, k, st);
   stage_end(c, t, st);
-  if (D.method == 1) hipEventRecord(c->ev_main[r], st);
+  if (c->sketch_after_C) hipEventRecord(c->ev_main[r], st);
 
   hipStreamWaitEvent(sd, c->ev_main[r], 0);
   t = stage_begin(c, SFK_STAGE_SKETCH, sd);
-  launch_sketch(D, k, sketch_src(D, k), sketch_dst(D, k), sd);
+  launch_sketch(L, k, sd);
   stage_end(c, t, sd);
   hipEventRecord(c->ev_sk[r], sd);
   t = stage_begin(c, SFK_STAGE_LS, sd);
-  launch_ls(D, k, sd);
+  launch_ls(L, k, sd);
   stage_end(c, t, sd);
   hipEventRecord(c->ev_ls[r], sd);
 
-  if (D.tau == 1) hipStreamWaitEvent(st, c->ev_ls[r], 0);
+  if (c->any_rew) hipStreamWaitEvent(st, c->ev_ls[r], 0);
   t = stage_begin(c, SFK_STAGE_P_UPDATE, st);
-  launch_stage_D(D, k, st);
+  launch_stage_D(L, k, st);
   stage_end(c, t, st);
 }
 
@@ -255,7 +267,7 @@ struct Layout {
 
 struct Plan {
   int64_t m, n, nnzA, nnzB;
-  int nw, vwA, vwB, d, N, log2L, nblk, nchunk;
+  int nw, nwmax, vwA, vwB, d, N, log2L, nblk, nchunk;
   bool transpose;
   // offsets
   size_t o_sc, o_err, o_scalar, o_part, o_sigw, o_sigp, o_H, o_T, o_rho;
@@ -277,20 +289,24 @@ static int pick_vw(int64_t nnz, int64_t rows, int user) {
   return 8;
 }
 
-static Plan make_plan(const sfk_csr *A, const sfk_csr *B, const sfk_params *p, int cus,
-                      int blocks_per_cu) {
+static int default_nws(const sfk_csr *A, const sfk_csr *B, const sfk_params *p, int cus,
+                       int blocks_per_cu) {
+  const int64_t nnzmax = std::max(A->nnz, B ? B->nnz : A->nnz);
+  const int cap = cus * (p->wg_per_cu ? p->wg_per_cu : std::max(1, blocks_per_cu));
+  int64_t nw = (nnzmax + 8191) / 8192;
+  nw = std::max<int64_t>(nw, (std::max(A->rows, A->cols) + 2047) / 2048);
+  nw = std::min<int64_t>(std::max<int64_t>(nw, 1), cap);
+  return (int)nw;
+}
+
+static Plan make_plan(const sfk_csr *A, const sfk_csr *B, const sfk_params *p, int cus, int nws) {
   Plan P{};
   P.m = A->rows;
   P.n = A->cols;
   P.nnzA = A->nnz;
   P.transpose = (B == nullptr);
   P.nnzB = B ? B->nnz : A->nnz;
-  const int64_t nnzmax = std::max(P.nnzA, P.nnzB);
-  const int cap = cus * (p->wg_per_cu ? p->wg_per_cu : std::max(1, blocks_per_cu));
-  int64_t nw = (nnzmax + 8191) / 8192;
-  nw = std::max<int64_t>(nw, (std::max(P.m, P.n) + 2047) / 2048);
-  nw = std::min<int64_t>(std::max<int64_t>(nw, 1), cap);
-  P.nw = (int)nw;
+  P.nw = nws;
   P.vwA = pick_vw(P.nnzA, P.m, p->vw);
   P.vwB = pick_vw(P.nnzB, P.n, p->vw);
   P.d = (int)(p->method == SFK_SFLSQR ? P.m : P.n);
@@ -308,6 +324,7 @@ static Plan make_plan(const sfk_csr *A, const sfk_csr *B, const sfk_params *p, i
   // sized for the largest grid any occupancy could give, so that the workspace size
   // does not depend on the device's register allocation
   const int nw_alloc = std::max(P.nw, cus * 8);
+  P.nwmax = nw_alloc;
   P.o_part = L_.take<double>((size_t)kNumPart * kMaxQ * nw_alloc);
   P.o_sigw = L_.take<double>(mi + 2);
   P.o_sigp = L_.take<double>(mi + 2);
@@ -360,7 +377,7 @@ extern "C" size_t sfk_workspace_bytes(const sfk_csr *A, const sfk_csr *B, const 
   if (validate(nullptr, A, B, p) != SFK_OK) return 0;
   int cus = device_cus();
   if (cus <= 0) cus = 256;
-  return make_plan(A, B, p, cus, 2).total;
+  return make_plan(A, B, p, cus, default_nws(A, B, p, cus, 2)).total;
 }
 
 // --------------------------------------------------------------------------
@@ -372,52 +389,54 @@ static T *at(void *base, size_t off) {
 }
 
 static sfk_status read_scal(sfk_ctx *c) {
-  HIPCHK(c, hipMemcpyAsync(c->h_scal, c->D.sc, sizeof(Scal), hipMemcpyDeviceToHost, c->stream));
+  const int nb = (int)c->inst.size();
+  for (int i = 0; i < nb; ++i)
+    HIPCHK(c, hipMemcpyAsync(c->h_scal + i, c->inst[i].D.sc, sizeof(Scal), hipMemcpyDeviceToHost,
+                             c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
-  c->k_done = c->h_scal->k_done;
-  c->stopped = c->h_scal->stopped;
-  c->breakdown = c->h_scal->breakdown;
-  c->halted = c->h_scal->halt;
+  for (int i = 0; i < nb; ++i) {
+    Inst &I = c->inst[i];
+    const Scal &S = c->h_scal[i];
+    I.k_done = S.k_done;
+    I.stopped = S.stopped;
+    I.breakdown = S.breakdown;
+    I.halted = S.halt || S.klimit <= S.k_done;
+    I.rhsnorm = S.rhsnorm;
+  }
   return SFK_OK;
 }
 
-static sfk_status init_impl(sfk_ctx *c, const sfk_csr *A, const sfk_csr *B, const double *b,
-                            void *workspace, size_t ws_bytes) {
-  const sfk_params &p = c->p;
-  const int cus = device_cus();
-  if (cus <= 0) return fail(c, SFK_EDEVICE, "no HIP device available");
+// Carves the workspace of one instance, checks its CSR structures, builds B = A^T
+// if needed, the row partitions and the sketch, and computes beta = ||b||.
+static sfk_status setup_instance(sfk_ctx *c, Inst &I, const sfk_csr *A, const sfk_csr *B,
+                                 const double *b, void *workspace, size_t ws_bytes, int cus,
+                                 int nws) {
+  const sfk_params &p = I.p;
   if ((A->nnz > 0 && (!A->rowptr || !A->colind || !A->val)) || !A->rowptr || !b)
     return fail(c, SFK_EINVAL, "A arrays and b must be device pointers");
   if (B && ((B->nnz > 0 && (!B->colind || !B->val)) || !B->rowptr))
     return fail(c, SFK_EINVAL, "B arrays must be device pointers");
-  const Plan P = make_plan(A, B, &p, cus, spmv_blocks_per_cu());
+  const Plan P = make_plan(A, B, &p, cus, nws);
   if (workspace) {
     if (ws_bytes < P.total)
       return fail(c, SFK_ENOMEM, "workspace of %zu bytes is smaller than the %zu required",
                   ws_bytes, P.total);
-    c->ws = workspace;
-    c->owns_ws = false;
+    I.ws = workspace;
+    I.owns_ws = false;
   } else {
-    hipError_t e = hipMalloc(&c->ws, P.total);
+    hipError_t e = hipMalloc(&I.ws, P.total);
     if (e != hipSuccess) {
-      c->ws = nullptr;
+      I.ws = nullptr;
       return fail(c, SFK_ENOMEM, "hipMalloc of %zu bytes failed: %s", P.total, hipGetErrorString(e));
     }
-    c->owns_ws = true;
+    I.owns_ws = true;
   }
-  c->ws_bytes = P.total;
-  HIPCHK(c, hipHostMalloc((void **)&c->h_scal, sizeof(Scal), hipHostMallocDefault));
-  HIPCHK(c, hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking));
-  for (int i = 0; i < sfk_ctx::kRing; ++i) {
-    HIPCHK(c, hipEventCreateWithFlags(&c->ev_main[i], hipEventDisableTiming));
-    HIPCHK(c, hipEventCreateWithFlags(&c->ev_sk[i], hipEventDisableTiming));
-    HIPCHK(c, hipEventCreateWithFlags(&c->ev_ls[i], hipEventDisableTiming));
-  }
-  void *w = c->ws;
+  I.ws_bytes = P.total;
+  void *w = I.ws;
   hipStream_t st = c->stream;
   HIPCHK(c, hipMemsetAsync(w, 0, P.total, st));
 
-  Dev &D = c->D;
+  Dev &D = I.D;
   std::memset(&D, 0, sizeof D);
   D.m = (int)P.m;
   D.n = (int)P.n;
@@ -432,9 +451,11 @@ static sfk_status init_impl(sfk_ctx *c, const sfk_csr *A, const sfk_csr *B, cons
   D.N = P.N;
   D.log2L = P.log2L;
   D.nblk = P.nblk;
-  D.nw = P.nw;
-  D.vwA = P.vwA;
-  D.vwB = P.vwB;
+  D.nws = P.nw;
+  D.nwv = P.nw;
+  D.nwmax = P.nwmax;
+  D.nsg = p.sketch == SFK_SK_SPARSE_SIGN ? (p.s * 64 + kWG - 1) / kWG
+        : p.sketch == SFK_SK_IDENTITY ? (p.s + kWG - 1) / kWG : 0;
   D.eps = p.eps;
   D.sk_scale = p.sketch == SFK_SK_SPARSE_SIGN ? 1.0 / std::sqrt((double)p.zeta)
              : p.sketch == SFK_SK_SRHT ? 1.0 / std::sqrt((double)p.s) : 1.0;
@@ -446,7 +467,7 @@ static sfk_status init_impl(sfk_ctx *c, const sfk_csr *A, const sfk_csr *B, cons
   D.P = at<double>(w, P.o_P);
   D.Z = at<double>(w, P.o_Z);
   D.wraw = at<double>(w, P.o_wraw);
-  D.zraw = at<double>(w, P.o_zraw);   // slot 1 starts at zraw + n
+  D.zraw = at<double>(w, P.o_zraw);
   D.x = at<double>(w, P.o_x);
   D.sk_rp = at<int>(w, P.o_skrp);
   D.sk_ent = at<int>(w, P.o_skent);
@@ -468,18 +489,18 @@ static sfk_status init_impl(sfk_ctx *c, const sfk_csr *A, const sfk_csr *B, cons
   D.R = at<double>(w, P.o_R);
   D.c = at<double>(w, P.o_c);
   D.y = at<double>(w, P.o_y);
-  c->d_err = at<int>(w, P.o_err);
-  c->d_scalar = at<double>(w, P.o_scalar);
-  c->d_ytmp = at<double>(w, P.o_ytmp);
+  I.d_err = at<int>(w, P.o_err);
+  I.d_scalar = at<double>(w, P.o_scalar);
+  I.d_ytmp = at<double>(w, P.o_ytmp);
 
   // structure checks
-  launch_csr_check(A->rowptr, A->colind, D.m, D.n, A->nnz, c->d_err, st);
+  launch_csr_check(A->rowptr, A->colind, D.m, D.n, A->nnz, I.d_err, st);
   if (B) {
-    launch_csr_check(B->rowptr, B->colind, D.n, D.m, B->nnz, c->d_err, st);
+    launch_csr_check(B->rowptr, B->colind, D.n, D.m, B->nnz, I.d_err, st);
     D.Brp = B->rowptr; D.Bci = B->colind; D.Bva = B->val;
   }
   int herr = 0;
-  HIPCHK(c, hipMemcpyAsync(&herr, c->d_err, sizeof(int), hipMemcpyDeviceToHost, st));
+  HIPCHK(c, hipMemcpyAsync(&herr, I.d_err, sizeof(int), hipMemcpyDeviceToHost, st));
   HIPCHK(c, hipStreamSynchronize(st));
   if (herr) return fail(c, SFK_EINVAL, "invalid CSR structure (code %d): row pointers must rise "
                         "from 0 to nnz and column indices lie in range", herr);
@@ -488,39 +509,117 @@ static sfk_status init_impl(sfk_ctx *c, const sfk_csr *A, const sfk_csr *B, cons
     int *bci = at<int>(w, P.o_bci);
     double *bva = at<double>(w, P.o_bva);
     launch_transpose(A->rowptr, A->colind, A->val, D.m, D.n, brp, bci, bva, at<int>(w, P.o_cursor),
-                     c->d_err, st);
+                     I.d_err, st);
     D.Brp = brp; D.Bci = bci; D.Bva = bva;
   }
-  launch_partition(D.Arp, D.m, P.nnzA, D.nw, at<int>(w, P.o_Apart), st);
-  launch_partition(D.Brp, D.n, P.nnzB, D.nw, at<int>(w, P.o_Bpart), st);
+  launch_partition(D.Arp, D.m, P.nnzA, D.nws, at<int>(w, P.o_Apart), st);
+  launch_partition(D.Brp, D.n, P.nnzB, D.nws, at<int>(w, P.o_Bpart), st);
 
   // sketch
   const uint64_t key0 = p.seed;
   const uint64_t key1 = 0ull + ((uint64_t)(uint32_t)p.instance << 32);
   const uint64_t key1_rows = 1ull + ((uint64_t)(uint32_t)p.instance << 32);
   int *scratch = p.sketch == SFK_SK_SPARSE_SIGN ? at<int>(w, P.o_chunk) : reinterpret_cast<int *>(D.zraw);
-  launch_sketch_build(D, key0, key1, key1_rows, scratch, c->d_err, st);
-  HIPCHK(c, hipMemcpyAsync(&herr, c->d_err, sizeof(int), hipMemcpyDeviceToHost, st));
+  launch_sketch_build(D, key0, key1, key1_rows, scratch, I.d_err, st);
+  HIPCHK(c, hipMemcpyAsync(&herr, I.d_err, sizeof(int), hipMemcpyDeviceToHost, st));
   HIPCHK(c, hipStreamSynchronize(st));
   if (herr) return fail(c, SFK_EINVAL, "initialisation failed (code %d): transposed rows longer "
                         "than 4096 entries or sketch generation exhausted", herr);
   HIPCHK(c, hipGetLastError());
 
-  // Algorithm 1 / 2 initial lines
+  // Algorithm 1 / 2, first line: beta = ||b||, w_1 = b / beta
   const int use_disc = (p.method == SFK_SFLSQR && p.noise_norm > 0.0) ? 1 : 0;
   launch_init_b(D, p.eta, p.noise_norm, p.tol, use_disc, st);
-  if (p.method == SFK_SFLSQR) launch_sketch(D, 0, b, D.skrhs, st);
-  launch_stage_C(D, 0, st);
-  if (p.method == SFK_SFLSMR) launch_sketch(D, 0, D.zraw, D.SK, st);
-  launch_init_rhs(D, st);
-  launch_stage_D(D, 0, st);
-  HIPCHK(c, hipGetLastError());
-  sfk_status s = read_scal(c);
+  return SFK_OK;
+}
+
+// Uploads the instance descriptors and the block maps of every stage type.
+static sfk_status build_launch(sfk_ctx *c) {
+  const int nb = (int)c->inst.size();
+  std::vector<int2> ms, mv, mg, mb, mc;
+  int smax = 0, maxitmax = 0;
+  for (int i = 0; i < nb; ++i) {
+    const Dev &D = c->inst[i].D;
+    for (int w = 0; w < D.nws; ++w) ms.push_back(make_int2(i, w));
+    for (int w = 0; w < D.nwv; ++w) mv.push_back(make_int2(i, w));
+    for (int w = 0; w < D.nsg; ++w) mg.push_back(make_int2(i, w));
+    if (D.sketch == SFK_SK_SRHT) {
+      for (int w = 0; w < D.nblk; ++w) mb.push_back(make_int2(i, w));
+      for (int w = 0; w < (D.s + kWG - 1) / kWG; ++w) mc.push_back(make_int2(i, w));
+    }
+    smax = std::max(smax, D.s);
+    maxitmax = std::max(maxitmax, D.maxit);
+    if (D.method == SFK_SFLSMR) c->sketch_after_C = true;
+    if (D.tau == SFK_TAU_REWEIGHT_L1) c->any_rew = true;
+  }
+  auto al = [](size_t v) { return (v + 255) / 256 * 256; };
+  const size_t o_dev = 0;
+  const size_t o_ms = al(o_dev + sizeof(Dev) * nb);
+  const size_t o_mv = al(o_ms + sizeof(int2) * ms.size());
+  const size_t o_mg = al(o_mv + sizeof(int2) * mv.size());
+  const size_t o_mb = al(o_mg + sizeof(int2) * mg.size());
+  const size_t o_mc = al(o_mb + sizeof(int2) * mb.size());
+  const size_t total = al(o_mc + sizeof(int2) * mc.size()) + 256;
+  HIPCHK(c, hipMalloc(&c->hdr, total));
+  std::vector<char> h(total, 0);
+  for (int i = 0; i < nb; ++i) std::memcpy(h.data() + o_dev + sizeof(Dev) * i, &c->inst[i].D, sizeof(Dev));
+  auto put = [&](size_t off, const std::vector<int2> &v) {
+    if (!v.empty()) std::memcpy(h.data() + off, v.data(), sizeof(int2) * v.size());
+  };
+  put(o_ms, ms); put(o_mv, mv); put(o_mg, mg); put(o_mb, mb); put(o_mc, mc);
+  HIPCHK(c, hipMemcpyAsync(c->hdr, h.data(), total, hipMemcpyHostToDevice, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  Launch &L = c->L;
+  char *base = static_cast<char *>(c->hdr);
+  L.devs = reinterpret_cast<const Dev *>(base + o_dev);
+  L.map_spmv = reinterpret_cast<const int2 *>(base + o_ms);
+  L.map_vec = reinterpret_cast<const int2 *>(base + o_mv);
+  L.map_sg = reinterpret_cast<const int2 *>(base + o_mg);
+  L.map_sb = reinterpret_cast<const int2 *>(base + o_mb);
+  L.map_sc = reinterpret_cast<const int2 *>(base + o_mc);
+  L.nspmv = (int)ms.size();
+  L.nvec = (int)mv.size();
+  L.nsg = (int)mg.size();
+  L.nsb = (int)mb.size();
+  L.nsc = (int)mc.size();
+  L.ninst = nb;
+  L.smax = smax;
+  L.maxitmax = maxitmax;
+  L.tau = c->any_rew ? 1 : 0;
+  c->maxitmax = maxitmax;
+  return SFK_OK;
+}
+
+static sfk_status create_streams(sfk_ctx *c, int nb) {
+  HIPCHK(c, hipHostMalloc((void **)&c->h_scal, sizeof(Scal) * nb, hipHostMallocDefault));
+  HIPCHK(c, hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking));
+  for (int i = 0; i < sfk_ctx::kRing; ++i) {
+    HIPCHK(c, hipEventCreateWithFlags(&c->ev_main[i], hipEventDisableTiming));
+    HIPCHK(c, hipEventCreateWithFlags(&c->ev_sk[i], hipEventDisableTiming));
+    HIPCHK(c, hipEventCreateWithFlags(&c->ev_ls[i], hipEventDisableTiming));
+  }
+  return SFK_OK;
+}
+
+// Algorithm 1 / 2 initial lines after every instance has its beta: z = B w_1,
+// the initial sketch (S b, or S B w_1), the rhs and the first basis vector.
+static sfk_status init_common(sfk_ctx *c) {
+  sfk_status s = build_launch(c);
   if (s != SFK_OK) return s;
-  if (c->h_scal->err & 16)
-    return fail(c, SFK_EINVAL, "right-hand side b is zero or not finite (||b|| = %g)", c->h_scal->beta);
-  if (c->h_scal->breakdown)
-    return fail(c, SFK_BREAKDOWN, "B b is zero: the first basis vector does not exist");
+  hipStream_t st = c->stream;
+  launch_stage_C(c->L, 0, st);
+  launch_sketch(c->L, 0, st);
+  for (auto &I : c->inst) launch_init_rhs(I.D, st);
+  launch_stage_D(c->L, 0, st);
+  HIPCHK(c, hipGetLastError());
+  s = read_scal(c);
+  if (s != SFK_OK) return s;
+  for (size_t i = 0; i < c->inst.size(); ++i) {
+    const Scal &S = c->h_scal[i];
+    if (S.err & 16)
+      return fail(c, SFK_EINVAL, "right-hand side b%s is zero or not finite (||b|| = %g)",
+                  c->inst.size() > 1 ? " of an instance" : "", S.beta);
+  }
   return SFK_OK;
 }
 
@@ -534,7 +633,9 @@ static void release(sfk_ctx *c) {
   }
   for (hipEvent_t e : c->ev_pool) hipEventDestroy(e);
   if (c->side) hipStreamDestroy(c->side);
-  if (c->owns_ws && c->ws) hipFree(c->ws);
+  for (auto &I : c->inst)
+    if (I.owns_ws && I.ws) hipFree(I.ws);
+  if (c->hdr) hipFree(c->hdr);
   if (c->h_scal) hipHostFree(c->h_scal);
   delete c;
 }
@@ -546,10 +647,64 @@ extern "C" sfk_status sfk_init(sfk_ctx **out, const sfk_csr *A, const sfk_csr *B
   *out = nullptr;
   sfk_status s = validate(nullptr, A, B, p);
   if (s != SFK_OK) return s;
+  const int cus = device_cus();
+  if (cus <= 0) return fail(nullptr, SFK_EDEVICE, "no HIP device available");
   sfk_ctx *c = new sfk_ctx();
-  c->p = *p;
   c->stream = static_cast<hipStream_t>(stream);
-  s = init_impl(c, A, B, b, workspace, workspace_bytes);
+  c->inst.resize(1);
+  c->inst[0].p = *p;
+  s = create_streams(c, 1);
+  if (s == SFK_OK)
+    s = setup_instance(c, c->inst[0], A, B, b, workspace, workspace_bytes, cus,
+                       default_nws(A, B, p, cus, spmv_blocks_per_cu()));
+  if (s == SFK_OK) s = init_common(c);
+  if (s != SFK_OK) {
+    g_err = c->err;
+    release(c);
+    return s;
+  }
+  *out = c;
+  return SFK_OK;
+}
+
+extern "C" sfk_status sfk_init_batch(sfk_ctx **out, int32_t nb, const sfk_csr *A,
+                                     const sfk_csr *B, const double *const *b,
+                                     const sfk_params *p, void *stream) {
+  if (!out) return fail(nullptr, SFK_EINVAL, "out must not be NULL");
+  *out = nullptr;
+  if (nb < 1 || nb > 4096) return fail(nullptr, SFK_EINVAL, "batch size %d not in [1, 4096]", nb);
+  if (!A || !b || !p) return fail(nullptr, SFK_EINVAL, "A, b and params arrays must not be NULL");
+  for (int i = 0; i < nb; ++i) {
+    const sfk_csr *Bi = (B && B[i].rows > 0) ? &B[i] : nullptr;
+    sfk_status s = validate(nullptr, &A[i], Bi, &p[i]);
+    if (s != SFK_OK) {
+      g_err = "instance " + std::to_string(i) + ": " + g_err;
+      return s;
+    }
+  }
+  const int cus = device_cus();
+  if (cus <= 0) return fail(nullptr, SFK_EDEVICE, "no HIP device available");
+  // one wave of SpMV workgroups over the whole batch, shared by nonzero count
+  const int G = cus * std::max(1, spmv_blocks_per_cu());
+  double tot = 0.0;
+  for (int i = 0; i < nb; ++i) {
+    const int64_t nz = std::max(A[i].nnz, (B && B[i].rows > 0) ? B[i].nnz : A[i].nnz);
+    tot += (double)nz;
+  }
+  sfk_ctx *c = new sfk_ctx();
+  c->stream = static_cast<hipStream_t>(stream);
+  c->inst.resize(nb);
+  sfk_status s = create_streams(c, nb);
+  for (int i = 0; i < nb && s == SFK_OK; ++i) {
+    c->inst[i].p = p[i];
+    const sfk_csr *Bi = (B && B[i].rows > 0) ? &B[i] : nullptr;
+    const int64_t nz = std::max(A[i].nnz, Bi ? Bi->nnz : A[i].nnz);
+    int nws = (int)std::lround(G * (double)nz / std::max(tot, 1.0));
+    nws = std::max(1, std::min(nws, default_nws(&A[i], Bi, &p[i], cus, spmv_blocks_per_cu())));
+    s = setup_instance(c, c->inst[i], &A[i], Bi, b[i], nullptr, 0, cus, nws);
+    if (s != SFK_OK) c->err = "instance " + std::to_string(i) + ": " + c->err;
+  }
+  if (s == SFK_OK) s = init_common(c);
   if (s != SFK_OK) {
     g_err = c->err;
     release(c);
@@ -566,81 +721,135 @@ extern "C" sfk_status sfk_iterate(sfk_ctx *c, int32_t k, int32_t *iters_done_hos
                                   int32_t *stopped_host) {
   if (!c) return fail(nullptr, SFK_EINVAL, "NULL context");
   if (k < 0) return fail(c, SFK_EINVAL, "k must be >= 0");
-  auto report = [&]() {
-    if (iters_done_host) *iters_done_host = c->k_done;
-    if (stopped_host) *stopped_host = c->stopped;
+  const int nb = (int)c->inst.size();
+  auto all_halted = [&]() {
+    for (auto &I : c->inst) if (!I.halted) return false;
+    return true;
   };
-  if (c->halted) {
+  auto report = [&]() {
+    if (nb == 1) {
+      if (iters_done_host) *iters_done_host = c->inst[0].k_done;
+      if (stopped_host) *stopped_host = c->inst[0].stopped;
+    } else {
+      if (iters_done_host) *iters_done_host = c->k_iter;
+      if (stopped_host) *stopped_host = all_halted() ? 1 : 0;
+    }
+  };
+  if (all_halted()) {
     report();
-    if (c->breakdown) return fail(c, SFK_BREAKDOWN, "the basis broke down at iteration %d", c->k_done);
-    return fail(c, SFK_ESTATE, "the run has stopped at iteration %d", c->k_done);
+    if (nb == 1 && c->inst[0].breakdown)
+      return fail(c, SFK_BREAKDOWN, "the basis broke down at iteration %d", c->inst[0].k_done);
+    return fail(c, SFK_ESTATE, "the run has stopped (iteration %d)", c->k_iter);
   }
-  const int room = c->p.maxit - c->k_done;
+  const int room = c->maxitmax - c->k_iter;
   if (k > room) return fail(c, SFK_ESTATE, "capacity maxit = %d exhausted (done %d, asked %d)",
-                            c->p.maxit, c->k_done, k);
-  const int k0 = c->k_done;
+                            c->maxitmax, c->k_iter, k);
+  const int k0 = c->k_iter;
   for (int i = 1; i <= k; ++i) enqueue_iteration(c, k0 + i);
   if (k > 0) HIPCHK(c, hipStreamWaitEvent(c->stream, c->ev_ls[(k0 + k) % sfk_ctx::kRing], 0));
   HIPCHK(c, hipGetLastError());
+  c->k_iter = k0 + k;
   sfk_status s = read_scal(c);
   if (s != SFK_OK) return s;
   collect_stage_times(c);
   report();
-  if (c->breakdown) return fail(c, SFK_BREAKDOWN, "the basis broke down after iteration %d", c->k_done);
+  if (nb == 1 && c->inst[0].breakdown)
+    return fail(c, SFK_BREAKDOWN, "the basis broke down after iteration %d", c->inst[0].k_done);
+  return SFK_OK;
+}
+
+static sfk_status instance_of(sfk_ctx *c, int i, Inst **I) {
+  if (!c) return fail(nullptr, SFK_EINVAL, "NULL context");
+  if (i < 0 || i >= (int)c->inst.size())
+    return fail(c, SFK_EINVAL, "instance %d not in [0, %d)", i, (int)c->inst.size());
+  *I = &c->inst[i];
+  return SFK_OK;
+}
+
+static sfk_status solution_impl(sfk_ctx *c, Inst &I, int j, double *x) {
+  if (!x) return fail(c, SFK_EINVAL, "x must not be NULL");
+  if (j < 0 || j > I.k_done) return fail(c, SFK_ESTATE, "iterate %d not available (done %d)", j, I.k_done);
+  if (j == 0) {
+    HIPCHK(c, hipMemsetAsync(x, 0, sizeof(double) * I.D.n, c->stream));
+  } else {
+    launch_backsub(I.D, j, I.d_ytmp, c->stream);
+    launch_solution(I.D, j, I.d_ytmp, x, c->stream);
+  }
+  HIPCHK(c, hipGetLastError());
+  HIPCHK(c, hipStreamSynchronize(c->stream));
   return SFK_OK;
 }
 
 extern "C" sfk_status sfk_solution_at(sfk_ctx *c, int32_t j, double *x) {
-  if (!c) return fail(nullptr, SFK_EINVAL, "NULL context");
-  if (!x) return fail(c, SFK_EINVAL, "x must not be NULL");
-  if (j < 0 || j > c->k_done) return fail(c, SFK_ESTATE, "iterate %d not available (done %d)", j, c->k_done);
-  if (j == 0) {
-    HIPCHK(c, hipMemsetAsync(x, 0, sizeof(double) * c->D.n, c->stream));
-  } else {
-    launch_backsub(c->D, j, c->d_ytmp, c->stream);
-    launch_solution(c->D, j, c->d_ytmp, x, c->stream);
-  }
-  HIPCHK(c, hipGetLastError());
-  HIPCHK(c, hipStreamSynchronize(c->stream));
-  return SFK_OK;
+  Inst *I;
+  sfk_status s = instance_of(c, 0, &I);
+  return s != SFK_OK ? s : solution_impl(c, *I, j, x);
 }
 
 extern "C" sfk_status sfk_solution(sfk_ctx *c, double *x) {
-  if (!c) return fail(nullptr, SFK_EINVAL, "NULL context");
-  if (!x) return fail(c, SFK_EINVAL, "x must not be NULL");
-  if (c->k_done == 0) {
-    HIPCHK(c, hipMemsetAsync(x, 0, sizeof(double) * c->D.n, c->stream));
-  } else {
-    launch_backsub(c->D, c->k_done, c->d_ytmp, c->stream);
-    launch_solution(c->D, c->k_done, c->d_ytmp, x, c->stream);
+  Inst *I;
+  sfk_status s = instance_of(c, 0, &I);
+  return s != SFK_OK ? s : solution_impl(c, *I, I->k_done, x);
+}
+
+extern "C" sfk_status sfk_instance_solution(sfk_ctx *c, int32_t i, double *x) {
+  Inst *I;
+  sfk_status s = instance_of(c, i, &I);
+  return s != SFK_OK ? s : solution_impl(c, *I, I->k_done, x);
+}
+
+static sfk_status norms_impl(sfk_ctx *c, Inst &I, double *out_host, int32_t cap,
+                             int32_t *count_host, double *rhs_norm_host) {
+  const int n = std::min(cap, I.k_done);
+  if (n > 0) {
+    if (!out_host) return fail(c, SFK_EINVAL, "out_host must not be NULL");
+    HIPCHK(c, hipMemcpy(out_host, I.D.rho, sizeof(double) * n, hipMemcpyDeviceToHost));
   }
-  HIPCHK(c, hipGetLastError());
-  HIPCHK(c, hipStreamSynchronize(c->stream));
+  if (count_host) *count_host = I.k_done;
+  if (rhs_norm_host) *rhs_norm_host = I.rhsnorm;
   return SFK_OK;
 }
 
 extern "C" sfk_status sfk_residual_norms(sfk_ctx *c, double *out_host, int32_t cap,
                                          int32_t *count_host, double *rhs_norm_host) {
-  if (!c) return fail(nullptr, SFK_EINVAL, "NULL context");
-  const int n = std::min(cap, c->k_done);
-  if (n > 0) {
-    if (!out_host) return fail(c, SFK_EINVAL, "out_host must not be NULL");
-    HIPCHK(c, hipMemcpy(out_host, c->D.rho, sizeof(double) * n, hipMemcpyDeviceToHost));
-  }
-  if (count_host) *count_host = c->k_done;
-  if (rhs_norm_host) *rhs_norm_host = c->h_scal->rhsnorm;
+  Inst *I;
+  sfk_status s = instance_of(c, 0, &I);
+  return s != SFK_OK ? s : norms_impl(c, *I, out_host, cap, count_host, rhs_norm_host);
+}
+
+extern "C" sfk_status sfk_instance_residual_norms(sfk_ctx *c, int32_t i, double *out_host,
+                                                  int32_t cap, int32_t *count_host,
+                                                  double *rhs_norm_host) {
+  Inst *I;
+  sfk_status s = instance_of(c, i, &I);
+  return s != SFK_OK ? s : norms_impl(c, *I, out_host, cap, count_host, rhs_norm_host);
+}
+
+extern "C" sfk_status sfk_instance_status(sfk_ctx *c, int32_t i, int32_t *iters_done_host,
+                                          int32_t *stopped_host, int32_t *breakdown_host) {
+  Inst *I;
+  sfk_status s = instance_of(c, i, &I);
+  if (s != SFK_OK) return s;
+  if (iters_done_host) *iters_done_host = I->k_done;
+  if (stopped_host) *stopped_host = I->stopped;
+  if (breakdown_host) *breakdown_host = I->breakdown;
   return SFK_OK;
 }
 
+extern "C" int32_t sfk_batch_size(const sfk_ctx *c) { return c ? (int32_t)c->inst.size() : 0; }
+
 extern "C" sfk_status sfk_true_residual(sfk_ctx *c, double *out_host) {
-  if (!c || !out_host) return fail(c, SFK_EINVAL, "NULL argument");
-  // D.x is scratch for tau = I and holds x_k itself for the reweighting
-  double *xtmp = c->D.x;
-  sfk_status s = sfk_solution(c, xtmp);
+  Inst *I;
+  sfk_status s = instance_of(c, 0, &I);
   if (s != SFK_OK) return s;
-  launch_true_residual(c->D, xtmp, c->d_scalar, c->stream);
+  if (!out_host) return fail(c, SFK_EINVAL, "NULL argument");
+  // D.x is scratch for tau = I and holds x_k itself for the reweighting
+  double *xtmp = I->D.x;
+  s = solution_impl(c, *I, I->k_done, xtmp);
+  if (s != SFK_OK) return s;
+  launch_true_residual(I->D, xtmp, I->d_scalar, c->stream);
   HIPCHK(c, hipGetLastError());
-  HIPCHK(c, hipMemcpyAsync(out_host, c->d_scalar, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipMemcpyAsync(out_host, I->d_scalar, sizeof(double), hipMemcpyDeviceToHost, c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
   return SFK_OK;
 }
@@ -674,10 +883,10 @@ extern "C" const char *sfk_last_error(const sfk_ctx *c) {
 
 extern "C" sfk_status sfk_sketch_sparse_sign(sfk_ctx *c, int32_t *rows_host, int8_t *neg_host) {
   if (!c) return fail(nullptr, SFK_EINVAL, "NULL context");
-  if (c->p.sketch != SFK_SK_SPARSE_SIGN) return fail(c, SFK_ESTATE, "sketch is not sparse-sign");
-  const size_t cnt = (size_t)c->D.d_sk * c->D.zeta;
+  if (c->inst[0].p.sketch != SFK_SK_SPARSE_SIGN) return fail(c, SFK_ESTATE, "sketch is not sparse-sign");
+  const size_t cnt = (size_t)c->inst[0].D.d_sk * c->inst[0].D.zeta;
   int *h = new int[cnt];
-  hipError_t e = hipMemcpy(h, c->D.sk_code, sizeof(int) * cnt, hipMemcpyDeviceToHost);
+  hipError_t e = hipMemcpy(h, c->inst[0].D.sk_code, sizeof(int) * cnt, hipMemcpyDeviceToHost);
   if (e != hipSuccess) { delete[] h; return fail(c, SFK_EDEVICE, "copy failed: %s", hipGetErrorString(e)); }
   for (size_t i = 0; i < cnt; ++i) {
     if (rows_host) rows_host[i] = h[i] >> 1;
@@ -690,14 +899,14 @@ extern "C" sfk_status sfk_sketch_sparse_sign(sfk_ctx *c, int32_t *rows_host, int
 extern "C" sfk_status sfk_sketch_srht(sfk_ctx *c, int32_t *rows_host, int8_t *neg_host,
                                       int64_t *N_host) {
   if (!c) return fail(nullptr, SFK_EINVAL, "NULL context");
-  if (c->p.sketch != SFK_SK_SRHT) return fail(c, SFK_ESTATE, "sketch is not SRHT");
-  const int N = c->D.N;
+  if (c->inst[0].p.sketch != SFK_SK_SRHT) return fail(c, SFK_ESTATE, "sketch is not SRHT");
+  const int N = c->inst[0].D.N;
   if (N_host) *N_host = N;
-  if (rows_host) HIPCHK(c, hipMemcpy(rows_host, c->D.srht_rows, sizeof(int) * c->D.s, hipMemcpyDeviceToHost));
+  if (rows_host) HIPCHK(c, hipMemcpy(rows_host, c->inst[0].D.srht_rows, sizeof(int) * c->inst[0].D.s, hipMemcpyDeviceToHost));
   if (neg_host) {
     const int nw = N / 64 + (N < 64 ? 1 : 0);
     unsigned long long *h = new unsigned long long[nw];
-    hipError_t e = hipMemcpy(h, c->D.srht_d, sizeof(unsigned long long) * nw, hipMemcpyDeviceToHost);
+    hipError_t e = hipMemcpy(h, c->inst[0].D.srht_d, sizeof(unsigned long long) * nw, hipMemcpyDeviceToHost);
     if (e != hipSuccess) { delete[] h; return fail(c, SFK_EDEVICE, "copy failed: %s", hipGetErrorString(e)); }
     for (int i = 0; i < N; ++i) neg_host[i] = (int8_t)((h[i >> 6] >> (i & 63)) & 1ull);
     delete[] h;
@@ -707,12 +916,12 @@ extern "C" sfk_status sfk_sketch_srht(sfk_ctx *c, int32_t *rows_host, int8_t *ne
 
 extern "C" sfk_status sfk_coefficients(sfk_ctx *c, double *H_host, double *T_host, int32_t k) {
   if (!c) return fail(nullptr, SFK_EINVAL, "NULL context");
-  if (k < 0 || k > c->k_done) return fail(c, SFK_ESTATE, "k = %d not available", k);
-  const int ld = c->p.maxit + 1;
+  if (k < 0 || k > c->inst[0].k_done) return fail(c, SFK_ESTATE, "k = %d not available", k);
+  const int ld = c->inst[0].p.maxit + 1;
   for (int j = 0; j < k; ++j) {
-    if (H_host) HIPCHK(c, hipMemcpy(H_host + (size_t)j * (k + 1), c->D.H + (size_t)j * ld,
+    if (H_host) HIPCHK(c, hipMemcpy(H_host + (size_t)j * (k + 1), c->inst[0].D.H + (size_t)j * ld,
                                     sizeof(double) * (k + 1), hipMemcpyDeviceToHost));
-    if (T_host) HIPCHK(c, hipMemcpy(T_host + (size_t)j * k, c->D.T + (size_t)j * ld,
+    if (T_host) HIPCHK(c, hipMemcpy(T_host + (size_t)j * k, c->inst[0].D.T + (size_t)j * ld,
                                     sizeof(double) * k, hipMemcpyDeviceToHost));
   }
   return SFK_OK;

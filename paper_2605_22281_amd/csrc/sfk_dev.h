@@ -47,7 +47,10 @@ struct Dev {
   int N;              // SRHT padded length
   int log2L;          // SRHT block length log2
   int nblk;           // SRHT blocks
-  int nw;             // data-parallel workgroups of every stage
+  int nws;            // SpMV workgroups of this instance (row ranges)
+  int nwv;            // vector-stage workgroups of this instance
+  int nwmax;          // stride of the per-stage partial-sum buffers
+  int nsg;            // sparse-sign sketch gather workgroups of this instance
   int vwA, vwB;       // SpMV lanes per row
   double eps;
   double sk_scale;    // 1/sqrt(zeta) or 1/sqrt(s)
@@ -55,7 +58,7 @@ struct Dev {
   const int *Arp, *Aci; const double *Ava;
   const int *Brp, *Bci; const double *Bva;
   const double *b;
-  const int *Apart, *Bpart;    // nnz-balanced row ranges, nw + 1 entries each
+  const int *Apart, *Bpart;    // nnz-balanced row ranges, nws + 1 entries each
   // vectors
   double *W;          // (ell + 2) * m, unnormalised w~_j
   double *P;          // (ell + 1) * n, unnormalised p~_j (unused when tau = I)
@@ -73,7 +76,7 @@ struct Dev {
   double *SK;         // s * (maxit + 1), sketched columns
   double *skrhs;      // s
   // stage reductions
-  double *part;       // kNumPart * kMaxQ * nw
+  double *part;       // kNumPart * kMaxQ * nwmax
   Scal *sc;
   double *sigw;       // maxit + 2: 1 / ||w~_j||
   double *sigp;       // maxit + 2: 1 / ||p~_j||
@@ -86,6 +89,15 @@ struct Dev {
   double *R;          // maxit * maxit, column-major
   double *c;          // s: Q^T rhs
   double *y;          // maxit: y_k (kept current for the reweighting)
+};
+
+// Launch geometry of a batch of instances: the device array of instance
+// descriptors and, per stage type, a block -> (instance, workgroup) map.
+struct Launch {
+  const Dev *devs;
+  const int2 *map_spmv, *map_vec, *map_sg, *map_sb, *map_sc;
+  int nspmv, nvec, nsg, nsb, nsc;   // grid sizes
+  int ninst, smax, maxitmax, tau, vwA, vwB;
 };
 
 __device__ __forceinline__ int wslot(const Dev &D, int j) { return j % (D.ell + 2); }

@@ -75,7 +75,12 @@ __device__ __forceinline__ void block_sum(const double (&v)[kMaxQ], int Q, doubl
 }
 
 __device__ __forceinline__ double *part_of(const Dev &D, int stage) {
-  return D.part + (size_t)stage * kMaxQ * D.nw;
+  return D.part + (size_t)stage * kMaxQ * D.nwmax;
+}
+
+// workgroups that produced a stage's partial sums
+__device__ __forceinline__ int producers(const Dev &D, int stage) {
+  return (stage == kStageB || stage == kStageD) ? D.nwv : D.nws;
 }
 
 // Totals of the Q partial sums that the previous stage left, in a fixed order
@@ -83,31 +88,33 @@ __device__ __forceinline__ double *part_of(const Dev &D, int stage) {
 template <int NT>
 __device__ void consume(const Dev &D, int stage, int Q, double *lds_w, double *tot) {
   const double *p = part_of(D, stage);
+  const int np = producers(D, stage);
   double acc[kMaxQ];
 #pragma unroll
   for (int q = 0; q < kMaxQ; ++q) acc[q] = 0.0;
-  for (int i = threadIdx.x; i < D.nw; i += NT) {
+  for (int i = threadIdx.x; i < np; i += NT) {
 #pragma unroll
     for (int q = 0; q < kMaxQ; ++q)
-      if (q < Q) acc[q] += p[(size_t)q * D.nw + i];
+      if (q < Q) acc[q] += p[(size_t)q * D.nwmax + i];
   }
   block_sum<NT>(acc, Q, lds_w, tot);
 }
 
 template <int NT>
-__device__ void produce(const Dev &D, int stage, int Q, const double (&acc)[kMaxQ],
+__device__ void produce(const Dev &D, int stage, int wid, int Q, const double (&acc)[kMaxQ],
                         double *lds_w, double *blk) {
   block_sum<NT>(acc, Q, lds_w, blk);
-  if (threadIdx.x < Q) part_of(D, stage)[(size_t)threadIdx.x * D.nw + blockIdx.x] = blk[threadIdx.x];
+  if (threadIdx.x < Q) part_of(D, stage)[(size_t)threadIdx.x * D.nwmax + wid] = blk[threadIdx.x];
 }
 
 __device__ __forceinline__ int ld_flag(const int *p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// stages of iteration k run only while the run is live and the basis reaches k
+// stages of iteration k run only while the instance is live, within its
+// capacity, and while its basis reaches k
 __device__ __forceinline__ bool skip_iter(const Dev &D, int k) {
-  return ld_flag(&D.sc->halt) != 0 || k > ld_flag(&D.sc->klimit);
+  return k > D.maxit || ld_flag(&D.sc->halt) != 0 || k > ld_flag(&D.sc->klimit);
 }
 
 __device__ __forceinline__ void chunk_range(int d, int nw, int wid, int &i0, int &i1) {
@@ -214,8 +221,11 @@ __device__ void spmv_stream(const int *rp, const int *ci, const double *va, cons
 // independent loads per lane in flight.
 // ---------------------------------------------------------------------------
 template <int VW, bool ISA>
-__global__ void __launch_bounds__(kSpmvWG, 8) k_spmv(Dev D, int k) {
+__global__ void __launch_bounds__(kSpmvWG, 8) k_spmv(const Dev *__restrict__ devs,
+                                                      const int2 *__restrict__ map, int k) {
   constexpr int NT = kSpmvWG;
+  const int2 bm = map[blockIdx.x];
+  const Dev &D = devs[bm.x];
   if (skip_iter(D, k)) return;
   __shared__ double lds_w[kMaxQ * (NT / 64)];
   __shared__ double tot[kMaxQ];
@@ -223,7 +233,7 @@ __global__ void __launch_bounds__(kSpmvWG, 8) k_spmv(Dev D, int k) {
   __shared__ int s_quit;
   __shared__ double ybuf[kRowsLDS];
   Scal *sc = D.sc;
-  const int wid = blockIdx.x;
+  const int wid = bm.y;
   const int ldh = D.maxit + 1;
 
   if (ISA) {
@@ -360,13 +370,17 @@ __global__ void __launch_bounds__(kSpmvWG, 8) k_spmv(Dev D, int k) {
 #pragma unroll
   for (int q = 0; q < kMaxQ; ++q) v[q] = (q < nwin) ? acc[q] : (q == nwin ? acc[kMaxEll + 1] : 0.0);
   __shared__ double blk[kMaxQ];
-  produce<NT>(D, ISA ? kStageA : kStageC, nwin + 1, v, lds_w, blk);
+  produce<NT>(D, ISA ? kStageA : kStageC, wid, nwin + 1, v, lds_w, blk);
 }
 
 // ---------------------------------------------------------------------------
 // B(k): consumes A(k) (dots, ||w||) -> h_jk; w~_{k+1} = w - sum h_jk w_j
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(kWG) k_wupdate(Dev D, int k) {
+__global__ void __launch_bounds__(kWG) k_wupdate(const Dev *__restrict__ devs,
+                                                const int2 *__restrict__ map, int k) {
+  const int2 bm = map[blockIdx.x];
+  const Dev &D = devs[bm.x];
+  const int wid = bm.y;
   if (skip_iter(D, k)) return;
   __shared__ double lds_w[kMaxQ * (kWG / 64)];
   __shared__ double tot[kMaxQ];
@@ -385,9 +399,9 @@ __global__ void __launch_bounds__(kWG) k_wupdate(Dev D, int k) {
       for (int i = 0; i < q; ++i) t -= h[i] * sc->Gw[wslot(D, jq) * ns + wslot(D, j0 + i)];
       h[q] = t;
       s_cf[q] = t * D.sigw[jq];
-      if (blockIdx.x == 0) D.H[(size_t)(k - 1) * ldh + (jq - 1)] = t;
+      if (wid == 0) D.H[(size_t)(k - 1) * ldh + (jq - 1)] = t;
     }
-    if (blockIdx.x == 0) sc->wpre = sqrt(tot[nwin]);
+    if (wid == 0) sc->wpre = sqrt(tot[nwin]);
   }
   __syncthreads();
   const double *win[kMaxEll + 1];
@@ -400,7 +414,7 @@ __global__ void __launch_bounds__(kWG) k_wupdate(Dev D, int k) {
   const double *wr = wrawk(D, k);
   double *out = wvec(D, k + 1);
   int i0, i1;
-  chunk_range(D.m, D.nw, blockIdx.x, i0, i1);
+  chunk_range(D.m, D.nwv, wid, i0, i1);
   double acc[kMaxQ];
 #pragma unroll
   for (int q = 0; q < kMaxQ; ++q) acc[q] = 0.0;
@@ -416,7 +430,7 @@ __global__ void __launch_bounds__(kWG) k_wupdate(Dev D, int k) {
     for (int q = 0; q < kMaxEll + 1; ++q)
       if (q < nwin) acc[1 + q] += v * wj[q];
   }
-  produce<kWG>(D, kStageB, nwin + 1, acc, lds_w, blk);
+  produce<kWG>(D, kStageB, wid, nwin + 1, acc, lds_w, blk);
 }
 
 // ---------------------------------------------------------------------------
@@ -424,7 +438,11 @@ __global__ void __launch_bounds__(kWG) k_wupdate(Dev D, int k) {
 // z~_{k+1} = tau(p~_{k+1}).  k = 0 is the initial step (empty window, x_0 = 0).
 // The reweighting assembles x_k = Z_k y_k on the fly (y_k from LS(k)).
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(kWG) k_pupdate(Dev D, int k) {
+__global__ void __launch_bounds__(kWG) k_pupdate(const Dev *__restrict__ devs,
+                                                const int2 *__restrict__ map, int k) {
+  const int2 bm = map[blockIdx.x];
+  const Dev &D = devs[bm.x];
+  const int wid = bm.y;
   if (skip_iter(D, k)) return;
   __shared__ double lds_w[kMaxQ * (kWG / 64)];
   __shared__ double tot[kMaxQ];
@@ -444,9 +462,9 @@ __global__ void __launch_bounds__(kWG) k_pupdate(Dev D, int k) {
       for (int i = 0; i < q; ++i) v -= t[i] * sc->Gp[pslot(D, jq) * ns + pslot(D, j0 + i)];
       t[q] = v;
       s_cf[q] = v * D.sigp[jq];
-      if (blockIdx.x == 0) D.T[(size_t)k * ldh + (jq - 1)] = v;
+      if (wid == 0) D.T[(size_t)k * ldh + (jq - 1)] = v;
     }
-    if (blockIdx.x == 0) sc->zpre = sqrt(tot[nwin]);
+    if (wid == 0) sc->zpre = sqrt(tot[nwin]);
   }
   const bool rew = D.tau == 1;
   if (rew)
@@ -464,7 +482,7 @@ __global__ void __launch_bounds__(kWG) k_pupdate(Dev D, int k) {
   double *pout = rew ? D.P + (size_t)pslot(D, k + 1) * D.n : zcol;
   const double eps2 = D.eps * D.eps;
   int i0, i1;
-  chunk_range(D.n, D.nw, blockIdx.x, i0, i1);
+  chunk_range(D.n, D.nwv, wid, i0, i1);
   double acc[kMaxQ];
 #pragma unroll
   for (int q = 0; q < kMaxQ; ++q) acc[q] = 0.0;
@@ -486,25 +504,40 @@ __global__ void __launch_bounds__(kWG) k_pupdate(Dev D, int k) {
     for (int q = 0; q < kMaxEll + 1; ++q)
       if (q < nwin) acc[1 + q] += v * pj[q];
   }
-  produce<kWG>(D, kStageD, nwin + 1, acc, lds_w, blk);
+  produce<kWG>(D, kStageD, wid, nwin + 1, acc, lds_w, blk);
 }
 
 // ---------------------------------------------------------------------------
-// Sketch application (side stream).  k > 0 marks the sketch of iteration k
-// (skipped once the run has halted); k = 0 is used at initialisation.
+// Sketch application (side stream).  k = 0 is the initial sketch (S b for
+// sFLSQR, S B w_1 for sFLSMR); k > 0 sketches the raw product of iteration k
+// (skipped once the instance has halted).  map[blockIdx.x] = (instance, tile).
 // ---------------------------------------------------------------------------
+__device__ __forceinline__ const double *sketch_in(const Dev &D, int k) {
+  if (k == 0) return D.method == 0 ? D.b : zrawk(D, 0);
+  return D.method == 0 ? wrawk(D, k) : zrawk(D, k);
+}
+__device__ __forceinline__ double *sketch_out(const Dev &D, int k) {
+  if (k == 0) return D.method == 0 ? D.skrhs : D.SK;
+  return D.method == 0 ? D.SK + (size_t)(k - 1) * D.s : D.SK + (size_t)k * D.s;
+}
+
 // sparse-sign: one wave per sketch row, over the row's (column, sign) entries
 // in increasing column order; identity: copy.
-__global__ void __launch_bounds__(kWG) k_sketch_gather(Dev D, int k, const double *v, double *dst) {
+__global__ void __launch_bounds__(kWG) k_sketch_gather(const Dev *__restrict__ devs,
+                                                      const int2 *__restrict__ map, int k) {
+  const int2 bm = map[blockIdx.x];
+  const Dev &D = devs[bm.x];
   if (k > 0 && skip_iter(D, k)) return;
+  const double *v = sketch_in(D, k);
+  double *dst = sketch_out(D, k);
   if (D.sketch == 2) {
-    const int i = blockIdx.x * kWG + threadIdx.x;
+    const int i = bm.y * kWG + threadIdx.x;
     if (i < D.s) dst[i] = v[i];
     return;
   }
-  const int wave = (blockIdx.x * kWG + threadIdx.x) >> 6;
+  const int wave = (bm.y * kWG + threadIdx.x) >> 6;
   const int lane = threadIdx.x & 63;
-  const int nwaves = (gridDim.x * kWG) >> 6;
+  const int nwaves = (D.nsg * kWG) >> 6;
   for (int r = wave; r < D.s; r += nwaves) {
     const int e0 = D.sk_rp[r], e1 = D.sk_rp[r + 1];
     double acc = 0.0;
@@ -521,11 +554,15 @@ __global__ void __launch_bounds__(kWG) k_sketch_gather(Dev D, int k, const doubl
 // SRHT, stage 1: per block of L = 2^log2L entries, u = D pad(v) staged in LDS and
 // transformed by the Sylvester-ordered Walsh-Hadamard butterflies; the entries
 // that the s selected rows need are kept: part[b][i] = (H_L u_b)[rows_i mod L].
-__global__ void __launch_bounds__(kWG) k_srht_blocks(Dev D, int k, const double *v) {
+__global__ void __launch_bounds__(kWG) k_srht_blocks(const Dev *__restrict__ devs,
+                                                    const int2 *__restrict__ map, int k) {
+  const int2 bm = map[blockIdx.x];
+  const Dev &D = devs[bm.x];
   if (k > 0 && skip_iter(D, k)) return;
   __shared__ double u[kSrhtL];
+  const double *v = sketch_in(D, k);
   const int L = 1 << D.log2L;
-  const int b = blockIdx.x;
+  const int b = bm.y;
   const int base = b * L;
   for (int i = threadIdx.x; i < L; i += kWG) {
     const int g = base + i;
@@ -551,10 +588,14 @@ __global__ void __launch_bounds__(kWG) k_srht_blocks(Dev D, int k, const double 
 }
 
 // SRHT, stage 2: dst_i = (1/sqrt(s)) sum_b (-1)^popcount((rows_i >> log2L) & b) part[b][i]
-__global__ void __launch_bounds__(kWG) k_srht_combine(Dev D, int k, double *dst) {
+__global__ void __launch_bounds__(kWG) k_srht_combine(const Dev *__restrict__ devs,
+                                                     const int2 *__restrict__ map, int k) {
+  const int2 bm = map[blockIdx.x];
+  const Dev &D = devs[bm.x];
   if (k > 0 && skip_iter(D, k)) return;
-  const int i = blockIdx.x * kWG + threadIdx.x;
+  const int i = bm.y * kWG + threadIdx.x;
   if (i >= D.s) return;
+  double *dst = sketch_out(D, k);
   const int hi = D.srht_rows[i] >> D.log2L;
   double acc = 0.0;
   for (int b = 0; b < D.nblk; ++b) {
@@ -632,7 +673,8 @@ __global__ void __launch_bounds__(64) k_backsub(Dev D, int j, double *yout) {
 // demand (the leading entries of c never change, so any earlier y_j is available).
 // ---------------------------------------------------------------------------
 template <int E, int PF, int ER>
-__global__ void __launch_bounds__(64) k_ls(Dev D, int k) {
+__global__ void __launch_bounds__(64) k_ls(const Dev *__restrict__ devs, int k) {
+  const Dev &D = devs[blockIdx.x];
   if (skip_iter(D, k)) return;
   __shared__ double s_tau[kMaxS];
   __shared__ double s_r[kMaxS];
@@ -807,7 +849,7 @@ __global__ void __launch_bounds__(kWG) k_true_residual(Dev D, const double *x) {
     s = wave_sum(s);
     if (lane == 0) { const double rr = D.b[r] - s; acc[0] += rr * rr; }
   }
-  produce<kWG>(D, kStageMisc, 1, acc, lds_w, blk);
+  produce<kWG>(D, kStageMisc, blockIdx.x, 1, acc, lds_w, blk);
 }
 
 __global__ void __launch_bounds__(kWG) k_finish_misc(Dev D, double *out) {
@@ -1048,15 +1090,17 @@ __global__ void __launch_bounds__(64) k_init_rhs(Dev D) {
 // ---------------------------------------------------------------------------
 // launch helpers (host side)
 // ---------------------------------------------------------------------------
+// Launch geometry of one batch of instances (device arrays built by the host).
 template <bool ISA>
-static void launch_spmv_vw(const Dev &D, int k, int vw, hipStream_t st) {
-  const dim3 g(D.nw), b(kSpmvWG);
+static void launch_spmv_vw(const Launch &L, int k, int vw, hipStream_t st) {
+  const dim3 g(L.nspmv), b(kSpmvWG);
+  const int2 *map = L.map_spmv;
   switch (vw) {
-    case 8: hipLaunchKernelGGL((k_spmv<8, ISA>), g, b, 0, st, D, k); break;
-    case 16: hipLaunchKernelGGL((k_spmv<16, ISA>), g, b, 0, st, D, k); break;
-    case 32: hipLaunchKernelGGL((k_spmv<32, ISA>), g, b, 0, st, D, k); break;
-    case 64: hipLaunchKernelGGL((k_spmv<64, ISA>), g, b, 0, st, D, k); break;
-    default: hipLaunchKernelGGL((k_spmv<0, ISA>), g, b, 0, st, D, k); break;
+    case 8: hipLaunchKernelGGL((k_spmv<8, ISA>), g, b, 0, st, L.devs, map, k); break;
+    case 16: hipLaunchKernelGGL((k_spmv<16, ISA>), g, b, 0, st, L.devs, map, k); break;
+    case 32: hipLaunchKernelGGL((k_spmv<32, ISA>), g, b, 0, st, L.devs, map, k); break;
+    case 64: hipLaunchKernelGGL((k_spmv<64, ISA>), g, b, 0, st, L.devs, map, k); break;
+    default: hipLaunchKernelGGL((k_spmv<0, ISA>), g, b, 0, st, L.devs, map, k); break;
   }
 }
 
@@ -1068,54 +1112,44 @@ int spmv_blocks_per_cu() {
   return nb > 0 ? nb : 1;
 }
 
-void launch_stage_A(const Dev &D, int k, hipStream_t st) { launch_spmv_vw<true>(D, k, D.vwA, st); }
-void launch_stage_C(const Dev &D, int k, hipStream_t st) { launch_spmv_vw<false>(D, k, D.vwB, st); }
-void launch_stage_B(const Dev &D, int k, hipStream_t st) {
-  hipLaunchKernelGGL(k_wupdate, dim3(D.nw), dim3(kWG), 0, st, D, k);
+void launch_stage_A(const Launch &L, int k, hipStream_t st) { launch_spmv_vw<true>(L, k, L.vwA, st); }
+void launch_stage_C(const Launch &L, int k, hipStream_t st) { launch_spmv_vw<false>(L, k, L.vwB, st); }
+void launch_stage_B(const Launch &L, int k, hipStream_t st) {
+  hipLaunchKernelGGL(k_wupdate, dim3(L.nvec), dim3(kWG), 0, st, L.devs, L.map_vec, k);
 }
-void launch_stage_D(const Dev &D, int k, hipStream_t st) {
-  const size_t sh = D.tau == 1 ? sizeof(double) * (size_t)max(1, k) : 0;
-  hipLaunchKernelGGL(k_pupdate, dim3(D.nw), dim3(kWG), sh, st, D, k);
+void launch_stage_D(const Launch &L, int k, hipStream_t st) {
+  const size_t sh = L.tau == 1 ? sizeof(double) * (size_t)max(1, k) : 0;
+  hipLaunchKernelGGL(k_pupdate, dim3(L.nvec), dim3(kWG), sh, st, L.devs, L.map_vec, k);
 }
 
-// sketch of v into dst; k > 0 marks an iteration stage (skipped once halted)
-void launch_sketch(const Dev &D, int k, const double *v, double *dst, hipStream_t st) {
-  if (D.sketch == 1) {
-    hipLaunchKernelGGL(k_srht_blocks, dim3(D.nblk), dim3(kWG), 0, st, D, k, v);
-    hipLaunchKernelGGL(k_srht_combine, dim3((D.s + kWG - 1) / kWG), dim3(kWG), 0, st, D, k, dst);
-  } else if (D.sketch == 2) {
-    hipLaunchKernelGGL(k_sketch_gather, dim3((D.s + kWG - 1) / kWG), dim3(kWG), 0, st, D, k, v, dst);
-  } else {
-    const int blocks = (D.s * 64 + kWG - 1) / kWG;
-    hipLaunchKernelGGL(k_sketch_gather, dim3(blocks), dim3(kWG), 0, st, D, k, v, dst);
+// sketch of iteration k (k = 0: the initial sketch) for every instance
+void launch_sketch(const Launch &L, int k, hipStream_t st) {
+  if (L.nsb > 0) {
+    hipLaunchKernelGGL(k_srht_blocks, dim3(L.nsb), dim3(kWG), 0, st, L.devs, L.map_sb, k);
+    hipLaunchKernelGGL(k_srht_combine, dim3(L.nsc), dim3(kWG), 0, st, L.devs, L.map_sc, k);
   }
-}
-
-// the raw vector the sketch of iteration k reads, and its destination column
-const double *sketch_src(const Dev &D, int k) {
-  return D.method == 0 ? D.wraw + (size_t)(k & 1) * D.m : D.zraw + (size_t)(k & 1) * D.n;
-}
-double *sketch_dst(const Dev &D, int k) {
-  return D.method == 0 ? D.SK + (size_t)(k - 1) * D.s : D.SK + (size_t)k * D.s;
+  if (L.nsg > 0)
+    hipLaunchKernelGGL(k_sketch_gather, dim3(L.nsg), dim3(kWG), 0, st, L.devs, L.map_sg, k);
 }
 
 template <int ER>
-static void launch_ls_er(const Dev &D, int k, hipStream_t st) {
-  const int s = D.s;
-  if (s <= 128) hipLaunchKernelGGL((k_ls<2, 4, ER>), dim3(1), dim3(64), 0, st, D, k);
-  else if (s <= 256) hipLaunchKernelGGL((k_ls<4, 4, ER>), dim3(1), dim3(64), 0, st, D, k);
-  else if (s <= 512) hipLaunchKernelGGL((k_ls<8, 4, ER>), dim3(1), dim3(64), 0, st, D, k);
-  else if (s <= 1024) hipLaunchKernelGGL((k_ls<16, 2, ER>), dim3(1), dim3(64), 0, st, D, k);
-  else hipLaunchKernelGGL((k_ls<32, 2, ER>), dim3(1), dim3(64), 0, st, D, k);
+static void launch_ls_er(const Launch &L, int k, hipStream_t st) {
+  const int s = L.smax;
+  const dim3 g(L.ninst), b(64);
+  if (s <= 128) hipLaunchKernelGGL((k_ls<2, 4, ER>), g, b, 0, st, L.devs, k);
+  else if (s <= 256) hipLaunchKernelGGL((k_ls<4, 4, ER>), g, b, 0, st, L.devs, k);
+  else if (s <= 512) hipLaunchKernelGGL((k_ls<8, 4, ER>), g, b, 0, st, L.devs, k);
+  else if (s <= 1024) hipLaunchKernelGGL((k_ls<16, 2, ER>), g, b, 0, st, L.devs, k);
+  else hipLaunchKernelGGL((k_ls<32, 2, ER>), g, b, 0, st, L.devs, k);
 }
 
 // ER = elements per lane of an R column (maxit <= 64 * ER)
-void launch_ls(const Dev &D, int k, hipStream_t st) {
-  if (D.maxit <= 128) launch_ls_er<2>(D, k, st);
-  else if (D.maxit <= 256) launch_ls_er<4>(D, k, st);
-  else if (D.maxit <= 512) launch_ls_er<8>(D, k, st);
-  else if (D.maxit <= 1024) launch_ls_er<16>(D, k, st);
-  else launch_ls_er<32>(D, k, st);
+void launch_ls(const Launch &L, int k, hipStream_t st) {
+  if (L.maxitmax <= 128) launch_ls_er<2>(L, k, st);
+  else if (L.maxitmax <= 256) launch_ls_er<4>(L, k, st);
+  else if (L.maxitmax <= 512) launch_ls_er<8>(L, k, st);
+  else if (L.maxitmax <= 1024) launch_ls_er<16>(L, k, st);
+  else launch_ls_er<32>(L, k, st);
 }
 
 void launch_backsub(const Dev &D, int j, double *yout, hipStream_t st) {
@@ -1175,7 +1209,7 @@ void launch_solution(const Dev &D, int kk, const double *yv, double *x, hipStrea
                      sizeof(double) * (size_t)max(1, kk), st, D, kk, yv, x);
 }
 void launch_true_residual(const Dev &D, const double *x, double *out, hipStream_t st) {
-  hipLaunchKernelGGL(k_true_residual, dim3(D.nw), dim3(kWG), 0, st, D, x);
+  hipLaunchKernelGGL(k_true_residual, dim3(D.nws), dim3(kWG), 0, st, D, x);
   hipLaunchKernelGGL(k_finish_misc, dim3(1), dim3(kWG), 0, st, D, out);
 }
 

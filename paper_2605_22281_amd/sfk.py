@@ -85,6 +85,11 @@ def lib() -> ctypes.CDLL:
         "sfk_coefficients": (I32, [P, PD, PD, I32]),
         "sfk_version": (ctypes.c_char_p, []),
         "sfk_set_timing": (I32, [P, I32]),
+        "sfk_init_batch": (I32, [ctypes.POINTER(P), I32, PCSR, PCSR, ctypes.POINTER(P), PPAR, P]),
+        "sfk_batch_size": (I32, [P]),
+        "sfk_instance_status": (I32, [P, I32, PI32, PI32, PI32]),
+        "sfk_instance_solution": (I32, [P, I32, P]),
+        "sfk_instance_residual_norms": (I32, [P, I32, PD, I32, PI32, PD]),
         "sfk_stage_times": (I32, [P, PD, PI32]),
     }
     for name, (res, args) in sig.items():
@@ -99,7 +104,9 @@ def exported_symbols() -> list[str]:
     return ["sfk_params_default", "sfk_validate", "sfk_workspace_bytes", "sfk_init", "sfk_iterate",
             "sfk_solution", "sfk_solution_at", "sfk_residual_norms", "sfk_true_residual",
             "sfk_destroy", "sfk_last_error", "sfk_sketch_sparse_sign", "sfk_sketch_srht",
-            "sfk_coefficients", "sfk_version", "sfk_set_timing", "sfk_stage_times"]
+            "sfk_coefficients", "sfk_version", "sfk_set_timing", "sfk_stage_times",
+            "sfk_init_batch", "sfk_batch_size", "sfk_instance_status", "sfk_instance_solution",
+            "sfk_instance_residual_norms"]
 
 
 def _check(status: int, ctx=None):
@@ -314,6 +321,63 @@ def stage_times(ctx: Context) -> dict:
     cnt = (ctypes.c_int32 * len(STAGES))()
     _check(lib().sfk_stage_times(ctx.handle, ms, cnt), ctx.handle)
     return {name: (ms[i], cnt[i]) for i, name in enumerate(STAGES)}
+
+
+class BatchContext:
+    """A context of independent instances advancing in lockstep."""
+
+    def __init__(self, handle, As, Bs, bs, ps, stream):
+        self.handle = handle
+        self.As, self.Bs, self.bs, self.ps, self.stream = As, Bs, bs, ps, stream
+        self.nb = len(As)
+
+    def __del__(self):
+        try:
+            if self.handle is not None and _lib is not None:
+                lib().sfk_destroy(self.handle)
+                self.handle = None
+        except Exception:
+            pass
+
+
+def init_batch(As: list, Bs: list | None, bs: list, ps: list, *, stream=None) -> BatchContext:
+    """sfk_init_batch: lists of DeviceCSR A_i, DeviceCSR-or-None B_i, CUDA b_i, Params p_i."""
+    import torch
+    nb = len(As)
+    Aarr = (CSR * nb)(*[A.c() for A in As])
+    Barr = None
+    if Bs is not None and any(B is not None for B in Bs):
+        Barr = (CSR * nb)(*[(B.c() if B is not None else CSR(0, 0, 0, None, None, None)) for B in Bs])
+    barr = (ctypes.c_void_p * nb)(*[b.data_ptr() for b in bs])
+    parr = (Params * nb)(*ps)
+    st_obj = stream if stream is not None else torch.cuda.current_stream(bs[0].device)
+    h = ctypes.c_void_p()
+    st = lib().sfk_init_batch(ctypes.byref(h), nb, Aarr, Barr, barr, parr, st_obj.cuda_stream)
+    _check(st)
+    return BatchContext(h, As, Bs, bs, ps, st_obj)
+
+
+def instance_status(ctx, i: int) -> tuple[int, bool, int]:
+    d, s, b = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+    _check(lib().sfk_instance_status(ctx.handle, i, ctypes.byref(d), ctypes.byref(s), ctypes.byref(b)),
+           ctx.handle)
+    return d.value, bool(s.value), b.value
+
+
+def instance_solution(ctx, i: int, n: int, out=None):
+    import torch
+    x = out if out is not None else torch.empty(n, dtype=torch.float64, device="cuda")
+    _check(lib().sfk_instance_solution(ctx.handle, i, x.data_ptr()), ctx.handle)
+    return x
+
+
+def instance_residual_norms(ctx, i: int, cap: int) -> tuple[np.ndarray, float]:
+    buf = (ctypes.c_double * max(1, cap))()
+    cnt = ctypes.c_int32()
+    rn = ctypes.c_double()
+    _check(lib().sfk_instance_residual_norms(ctx.handle, i, buf, max(1, cap), ctypes.byref(cnt),
+                                             ctypes.byref(rn)), ctx.handle)
+    return np.array(buf[: min(cnt.value, cap)]), rn.value
 
 
 def version() -> str:
