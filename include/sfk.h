@@ -171,6 +171,27 @@ const char *sfk_last_error(const sfk_ctx *ctx);
 sfk_status sfk_init_batch(sfk_ctx **out, int32_t nb, const sfk_csr *A, const sfk_csr *B,
                           const double *const *b, const sfk_params *p, void *stream);
 
+/* ---- right-hand sides sharing one operator pair ----------------------------- */
+
+/* Creates a context holding R right-hand sides (1 <= R <= 64) of one problem
+ * pair A (m x n), B (n x m, or NULL for A^T built on the device), e.g. 32
+ * phantoms measured with one scanner geometry.  b_block (device) holds the R
+ * right-hand sides column after column: b_r = b_block + r * m.  p[r] gives
+ * the parameters of right-hand side r; they must agree in method, ell, maxit,
+ * sketch kind, s, zeta (sparse-sign) and tau / eps, and may differ in seed and
+ * instance (each right-hand side draws its own sketch), eta, noise_norm and
+ * tol (each has its own stop test).  Every iteration reads A and B once for
+ * all right-hand sides: the long vectors are stored interleaved (element i of
+ * right-hand side r next to that of r + 1), so the products run as a sparse
+ * matrix times a block of vectors.  Each right-hand side is an instance of the
+ * context: sfk_instance_status / _solution / _residual_norms report it, and
+ * one that stops is skipped from then on while the others continue.
+ * Workspaces are allocated by the library; A, B and b_block are borrowed and
+ * must outlive the context.  SFK_EINVAL for an R out of range, parameters that
+ * differ where they must agree, or any error sfk_init reports. */
+sfk_status sfk_init_multi(sfk_ctx **out, const sfk_csr *A, const sfk_csr *B,
+                          const double *b_block, int32_t R, const sfk_params *p, void *stream);
+
 /* Number of instances of a context (1 for sfk_init). */
 int32_t sfk_batch_size(const sfk_ctx *ctx);
 
@@ -185,6 +206,9 @@ sfk_status sfk_instance_solution(sfk_ctx *ctx, int32_t i, double *x);
 /* rho_1..rho_k of instance i (see sfk_residual_norms). */
 sfk_status sfk_instance_residual_norms(sfk_ctx *ctx, int32_t i, double *out_host, int32_t cap,
                                        int32_t *count_host, double *rhs_norm_host);
+
+/* ||b_i - A_i x_k|| of instance i at its own k (see sfk_true_residual). */
+sfk_status sfk_instance_true_residual(sfk_ctx *ctx, int32_t i, double *out_host);
 
 /* ---- introspection, for parity tests ------------------------------------ */
 

@@ -1,8 +1,10 @@
 // Host side of the C ABI declared in include/sfk.h: validation, workspace
 // layout, initialisation and the per-iteration stage sequence.  A context holds
-// one instance (sfk_init) or a batch of independent instances (sfk_init_batch)
-// that advance in lockstep: every stage kernel serves all instances of the
-// context in one launch through a block -> (instance, workgroup) map.
+// one instance (sfk_init), a batch of independent instances (sfk_init_batch),
+// or R right-hand sides sharing one operator pair (sfk_init_multi).  They
+// advance in lockstep: every stage kernel serves all instances of the context
+// in one launch, through a block -> (instance, workgroup) map for a batch, or
+// over interleaved vectors for shared operators.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -38,6 +40,8 @@ void launch_sketch_build(const Dev &D, uint64_t key0, uint64_t key1, uint64_t ke
                          int *scratch, int *err, hipStream_t st);
 void launch_solution(const Dev &D, int kk, const double *yv, double *x, hipStream_t st);
 void launch_true_residual(const Dev &D, const double *x, double *out, hipStream_t st);
+void launch_group_stage(const Grp &G, int stage, int k, hipStream_t st);
+int gspmm_blocks_per_cu(int RS);
 }  // namespace sfk
 
 using namespace sfk;
@@ -53,6 +57,7 @@ struct Inst {
   int *d_err = nullptr;
   double *d_scalar = nullptr;     // one double of scratch (true residual)
   double *d_ytmp = nullptr;       // maxit
+  int *chunk_scratch = nullptr;   // sparse-sign build scratch
   int k_done = 0, stopped = 0, breakdown = 0, halted = 0;
   double rhsnorm = 0.0;
 };
@@ -70,6 +75,9 @@ struct sfk_ctx {
   int maxitmax = 0;
   bool sketch_after_C = false;      // an sFLSMR instance sketches B w_{k+1}
   bool any_rew = false;
+  bool multi = false;               // right-hand sides sharing A and B (stages via grp)
+  Grp grp{};
+  void *gws = nullptr;              // workspace of the shared arrays
   std::string err;
   // optional per-stage timing with HIP events
   bool timing = false;
@@ -116,20 +124,33 @@ static void collect_stage_times(sfk_ctx *c) {
 // double-buffered by iteration parity, so iteration k + 2 waits for the sketch
 // of iteration k only.  The reweighting needs y_k before D(k), so it waits for
 // LS(k).
+static void run_stage(sfk_ctx *c, int stage, int k, hipStream_t st) {
+  if (c->multi) {
+    launch_group_stage(c->grp, stage, k, st);
+    return;
+  }
+  switch (stage) {
+    case kStageA: launch_stage_A(c->L, k, st); break;
+    case kStageB: launch_stage_B(c->L, k, st); break;
+    case kStageC: launch_stage_C(c->L, k, st); break;
+    default: launch_stage_D(c->L, k, st); break;
+  }
+}
+
 static void enqueue_iteration(sfk_ctx *c, int k) {
   const Launch &L = c->L;
   hipStream_t st = c->stream, sd = c->side;
   const int r = k % sfk_ctx::kRing;
   if (k >= 3) hipStreamWaitEvent(st, c->ev_sk[(k - 2) % sfk_ctx::kRing], 0);
   int t = stage_begin(c, SFK_STAGE_SPMV_A, st);
-  launch_stage_A(L, k, st);
+  run_stage(c, kStageA, k, st);
   stage_end(c, t, st);
   t = stage_begin(c, SFK_STAGE_W_UPDATE, st);
-  launch_stage_B(L, k, st);
+  run_stage(c, kStageB, k, st);
   stage_end(c, t, st);
   if (!c->sketch_after_C) hipEventRecord(c->ev_main[r], st);
   t = stage_begin(c, SFK_STAGE_SPMV_B, st);
-  launch_stage_C(L, k, st);
+  run_stage(c, kStageC, k, st);
   stage_end(c, t, st);
   if (c->sketch_after_C) hipEventRecord(c->ev_main[r], st);
 
@@ -145,7 +166,7 @@ static void enqueue_iteration(sfk_ctx *c, int k) {
 
   if (c->any_rew) hipStreamWaitEvent(st, c->ev_ls[r], 0);
   t = stage_begin(c, SFK_STAGE_P_UPDATE, st);
-  launch_stage_D(L, k, st);
+  run_stage(c, kStageD, k, st);
   stage_end(c, t, st);
 }
 
@@ -299,7 +320,11 @@ static int default_nws(const sfk_csr *A, const sfk_csr *B, const sfk_params *p, 
   return (int)nw;
 }
 
-static Plan make_plan(const sfk_csr *A, const sfk_csr *B, const sfk_params *p, int cus, int nws) {
+// member = true: a right-hand side of a shared-operator group, whose long
+// vectors, row partitions and transposed B live in the group's workspace; its
+// own x (n) is then contiguous scratch for the true residual.
+static Plan make_plan(const sfk_csr *A, const sfk_csr *B, const sfk_params *p, int cus, int nws,
+                      bool member = false) {
   Plan P{};
   P.m = A->rows;
   P.n = A->cols;
@@ -331,14 +356,15 @@ static Plan make_plan(const sfk_csr *A, const sfk_csr *B, const sfk_params *p, i
   P.o_H = L_.take<double>((mi + 1) * mi);
   P.o_T = L_.take<double>((mi + 1) * (mi + 1));
   P.o_rho = L_.take<double>(mi);
-  P.o_W = L_.take<double>((ell + 2) * m);
-  P.o_P = L_.take<double>(p->tau == SFK_TAU_REWEIGHT_L1 ? (ell + 1) * n : 1);
-  P.o_Z = L_.take<double>((mi + 1) * n);      // z~_1 .. z~_{maxit+1}
-  P.o_wraw = L_.take<double>(2 * m);
-  P.o_zraw = L_.take<double>(2 * std::max<int64_t>(n, (P.N + 1) / 2 + 1));
+  const int64_t vm = member ? 0 : 1;
+  P.o_W = L_.take<double>(vm * (ell + 2) * m + 1);
+  P.o_P = L_.take<double>(p->tau == SFK_TAU_REWEIGHT_L1 ? vm * (ell + 1) * n + 1 : 1);
+  P.o_Z = L_.take<double>(vm * (mi + 1) * n + 1);      // z~_1 .. z~_{maxit+1}
+  P.o_wraw = L_.take<double>(vm * 2 * m + 1);
+  P.o_zraw = L_.take<double>(vm * 2 * std::max<int64_t>(n, (P.N + 1) / 2 + 1) + 1);
   P.o_x = L_.take<double>(n);
-  P.o_Apart = L_.take<int>(nw_alloc + 1);
-  P.o_Bpart = L_.take<int>(nw_alloc + 1);
+  P.o_Apart = L_.take<int>(vm * (nw_alloc + 1) + 1);
+  P.o_Bpart = L_.take<int>(vm * (nw_alloc + 1) + 1);
   const bool ss = p->sketch == SFK_SK_SPARSE_SIGN;
   const bool sr = p->sketch == SFK_SK_SRHT;
   P.o_skcode = L_.take<int>(ss ? zeta * P.d : 1);
@@ -356,7 +382,7 @@ static Plan make_plan(const sfk_csr *A, const sfk_csr *B, const sfk_params *p, i
   P.o_c = L_.take<double>(s);
   P.o_y = L_.take<double>(mi);
   P.o_ytmp = L_.take<double>(mi);
-  if (P.transpose) {
+  if (P.transpose && !member) {
     P.o_brp = L_.take<int>(n + 1);
     P.o_bci = L_.take<int>(P.nnzB);
     P.o_bva = L_.take<double>(P.nnzB);
@@ -406,17 +432,42 @@ static sfk_status read_scal(sfk_ctx *c) {
   return SFK_OK;
 }
 
+// Builds the instance's sketch from its seed and computes beta = ||b||, w~_1 = b
+// (Algorithm 1 / 2, first line).
+static sfk_status setup_sketch_and_b(sfk_ctx *c, Inst &I, hipStream_t st) {
+  const sfk_params &p = I.p;
+  Dev &D = I.D;
+  const uint64_t key0 = p.seed;
+  const uint64_t key1 = 0ull + ((uint64_t)(uint32_t)p.instance << 32);
+  const uint64_t key1_rows = 1ull + ((uint64_t)(uint32_t)p.instance << 32);
+  // SRHT: the row draw permutes an index array of N ints held in the (not yet
+  // used) raw product buffer
+  int *scratch = p.sketch == SFK_SK_SPARSE_SIGN ? I.chunk_scratch : reinterpret_cast<int *>(D.zraw);
+  launch_sketch_build(D, key0, key1, key1_rows, scratch, I.d_err, st);
+  int herr = 0;
+  HIPCHK(c, hipMemcpyAsync(&herr, I.d_err, sizeof(int), hipMemcpyDeviceToHost, st));
+  HIPCHK(c, hipStreamSynchronize(st));
+  if (herr) return fail(c, SFK_EINVAL, "initialisation failed (code %d): transposed rows longer "
+                        "than 4096 entries or sketch generation exhausted", herr);
+  HIPCHK(c, hipGetLastError());
+  const int use_disc = (p.method == SFK_SFLSQR && p.noise_norm > 0.0) ? 1 : 0;
+  launch_init_b(D, p.eta, p.noise_norm, p.tol, use_disc, st);
+  return SFK_OK;
+}
+
 // Carves the workspace of one instance, checks its CSR structures, builds B = A^T
 // if needed, the row partitions and the sketch, and computes beta = ||b||.
+// grp != NULL: right-hand side r of a shared-operator group whose shared
+// arrays (vectors, partitions, B) are already set up.
 static sfk_status setup_instance(sfk_ctx *c, Inst &I, const sfk_csr *A, const sfk_csr *B,
                                  const double *b, void *workspace, size_t ws_bytes, int cus,
-                                 int nws) {
+                                 int nws, const Grp *grp = nullptr, int r = 0) {
   const sfk_params &p = I.p;
   if ((A->nnz > 0 && (!A->rowptr || !A->colind || !A->val)) || !A->rowptr || !b)
     return fail(c, SFK_EINVAL, "A arrays and b must be device pointers");
   if (B && ((B->nnz > 0 && (!B->colind || !B->val)) || !B->rowptr))
     return fail(c, SFK_EINVAL, "B arrays must be device pointers");
-  const Plan P = make_plan(A, B, &p, cus, nws);
+  const Plan P = make_plan(A, B, &p, cus, nws, grp != nullptr);
   if (workspace) {
     if (ws_bytes < P.total)
       return fail(c, SFK_ENOMEM, "workspace of %zu bytes is smaller than the %zu required",
@@ -453,6 +504,7 @@ static sfk_status setup_instance(sfk_ctx *c, Inst &I, const sfk_csr *A, const sf
   D.nblk = P.nblk;
   D.nws = P.nw;
   D.nwv = P.nw;
+  D.vs = 1;
   D.nwmax = P.nwmax;
   D.nsg = p.sketch == SFK_SK_SPARSE_SIGN ? (p.s * 64 + kWG - 1) / kWG
         : p.sketch == SFK_SK_IDENTITY ? (p.s + kWG - 1) / kWG : 0;
@@ -492,6 +544,20 @@ static sfk_status setup_instance(sfk_ctx *c, Inst &I, const sfk_csr *A, const sf
   I.d_err = at<int>(w, P.o_err);
   I.d_scalar = at<double>(w, P.o_scalar);
   I.d_ytmp = at<double>(w, P.o_ytmp);
+  I.chunk_scratch = at<int>(w, P.o_chunk);
+
+  if (grp) {
+    D.vs = grp->RS;
+    D.W = grp->W + r;
+    D.P = grp->P + r;
+    D.Z = grp->Z + r;
+    D.wraw = grp->wraw + r;
+    D.zraw = grp->zraw + r;
+    D.Brp = grp->Brp; D.Bci = grp->Bci; D.Bva = grp->Bva;
+    D.Apart = grp->Apart;
+    D.Bpart = grp->Bpart;
+    return setup_sketch_and_b(c, I, st);
+  }
 
   // structure checks
   launch_csr_check(A->rowptr, A->colind, D.m, D.n, A->nnz, I.d_err, st);
@@ -515,37 +581,37 @@ static sfk_status setup_instance(sfk_ctx *c, Inst &I, const sfk_csr *A, const sf
   launch_partition(D.Arp, D.m, P.nnzA, D.nws, at<int>(w, P.o_Apart), st);
   launch_partition(D.Brp, D.n, P.nnzB, D.nws, at<int>(w, P.o_Bpart), st);
 
-  // sketch
-  const uint64_t key0 = p.seed;
-  const uint64_t key1 = 0ull + ((uint64_t)(uint32_t)p.instance << 32);
-  const uint64_t key1_rows = 1ull + ((uint64_t)(uint32_t)p.instance << 32);
-  int *scratch = p.sketch == SFK_SK_SPARSE_SIGN ? at<int>(w, P.o_chunk) : reinterpret_cast<int *>(D.zraw);
-  launch_sketch_build(D, key0, key1, key1_rows, scratch, I.d_err, st);
-  HIPCHK(c, hipMemcpyAsync(&herr, I.d_err, sizeof(int), hipMemcpyDeviceToHost, st));
-  HIPCHK(c, hipStreamSynchronize(st));
-  if (herr) return fail(c, SFK_EINVAL, "initialisation failed (code %d): transposed rows longer "
-                        "than 4096 entries or sketch generation exhausted", herr);
-  HIPCHK(c, hipGetLastError());
-
-  // Algorithm 1 / 2, first line: beta = ||b||, w_1 = b / beta
-  const int use_disc = (p.method == SFK_SFLSQR && p.noise_norm > 0.0) ? 1 : 0;
-  launch_init_b(D, p.eta, p.noise_norm, p.tol, use_disc, st);
-  return SFK_OK;
+  return setup_sketch_and_b(c, I, st);
 }
-
 // Uploads the instance descriptors and the block maps of every stage type.
 static sfk_status build_launch(sfk_ctx *c) {
   const int nb = (int)c->inst.size();
   std::vector<int2> ms, mv, mg, mb, mc;
   int smax = 0, maxitmax = 0;
+  if (c->multi) {
+    // right-hand sides of one group have identical sketch shapes; ordering the
+    // sketch blocks tile-major puts the blocks that read the same interleaved
+    // rows next to each other
+    const Dev &D0 = c->inst[0].D;
+    for (int w = 0; w < D0.nsg; ++w)
+      for (int i = 0; i < nb; ++i) mg.push_back(make_int2(i, w));
+    if (D0.sketch == SFK_SK_SRHT) {
+      for (int w = 0; w < D0.nblk; ++w)
+        for (int i = 0; i < nb; ++i) mb.push_back(make_int2(i, w));
+      for (int w = 0; w < (D0.s + kWG - 1) / kWG; ++w)
+        for (int i = 0; i < nb; ++i) mc.push_back(make_int2(i, w));
+    }
+  }
   for (int i = 0; i < nb; ++i) {
     const Dev &D = c->inst[i].D;
-    for (int w = 0; w < D.nws; ++w) ms.push_back(make_int2(i, w));
-    for (int w = 0; w < D.nwv; ++w) mv.push_back(make_int2(i, w));
-    for (int w = 0; w < D.nsg; ++w) mg.push_back(make_int2(i, w));
-    if (D.sketch == SFK_SK_SRHT) {
-      for (int w = 0; w < D.nblk; ++w) mb.push_back(make_int2(i, w));
-      for (int w = 0; w < (D.s + kWG - 1) / kWG; ++w) mc.push_back(make_int2(i, w));
+    if (!c->multi) {
+      for (int w = 0; w < D.nws; ++w) ms.push_back(make_int2(i, w));
+      for (int w = 0; w < D.nwv; ++w) mv.push_back(make_int2(i, w));
+      for (int w = 0; w < D.nsg; ++w) mg.push_back(make_int2(i, w));
+      if (D.sketch == SFK_SK_SRHT) {
+        for (int w = 0; w < D.nblk; ++w) mb.push_back(make_int2(i, w));
+        for (int w = 0; w < (D.s + kWG - 1) / kWG; ++w) mc.push_back(make_int2(i, w));
+      }
     }
     smax = std::max(smax, D.s);
     maxitmax = std::max(maxitmax, D.maxit);
@@ -587,6 +653,7 @@ static sfk_status build_launch(sfk_ctx *c) {
   L.maxitmax = maxitmax;
   L.tau = c->any_rew ? 1 : 0;
   c->maxitmax = maxitmax;
+  c->grp.devs = L.devs;
   return SFK_OK;
 }
 
@@ -607,10 +674,10 @@ static sfk_status init_common(sfk_ctx *c) {
   sfk_status s = build_launch(c);
   if (s != SFK_OK) return s;
   hipStream_t st = c->stream;
-  launch_stage_C(c->L, 0, st);
+  run_stage(c, kStageC, 0, st);
   launch_sketch(c->L, 0, st);
   for (auto &I : c->inst) launch_init_rhs(I.D, st);
-  launch_stage_D(c->L, 0, st);
+  run_stage(c, kStageD, 0, st);
   HIPCHK(c, hipGetLastError());
   s = read_scal(c);
   if (s != SFK_OK) return s;
@@ -635,6 +702,7 @@ static void release(sfk_ctx *c) {
   if (c->side) hipStreamDestroy(c->side);
   for (auto &I : c->inst)
     if (I.owns_ws && I.ws) hipFree(I.ws);
+  if (c->gws) hipFree(c->gws);
   if (c->hdr) hipFree(c->hdr);
   if (c->h_scal) hipHostFree(c->h_scal);
   delete c;
@@ -703,6 +771,149 @@ extern "C" sfk_status sfk_init_batch(sfk_ctx **out, int32_t nb, const sfk_csr *A
     nws = std::max(1, std::min(nws, default_nws(&A[i], Bi, &p[i], cus, spmv_blocks_per_cu())));
     s = setup_instance(c, c->inst[i], &A[i], Bi, b[i], nullptr, 0, cus, nws);
     if (s != SFK_OK) c->err = "instance " + std::to_string(i) + ": " + c->err;
+  }
+  if (s == SFK_OK) s = init_common(c);
+  if (s != SFK_OK) {
+    g_err = c->err;
+    release(c);
+    return s;
+  }
+  *out = c;
+  return SFK_OK;
+}
+
+// --------------------------------------------------------------------------
+// right-hand sides sharing one operator pair
+// --------------------------------------------------------------------------
+static sfk_status same_params(const sfk_params &a, const sfk_params &b, int r) {
+  const char *what = nullptr;
+  if (a.method != b.method) what = "method";
+  else if (a.ell != b.ell) what = "ell";
+  else if (a.maxit != b.maxit) what = "maxit";
+  else if (a.sketch != b.sketch) what = "sketch";
+  else if (a.s != b.s) what = "s";
+  else if (a.sketch == SFK_SK_SPARSE_SIGN && a.zeta != b.zeta) what = "zeta";
+  else if (a.tau != b.tau) what = "tau";
+  else if (a.tau == SFK_TAU_REWEIGHT_L1 && a.eps != b.eps) what = "eps";
+  if (what)
+    return fail(nullptr, SFK_EINVAL, "right-hand side %d: '%s' differs from right-hand side 0 "
+                "(right-hand sides sharing A and B may differ only in seed, instance, eta, "
+                "noise_norm and tol)", r, what);
+  return SFK_OK;
+}
+
+extern "C" sfk_status sfk_init_multi(sfk_ctx **out, const sfk_csr *A, const sfk_csr *B,
+                                     const double *b_block, int32_t R, const sfk_params *p,
+                                     void *stream) {
+  if (!out) return fail(nullptr, SFK_EINVAL, "out must not be NULL");
+  *out = nullptr;
+  if (R < 1 || R > kMaxRhs) return fail(nullptr, SFK_EINVAL, "R = %d not in [1, %d]", R, kMaxRhs);
+  if (!A || !b_block || !p) return fail(nullptr, SFK_EINVAL, "A, b_block and params must not be NULL");
+  for (int r = 0; r < R; ++r) {
+    sfk_status s = validate(nullptr, A, B, &p[r]);
+    if (s != SFK_OK) {
+      g_err = "right-hand side " + std::to_string(r) + ": " + g_err;
+      return s;
+    }
+    s = same_params(p[0], p[r], r);
+    if (s != SFK_OK) return s;
+  }
+  if ((A->nnz > 0 && (!A->colind || !A->val)) || !A->rowptr)
+    return fail(nullptr, SFK_EINVAL, "A arrays must be device pointers");
+  if (B && ((B->nnz > 0 && (!B->colind || !B->val)) || !B->rowptr))
+    return fail(nullptr, SFK_EINVAL, "B arrays must be device pointers");
+  const int cus = device_cus();
+  if (cus <= 0) return fail(nullptr, SFK_EDEVICE, "no HIP device available");
+  int RS = 8;
+  while (RS < R) RS <<= 1;
+  const sfk_params &p0 = p[0];
+  const int64_t m = A->rows, n = A->cols, nnzA = A->nnz, nnzB = B ? B->nnz : A->nnz;
+  const int64_t ell = p0.ell, mi = p0.maxit;
+  const int bpc = gspmm_blocks_per_cu(RS);
+  const int cap = cus * (p0.wg_per_cu ? p0.wg_per_cu : bpc);
+  int64_t nw64 = std::max((std::max(nnzA, nnzB) + 8191) / 8192, (std::max(m, n) + 2047) / 2048);
+  const int nw = (int)std::min<int64_t>(std::max<int64_t>(nw64, 1), cap);
+  const int64_t d = p0.method == SFK_SFLSQR ? m : n;
+  const int64_t N = next_pow2(d);
+
+  Layout L_;
+  const size_t o_err = L_.take<int>(1);
+  const size_t o_W = L_.take<double>((ell + 2) * m * RS);
+  const size_t o_P = L_.take<double>(p0.tau == SFK_TAU_REWEIGHT_L1 ? (ell + 1) * n * RS : 1);
+  const size_t o_Z = L_.take<double>((mi + 1) * n * RS);
+  const size_t o_wraw = L_.take<double>(2 * m * RS);
+  const size_t o_zraw = L_.take<double>(2 * std::max<int64_t>(n, (N + 1) / 2 + 1) * RS);
+  const size_t o_x = L_.take<double>(p0.tau == SFK_TAU_REWEIGHT_L1 ? n * RS : 1);
+  const size_t o_Apart = L_.take<int>(nw + 1);
+  const size_t o_Bpart = L_.take<int>(nw + 1);
+  const size_t o_coef = L_.take<double>((size_t)RS * kCoefStride);
+  const size_t o_act = L_.take<int>(RS);
+  const size_t o_gx = L_.take<double>(p0.tau == SFK_TAU_REWEIGHT_L1 ? mi * RS : 1);
+  size_t o_brp = 0, o_bci = 0, o_bva = 0, o_cursor = 0;
+  if (!B) {
+    o_brp = L_.take<int>(n + 1);
+    o_bci = L_.take<int>(nnzB);
+    o_bva = L_.take<double>(nnzB);
+    o_cursor = L_.take<int>(n);
+  }
+  const size_t total = L_.off;
+
+  sfk_ctx *c = new sfk_ctx();
+  c->stream = static_cast<hipStream_t>(stream);
+  c->multi = true;
+  c->inst.resize(R);
+  sfk_status s = create_streams(c, R);
+  hipStream_t st = c->stream;
+  Grp &G = c->grp;
+  auto setup_group = [&]() -> sfk_status {
+    hipError_t e = hipMalloc(&c->gws, total);
+    if (e != hipSuccess) {
+      c->gws = nullptr;
+      return fail(c, SFK_ENOMEM, "hipMalloc of %zu bytes failed: %s", total, hipGetErrorString(e));
+    }
+    void *w = c->gws;
+    HIPCHK(c, hipMemsetAsync(w, 0, total, st));
+    int *err = at<int>(w, o_err);
+    G.R = R; G.RS = RS;
+    G.m = (int)m; G.n = (int)n; G.ell = p0.ell; G.maxit = p0.maxit; G.tau = p0.tau;
+    G.nws = nw; G.nwv = nw; G.eps = p0.eps;
+    G.Arp = A->rowptr; G.Aci = A->colind; G.Ava = A->val;
+    G.W = at<double>(w, o_W); G.P = at<double>(w, o_P); G.Z = at<double>(w, o_Z);
+    G.wraw = at<double>(w, o_wraw); G.zraw = at<double>(w, o_zraw); G.x = at<double>(w, o_x);
+    G.Apart = at<int>(w, o_Apart); G.Bpart = at<int>(w, o_Bpart);
+    G.coef = at<double>(w, o_coef); G.act = at<int>(w, o_act); G.gx = at<double>(w, o_gx);
+    launch_csr_check(A->rowptr, A->colind, (int)m, (int)n, nnzA, err, st);
+    if (B) {
+      launch_csr_check(B->rowptr, B->colind, (int)n, (int)m, nnzB, err, st);
+      G.Brp = B->rowptr; G.Bci = B->colind; G.Bva = B->val;
+    }
+    int herr = 0;
+    HIPCHK(c, hipMemcpyAsync(&herr, err, sizeof(int), hipMemcpyDeviceToHost, st));
+    HIPCHK(c, hipStreamSynchronize(st));
+    if (herr) return fail(c, SFK_EINVAL, "invalid CSR structure (code %d): row pointers must rise "
+                          "from 0 to nnz and column indices lie in range", herr);
+    if (!B) {
+      int *brp = at<int>(w, o_brp);
+      int *bci = at<int>(w, o_bci);
+      double *bva = at<double>(w, o_bva);
+      launch_transpose(A->rowptr, A->colind, A->val, (int)m, (int)n, brp, bci, bva,
+                       at<int>(w, o_cursor), err, st);
+      G.Brp = brp; G.Bci = bci; G.Bva = bva;
+      HIPCHK(c, hipMemcpyAsync(&herr, err, sizeof(int), hipMemcpyDeviceToHost, st));
+      HIPCHK(c, hipStreamSynchronize(st));
+      if (herr) return fail(c, SFK_EINVAL, "transposing A failed (code %d): a column of A has "
+                            "more than 4096 entries", herr);
+    }
+    launch_partition(G.Arp, (int)m, nnzA, nw, at<int>(w, o_Apart), st);
+    launch_partition(G.Brp, (int)n, nnzB, nw, at<int>(w, o_Bpart), st);
+    HIPCHK(c, hipGetLastError());
+    return SFK_OK;
+  };
+  if (s == SFK_OK) s = setup_group();
+  for (int r = 0; r < R && s == SFK_OK; ++r) {
+    c->inst[r].p = p[r];
+    s = setup_instance(c, c->inst[r], A, B, b_block + (size_t)r * m, nullptr, 0, cus, nw, &G, r);
+    if (s != SFK_OK) c->err = "right-hand side " + std::to_string(r) + ": " + c->err;
   }
   if (s == SFK_OK) s = init_common(c);
   if (s != SFK_OK) {
@@ -838,20 +1049,30 @@ extern "C" sfk_status sfk_instance_status(sfk_ctx *c, int32_t i, int32_t *iters_
 
 extern "C" int32_t sfk_batch_size(const sfk_ctx *c) { return c ? (int32_t)c->inst.size() : 0; }
 
+static sfk_status true_residual_impl(sfk_ctx *c, Inst &I, double *out_host) {
+  if (!out_host) return fail(c, SFK_EINVAL, "NULL argument");
+  // D.x is contiguous scratch here (tau = I), holds x_k itself (reweighting,
+  // single instance) or is a right-hand side's own scratch (shared operators)
+  double *xtmp = I.D.x;
+  sfk_status s = solution_impl(c, I, I.k_done, xtmp);
+  if (s != SFK_OK) return s;
+  launch_true_residual(I.D, xtmp, I.d_scalar, c->stream);
+  HIPCHK(c, hipGetLastError());
+  HIPCHK(c, hipMemcpyAsync(out_host, I.d_scalar, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  return SFK_OK;
+}
+
 extern "C" sfk_status sfk_true_residual(sfk_ctx *c, double *out_host) {
   Inst *I;
   sfk_status s = instance_of(c, 0, &I);
-  if (s != SFK_OK) return s;
-  if (!out_host) return fail(c, SFK_EINVAL, "NULL argument");
-  // D.x is scratch for tau = I and holds x_k itself for the reweighting
-  double *xtmp = I->D.x;
-  s = solution_impl(c, *I, I->k_done, xtmp);
-  if (s != SFK_OK) return s;
-  launch_true_residual(I->D, xtmp, I->d_scalar, c->stream);
-  HIPCHK(c, hipGetLastError());
-  HIPCHK(c, hipMemcpyAsync(out_host, I->d_scalar, sizeof(double), hipMemcpyDeviceToHost, c->stream));
-  HIPCHK(c, hipStreamSynchronize(c->stream));
-  return SFK_OK;
+  return s != SFK_OK ? s : true_residual_impl(c, *I, out_host);
+}
+
+extern "C" sfk_status sfk_instance_true_residual(sfk_ctx *c, int32_t i, double *out_host) {
+  Inst *I;
+  sfk_status s = instance_of(c, i, &I);
+  return s != SFK_OK ? s : true_residual_impl(c, *I, out_host);
 }
 
 extern "C" sfk_status sfk_set_timing(sfk_ctx *c, int32_t on) {

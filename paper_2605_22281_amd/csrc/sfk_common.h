@@ -1,0 +1,207 @@
+// Device helpers shared by the single-instance, batched and multi-RHS stage
+// kernels: workgroup reductions, per-stage partial sums, run flags, and the
+// scalar steps that turn a stage's reduced sums into the recurrence
+// coefficients of eq. (FGK) (modified Gram-Schmidt via the window's Gram
+// matrix, norms, breakdown tests).
+#pragma once
+
+#include "sfk_dev.h"
+
+namespace sfk {
+
+// ---------------------------------------------------------------------------
+// reductions
+// ---------------------------------------------------------------------------
+template <int W>
+__device__ __forceinline__ double group_sum(double v) {
+#pragma unroll
+  for (int o = W / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, W);
+  return v;
+}
+
+__device__ __forceinline__ double wave_sum(double v) { return group_sum<64>(v); }
+
+// Sum of Q per-thread values over a workgroup of NT threads, result in out[0..Q)
+// (LDS, visible to all threads on return).  lds_w holds kMaxQ * NT / 64 doubles.
+template <int NT>
+__device__ __forceinline__ void block_sum(const double (&v)[kMaxQ], int Q, double *lds_w,
+                                          double *out) {
+  constexpr int NWV = NT / 64;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+  for (int q = 0; q < kMaxQ; ++q) {
+    if (q < Q) {
+      const double t = wave_sum(v[q]);
+      if (lane == 0) lds_w[q * NWV + wv] = t;
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x < Q) {
+    double t = 0.0;
+    for (int w = 0; w < NWV; ++w) t += lds_w[threadIdx.x * NWV + w];
+    out[threadIdx.x] = t;
+  }
+  __syncthreads();
+}
+
+__device__ __forceinline__ double *part_of(const Dev &D, int stage) {
+  return D.part + (size_t)stage * kMaxQ * D.nwmax;
+}
+
+// workgroups that produced a stage's partial sums
+__device__ __forceinline__ int producers(const Dev &D, int stage) {
+  return (stage == kStageB || stage == kStageD) ? D.nwv : D.nws;
+}
+
+// Totals of the Q partial sums that the previous stage left, in a fixed order
+// (every workgroup obtains identical values).
+template <int NT>
+__device__ void consume(const Dev &D, int stage, int Q, double *lds_w, double *tot) {
+  const double *p = part_of(D, stage);
+  const int np = producers(D, stage);
+  double acc[kMaxQ];
+#pragma unroll
+  for (int q = 0; q < kMaxQ; ++q) acc[q] = 0.0;
+  for (int i = threadIdx.x; i < np; i += NT) {
+#pragma unroll
+    for (int q = 0; q < kMaxQ; ++q)
+      if (q < Q) acc[q] += p[(size_t)q * D.nwmax + i];
+  }
+  block_sum<NT>(acc, Q, lds_w, tot);
+}
+
+template <int NT>
+__device__ void produce(const Dev &D, int stage, int wid, int Q, const double (&acc)[kMaxQ],
+                        double *lds_w, double *blk) {
+  block_sum<NT>(acc, Q, lds_w, blk);
+  if (threadIdx.x < Q) part_of(D, stage)[(size_t)threadIdx.x * D.nwmax + wid] = blk[threadIdx.x];
+}
+
+__device__ __forceinline__ int ld_flag(const int *p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// stages of iteration k run only while the instance is live, within its
+// capacity, and while its basis reaches k
+__device__ __forceinline__ bool skip_iter(const Dev &D, int k) {
+  return k > D.maxit || ld_flag(&D.sc->halt) != 0 || k > ld_flag(&D.sc->klimit);
+}
+
+__device__ __forceinline__ void chunk_range(int d, int nw, int wid, int &i0, int &i1) {
+  const int per = (d + nw - 1) / nw;
+  i0 = min(d, wid * per);
+  i1 = min(d, i0 + per);
+}
+
+// windows (1-based basis indices)
+__device__ __forceinline__ int wwin0(const Dev &D, int k) { return max(1, k - D.ell); }      // A(k), B(k)
+__device__ __forceinline__ int pwin0(const Dev &D, int k) { return max(1, k + 1 - D.ell); }  // C(k), D(k)
+
+
+// ---------------------------------------------------------------------------
+// Scalar steps (one thread).  tot[] holds the reduced partial sums of the
+// producing stage; 'store' is true in exactly one workgroup per instance, which
+// writes the persistent coefficients (H, T, inverse norms, Gram entries, flags).
+// ---------------------------------------------------------------------------
+
+// after D(k-1): t_kk = ||p~_k||, sigp_k and the Gram entries of p_k.  Returns
+// 1 / t_kk, or 0 when the basis cannot grow (breakdown: klimit = k - 1).
+__device__ inline double finish_p_norm(const Dev &D, int k, const double *tot, bool store) {
+  Scal *sc = D.sc;
+  const int ldh = D.maxit + 1;
+  const int j0 = wwin0(D, k);              // D(k-1) window: [max(1,k-ell), k-1]
+  const int nwin = k - j0;
+  const double t = sqrt(tot[0]);
+  const bool quit = (t <= kBreakdownTol * sc->zpre || t == 0.0);
+  if (store) {
+    D.T[(size_t)(k - 1) * ldh + (k - 1)] = t;
+    if (quit) {
+      atomicOr(&sc->breakdown, 1);
+      atomicMin(&sc->klimit, k - 1);
+    } else {
+      const double sg = 1.0 / t;
+      D.sigp[k] = sg;
+      const int ns = D.ell + 1, sk = pslot(D, k);
+      sc->Gp[sk * ns + sk] = 1.0;
+      for (int q = 0; q < nwin; ++q) {
+        const int j = j0 + q;
+        if (j < k + 1 - D.ell) continue;
+        const double g = sg * D.sigp[j] * tot[1 + q];
+        sc->Gp[sk * ns + pslot(D, j)] = g;
+        sc->Gp[pslot(D, j) * ns + sk] = g;
+      }
+    }
+  }
+  return quit ? 0.0 : 1.0 / t;
+}
+
+// after A(k): h_jk by modified Gram-Schmidt over the window j = max(1,k-ell)..k,
+// h_q = <w_jq, w> - sum_{i<q} h_i <w_jq, w_ji>.  cf[q] = h_q * sigw_jq multiplies w~_jq.
+__device__ inline void finish_w_coeffs(const Dev &D, int k, const double *tot, double *cf,
+                                       bool store) {
+  Scal *sc = D.sc;
+  const int j0 = wwin0(D, k), nwin = k - j0 + 1;
+  const int ns = D.ell + 2, ldh = D.maxit + 1;
+  double h[kMaxEll + 1];
+  for (int q = 0; q < nwin; ++q) {
+    const int jq = j0 + q;
+    double t = D.sigw[jq] * tot[q];
+    for (int i = 0; i < q; ++i) t -= h[i] * sc->Gw[wslot(D, jq) * ns + wslot(D, j0 + i)];
+    h[q] = t;
+    cf[q] = t * D.sigw[jq];
+    if (store) D.H[(size_t)(k - 1) * ldh + (jq - 1)] = t;
+  }
+  if (store) sc->wpre = sqrt(tot[nwin]);
+}
+
+// after B(k): h_{k+1,k} = ||w~_{k+1}||, sigw_{k+1}, Gram entries of w_{k+1}.
+// Returns 1 / h, or 0 at a happy breakdown (h = 0: recorded in sc->happy).
+__device__ inline double finish_w_norm(const Dev &D, int k, const double *tot, bool store) {
+  Scal *sc = D.sc;
+  const int ldh = D.maxit + 1;
+  const int j0 = wwin0(D, k);
+  const int nwin = k - j0 + 1;
+  const double h = sqrt(tot[0]);
+  const bool happy = (h <= kBreakdownTol * sc->wpre || h == 0.0);
+  const double scale = happy ? 0.0 : 1.0 / h;
+  if (store) {
+    D.H[(size_t)(k - 1) * ldh + k] = happy ? 0.0 : h;
+    D.sigw[k + 1] = scale;
+    if (happy) {
+      sc->happy = k;
+    } else {
+      const int ns = D.ell + 2, sk = wslot(D, k + 1);
+      sc->Gw[sk * ns + sk] = 1.0;
+      for (int q = 0; q < nwin; ++q) {
+        const int j = j0 + q;
+        if (j < k + 1 - D.ell) continue;
+        const double g = scale * D.sigw[j] * tot[1 + q];
+        sc->Gw[sk * ns + wslot(D, j)] = g;
+        sc->Gw[wslot(D, j) * ns + sk] = g;
+      }
+    }
+  }
+  return scale;
+}
+
+// after C(k): t_{j,k+1} by modified Gram-Schmidt over j = max(1,k+1-ell)..k;
+// cf[q] multiplies p~_jq.
+__device__ inline void finish_p_coeffs(const Dev &D, int k, const double *tot, double *cf,
+                                       bool store) {
+  Scal *sc = D.sc;
+  const int j0 = pwin0(D, k);
+  const int nwin = k >= j0 ? k - j0 + 1 : 0;
+  const int ns = D.ell + 1, ldh = D.maxit + 1;
+  double t[kMaxEll + 1];
+  for (int q = 0; q < nwin; ++q) {
+    const int jq = j0 + q;
+    double v = D.sigp[jq] * tot[q];
+    for (int i = 0; i < q; ++i) v -= t[i] * sc->Gp[pslot(D, jq) * ns + pslot(D, j0 + i)];
+    t[q] = v;
+    cf[q] = v * D.sigp[jq];
+    if (store) D.T[(size_t)k * ldh + (jq - 1)] = v;
+  }
+  if (store) sc->zpre = sqrt(tot[nwin]);
+}
+
+}  // namespace sfk

@@ -52,6 +52,8 @@ struct Dev {
   int nwmax;          // stride of the per-stage partial-sum buffers
   int nsg;            // sparse-sign sketch gather workgroups of this instance
   int vwA, vwB;       // SpMV lanes per row
+  int vs;             // element stride of W, P, Z, wraw, zraw, x: 1, or the
+                      // interleave width when right-hand sides share A and B
   double eps;
   double sk_scale;    // 1/sqrt(zeta) or 1/sqrt(s)
   // operators
@@ -100,14 +102,43 @@ struct Launch {
   int ninst, smax, maxitmax, tau, vwA, vwB;
 };
 
+// Right-hand sides that share one operator pair A, B (a group): the long
+// vectors of all of them are interleaved, element i of right-hand side r at
+// [i * RS + r], so that one pass over A or B serves every right-hand side and
+// each gathered row of the source block is RS contiguous doubles.  The
+// per-right-hand-side state (sketch, least squares, coefficients, flags) stays
+// in the R instance descriptors devs[0..R).
+constexpr int kCoefStride = 16;            // >= kMaxEll + 2
+constexpr int kMaxRhs = 64;
+struct Grp {
+  int R, RS;          // right-hand sides, interleave width (power of two, 8..64)
+  int m, n, ell, maxit, tau, nws, nwv;
+  double eps;
+  const int *Arp, *Aci; const double *Ava;
+  const int *Brp, *Bci; const double *Bva;
+  const int *Apart, *Bpart;
+  double *W;          // (ell + 2) slots of m * RS
+  double *P;          // (ell + 1) slots of n * RS (reweighting only)
+  double *Z;          // (maxit + 1) columns of n * RS
+  double *wraw;       // 2 * m * RS
+  double *zraw;       // 2 * n * RS (at least)
+  double *x;          // n * RS, x_k for the reweighting
+  double *coef;       // RS * kCoefStride: coefficients of the stage about to run
+  int *act;           // RS: 1 if the right-hand side takes part in that stage
+  double *gx;         // maxit * RS: sigp_{j+1} y_j per right-hand side, [j * RS + r]
+  const Dev *devs;    // R instance descriptors (device memory)
+};
+
 __device__ __forceinline__ int wslot(const Dev &D, int j) { return j % (D.ell + 2); }
 __device__ __forceinline__ int pslot(const Dev &D, int j) { return j % (D.ell + 1); }
-__device__ __forceinline__ double *wrawk(const Dev &D, int k) { return D.wraw + (size_t)(k & 1) * D.m; }
-__device__ __forceinline__ double *zrawk(const Dev &D, int k) { return D.zraw + (size_t)(k & 1) * D.n; }
-__device__ __forceinline__ double *wvec(const Dev &D, int j) { return D.W + (size_t)wslot(D, j) * D.m; }
+// vectors of one instance; element i of each is at [i * D.vs]
+__device__ __forceinline__ double *wrawk(const Dev &D, int k) { return D.wraw + (size_t)(k & 1) * D.m * D.vs; }
+__device__ __forceinline__ double *zrawk(const Dev &D, int k) { return D.zraw + (size_t)(k & 1) * D.n * D.vs; }
+__device__ __forceinline__ double *wvec(const Dev &D, int j) { return D.W + (size_t)wslot(D, j) * D.m * D.vs; }
+__device__ __forceinline__ double *zcol(const Dev &D, int j) { return D.Z + (size_t)j * D.n * D.vs; }
 __device__ __forceinline__ double *pvec(const Dev &D, int j) {
   // with tau = I the stored basis column z~_j is p~_j itself
-  return D.tau == 0 ? D.Z + (size_t)(j - 1) * D.n : D.P + (size_t)pslot(D, j) * D.n;
+  return D.tau == 0 ? zcol(D, j - 1) : D.P + (size_t)pslot(D, j) * D.n * D.vs;
 }
 
 }  // namespace sfk

@@ -17,8 +17,13 @@
 // arithmetic), the norms, and the breakdown tests.  Workgroup 0 stores the
 // recurrence coefficients.  Vectors stay unnormalised (w~, p~); their inverse
 // norms (sigw, sigp) are folded into the consumers.
+//
+// The stage kernels A-D in this file serve instances with contiguous vectors
+// (Dev::vs == 1); right-hand sides that share one operator pair run the
+// interleaved stage kernels of sfk_multi.hip.  Sketch, least-squares, solution
+// and initialisation kernels here serve both.
 
-#include "sfk_dev.h"
+#include "sfk_common.h"
 
 namespace sfk {
 
@@ -38,94 +43,6 @@ __device__ __forceinline__ void philox4x64_10(uint64_t c[4], uint64_t k0, uint64
     c[0] = n0; c[1] = lo1; c[2] = n2; c[3] = lo0;
   }
 }
-
-// ---------------------------------------------------------------------------
-// reductions
-// ---------------------------------------------------------------------------
-template <int W>
-__device__ __forceinline__ double group_sum(double v) {
-#pragma unroll
-  for (int o = W / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, W);
-  return v;
-}
-
-__device__ __forceinline__ double wave_sum(double v) { return group_sum<64>(v); }
-
-// Sum of Q per-thread values over a workgroup of NT threads, result in out[0..Q)
-// (LDS, visible to all threads on return).  lds_w holds kMaxQ * NT / 64 doubles.
-template <int NT>
-__device__ __forceinline__ void block_sum(const double (&v)[kMaxQ], int Q, double *lds_w,
-                                          double *out) {
-  constexpr int NWV = NT / 64;
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-#pragma unroll
-  for (int q = 0; q < kMaxQ; ++q) {
-    if (q < Q) {
-      const double t = wave_sum(v[q]);
-      if (lane == 0) lds_w[q * NWV + wv] = t;
-    }
-  }
-  __syncthreads();
-  if (threadIdx.x < Q) {
-    double t = 0.0;
-    for (int w = 0; w < NWV; ++w) t += lds_w[threadIdx.x * NWV + w];
-    out[threadIdx.x] = t;
-  }
-  __syncthreads();
-}
-
-__device__ __forceinline__ double *part_of(const Dev &D, int stage) {
-  return D.part + (size_t)stage * kMaxQ * D.nwmax;
-}
-
-// workgroups that produced a stage's partial sums
-__device__ __forceinline__ int producers(const Dev &D, int stage) {
-  return (stage == kStageB || stage == kStageD) ? D.nwv : D.nws;
-}
-
-// Totals of the Q partial sums that the previous stage left, in a fixed order
-// (every workgroup obtains identical values).
-template <int NT>
-__device__ void consume(const Dev &D, int stage, int Q, double *lds_w, double *tot) {
-  const double *p = part_of(D, stage);
-  const int np = producers(D, stage);
-  double acc[kMaxQ];
-#pragma unroll
-  for (int q = 0; q < kMaxQ; ++q) acc[q] = 0.0;
-  for (int i = threadIdx.x; i < np; i += NT) {
-#pragma unroll
-    for (int q = 0; q < kMaxQ; ++q)
-      if (q < Q) acc[q] += p[(size_t)q * D.nwmax + i];
-  }
-  block_sum<NT>(acc, Q, lds_w, tot);
-}
-
-template <int NT>
-__device__ void produce(const Dev &D, int stage, int wid, int Q, const double (&acc)[kMaxQ],
-                        double *lds_w, double *blk) {
-  block_sum<NT>(acc, Q, lds_w, blk);
-  if (threadIdx.x < Q) part_of(D, stage)[(size_t)threadIdx.x * D.nwmax + wid] = blk[threadIdx.x];
-}
-
-__device__ __forceinline__ int ld_flag(const int *p) {
-  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-// stages of iteration k run only while the instance is live, within its
-// capacity, and while its basis reaches k
-__device__ __forceinline__ bool skip_iter(const Dev &D, int k) {
-  return k > D.maxit || ld_flag(&D.sc->halt) != 0 || k > ld_flag(&D.sc->klimit);
-}
-
-__device__ __forceinline__ void chunk_range(int d, int nw, int wid, int &i0, int &i1) {
-  const int per = (d + nw - 1) / nw;
-  i0 = min(d, wid * per);
-  i1 = min(d, i0 + per);
-}
-
-// windows (1-based basis indices)
-__device__ __forceinline__ int wwin0(const Dev &D, int k) { return max(1, k - D.ell); }      // A(k), B(k)
-__device__ __forceinline__ int pwin0(const Dev &D, int k) { return max(1, k + 1 - D.ell); }  // C(k), D(k)
 
 // ---------------------------------------------------------------------------
 // CSR-stream product of one workgroup's rows [r0, r1) (whole rows, contiguous
@@ -232,71 +149,23 @@ __global__ void __launch_bounds__(kSpmvWG, 8) k_spmv(const Dev *__restrict__ dev
   __shared__ double s_scale;
   __shared__ int s_quit;
   __shared__ double ybuf[kRowsLDS];
-  Scal *sc = D.sc;
   const int wid = bm.y;
-  const int ldh = D.maxit + 1;
 
   if (ISA) {
     // ---- finish D(k-1): t_kk = ||p~_k||, Gram entries of p_k
-    const int j0 = wwin0(D, k);              // D(k-1) window: [max(1,k-ell), k-1]
-    const int nwin = k - j0;
-    consume<NT>(D, kStageD, nwin + 1, lds_w, tot);
+    consume<NT>(D, kStageD, k - wwin0(D, k) + 1, lds_w, tot);
     if (threadIdx.x == 0) {
-      const double t = sqrt(tot[0]);
-      const int quit = (t <= kBreakdownTol * sc->zpre || t == 0.0) ? 1 : 0;
-      s_quit = quit;
-      s_scale = quit ? 0.0 : 1.0 / t;
-      if (wid == 0) {
-        D.T[(size_t)(k - 1) * ldh + (k - 1)] = t;
-        if (quit) {
-          atomicOr(&sc->breakdown, 1);
-          atomicMin(&sc->klimit, k - 1);
-        } else {
-          const double sg = 1.0 / t;
-          D.sigp[k] = sg;
-          const int ns = D.ell + 1, sk = pslot(D, k);
-          sc->Gp[sk * ns + sk] = 1.0;
-          for (int q = 0; q < nwin; ++q) {
-            const int j = j0 + q;
-            if (j < k + 1 - D.ell) continue;
-            const double g = sg * D.sigp[j] * tot[1 + q];
-            sc->Gp[sk * ns + pslot(D, j)] = g;
-            sc->Gp[pslot(D, j) * ns + sk] = g;
-          }
-        }
-      }
+      const double sg = finish_p_norm(D, k, tot, wid == 0);
+      s_quit = sg == 0.0;
+      s_scale = sg;
     }
     __syncthreads();
     if (s_quit) return;
   } else {
     if (k >= 1) {
       // ---- finish B(k): h_{k+1,k} = ||w~_{k+1}||, Gram entries of w_{k+1}
-      const int j0 = wwin0(D, k);
-      const int nwin = k - j0 + 1;
-      consume<NT>(D, kStageB, nwin + 1, lds_w, tot);
-      if (threadIdx.x == 0) {
-        const double h = sqrt(tot[0]);
-        const bool happy = (h <= kBreakdownTol * sc->wpre || h == 0.0);
-        s_scale = happy ? 0.0 : 1.0 / h;
-        if (wid == 0) {
-          D.H[(size_t)(k - 1) * ldh + k] = happy ? 0.0 : h;
-          D.sigw[k + 1] = s_scale;
-          if (happy) {
-            sc->happy = k;
-          } else {
-            const double sg = 1.0 / h;
-            const int ns = D.ell + 2, sk = wslot(D, k + 1);
-            sc->Gw[sk * ns + sk] = 1.0;
-            for (int q = 0; q < nwin; ++q) {
-              const int j = j0 + q;
-              if (j < k + 1 - D.ell) continue;
-              const double g = sg * D.sigw[j] * tot[1 + q];
-              sc->Gw[sk * ns + wslot(D, j)] = g;
-              sc->Gw[wslot(D, j) * ns + sk] = g;
-            }
-          }
-        }
-      }
+      consume<NT>(D, kStageB, k - wwin0(D, k) + 2, lds_w, tot);
+      if (threadIdx.x == 0) s_scale = finish_w_norm(D, k, tot, wid == 0);
     } else if (threadIdx.x == 0) {
       s_scale = D.sigw[1];
     }
@@ -386,23 +255,9 @@ __global__ void __launch_bounds__(kWG) k_wupdate(const Dev *__restrict__ devs,
   __shared__ double tot[kMaxQ];
   __shared__ double blk[kMaxQ];
   __shared__ double s_cf[kMaxEll + 1];
-  Scal *sc = D.sc;
   const int j0 = wwin0(D, k), nwin = k - j0 + 1;
   consume<kWG>(D, kStageA, nwin + 1, lds_w, tot);
-  if (threadIdx.x == 0) {
-    // modified Gram-Schmidt coefficients: h_q = <w_jq, w> - sum_{i<q} h_i <w_jq, w_ji>
-    const int ns = D.ell + 2, ldh = D.maxit + 1;
-    double h[kMaxEll + 1];
-    for (int q = 0; q < nwin; ++q) {
-      const int jq = j0 + q;
-      double t = D.sigw[jq] * tot[q];
-      for (int i = 0; i < q; ++i) t -= h[i] * sc->Gw[wslot(D, jq) * ns + wslot(D, j0 + i)];
-      h[q] = t;
-      s_cf[q] = t * D.sigw[jq];
-      if (wid == 0) D.H[(size_t)(k - 1) * ldh + (jq - 1)] = t;
-    }
-    if (wid == 0) sc->wpre = sqrt(tot[nwin]);
-  }
+  if (threadIdx.x == 0) finish_w_coeffs(D, k, tot, s_cf, wid == 0);
   __syncthreads();
   const double *win[kMaxEll + 1];
   double cf[kMaxEll + 1];
@@ -449,23 +304,10 @@ __global__ void __launch_bounds__(kWG) k_pupdate(const Dev *__restrict__ devs,
   __shared__ double blk[kMaxQ];
   __shared__ double s_cf[kMaxEll + 1];
   extern __shared__ double coefx[];  // k coefficients of x_k (reweighting)
-  Scal *sc = D.sc;
   const int j0 = pwin0(D, k);
   const int nwin = k >= j0 ? k - j0 + 1 : 0;
   consume<kWG>(D, kStageC, nwin + 1, lds_w, tot);
-  if (threadIdx.x == 0) {
-    const int ns = D.ell + 1, ldh = D.maxit + 1;
-    double t[kMaxEll + 1];
-    for (int q = 0; q < nwin; ++q) {
-      const int jq = j0 + q;
-      double v = D.sigp[jq] * tot[q];
-      for (int i = 0; i < q; ++i) v -= t[i] * sc->Gp[pslot(D, jq) * ns + pslot(D, j0 + i)];
-      t[q] = v;
-      s_cf[q] = v * D.sigp[jq];
-      if (wid == 0) D.T[(size_t)k * ldh + (jq - 1)] = v;
-    }
-    if (wid == 0) sc->zpre = sqrt(tot[nwin]);
-  }
+  if (threadIdx.x == 0) finish_p_coeffs(D, k, tot, s_cf, wid == 0);
   const bool rew = D.tau == 1;
   if (rew)
     for (int j = threadIdx.x; j < k; j += kWG) coefx[j] = D.sigp[j + 1] * D.y[j];
@@ -478,8 +320,8 @@ __global__ void __launch_bounds__(kWG) k_pupdate(const Dev *__restrict__ devs,
     cf[q] = (q < nwin) ? s_cf[q] : 0.0;
   }
   const double *zr = zrawk(D, k);
-  double *zcol = D.Z + (size_t)k * D.n;
-  double *pout = rew ? D.P + (size_t)pslot(D, k + 1) * D.n : zcol;
+  double *zout = D.Z + (size_t)k * D.n;
+  double *pout = rew ? D.P + (size_t)pslot(D, k + 1) * D.n : zout;
   const double eps2 = D.eps * D.eps;
   int i0, i1;
   chunk_range(D.n, D.nwv, wid, i0, i1);
@@ -497,7 +339,7 @@ __global__ void __launch_bounds__(kWG) k_pupdate(const Dev *__restrict__ devs,
       double xi = 0.0;
       for (int j = 0; j < k; ++j) xi += coefx[j] * D.Z[(size_t)j * D.n + i];
       D.x[i] = xi;
-      zcol[i] = sqrt(sqrt(xi * xi + eps2)) * v;
+      zout[i] = sqrt(sqrt(xi * xi + eps2)) * v;
     }
     acc[0] += v * v;
 #pragma unroll
@@ -512,7 +354,8 @@ __global__ void __launch_bounds__(kWG) k_pupdate(const Dev *__restrict__ devs,
 // sFLSQR, S B w_1 for sFLSMR); k > 0 sketches the raw product of iteration k
 // (skipped once the instance has halted).  map[blockIdx.x] = (instance, tile).
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ const double *sketch_in(const Dev &D, int k) {
+__device__ __forceinline__ const double *sketch_in(const Dev &D, int k, int &stride) {
+  stride = (k == 0 && D.method == 0) ? 1 : D.vs;   // b is always contiguous
   if (k == 0) return D.method == 0 ? D.b : zrawk(D, 0);
   return D.method == 0 ? wrawk(D, k) : zrawk(D, k);
 }
@@ -528,11 +371,12 @@ __global__ void __launch_bounds__(kWG) k_sketch_gather(const Dev *__restrict__ d
   const int2 bm = map[blockIdx.x];
   const Dev &D = devs[bm.x];
   if (k > 0 && skip_iter(D, k)) return;
-  const double *v = sketch_in(D, k);
+  int vs;
+  const double *v = sketch_in(D, k, vs);
   double *dst = sketch_out(D, k);
   if (D.sketch == 2) {
     const int i = bm.y * kWG + threadIdx.x;
-    if (i < D.s) dst[i] = v[i];
+    if (i < D.s) dst[i] = v[(size_t)i * vs];
     return;
   }
   const int wave = (bm.y * kWG + threadIdx.x) >> 6;
@@ -543,7 +387,7 @@ __global__ void __launch_bounds__(kWG) k_sketch_gather(const Dev *__restrict__ d
     double acc = 0.0;
     for (int e = e0 + lane; e < e1; e += 64) {
       const int code = D.sk_ent[e];
-      const double val = v[code & 0x7fffffff];
+      const double val = v[(size_t)(code & 0x7fffffff) * vs];
       acc += code < 0 ? -val : val;
     }
     acc = wave_sum(acc);
@@ -560,7 +404,8 @@ __global__ void __launch_bounds__(kWG) k_srht_blocks(const Dev *__restrict__ dev
   const Dev &D = devs[bm.x];
   if (k > 0 && skip_iter(D, k)) return;
   __shared__ double u[kSrhtL];
-  const double *v = sketch_in(D, k);
+  int vs;
+  const double *v = sketch_in(D, k, vs);
   const int L = 1 << D.log2L;
   const int b = bm.y;
   const int base = b * L;
@@ -569,7 +414,8 @@ __global__ void __launch_bounds__(kWG) k_srht_blocks(const Dev *__restrict__ dev
     double val = 0.0;
     if (g < D.d_sk) {
       const unsigned long long w = D.srht_d[g >> 6];
-      val = ((w >> (g & 63)) & 1ull) ? -v[g] : v[g];
+      const double vg = v[(size_t)g * vs];
+      val = ((w >> (g & 63)) & 1ull) ? -vg : vg;
     }
     u[i] = val;
   }
@@ -830,7 +676,7 @@ __global__ void __launch_bounds__(kWG) k_solution(Dev D, int kk, const double *y
   const int i = blockIdx.x * kWG + threadIdx.x;
   if (i >= D.n) return;
   double xi = 0.0;
-  for (int j = 0; j < kk; ++j) xi += cf[j] * D.Z[(size_t)j * D.n + i];
+  for (int j = 0; j < kk; ++j) xi += cf[j] * zcol(D, j)[(size_t)i * D.vs];
   x[i] = xi;
 }
 
@@ -1057,7 +903,7 @@ __global__ void __launch_bounds__(1024) k_init_b(Dev D, double eta, double noise
   double *w1 = wvec(D, 1);
   for (int i = threadIdx.x; i < D.m; i += 1024) {
     const double v = D.b[i];
-    w1[i] = v;
+    w1[(size_t)i * D.vs] = v;
     acc[0] += v * v;
   }
   block_sum<1024>(acc, 1, lds_w, tot);

@@ -1,0 +1,350 @@
+// Stage kernels for R right-hand sides that share the operator pair A, B
+// (paper Algorithm 1 / Algorithm 2 run R times side by side, eq. (FGK) for
+// each).  The long vectors of all right-hand sides are interleaved (element i
+// of right-hand side r at [i * RS + r]), so one pass over the CSR arrays of A
+// or B serves every right-hand side: a sparse matrix times a block of RS
+// vectors, where each nonzero gathers one contiguous row of RS doubles.
+//
+// Every stage X of iteration k is two launches on the main stream:
+//   k_gfinish<X>  one workgroup per right-hand side reduces the partial sums
+//                 the previous stage left for it (fixed order), runs the same
+//                 scalar step as the single-instance path (Gram-Schmidt
+//                 coefficients, norms, breakdown tests), and writes the
+//                 coefficients of X and an "active" flag to a small table;
+//   stage kernel  streams the interleaved vectors once for all right-hand
+//                 sides; a right-hand side that has stopped, broken down or
+//                 reached its capacity is inactive, and nothing of it is
+//                 written.
+// The sketch and least-squares kernels stay per instance (sfk_kernels.hip),
+// reading the interleaved raw products with stride RS.
+
+#include "sfk_common.h"
+
+namespace sfk {
+
+constexpr int kGWG = 512;   // threads per SpMM workgroup
+
+__device__ __forceinline__ double *gwvec(const Grp &G, int j) {
+  return G.W + (size_t)(j % (G.ell + 2)) * G.m * G.RS;
+}
+__device__ __forceinline__ double *gzcol(const Grp &G, int j) {
+  return G.Z + (size_t)j * G.n * G.RS;
+}
+__device__ __forceinline__ double *gpvec(const Grp &G, int j) {
+  return G.tau == 0 ? gzcol(G, j - 1) : G.P + (size_t)(j % (G.ell + 1)) * G.n * G.RS;
+}
+
+// ---------------------------------------------------------------------------
+// Scalar step of stage ST (kStageA..kStageD) for right-hand side blockIdx.x.
+// ---------------------------------------------------------------------------
+template <int ST>
+__global__ void __launch_bounds__(kWG) k_gfinish(Grp G, int k) {
+  const int r = blockIdx.x;
+  const Dev &D = G.devs[r];
+  __shared__ double lds_w[kMaxQ * (kWG / 64)];
+  __shared__ double tot[kMaxQ];
+  __shared__ int s_on;
+  double *cf = G.coef + (size_t)r * kCoefStride;
+  if (threadIdx.x == 0) s_on = skip_iter(D, k) ? 0 : 1;
+  __syncthreads();
+  if (!s_on) {
+    if (threadIdx.x < kCoefStride) cf[threadIdx.x] = 0.0;
+    if (threadIdx.x == 0) G.act[r] = 0;
+    return;
+  }
+  if (ST == kStageA) {
+    // before A(k): t_kk = ||p~_k|| from D(k-1); a breakdown ends the basis
+    consume<kWG>(D, kStageD, k - wwin0(D, k) + 1, lds_w, tot);
+    if (threadIdx.x == 0) {
+      const double sg = finish_p_norm(D, k, tot, true);
+      cf[0] = sg;
+      G.act[r] = sg != 0.0;
+    }
+  } else if (ST == kStageB) {
+    // before B(k): h_jk from the dots of A(k)
+    consume<kWG>(D, kStageA, k - wwin0(D, k) + 2, lds_w, tot);
+    if (threadIdx.x == 0) {
+      finish_w_coeffs(D, k, tot, cf, true);
+      G.act[r] = 1;
+    }
+  } else if (ST == kStageC) {
+    // before C(k): h_{k+1,k} = ||w~_{k+1}|| from B(k); C(0) scales w~_1 by 1/beta
+    if (k >= 1) consume<kWG>(D, kStageB, k - wwin0(D, k) + 2, lds_w, tot);
+    if (threadIdx.x == 0) {
+      cf[0] = k >= 1 ? finish_w_norm(D, k, tot, true) : D.sigw[1];
+      G.act[r] = 1;
+    }
+  } else {
+    // before D(k): t_j,k+1 from the dots of C(k); the reweighting also needs
+    // the coefficients of x_k = sum_j sigp_{j+1} y_j z~_{j+1}
+    const int j0 = pwin0(D, k);
+    const int nwin = k >= j0 ? k - j0 + 1 : 0;
+    consume<kWG>(D, kStageC, nwin + 1, lds_w, tot);
+    if (threadIdx.x == 0) {
+      finish_p_coeffs(D, k, tot, cf, true);
+      G.act[r] = 1;
+    }
+    if (D.tau == 1)
+      for (int j = threadIdx.x; j < k; j += kWG) G.gx[(size_t)j * G.RS + r] = D.sigp[j + 1] * D.y[j];
+  }
+}
+
+__device__ __forceinline__ bool any_active(const Grp &G, int *s_any) {
+  if (threadIdx.x == 0) {
+    int a = 0;
+    for (int r = 0; r < G.R; ++r) a |= G.act[r];
+    *s_any = a;
+  }
+  __syncthreads();
+  return *s_any != 0;
+}
+
+// Per-right-hand-side block totals of Q partial sums.  v[q] of a thread
+// belongs to right-hand side threadIdx.x % RS (lanes with g > 0 of the SpMM
+// pass zeros).  Threads r < R store the totals of right-hand side r at
+// workgroup slot wid of its partial-sum buffer for 'stage'.
+template <int RS, int NT>
+__device__ void produce_rhs(const Grp &G, int stage, int wid, int Q, const double (&v)[kMaxQ],
+                            double *red) {
+  constexpr int NWV = NT / 64;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+  for (int q = 0; q < kMaxQ; ++q) {
+    if (q < Q) {
+      double t = v[q];
+#pragma unroll
+      for (int o = RS; o < 64; o <<= 1) t += __shfl_xor(t, o, 64);
+      if (lane < RS) red[wv * RS + lane] = t;
+      __syncthreads();
+      if (threadIdx.x < G.R && G.act[threadIdx.x]) {
+        double s = 0.0;
+        for (int w = 0; w < NWV; ++w) s += red[w * RS + threadIdx.x];
+        const Dev &D = G.devs[threadIdx.x];
+        part_of(D, stage)[(size_t)q * D.nwmax + wid] = s;
+      }
+      __syncthreads();
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// A(k) / C(k): Y = scale * Op X for the block of RS vectors, with the window
+// dot products and the norm of each right-hand side's product.
+//   ISA = true : Y = A Z~_k,       window w~_j, j = max(1,k-ell)..k
+//   ISA = false: Y = B W~_{k+1},   window p~_j, j = max(1,k+1-ell)..k
+// A wave handles one row at a time: lane = g * RS + r works on right-hand
+// side r and nonzeros g, g + 64/RS, ... of the row; four gathers in flight.
+// ---------------------------------------------------------------------------
+template <int RS, bool ISA>
+__global__ void __launch_bounds__(kGWG) k_gspmm(Grp G, int k) {
+  constexpr int NG = 64 / RS;
+  constexpr int NWV = kGWG / 64;
+  __shared__ int s_any;
+  __shared__ double red[NWV * RS];
+  if (!any_active(G, &s_any)) return;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int g = lane / RS, j = lane % RS;
+  const bool on = j < G.R && G.act[j] != 0;
+  const double scale = G.coef[(size_t)j * kCoefStride];
+  const int wid = blockIdx.x;
+
+  const int *rp = ISA ? G.Arp : G.Brp;
+  const int *ci = ISA ? G.Aci : G.Bci;
+  const double *va = ISA ? G.Ava : G.Bva;
+  const int *part = ISA ? G.Apart : G.Bpart;
+  const double *xin = (ISA ? gzcol(G, k - 1) : gwvec(G, k + 1)) + j;
+  double *yout = ISA ? G.wraw + (size_t)(k & 1) * G.m * RS : G.zraw + (size_t)(k & 1) * G.n * RS;
+  int j0, nwin;
+  if (ISA) { j0 = max(1, k - G.ell); nwin = k - j0 + 1; }
+  else { j0 = max(1, k + 1 - G.ell); nwin = k >= j0 ? k - j0 + 1 : 0; }
+  const double *win[kMaxEll + 1];
+#pragma unroll
+  for (int q = 0; q < kMaxEll + 1; ++q)
+    win[q] = (q < nwin) ? (ISA ? gwvec(G, j0 + q) : gpvec(G, j0 + q)) : nullptr;
+  double acc[kMaxQ];
+#pragma unroll
+  for (int q = 0; q < kMaxQ; ++q) acc[q] = 0.0;
+
+  const int r0 = part[wid], r1 = part[wid + 1];
+  for (int row = r0 + wv; row < r1; row += NWV) {
+    const int e0 = rp[row], e1 = rp[row + 1];
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+    int e = e0 + g;
+    for (; e + 3 * NG < e1; e += 4 * NG) {
+      const double v0 = va[e], v1 = va[e + NG], v2 = va[e + 2 * NG], v3 = va[e + 3 * NG];
+      const int c0 = ci[e], c1 = ci[e + NG], c2 = ci[e + 2 * NG], c3 = ci[e + 3 * NG];
+      a0 += v0 * xin[(size_t)c0 * RS];
+      a1 += v1 * xin[(size_t)c1 * RS];
+      a2 += v2 * xin[(size_t)c2 * RS];
+      a3 += v3 * xin[(size_t)c3 * RS];
+    }
+    for (; e < e1; e += NG) a0 += va[e] * xin[(size_t)ci[e] * RS];
+    double sum = (a0 + a1) + (a2 + a3);
+#pragma unroll
+    for (int o = RS; o < 64; o <<= 1) sum += __shfl_xor(sum, o, 64);
+    if (g == 0) {
+      const size_t at = (size_t)row * RS + j;
+      const double y = sum * scale;
+      if (on) yout[at] = y;
+#pragma unroll
+      for (int q = 0; q < kMaxEll + 1; ++q)
+        if (q < nwin) acc[q] += win[q][at] * y;
+      acc[kMaxEll + 1] += y * y;
+    }
+  }
+  double v[kMaxQ];
+#pragma unroll
+  for (int q = 0; q < kMaxQ; ++q) v[q] = (q < nwin) ? acc[q] : (q == nwin ? acc[kMaxEll + 1] : 0.0);
+  produce_rhs<RS, kGWG>(G, ISA ? kStageA : kStageC, wid, nwin + 1, v, red);
+}
+
+// ---------------------------------------------------------------------------
+// B(k): w~_{k+1} = w - sum_j h_jk w~_j sigw_j for every right-hand side, with
+// ||w~_{k+1}||^2 and the Gram entries <w~_{k+1}, w~_j>.  Thread t always works
+// on right-hand side t % RS (kWG is a multiple of RS).
+// ---------------------------------------------------------------------------
+template <int RS>
+__global__ void __launch_bounds__(kWG) k_gwupdate(Grp G, int k) {
+  __shared__ int s_any;
+  __shared__ double red[(kWG / 64) * RS];
+  if (!any_active(G, &s_any)) return;
+  const int j = threadIdx.x % RS;
+  const bool on = j < G.R && G.act[j] != 0;
+  const int wid = blockIdx.x;
+  const int j0 = max(1, k - G.ell), nwin = k - j0 + 1;
+  const double *win[kMaxEll + 1];
+  double cf[kMaxEll + 1];
+#pragma unroll
+  for (int q = 0; q < kMaxEll + 1; ++q) {
+    win[q] = (q < nwin) ? gwvec(G, j0 + q) : nullptr;
+    cf[q] = (q < nwin) ? G.coef[(size_t)j * kCoefStride + q] : 0.0;
+  }
+  const double *wr = G.wraw + (size_t)(k & 1) * G.m * RS;
+  double *out = gwvec(G, k + 1);
+  int i0, i1;
+  chunk_range(G.m, G.nwv, wid, i0, i1);
+  double acc[kMaxQ];
+#pragma unroll
+  for (int q = 0; q < kMaxQ; ++q) acc[q] = 0.0;
+  const size_t e1 = (size_t)i1 * RS;
+  for (size_t e = (size_t)i0 * RS + threadIdx.x; e < e1; e += kWG) {
+    double v = wr[e];
+    double wj[kMaxEll + 1];
+#pragma unroll
+    for (int q = 0; q < kMaxEll + 1; ++q)
+      if (q < nwin) { wj[q] = win[q][e]; v -= cf[q] * wj[q]; }
+    if (on) out[e] = v;
+    acc[0] += v * v;
+#pragma unroll
+    for (int q = 0; q < kMaxEll + 1; ++q)
+      if (q < nwin) acc[1 + q] += v * wj[q];
+  }
+  produce_rhs<RS, kWG>(G, kStageB, wid, nwin + 1, acc, red);
+}
+
+// ---------------------------------------------------------------------------
+// D(k): p~_{k+1} = z - sum_j t_j,k+1 p~_j sigp_j, z~_{k+1} = tau(p~_{k+1}), with
+// ||p~_{k+1}||^2 and the Gram entries.  The reweighting forms x_k on the fly.
+// ---------------------------------------------------------------------------
+template <int RS>
+__global__ void __launch_bounds__(kWG) k_gpupdate(Grp G, int k) {
+  __shared__ int s_any;
+  __shared__ double red[(kWG / 64) * RS];
+  if (!any_active(G, &s_any)) return;
+  const int j = threadIdx.x % RS;
+  const bool on = j < G.R && G.act[j] != 0;
+  const int wid = blockIdx.x;
+  const int j0 = max(1, k + 1 - G.ell);
+  const int nwin = k >= j0 ? k - j0 + 1 : 0;
+  const double *win[kMaxEll + 1];
+  double cf[kMaxEll + 1];
+#pragma unroll
+  for (int q = 0; q < kMaxEll + 1; ++q) {
+    win[q] = (q < nwin) ? gpvec(G, j0 + q) : nullptr;
+    cf[q] = (q < nwin) ? G.coef[(size_t)j * kCoefStride + q] : 0.0;
+  }
+  const bool rew = G.tau == 1;
+  const double *zr = G.zraw + (size_t)(k & 1) * G.n * RS;
+  double *zout = gzcol(G, k);
+  double *pout = rew ? G.P + (size_t)((k + 1) % (G.ell + 1)) * G.n * RS : zout;
+  const double eps2 = G.eps * G.eps;
+  const size_t colstride = (size_t)G.n * RS;
+  int i0, i1;
+  chunk_range(G.n, G.nwv, wid, i0, i1);
+  double acc[kMaxQ];
+#pragma unroll
+  for (int q = 0; q < kMaxQ; ++q) acc[q] = 0.0;
+  const size_t e1 = (size_t)i1 * RS;
+  for (size_t e = (size_t)i0 * RS + threadIdx.x; e < e1; e += kWG) {
+    double v = zr[e];
+    double pj[kMaxEll + 1];
+#pragma unroll
+    for (int q = 0; q < kMaxEll + 1; ++q)
+      if (q < nwin) { pj[q] = win[q][e]; v -= cf[q] * pj[q]; }
+    if (on) pout[e] = v;
+    if (rew) {
+      double xi = 0.0;
+      for (int jj = 0; jj < k; ++jj) xi += G.gx[(size_t)jj * RS + j] * G.Z[(size_t)jj * colstride + e];
+      if (on) {
+        G.x[e] = xi;
+        zout[e] = sqrt(sqrt(xi * xi + eps2)) * v;
+      }
+    }
+    acc[0] += v * v;
+#pragma unroll
+    for (int q = 0; q < kMaxEll + 1; ++q)
+      if (q < nwin) acc[1 + q] += v * pj[q];
+  }
+  produce_rhs<RS, kWG>(G, kStageD, wid, nwin + 1, acc, red);
+}
+
+// ---------------------------------------------------------------------------
+// host-side launchers
+// ---------------------------------------------------------------------------
+template <int RS>
+static void launch_group_rs(const Grp &G, int stage, int k, hipStream_t st) {
+  const dim3 fin(G.R), fb(kWG);
+  switch (stage) {
+    case kStageA:
+      hipLaunchKernelGGL(k_gfinish<kStageA>, fin, fb, 0, st, G, k);
+      hipLaunchKernelGGL((k_gspmm<RS, true>), dim3(G.nws), dim3(kGWG), 0, st, G, k);
+      break;
+    case kStageB:
+      hipLaunchKernelGGL(k_gfinish<kStageB>, fin, fb, 0, st, G, k);
+      hipLaunchKernelGGL(k_gwupdate<RS>, dim3(G.nwv), dim3(kWG), 0, st, G, k);
+      break;
+    case kStageC:
+      hipLaunchKernelGGL(k_gfinish<kStageC>, fin, fb, 0, st, G, k);
+      hipLaunchKernelGGL((k_gspmm<RS, false>), dim3(G.nws), dim3(kGWG), 0, st, G, k);
+      break;
+    default:
+      hipLaunchKernelGGL(k_gfinish<kStageD>, fin, fb, 0, st, G, k);
+      hipLaunchKernelGGL(k_gpupdate<RS>, dim3(G.nwv), dim3(kWG), 0, st, G, k);
+      break;
+  }
+}
+
+// stage kA..kD of iteration k for every right-hand side of the group
+void launch_group_stage(const Grp &G, int stage, int k, hipStream_t st) {
+  switch (G.RS) {
+    case 8: launch_group_rs<8>(G, stage, k, st); break;
+    case 16: launch_group_rs<16>(G, stage, k, st); break;
+    case 32: launch_group_rs<32>(G, stage, k, st); break;
+    default: launch_group_rs<64>(G, stage, k, st); break;
+  }
+}
+
+// resident SpMM workgroups per CU for interleave width RS
+int gspmm_blocks_per_cu(int RS) {
+  int nb = 0;
+  hipError_t e;
+  switch (RS) {
+    case 8: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_gspmm<8, true>, kGWG, 0); break;
+    case 16: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_gspmm<16, true>, kGWG, 0); break;
+    case 32: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_gspmm<32, true>, kGWG, 0); break;
+    default: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_gspmm<64, true>, kGWG, 0); break;
+  }
+  return (e == hipSuccess && nb > 0) ? nb : 1;
+}
+
+}  // namespace sfk

@@ -290,6 +290,27 @@ def batch_instances(count: int = 32, sides=(128, 192, 256, 384), seed: int = 4,
     return out
 
 
+def multi_rhs(P: Problem, R: int, *, seed: int = 5, noise=None) -> tuple[np.ndarray, np.ndarray,
+                                                                         np.ndarray]:
+    """R right-hand sides for the operator of P: right-hand side r measures its
+    own phantom (ellipses, or sparse like P's if P's phantom is sparse) at its
+    own noise level (P's level if noise is None, else noise[r]).  Returns
+    (b (R, m), x_true (R, n), noise_norm (R,))."""
+    sparse = float(np.mean(P.x_true != 0)) < 0.5
+    rel = float(P.noise_norm / np.linalg.norm(P.A @ P.x_true)) if noise is None else None
+    bs, xs, dns = [], [], []
+    for r in range(R):
+        off = seed + INSTANCE_STRIDE * (r + 1)
+        x = sparse_phantom(P.N, SEED_PHANTOM + off) if sparse else ellipse_phantom(P.N, SEED_PHANTOM + off)
+        bt = P.A @ x
+        level = noise[r] if noise is not None else rel
+        b, dn = add_noise(bt, level, SEED_NOISE + off)
+        bs.append(b)
+        xs.append(x)
+        dns.append(dn)
+    return np.stack(bs), np.stack(xs), np.array(dns)
+
+
 def small_ct(N: int = 16, n_angles: int = 12, n_det: int | None = None, *, noise: float = 0.01,
              seed_offset: int = 7, unmatched: bool = False, phantom: str = "ellipses") -> Problem:
     """A small CT problem for quick tests."""

@@ -90,6 +90,8 @@ def lib() -> ctypes.CDLL:
         "sfk_instance_status": (I32, [P, I32, PI32, PI32, PI32]),
         "sfk_instance_solution": (I32, [P, I32, P]),
         "sfk_instance_residual_norms": (I32, [P, I32, PD, I32, PI32, PD]),
+        "sfk_instance_true_residual": (I32, [P, I32, PD]),
+        "sfk_init_multi": (I32, [ctypes.POINTER(P), PCSR, PCSR, P, I32, PPAR, P]),
         "sfk_stage_times": (I32, [P, PD, PI32]),
     }
     for name, (res, args) in sig.items():
@@ -106,7 +108,7 @@ def exported_symbols() -> list[str]:
             "sfk_destroy", "sfk_last_error", "sfk_sketch_sparse_sign", "sfk_sketch_srht",
             "sfk_coefficients", "sfk_version", "sfk_set_timing", "sfk_stage_times",
             "sfk_init_batch", "sfk_batch_size", "sfk_instance_status", "sfk_instance_solution",
-            "sfk_instance_residual_norms"]
+            "sfk_instance_residual_norms", "sfk_instance_true_residual", "sfk_init_multi"]
 
 
 def _check(status: int, ctx=None):
@@ -329,7 +331,7 @@ class BatchContext:
     def __init__(self, handle, As, Bs, bs, ps, stream):
         self.handle = handle
         self.As, self.Bs, self.bs, self.ps, self.stream = As, Bs, bs, ps, stream
-        self.nb = len(As)
+        self.nb = len(ps)
 
     def __del__(self):
         try:
@@ -355,6 +357,31 @@ def init_batch(As: list, Bs: list | None, bs: list, ps: list, *, stream=None) ->
     st = lib().sfk_init_batch(ctypes.byref(h), nb, Aarr, Barr, barr, parr, st_obj.cuda_stream)
     _check(st)
     return BatchContext(h, As, Bs, bs, ps, st_obj)
+
+
+def init_multi(A: DeviceCSR, B: DeviceCSR | None, b_block, ps: list, *, stream=None) -> BatchContext:
+    """sfk_init_multi: R right-hand sides sharing A and B.  b_block is a CUDA
+    float64 tensor of shape (R, m) (right-hand side r in row r, contiguous);
+    ps holds R Params that agree except in seed, instance, eta, noise_norm, tol."""
+    import torch
+    R = len(ps)
+    if tuple(b_block.shape) != (R, A.rows) or not b_block.is_contiguous() \
+            or b_block.dtype != torch.float64:
+        raise ValueError(f"b_block must be a contiguous float64 tensor of shape ({R}, {A.rows})")
+    parr = (Params * R)(*ps)
+    st_obj = stream if stream is not None else torch.cuda.current_stream(b_block.device)
+    h = ctypes.c_void_p()
+    Bc = ctypes.byref(B.c()) if B is not None else None
+    st = lib().sfk_init_multi(ctypes.byref(h), ctypes.byref(A.c()), Bc, b_block.data_ptr(), R, parr,
+                              st_obj.cuda_stream)
+    _check(st)
+    return BatchContext(h, [A], [B], [b_block], ps, st_obj)
+
+
+def instance_true_residual(ctx, i: int) -> float:
+    out = ctypes.c_double()
+    _check(lib().sfk_instance_true_residual(ctx.handle, i, ctypes.byref(out)), ctx.handle)
+    return out.value
 
 
 def instance_status(ctx, i: int) -> tuple[int, bool, int]:
