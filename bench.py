@@ -9,6 +9,18 @@ s = 400 rows, 200 iterations, FP64.  One step = one iteration of the method
 squares, back-projection, flexible preconditioner).  Inputs are resident in HBM
 before the timed region; the context set-up (init) is outside it.
 
+Batched throughput, reported beside the plain figure (same JSON line):
+  * shared operator: R = 32 right-hand sides of the default workload's A and B
+    (own phantom, own SRHT seed each) in one context, against a loop of 32
+    plain solves on the same GPU; both run the same number of iterations, and
+    every right-hand side's x_10 must agree with its plain run to 1e-8 relative;
+  * heterogeneous: 32 independent instances, image side drawn from
+    {128, 192, 256, 384} (angles 0.7 side, bins ceil(sqrt(2) side)), own
+    ellipse phantom and noise U[0.5%, 3%], sFLSQR with B = A^T built on the
+    device, sparse-sign s = 201, zeta = 8, up to 100 iterations with the
+    discrepancy principle per instance, against a plain loop over the same 32.
+Set-up (init) is outside every timed region.
+
 Prints one JSON line.  --gpus N with N > 1 is refused: this build runs on one
 GPU.
 """
@@ -72,6 +84,101 @@ def copy_calibration(nbytes: int = 1 << 30):
     print(json.dumps({"copy_bytes_read": nbytes, "copy_bytes_written": nbytes, "launches": 3}))
 
 
+def _timed_iterate(sfk, torch, ctx, k):
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    done, stopped, st = sfk.iterate(ctx, k)
+    torch.cuda.synchronize()
+    return time.perf_counter() - t0, done
+
+
+def multi_rhs_bench(P, cfg, A, B, R: int, K: int):
+    """R right-hand sides sharing A and B in one context vs a loop of R plain
+    solves, K iterations each (init outside the timed regions)."""
+    import numpy as np
+    import torch
+    from paper_2605_22281_amd import inputs, sfk
+    b, xt, _ = inputs.multi_rhs(P, R, seed=21)
+    bb = torch.from_numpy(np.ascontiguousarray(b)).cuda()
+    ps = [sfk.params(cfg["method"], ell=2, maxit=K, sketch=cfg["sketch"], s=cfg["s"],
+                     zeta=cfg["zeta"], seed=3100 + r, tau=cfg["tau"], eps=1e-3) for r in range(R)]
+    warm = sfk.init_multi(A, B, bb, ps)
+    sfk.iterate(warm, min(K, 10))
+    sfk.destroy(warm)
+    ctx = sfk.init_multi(A, B, bb, ps)
+    tb, done = _timed_iterate(sfk, torch, ctx, K)
+    if done != K:
+        raise SystemExit(f"shared-operator run ended after {done} of {K} iterations")
+    kc = min(10, K)
+    xb10 = [sfk.instance_solution_at(ctx, r, kc, P.n).cpu().numpy() for r in range(R)]
+    xbK = [sfk.instance_solution(ctx, r, P.n).cpu().numpy() for r in range(R)]
+    sfk.destroy(ctx)
+    ctx = sfk.init_multi(A, B, bb, ps)
+    sfk.set_timing(ctx, True)
+    sfk.iterate(ctx, K)
+    times = sfk.stage_times(ctx)
+    sfk.destroy(ctx)
+    tp, worst10, err_b, err_p = 0.0, 0.0, [], []
+    for r in range(R):
+        c = sfk.init(A, B, bb[r], ps[r])
+        dt, d = _timed_iterate(sfk, torch, c, K)
+        if d != K:
+            raise SystemExit(f"plain run {r} ended after {d} of {K} iterations")
+        tp += dt
+        x10 = sfk.solution_at(c, kc).cpu().numpy()
+        xK = sfk.solution(c).cpu().numpy()
+        sfk.destroy(c)
+        worst10 = max(worst10, float(np.linalg.norm(xb10[r] - x10) / np.linalg.norm(x10)))
+        nt = np.linalg.norm(xt[r])
+        err_b.append(float(np.linalg.norm(xbK[r] - xt[r]) / nt))
+        err_p.append(float(np.linalg.norm(xK - xt[r]) / nt))
+    rate_b, rate_p = R * K / tb, R * K / tp
+    return {"R": R, "iterations": K, "workload": cfg["desc"] + f", {R} right-hand sides",
+            "rhs_iterations_per_s": rate_b, "plain_rhs_iterations_per_s": rate_p,
+            "speedup": rate_b / rate_p, "ms_per_batched_step": tb * 1e3 / K,
+            "max_rel_diff_x10_vs_plain": worst10,
+            "mean_rel_error_vs_truth": {"batched": float(np.mean(err_b)),
+                                        "plain": float(np.mean(err_p))},
+            "max_abs_diff_rel_error_vs_truth": float(np.max(np.abs(np.array(err_b) - np.array(err_p)))),
+            "stage_avg_ms": {k: (v[0] / v[1] if v[1] else 0.0) for k, v in times.items()}}
+
+
+def hetero_bench(count: int = 32, maxit: int = 100):
+    """Independent instances of uneven sizes in one context vs a plain loop."""
+    import numpy as np
+    import torch
+    from paper_2605_22281_amd import inputs, sfk
+    probs = inputs.batch_instances(count)
+    As = [sfk.to_device_csr(P.A) for P in probs]       # separate device copies
+    bs = [torch.from_numpy(np.ascontiguousarray(P.b)).cuda() for P in probs]
+    ps = [sfk.params("sflsqr", ell=2, maxit=maxit, sketch="sparse_sign", s=201, zeta=8,
+                     seed=5000 + i, noise_norm=P.noise_norm, eta=1.01) for i, P in enumerate(probs)]
+    warm = sfk.init_batch(As, None, bs, ps)
+    sfk.iterate(warm, 5)
+    sfk.destroy(warm)
+    ctx = sfk.init_batch(As, None, bs, ps)
+    tb, _ = _timed_iterate(sfk, torch, ctx, maxit)
+    kb = [sfk.instance_status(ctx, i)[0] for i in range(count)]
+    xb = [sfk.instance_solution(ctx, i, P.n).cpu().numpy() for i, P in enumerate(probs)]
+    sfk.destroy(ctx)
+    tp, kp, worst = 0.0, [], 0.0
+    for i, P in enumerate(probs):
+        c = sfk.init(As[i], None, bs[i], ps[i])
+        dt, d = _timed_iterate(sfk, torch, c, maxit)
+        tp += dt
+        kp.append(d)
+        x = sfk.solution(c).cpu().numpy()
+        sfk.destroy(c)
+        worst = max(worst, float(np.linalg.norm(xb[i] - x) / np.linalg.norm(x)))
+    its = sum(kb)
+    return {"instances": count, "sides": sorted({P.N for P in probs}),
+            "nnz_total": int(sum(P.A.nnz for P in probs)), "maxit": maxit,
+            "instance_iterations": its, "iterations_equal_plain": kb == kp,
+            "instance_iterations_per_s": its / tb, "plain_instance_iterations_per_s": sum(kp) / tp,
+            "speedup": (its / tb) / (sum(kp) / tp), "batched_s": tb, "plain_loop_s": tp,
+            "max_rel_diff_x_vs_plain": worst}
+
+
 def cpu_baseline(P, cfg, sample_iters: int):
     from oracle import fgk, sketches
     try:
@@ -112,6 +219,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-iters", type=int, default=40)
     ap.add_argument("--copy-calibration", action="store_true")
+    ap.add_argument("--batched", default="all", choices=["all", "multi", "hetero", "none"])
+    ap.add_argument("--rhs", type=int, default=32)
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -214,6 +323,17 @@ def main():
         "iteration_GBps": iter_bytes / (ms_per_step * 1e-3) / 1e9,
         "stage_avg_ms": stage_avg,
     }
+    if args.batched in ("all", "multi"):
+        log(f"bench: shared operator, {args.rhs} right-hand sides x {K} iterations, and plain loop")
+        mr = multi_rhs_bench(P, cfg, A, B, args.rhs, K)
+        out["batched_multi_rhs"] = mr
+        out["batched_plain_speedup"] = mr["speedup"]
+        log(f"bench: shared operator speedup {mr['speedup']:.2f}x")
+    if args.batched in ("all", "hetero"):
+        log("bench: heterogeneous batch of 32 instances, and plain loop")
+        hb = hetero_bench()
+        out["batched_heterogeneous"] = hb
+        log(f"bench: heterogeneous speedup {hb['speedup']:.2f}x")
     if not args.no_cpu_baseline:
         log(f"bench: oracle baseline, {args.cpu_sample_iters} iterations")
         out["cpu_baseline"] = cpu_baseline(P, cfg, args.cpu_sample_iters)

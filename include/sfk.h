@@ -203,6 +203,9 @@ sfk_status sfk_instance_status(sfk_ctx *ctx, int32_t i, int32_t *iters_done_host
 /* x_k of instance i at its own k (device n_i-vector x). */
 sfk_status sfk_instance_solution(sfk_ctx *ctx, int32_t i, double *x);
 
+/* x_j of instance i for 0 <= j <= its k (see sfk_solution_at). */
+sfk_status sfk_instance_solution_at(sfk_ctx *ctx, int32_t i, int32_t j, double *x);
+
 /* rho_1..rho_k of instance i (see sfk_residual_norms). */
 sfk_status sfk_instance_residual_norms(sfk_ctx *ctx, int32_t i, double *out_host, int32_t cap,
                                        int32_t *count_host, double *rhs_norm_host);

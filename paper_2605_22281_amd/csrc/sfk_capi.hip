@@ -42,6 +42,18 @@ void launch_solution(const Dev &D, int kk, const double *yv, double *x, hipStrea
 void launch_true_residual(const Dev &D, const double *x, double *out, hipStream_t st);
 void launch_group_stage(const Grp &G, int stage, int k, hipStream_t st);
 int gspmm_blocks_per_cu(int RS);
+int gspmm_x_blocks_per_cu(int RS);
+void launch_scan(int *a, int len, hipStream_t st);
+void launch_xs_count(const int *rp, const int *ci, int rows, int NS, const int *cb, int *touch,
+                     int *rowcnt, int *err, hipStream_t st);
+void launch_xs_fill1(const int *rp, const int *ci, int rows, int NS, const int *cb,
+                     const int *touch, const int *crp, int *slot, int *seglen, int *segsrc,
+                     int *segrow, hipStream_t st);
+void launch_xs_fill2(const int *ci, const double *va, int nseg, const int *pos, const int *segsrc,
+                     const int *segrow, const int *slot, int RS, int4 *seg, XNz *xnz,
+                     hipStream_t st);
+void launch_xs_part(const int *touch, int rows, int NS, int nseg, const int *pos, int nbs,
+                    int *spart, hipStream_t st);
 }  // namespace sfk
 
 using namespace sfk;
@@ -78,6 +90,7 @@ struct sfk_ctx {
   bool multi = false;               // right-hand sides sharing A and B (stages via grp)
   Grp grp{};
   void *gws = nullptr;              // workspace of the shared arrays
+  std::vector<void *> xmem;         // sliced copies of A and B
   std::string err;
   // optional per-stage timing with HIP events
   bool timing = false;
@@ -703,6 +716,7 @@ static void release(sfk_ctx *c) {
   for (auto &I : c->inst)
     if (I.owns_ws && I.ws) hipFree(I.ws);
   if (c->gws) hipFree(c->gws);
+  for (void *q : c->xmem) hipFree(q);
   if (c->hdr) hipFree(c->hdr);
   if (c->h_scal) hipHostFree(c->h_scal);
   delete c;
@@ -799,6 +813,92 @@ static sfk_status same_params(const sfk_params &a, const sfk_params &b, int r) {
     return fail(nullptr, SFK_EINVAL, "right-hand side %d: '%s' differs from right-hand side 0 "
                 "(right-hand sides sharing A and B may differ only in seed, instance, eta, "
                 "noise_norm and tol)", r, what);
+  return SFK_OK;
+}
+
+// Column-sliced copy of one operator (rows x cols CSR on the device) for the
+// shared-operator products: slices of at most ~2 MB of source-block rows each,
+// a multiple of kXcds of them, nbs workgroups per slice.  *ok = false (and
+// SFK_OK) when the operator cannot be sliced (columns not increasing within a
+// row, or index ranges beyond 32-bit offsets): the row kernel is used instead.
+static sfk_status build_xop(sfk_ctx *c, XOp &X, const int *rp, const int *ci, const double *va,
+                            int rows, int cols, int64_t nnz, int RS, int cus, bool *ok) {
+  hipStream_t st = c->stream;
+  *ok = false;
+  const int64_t cps = std::max<int64_t>(1, (int64_t)(2 << 20) / (RS * (int64_t)sizeof(double)));
+  const int64_t per = (int64_t)kXcds * cps;
+  const int NS = (int)(kXcds * std::max<int64_t>(1, (cols + per - 1) / per));
+  if ((int64_t)NS * rows + 1 >= (1ll << 31) || nnz + kXPad >= (1ll << 31) ||
+      (int64_t)cols * RS * (int64_t)sizeof(double) >= (1ll << 31))
+    return SFK_OK;
+
+  const int nbs = std::max(1, cus * gspmm_x_blocks_per_cu(RS) / kXcds);
+  Layout L1;
+  const size_t o_cb = L1.take<int>(NS + 1);
+  const size_t o_touch = L1.take<int>((size_t)NS * rows + 1);
+  const size_t o_err = L1.take<int>(1);
+  const size_t s1 = L1.off;
+  void *scr = nullptr;
+  HIPCHK(c, hipMalloc(&scr, s1));
+  struct Guard {
+    void *p;
+    ~Guard() { if (p) hipFree(p); }
+  } g1{scr};
+  void *crp_mem = nullptr;
+  HIPCHK(c, hipMalloc(&crp_mem, sizeof(int) * ((size_t)rows + 1)));
+  c->xmem.push_back(crp_mem);
+  int *cb = at<int>(scr, o_cb), *touch = at<int>(scr, o_touch), *err = at<int>(scr, o_err);
+  int *crp = static_cast<int *>(crp_mem);
+  std::vector<int> hcb(NS + 1);
+  for (int q = 0; q <= NS; ++q) hcb[q] = (int)((int64_t)q * cols / NS);
+  HIPCHK(c, hipMemsetAsync(scr, 0, s1, st));
+  HIPCHK(c, hipMemsetAsync(crp, 0, sizeof(int) * ((size_t)rows + 1), st));
+  HIPCHK(c, hipMemcpyAsync(cb, hcb.data(), sizeof(int) * (NS + 1), hipMemcpyHostToDevice, st));
+  launch_xs_count(rp, ci, rows, NS, cb, touch, crp, err, st);
+  int herr = 0;
+  HIPCHK(c, hipMemcpyAsync(&herr, err, sizeof(int), hipMemcpyDeviceToHost, st));
+  HIPCHK(c, hipStreamSynchronize(st));
+  if (herr) return SFK_OK;            // unsorted columns: keep the row kernel
+  launch_scan(touch, NS * rows + 1, st);
+  launch_scan(crp, rows + 1, st);
+  int nseg = 0;
+  HIPCHK(c, hipMemcpyAsync(&nseg, touch + (size_t)NS * rows, sizeof(int), hipMemcpyDeviceToHost, st));
+  HIPCHK(c, hipStreamSynchronize(st));
+  if (nseg <= 0) return SFK_OK;       // no nonzeros: keep the row kernel
+  Layout L2;
+  const size_t o_seg = L2.take<int4>(std::max(nseg, 1));
+  const size_t o_spart = L2.take<int>((size_t)NS * (nbs + 1));
+  const size_t o_nz = L2.take<XNz>(nnz + kXPad);
+  const size_t o_part = L2.take<double>((size_t)std::max(nseg, 1) * RS);
+  void *mem = nullptr;
+  HIPCHK(c, hipMalloc(&mem, L2.off));
+  c->xmem.push_back(mem);
+  Layout L3;
+  const size_t o_len = L3.take<int>((size_t)nseg + 1);
+  const size_t o_src = L3.take<int>(std::max(nseg, 1));
+  const size_t o_row = L3.take<int>(std::max(nseg, 1));
+  const size_t o_slot = L3.take<int>(std::max(nseg, 1));
+  void *scr2 = nullptr;
+  HIPCHK(c, hipMalloc(&scr2, L3.off));
+  Guard g2{scr2};
+  HIPCHK(c, hipMemsetAsync(mem, 0, L2.off, st));
+  HIPCHK(c, hipMemsetAsync(scr2, 0, L3.off, st));
+  int *seglen = at<int>(scr2, o_len), *segsrc = at<int>(scr2, o_src), *segrow = at<int>(scr2, o_row);
+  int *slot = at<int>(scr2, o_slot);
+  launch_xs_fill1(rp, ci, rows, NS, cb, touch, crp, slot, seglen, segsrc, segrow, st);
+  launch_scan(seglen, nseg + 1, st);
+  launch_xs_fill2(ci, va, nseg, seglen, segsrc, segrow, slot, RS, at<int4>(mem, o_seg),
+                  at<XNz>(mem, o_nz), st);
+  launch_xs_part(touch, rows, NS, nseg, seglen, nbs, at<int>(mem, o_spart), st);
+  HIPCHK(c, hipGetLastError());
+  HIPCHK(c, hipStreamSynchronize(st));
+  X.rows = rows; X.cols = cols; X.NS = NS; X.nbs = nbs; X.nseg = nseg;
+  X.seg = at<int4>(mem, o_seg);
+  X.spart = at<int>(mem, o_spart);
+  X.nz = at<XNz>(mem, o_nz);
+  X.crp = crp;
+  X.part = at<double>(mem, o_part);
+  *ok = true;
   return SFK_OK;
 }
 
@@ -910,6 +1010,14 @@ extern "C" sfk_status sfk_init_multi(sfk_ctx **out, const sfk_csr *A, const sfk_
     return SFK_OK;
   };
   if (s == SFK_OK) s = setup_group();
+  // sliced products unless the row kernel is asked for (vw != 0) or an operator
+  // cannot be sliced
+  if (s == SFK_OK && p0.vw == 0) {
+    bool oka = false, okb = false;
+    s = build_xop(c, G.xa, G.Arp, G.Aci, G.Ava, (int)m, (int)n, nnzA, RS, cus, &oka);
+    if (s == SFK_OK && oka) s = build_xop(c, G.xb, G.Brp, G.Bci, G.Bva, (int)n, (int)m, nnzB, RS, cus, &okb);
+    G.sliced = (oka && okb) ? 1 : 0;
+  }
   for (int r = 0; r < R && s == SFK_OK; ++r) {
     c->inst[r].p = p[r];
     s = setup_instance(c, c->inst[r], A, B, b_block + (size_t)r * m, nullptr, 0, cus, nw, &G, r);
@@ -1007,6 +1115,12 @@ extern "C" sfk_status sfk_instance_solution(sfk_ctx *c, int32_t i, double *x) {
   Inst *I;
   sfk_status s = instance_of(c, i, &I);
   return s != SFK_OK ? s : solution_impl(c, *I, I->k_done, x);
+}
+
+extern "C" sfk_status sfk_instance_solution_at(sfk_ctx *c, int32_t i, int32_t j, double *x) {
+  Inst *I;
+  sfk_status s = instance_of(c, i, &I);
+  return s != SFK_OK ? s : solution_impl(c, *I, j, x);
 }
 
 static sfk_status norms_impl(sfk_ctx *c, Inst &I, double *out_host, int32_t cap,

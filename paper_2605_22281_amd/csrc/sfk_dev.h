@@ -110,6 +110,33 @@ struct Launch {
 // in the R instance descriptors devs[0..R).
 constexpr int kCoefStride = 16;            // >= kMaxEll + 2
 constexpr int kMaxRhs = 64;
+constexpr int kXPad = 256;                 // tail padding of the sliced nonzero copy
+constexpr int kXcds = 8;                   // L2 domains; workgroup b runs on domain b % 8
+
+// Column-sliced copy of one operator for the shared-operator products.  The
+// columns are cut into NS ranges (a multiple of kXcds, each small enough that
+// its rows of the source block stay in one L2), and each row's nonzeros in a
+// range form a segment.  The workgroups of slice s all run on L2 domain s % 8,
+// so every gather of a slice hits the same L2.  Each segment leaves a partial
+// row of RS sums in a row-major slot (the partials of row i are slots
+// crp[i] .. crp[i + 1] - 1, in slice order); a combine pass adds them.
+// one nonzero of the sliced copy: value and byte offset of its source row in
+// the interleaved block (column * RS * 8)
+struct alignas(16) XNz {
+  double v;
+  int off;
+  int pad;
+};
+
+struct XOp {
+  int rows, cols, NS, nbs, nseg;
+  const int4 *seg;      // nseg: (row, first, end, slot) into nz; slice-major, rows ascending
+  const int *spart;     // NS * (nbs + 1): segment range of each workgroup of a slice
+  const XNz *nz;        // nnz + kXPad (padding: value 0, offset 0)
+  const int *crp;       // rows + 1
+  double *part;         // nseg * RS, slot-major
+};
+
 struct Grp {
   int R, RS;          // right-hand sides, interleave width (power of two, 8..64)
   int m, n, ell, maxit, tau, nws, nwv;
@@ -127,6 +154,8 @@ struct Grp {
   int *act;           // RS: 1 if the right-hand side takes part in that stage
   double *gx;         // maxit * RS: sigp_{j+1} y_j per right-hand side, [j * RS + r]
   const Dev *devs;    // R instance descriptors (device memory)
+  int sliced;         // 1: products through xa / xb; 0: row kernel on the CSR arrays
+  XOp xa, xb;         // sliced A and B
 };
 
 __device__ __forceinline__ int wslot(const Dev &D, int j) { return j % (D.ell + 2); }

@@ -1013,6 +1013,9 @@ void launch_init_b(const Dev &D, double eta, double noise, double tol_user, int 
 void launch_init_rhs(const Dev &D, hipStream_t st) {
   hipLaunchKernelGGL(k_init_rhs, dim3(1), dim3(64), 0, st, D);
 }
+void launch_scan(int *a, int len, hipStream_t st) {
+  hipLaunchKernelGGL(k_scan_single, dim3(1), dim3(1024), 0, st, a, len);
+}
 void launch_csr_check(const int *rp, const int *ci, int rows, int cols, long long nnz, int *err,
                       hipStream_t st) {
   hipLaunchKernelGGL(k_csr_check, dim3((rows + 1 + 255) / 256), dim3(256), 0, st, rp, ci, rows,

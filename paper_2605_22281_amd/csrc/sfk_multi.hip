@@ -199,6 +199,282 @@ __global__ void __launch_bounds__(kGWG) k_gspmm(Grp G, int k) {
 }
 
 // ---------------------------------------------------------------------------
+// Sliced products.  A(k) / C(k) as two passes:
+//   k_gspmm_x   one partial row per segment, sum_e val[e] X[col[e], :], with no
+//               scaling; workgroup b works on slice 8 * (b / (8 nbs)) + b % 8,
+//               so all workgroups of a slice share one L2 domain.  A lane
+//               holds two right-hand sides (16-byte gathers through a buffer
+//               resource with 32-bit offsets).  A wave reads the 16-byte
+//               records (value, source-row offset) of 64 nonzeros with one
+//               load and passes each lane group its record by a cross-lane
+//               broadcast, so only the gathers return data per lane;
+//   k_gcombine  y = scale * (sum of the row's partials in slice order), the
+//               window dot products and the norm, per right-hand side.
+// ---------------------------------------------------------------------------
+// Hands the lanes of a nonzero group the record another lane holds.
+// row_newbcast:I copies lane I of every row of 16 lanes to the whole row (one
+// VALU op); ds_bpermute reads any lane (the address is the source lane * 4).
+template <int I>
+__device__ __forceinline__ int row_bcast(int x) {
+  return __builtin_amdgcn_update_dpp(0, x, 0x150 + I, 0xf, 0xf, false);
+}
+__device__ __forceinline__ int row_bcast_i(int x, int i) {
+  switch (i) {   // i is a compile-time constant at every call site after unrolling
+    case 0: return row_bcast<0>(x);    case 1: return row_bcast<1>(x);
+    case 2: return row_bcast<2>(x);    case 3: return row_bcast<3>(x);
+    case 4: return row_bcast<4>(x);    case 5: return row_bcast<5>(x);
+    case 6: return row_bcast<6>(x);    case 7: return row_bcast<7>(x);
+    case 8: return row_bcast<8>(x);    case 9: return row_bcast<9>(x);
+    case 10: return row_bcast<10>(x);  case 11: return row_bcast<11>(x);
+    case 12: return row_bcast<12>(x);  case 13: return row_bcast<13>(x);
+    case 14: return row_bcast<14>(x);  default: return row_bcast<15>(x);
+  }
+}
+
+template <int RS, bool ISA>
+__global__ void __launch_bounds__(kGWG) k_gspmm_x(Grp G, const int4 *__restrict__ segs,
+                                                 const int *__restrict__ spart,
+                                                 const XNz *__restrict__ nz, int k) {
+  constexpr int LPR = RS / 2;          // lanes per nonzero (two right-hand sides per lane)
+  constexpr int NPS = 64 / LPR;        // nonzeros per wave step
+  constexpr int NSTEP = 64 / NPS;      // wave steps per chunk of 64 records
+  constexpr int U = 4;                 // wave steps per unrolled block
+  constexpr bool BC = LPR == 16;       // a nonzero group is a DPP row
+  constexpr int NWV = kGWG / 64;
+  static_assert(64 <= kXPad, "padding of the sliced copy too small");
+  __shared__ int s_any;
+  if (!any_active(G, &s_any)) return;
+  const XOp &X = ISA ? G.xa : G.xb;
+  const int lane = threadIdx.x & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int g = lane / LPR;
+  const int j2 = (lane % LPR) * 2;
+  // record of a chunk that this lane loads: wave step i of group g uses record
+  // i * NPS + g, held by lane 16 g + i (row broadcast) or by lane i * NPS + g
+  const int rl = BC ? (lane & 15) * NPS + (lane >> 4) : lane;
+  const int per_phase = kXcds * X.nbs;
+  const int b = blockIdx.x;
+  const int sl = kXcds * (b / per_phase) + b % kXcds;
+  const int q = (b % per_phase) / kXcds;
+  const int t0 = spart[sl * (X.nbs + 1) + q], t1 = spart[sl * (X.nbs + 1) + q + 1];
+  // the source block as a buffer: 32-bit offsets, reads past its end return 0
+  const double *xbase = ISA ? gzcol(G, k - 1) : gwvec(G, k + 1);
+  const int xbytes = X.cols * RS * (int)sizeof(double);
+  const __amdgpu_buffer_rsrc_t xr =
+      __builtin_amdgcn_make_buffer_rsrc(const_cast<double *>(xbase), (short)0, xbytes, 0x00020000);
+  const int loff = j2 * (int)sizeof(double);
+  for (int t = t0 + wv; t < t1; t += NWV) {
+    const int4 sg = segs[t];
+    const int end = sg.z;
+    double ax[U], ay[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) ax[u] = ay[u] = 0.0;
+    for (int cb = sg.y; cb < end; cb += 64) {
+      // one coalesced load of 64 records; past the segment's end they belong to
+      // the next segment or the padding (valid offsets, values masked below)
+      const XNz z = nz[cb + rl];               // < end + 64 <= nnz + kXPad
+      const int zo = z.off;
+      const int zl = __double2loint(z.v), zh = __double2hiint(z.v);
+      const int rem = end - cb;
+#pragma unroll
+      for (int i0 = 0; i0 < NSTEP; i0 += U) {
+        if (i0 * NPS < rem) {
+#pragma unroll
+          for (int u = 0; u < U; ++u) {
+            const int i = i0 + u;
+            int off, vl, vh;
+            if (BC) {
+              off = row_bcast_i(zo, i);
+              vl = row_bcast_i(zl, i);
+              vh = row_bcast_i(zh, i);
+            } else {
+              const int src = (i * NPS + g) * 4;
+              off = __builtin_amdgcn_ds_bpermute(src, zo);
+              vl = __builtin_amdgcn_ds_bpermute(src, zl);
+              vh = __builtin_amdgcn_ds_bpermute(src, zh);
+            }
+            const double v = (i * NPS + g < rem) ? __hiloint2double(vh, vl) : 0.0;
+            const auto raw = __builtin_amdgcn_raw_buffer_load_b128(xr, off + loff, 0, 0);
+            double2 xv;
+            __builtin_memcpy(&xv, &raw, sizeof xv);
+            ax[u] += v * xv.x;
+            ay[u] += v * xv.y;
+          }
+        }
+      }
+    }
+    double sx = (ax[0] + ax[1]) + (ax[2] + ax[3]);
+    double sy = (ay[0] + ay[1]) + (ay[2] + ay[3]);
+#pragma unroll
+    for (int o = LPR; o < 64; o <<= 1) {
+      sx += __shfl_xor(sx, o, 64);
+      sy += __shfl_xor(sy, o, 64);
+    }
+    if (g == 0) *reinterpret_cast<double2 *>(X.part + (size_t)sg.w * RS + j2) = make_double2(sx, sy);
+  }
+}
+
+template <int RS, bool ISA>
+__global__ void __launch_bounds__(kWG) k_gcombine(Grp G, int k) {
+  __shared__ int s_any;
+  __shared__ double red[(kWG / 64) * RS];
+  if (!any_active(G, &s_any)) return;
+  const XOp &X = ISA ? G.xa : G.xb;
+  const int j = threadIdx.x % RS;
+  const bool on = j < G.R && G.act[j] != 0;
+  const double scale = G.coef[(size_t)j * kCoefStride];
+  const int wid = blockIdx.x;
+  const int rows = ISA ? G.m : G.n;
+  double *yout = ISA ? G.wraw + (size_t)(k & 1) * G.m * RS : G.zraw + (size_t)(k & 1) * G.n * RS;
+  int j0, nwin;
+  if (ISA) { j0 = max(1, k - G.ell); nwin = k - j0 + 1; }
+  else { j0 = max(1, k + 1 - G.ell); nwin = k >= j0 ? k - j0 + 1 : 0; }
+  const double *win[kMaxEll + 1];
+#pragma unroll
+  for (int q = 0; q < kMaxEll + 1; ++q)
+    win[q] = (q < nwin) ? (ISA ? gwvec(G, j0 + q) : gpvec(G, j0 + q)) : nullptr;
+  double acc[kMaxQ];
+#pragma unroll
+  for (int q = 0; q < kMaxQ; ++q) acc[q] = 0.0;
+  int i0, i1;
+  chunk_range(rows, G.nwv, wid, i0, i1);
+  const size_t e1 = (size_t)i1 * RS;
+  for (size_t e = (size_t)i0 * RS + threadIdx.x; e < e1; e += kWG) {
+    const int i = (int)(e / RS);
+    double sum = 0.0;
+    const double *pr = X.part + (size_t)X.crp[i] * RS + j;
+    const int np = X.crp[i + 1] - X.crp[i];
+    for (int t = 0; t < np; ++t) sum += pr[(size_t)t * RS];
+    const double y = sum * scale;
+    if (on) yout[e] = y;
+#pragma unroll
+    for (int q = 0; q < kMaxEll + 1; ++q)
+      if (q < nwin) acc[q] += win[q][e] * y;
+    acc[kMaxEll + 1] += y * y;
+  }
+  double v[kMaxQ];
+#pragma unroll
+  for (int q = 0; q < kMaxQ; ++q) v[q] = (q < nwin) ? acc[q] : (q == nwin ? acc[kMaxEll + 1] : 0.0);
+  produce_rhs<RS, kWG>(G, ISA ? kStageA : kStageC, wid, nwin + 1, v, red);
+}
+
+// ---------------------------------------------------------------------------
+// Building the sliced copy (initialisation).  Columns of every row must be in
+// increasing order (checked; err bit 32 otherwise).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int slice_of(const int *cb, int NS, int c, int s) {
+  while (s + 1 < NS && c >= cb[s + 1]) ++s;
+  return s;
+}
+
+// touch[s * rows + i] = 1 if row i has nonzeros in slice s; rowcnt[i] = segments of row i
+__global__ void k_xs_count(const int *rp, const int *ci, int rows, int NS, const int *cb,
+                           int *touch, int *rowcnt, int *err) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= rows) return;
+  int s = -1, cnt = 0, prev = -1;
+  for (int e = rp[i]; e < rp[i + 1]; ++e) {
+    const int c = ci[e];
+    if (c <= prev) { atomicOr(err, 32); return; }
+    prev = c;
+    const int sc = slice_of(cb, NS, c, s < 0 ? 0 : s);
+    if (sc != s) {
+      s = sc;
+      touch[(size_t)s * rows + i] = 1;
+      ++cnt;
+    }
+  }
+  rowcnt[i] = cnt;
+}
+
+// per row, with touch and rowcnt scanned: segment id of each of its segments
+// and the row-major slot of its partial
+__global__ void k_xs_fill1(const int *rp, const int *ci, int rows, int NS, const int *cb,
+                           const int *touch, const int *crp, int *slot, int *seglen, int *segsrc,
+                           int *segrow) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= rows) return;
+  int s = -1, t = crp[i], beg = 0, id = 0;
+  const int e1 = rp[i + 1];
+  for (int e = rp[i]; e <= e1; ++e) {
+    const int sc = e < e1 ? slice_of(cb, NS, ci[e], s < 0 ? 0 : s) : -2;
+    if (sc != s) {
+      if (s >= 0) {
+        seglen[id] = e - beg;
+        segsrc[id] = beg;
+        segrow[id] = i;
+        slot[id] = t++;
+      }
+      if (sc >= 0) {
+        s = sc;
+        beg = e;
+        id = touch[(size_t)s * rows + i];
+      }
+    }
+  }
+}
+
+// per segment: descriptor and the slice-major copy of its nonzeros
+__global__ void k_xs_fill2(const int *ci, const double *va, int nseg, const int *pos,
+                           const int *segsrc, const int *segrow, const int *slot, int RS,
+                           int4 *seg, XNz *xnz) {
+  const int id = blockIdx.x * blockDim.x + threadIdx.x;
+  if (id >= nseg) return;
+  const int p0 = pos[id], len = pos[id + 1] - p0, src = segsrc[id];
+  seg[id] = make_int4(segrow[id], p0, p0 + len, slot[id]);
+  for (int e = 0; e < len; ++e) {
+    XNz z;
+    z.v = va[src + e];
+    z.off = ci[src + e] * RS * (int)sizeof(double);
+    z.pad = 0;
+    xnz[p0 + e] = z;
+  }
+}
+
+// nonzero-balanced segment ranges of the nbs workgroups of each slice
+__global__ void k_xs_part(const int *touch, int rows, int NS, int nseg, const int *pos, int nbs,
+                          int *spart) {
+  const int id = blockIdx.x * blockDim.x + threadIdx.x;
+  if (id >= NS * (nbs + 1)) return;
+  const int s = id / (nbs + 1), q = id % (nbs + 1);
+  const int a = touch[(size_t)s * rows];
+  const int z = s + 1 < NS ? touch[(size_t)(s + 1) * rows] : nseg;
+  if (q == nbs) { spart[id] = z; return; }
+  const long long lo_nz = pos[a], hi_nz = pos[z];
+  const long long target = lo_nz + (hi_nz - lo_nz) * q / nbs;
+  int lo = a, hi = z;
+  while (lo < hi) {
+    const int mid = (lo + hi) >> 1;
+    if ((long long)pos[mid] < target) lo = mid + 1; else hi = mid;
+  }
+  spart[id] = lo;
+}
+
+void launch_xs_count(const int *rp, const int *ci, int rows, int NS, const int *cb, int *touch,
+                     int *rowcnt, int *err, hipStream_t st) {
+  hipLaunchKernelGGL(k_xs_count, dim3((rows + 255) / 256), dim3(256), 0, st, rp, ci, rows, NS, cb,
+                     touch, rowcnt, err);
+}
+void launch_xs_fill1(const int *rp, const int *ci, int rows, int NS, const int *cb,
+                     const int *touch, const int *crp, int *slot, int *seglen, int *segsrc,
+                     int *segrow, hipStream_t st) {
+  hipLaunchKernelGGL(k_xs_fill1, dim3((rows + 255) / 256), dim3(256), 0, st, rp, ci, rows, NS, cb,
+                     touch, crp, slot, seglen, segsrc, segrow);
+}
+void launch_xs_fill2(const int *ci, const double *va, int nseg, const int *pos, const int *segsrc,
+                     const int *segrow, const int *slot, int RS, int4 *seg, XNz *xnz,
+                     hipStream_t st) {
+  hipLaunchKernelGGL(k_xs_fill2, dim3((nseg + 255) / 256), dim3(256), 0, st, ci, va, nseg, pos,
+                     segsrc, segrow, slot, RS, seg, xnz);
+}
+void launch_xs_part(const int *touch, int rows, int NS, int nseg, const int *pos, int nbs,
+                    int *spart, hipStream_t st) {
+  const int tot = NS * (nbs + 1);
+  hipLaunchKernelGGL(k_xs_part, dim3((tot + 255) / 256), dim3(256), 0, st, touch, rows, NS, nseg,
+                     pos, nbs, spart);
+}
+
+// ---------------------------------------------------------------------------
 // B(k): w~_{k+1} = w - sum_j h_jk w~_j sigw_j for every right-hand side, with
 // ||w~_{k+1}||^2 and the Gram entries <w~_{k+1}, w~_j>.  Thread t always works
 // on right-hand side t % RS (kWG is a multiple of RS).
@@ -301,13 +577,25 @@ __global__ void __launch_bounds__(kWG) k_gpupdate(Grp G, int k) {
 // ---------------------------------------------------------------------------
 // host-side launchers
 // ---------------------------------------------------------------------------
+template <int RS, bool ISA>
+static void launch_product(const Grp &G, int k, hipStream_t st) {
+  if (G.sliced) {
+    const XOp &X = ISA ? G.xa : G.xb;
+    hipLaunchKernelGGL((k_gspmm_x<RS, ISA>), dim3(X.NS * X.nbs), dim3(kGWG), 0, st, G, X.seg,
+                       X.spart, X.nz, k);
+    hipLaunchKernelGGL((k_gcombine<RS, ISA>), dim3(G.nwv), dim3(kWG), 0, st, G, k);
+  } else {
+    hipLaunchKernelGGL((k_gspmm<RS, ISA>), dim3(G.nws), dim3(kGWG), 0, st, G, k);
+  }
+}
+
 template <int RS>
 static void launch_group_rs(const Grp &G, int stage, int k, hipStream_t st) {
   const dim3 fin(G.R), fb(kWG);
   switch (stage) {
     case kStageA:
       hipLaunchKernelGGL(k_gfinish<kStageA>, fin, fb, 0, st, G, k);
-      hipLaunchKernelGGL((k_gspmm<RS, true>), dim3(G.nws), dim3(kGWG), 0, st, G, k);
+      launch_product<RS, true>(G, k, st);
       break;
     case kStageB:
       hipLaunchKernelGGL(k_gfinish<kStageB>, fin, fb, 0, st, G, k);
@@ -315,7 +603,7 @@ static void launch_group_rs(const Grp &G, int stage, int k, hipStream_t st) {
       break;
     case kStageC:
       hipLaunchKernelGGL(k_gfinish<kStageC>, fin, fb, 0, st, G, k);
-      hipLaunchKernelGGL((k_gspmm<RS, false>), dim3(G.nws), dim3(kGWG), 0, st, G, k);
+      launch_product<RS, false>(G, k, st);
       break;
     default:
       hipLaunchKernelGGL(k_gfinish<kStageD>, fin, fb, 0, st, G, k);
@@ -332,6 +620,19 @@ void launch_group_stage(const Grp &G, int stage, int k, hipStream_t st) {
     case 32: launch_group_rs<32>(G, stage, k, st); break;
     default: launch_group_rs<64>(G, stage, k, st); break;
   }
+}
+
+// resident sliced-SpMM workgroups per CU for interleave width RS
+int gspmm_x_blocks_per_cu(int RS) {
+  int nb = 0;
+  hipError_t e;
+  switch (RS) {
+    case 8: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_gspmm_x<8, true>, kGWG, 0); break;
+    case 16: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_gspmm_x<16, true>, kGWG, 0); break;
+    case 32: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_gspmm_x<32, true>, kGWG, 0); break;
+    default: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_gspmm_x<64, true>, kGWG, 0); break;
+  }
+  return (e == hipSuccess && nb > 0) ? nb : 1;
 }
 
 // resident SpMM workgroups per CU for interleave width RS

@@ -27,6 +27,7 @@ available; these are the stand-ins):
 from __future__ import annotations
 
 import dataclasses
+import functools
 import math
 
 import numpy as np
@@ -53,6 +54,7 @@ def geometry_for_side(side: int) -> tuple[int, int]:
     return int(round(0.7 * side)), int(math.ceil(math.sqrt(2.0) * side))
 
 
+@functools.lru_cache(maxsize=8)
 def siddon_matrix(N: int, n_angles: int, n_det: int, chunk_rays: int = 16384) -> sp.csr_matrix:
     """Exact ray/pixel intersection lengths, CSR (m = n_angles * n_det, n = N * N).
 
@@ -124,6 +126,7 @@ def siddon_matrix(N: int, n_angles: int, n_det: int, chunk_rays: int = 16384) ->
     return _as_int32_csr(A)
 
 
+@functools.lru_cache(maxsize=4)
 def pixel_driven_backprojector(N: int, n_angles: int, n_det: int) -> sp.csr_matrix:
     """Unmatched back-projector B (n x m), linear interpolation between bins."""
     n = N * N
@@ -275,7 +278,8 @@ def workload(name: str) -> Problem:
 
 def batch_instances(count: int = 32, sides=(128, 192, 256, 384), seed: int = 4,
                     max_side: int | None = None) -> list[Problem]:
-    """Heterogeneous batch: sides drawn uniformly, own phantom, noise U[0.5%, 3%]."""
+    """Heterogeneous batch: sides drawn uniformly, own phantom, noise U[0.5%, 3%].
+    Instances of equal side share the (cached, read-only) projection matrix."""
     rng = np.random.default_rng(SEED_PHANTOM + seed)
     out = []
     for i in range(count):

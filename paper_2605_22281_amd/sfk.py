@@ -89,6 +89,7 @@ def lib() -> ctypes.CDLL:
         "sfk_batch_size": (I32, [P]),
         "sfk_instance_status": (I32, [P, I32, PI32, PI32, PI32]),
         "sfk_instance_solution": (I32, [P, I32, P]),
+        "sfk_instance_solution_at": (I32, [P, I32, I32, P]),
         "sfk_instance_residual_norms": (I32, [P, I32, PD, I32, PI32, PD]),
         "sfk_instance_true_residual": (I32, [P, I32, PD]),
         "sfk_init_multi": (I32, [ctypes.POINTER(P), PCSR, PCSR, P, I32, PPAR, P]),
@@ -108,7 +109,8 @@ def exported_symbols() -> list[str]:
             "sfk_destroy", "sfk_last_error", "sfk_sketch_sparse_sign", "sfk_sketch_srht",
             "sfk_coefficients", "sfk_version", "sfk_set_timing", "sfk_stage_times",
             "sfk_init_batch", "sfk_batch_size", "sfk_instance_status", "sfk_instance_solution",
-            "sfk_instance_residual_norms", "sfk_instance_true_residual", "sfk_init_multi"]
+            "sfk_instance_residual_norms", "sfk_instance_true_residual", "sfk_init_multi",
+            "sfk_instance_solution_at"]
 
 
 def _check(status: int, ctx=None):
@@ -395,6 +397,13 @@ def instance_solution(ctx, i: int, n: int, out=None):
     import torch
     x = out if out is not None else torch.empty(n, dtype=torch.float64, device="cuda")
     _check(lib().sfk_instance_solution(ctx.handle, i, x.data_ptr()), ctx.handle)
+    return x
+
+
+def instance_solution_at(ctx, i: int, j: int, n: int, out=None):
+    import torch
+    x = out if out is not None else torch.empty(n, dtype=torch.float64, device="cuda")
+    _check(lib().sfk_instance_solution_at(ctx.handle, i, j, x.data_ptr()), ctx.handle)
     return x
 
 

@@ -204,3 +204,28 @@ def test_shared_operator_ct256_32_rhs():
         worst = max(worst, e)
         assert e <= 1e-8, (r, e)
     say(f"ct256 32 rhs vs plain runs at k=10: worst rel {worst:.2e}")
+
+
+def test_shared_operator_row_kernel_matches_sliced():
+    """The row kernel on the caller's CSR arrays (vw != 0) and the column-sliced
+    products give the same iterates (both checked against the oracle)."""
+    from paper_2605_22281_amd import sfk
+    say("case: shared operator, row kernel vs sliced products")
+    P = _problem(24, True, 92)
+    R = 12
+    b, _, _ = inputs.multi_rhs(P, R, seed=14)
+    A = sfk.to_device_csr(P.A)
+    B = sfk.to_device_csr(P.B)
+    bb = torch.from_numpy(np.ascontiguousarray(b)).cuda()
+    xs = {}
+    for vw in (0, -1):
+        ps = [sfk.params("sflsmr", maxit=MAXIT, sketch="sparse_sign", s=90, seed=300 + r, vw=vw)
+              for r in range(R)]
+        ctx = sfk.init_multi(A, B, bb, ps)
+        sfk.iterate(ctx, MAXIT)
+        xs[vw] = [sfk.instance_solution(ctx, r, P.n).cpu().numpy() for r in range(R)]
+    for r in range(R):
+        S = sketches.SparseSign(P.n, 90, 8, 300 + r)
+        orc = fgk.sketched_flexible(P.A, b[r], S, method="sflsmr", B=P.B, maxit=MAXIT, ell=2)
+        assert rel(xs[0][r], orc.x) <= 1e-8 and rel(xs[-1][r], orc.x) <= 1e-8, r
+        assert rel(xs[0][r], xs[-1][r]) <= 1e-10, r
