@@ -43,15 +43,16 @@ void launch_true_residual(const Dev &D, const double *x, double *out, hipStream_
 void launch_group_stage(const Grp &G, int stage, int k, hipStream_t st);
 int gspmm_blocks_per_cu(int RS);
 int gspmm_x_blocks_per_cu(int RS);
+int gspmm_x_units_per_block(int RS);
 void launch_scan(int *a, int len, hipStream_t st);
 void launch_xs_count(const int *rp, const int *ci, int rows, int NS, const int *cb, int *touch,
                      int *rowcnt, int *err, hipStream_t st);
 void launch_xs_fill1(const int *rp, const int *ci, int rows, int NS, const int *cb,
                      const int *touch, const int *crp, int *slot, int *seglen, int *segsrc,
-                     int *segrow, hipStream_t st);
+                     int *segrow, int *segcnt, hipStream_t st);
 void launch_xs_fill2(const int *ci, const double *va, int nseg, const int *pos, const int *segsrc,
-                     const int *segrow, const int *slot, int RS, int4 *seg, XNz *xnz,
-                     hipStream_t st);
+                     const int *segrow, const int *segcnt, const int *slot, int RS, int4 *seg,
+                     XNz *xnz, hipStream_t st);
 void launch_xs_part(const int *touch, int rows, int NS, int nseg, const int *pos, int nbs,
                     int *spart, hipStream_t st);
 }  // namespace sfk
@@ -828,11 +829,13 @@ static sfk_status build_xop(sfk_ctx *c, XOp &X, const int *rp, const int *ci, co
   const int64_t cps = std::max<int64_t>(1, (int64_t)(2 << 20) / (RS * (int64_t)sizeof(double)));
   const int64_t per = (int64_t)kXcds * cps;
   const int NS = (int)(kXcds * std::max<int64_t>(1, (cols + per - 1) / per));
-  if ((int64_t)NS * rows + 1 >= (1ll << 31) || nnz + kXPad >= (1ll << 31) ||
+  if ((int64_t)NS * rows + 1 >= (1ll << 31) || nnz * 4 + kXPad >= (1ll << 31) ||
+      (int64_t)NS * cus * 64 * 16 >= (1ll << 31) ||
       (int64_t)cols * RS * (int64_t)sizeof(double) >= (1ll << 31))
     return SFK_OK;
 
   const int nbs = std::max(1, cus * gspmm_x_blocks_per_cu(RS) / kXcds);
+  const int upb = gspmm_x_units_per_block(RS);     // lane groups per workgroup
   Layout L1;
   const size_t o_cb = L1.take<int>(NS + 1);
   const size_t o_touch = L1.take<int>((size_t)NS * rows + 1);
@@ -867,8 +870,10 @@ static sfk_status build_xop(sfk_ctx *c, XOp &X, const int *rp, const int *ci, co
   if (nseg <= 0) return SFK_OK;       // no nonzeros: keep the row kernel
   Layout L2;
   const size_t o_seg = L2.take<int4>(std::max(nseg, 1));
-  const size_t o_spart = L2.take<int>((size_t)NS * (nbs + 1));
-  const size_t o_nz = L2.take<XNz>(nnz + kXPad);
+  const size_t o_spart = L2.take<int>((size_t)NS * ((size_t)nbs * upb + 1));
+  // each segment grows by at most kSegAlign - 1 padding nonzeros
+  const int64_t nzcap = nnz + (int64_t)nseg * (kSegAlign - 1) + kXPad;
+  const size_t o_nz = L2.take<XNz>(nzcap);
   const size_t o_part = L2.take<double>((size_t)std::max(nseg, 1) * RS);
   void *mem = nullptr;
   HIPCHK(c, hipMalloc(&mem, L2.off));
@@ -878,21 +883,26 @@ static sfk_status build_xop(sfk_ctx *c, XOp &X, const int *rp, const int *ci, co
   const size_t o_src = L3.take<int>(std::max(nseg, 1));
   const size_t o_row = L3.take<int>(std::max(nseg, 1));
   const size_t o_slot = L3.take<int>(std::max(nseg, 1));
+  const size_t o_cnt = L3.take<int>(std::max(nseg, 1));
   void *scr2 = nullptr;
   HIPCHK(c, hipMalloc(&scr2, L3.off));
   Guard g2{scr2};
   HIPCHK(c, hipMemsetAsync(mem, 0, L2.off, st));
   HIPCHK(c, hipMemsetAsync(scr2, 0, L3.off, st));
   int *seglen = at<int>(scr2, o_len), *segsrc = at<int>(scr2, o_src), *segrow = at<int>(scr2, o_row);
-  int *slot = at<int>(scr2, o_slot);
-  launch_xs_fill1(rp, ci, rows, NS, cb, touch, crp, slot, seglen, segsrc, segrow, st);
+  int *slot = at<int>(scr2, o_slot), *segcnt = at<int>(scr2, o_cnt);
+  launch_xs_fill1(rp, ci, rows, NS, cb, touch, crp, slot, seglen, segsrc, segrow, segcnt, st);
   launch_scan(seglen, nseg + 1, st);
-  launch_xs_fill2(ci, va, nseg, seglen, segsrc, segrow, slot, RS, at<int4>(mem, o_seg),
+  int nzpad = 0;      // nonzeros of the padded copy
+  HIPCHK(c, hipMemcpyAsync(&nzpad, seglen + nseg, sizeof(int), hipMemcpyDeviceToHost, st));
+  HIPCHK(c, hipStreamSynchronize(st));
+  if ((int64_t)nzpad + kXPad > nzcap) return fail(c, SFK_EDEVICE, "sliced copy larger than planned");
+  launch_xs_fill2(ci, va, nseg, seglen, segsrc, segrow, segcnt, slot, RS, at<int4>(mem, o_seg),
                   at<XNz>(mem, o_nz), st);
-  launch_xs_part(touch, rows, NS, nseg, seglen, nbs, at<int>(mem, o_spart), st);
+  launch_xs_part(touch, rows, NS, nseg, seglen, nbs * upb, at<int>(mem, o_spart), st);
   HIPCHK(c, hipGetLastError());
   HIPCHK(c, hipStreamSynchronize(st));
-  X.rows = rows; X.cols = cols; X.NS = NS; X.nbs = nbs; X.nseg = nseg;
+  X.rows = rows; X.cols = cols; X.NS = NS; X.nbs = nbs; X.nseg = nseg; X.upb = upb;
   X.seg = at<int4>(mem, o_seg);
   X.spart = at<int>(mem, o_spart);
   X.nz = at<XNz>(mem, o_nz);

@@ -112,6 +112,8 @@ constexpr int kCoefStride = 16;            // >= kMaxEll + 2
 constexpr int kMaxRhs = 64;
 constexpr int kXPad = 256;                 // tail padding of the sliced nonzero copy
 constexpr int kXcds = 8;                   // L2 domains; workgroup b runs on domain b % 8
+constexpr int kSegAlign = 4;               // segments of the sliced copy padded to this many nonzeros
+constexpr int kXPadOff = 0x7fffff00;       // offset of a padding nonzero: past any source block
 
 // Column-sliced copy of one operator for the shared-operator products.  The
 // columns are cut into NS ranges (a multiple of kXcds, each small enough that
@@ -130,8 +132,10 @@ struct alignas(16) XNz {
 
 struct XOp {
   int rows, cols, NS, nbs, nseg;
-  const int4 *seg;      // nseg: (row, first, end, slot) into nz; slice-major, rows ascending
-  const int *spart;     // NS * (nbs + 1): segment range of each workgroup of a slice
+  int upb;              // work units per workgroup (one per lane group of a wave)
+  const int4 *seg;      // nseg: (row, first, end, slot) into nz, end - first a multiple of
+                        // kSegAlign (padding: value 0, offset kXPadOff); slice-major, rows ascending
+  const int *spart;     // NS * (nbs * upb + 1): segment range of each work unit of a slice
   const XNz *nz;        // nnz + kXPad (padding: value 0, offset 0)
   const int *crp;       // rows + 1
   double *part;         // nseg * RS, slot-major

@@ -231,86 +231,114 @@ __device__ __forceinline__ int row_bcast_i(int x, int i) {
   }
 }
 
+template <int LPR>
+__device__ __forceinline__ int group_bcast(int x, int i) {
+  if (LPR == 16) return row_bcast_i(x, i);
+  return __builtin_amdgcn_ds_bpermute(((threadIdx.x & 63) / LPR * LPR + i) * 4, x);
+}
+
+// Each lane group (LPR lanes, two right-hand sides per lane) streams its own
+// contiguous range of whole segments, one nonzero per wave step: its lanes
+// load the group's next LPR records with one load, a cross-lane broadcast
+// hands step i the record of lane i of the group, U gathers are in flight at
+// once, and when a segment ends the group stores its sums to the segment's
+// partial slot (no reduction across lanes).
 template <int RS, bool ISA>
 __global__ void __launch_bounds__(kGWG) k_gspmm_x(Grp G, const int4 *__restrict__ segs,
                                                  const int *__restrict__ spart,
                                                  const XNz *__restrict__ nz, int k) {
-  constexpr int LPR = RS / 2;          // lanes per nonzero (two right-hand sides per lane)
-  constexpr int NPS = 64 / LPR;        // nonzeros per wave step
-  constexpr int NSTEP = 64 / NPS;      // wave steps per chunk of 64 records
-  constexpr int U = 4;                 // wave steps per unrolled block
-  constexpr bool BC = LPR == 16;       // a nonzero group is a DPP row
+  constexpr int LPR = RS / 2;          // lanes per group = records per chunk
+  constexpr int NPS = 64 / LPR;        // groups per wave
   constexpr int NWV = kGWG / 64;
-  static_assert(64 <= kXPad, "padding of the sliced copy too small");
+  constexpr int U = 4;                 // gathers in flight per lane
+  static_assert(LPR % U == 0 && LPR <= kXPad && U == kSegAlign, "chunk layout");
   __shared__ int s_any;
   if (!any_active(G, &s_any)) return;
   const XOp &X = ISA ? G.xa : G.xb;
   const int lane = threadIdx.x & 63;
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int g = lane / LPR;
-  const int j2 = (lane % LPR) * 2;
-  // record of a chunk that this lane loads: wave step i of group g uses record
-  // i * NPS + g, held by lane 16 g + i (row broadcast) or by lane i * NPS + g
-  const int rl = BC ? (lane & 15) * NPS + (lane >> 4) : lane;
+  const int g = lane / LPR, li = lane % LPR;
+  const int j2 = li * 2;
   const int per_phase = kXcds * X.nbs;
   const int b = blockIdx.x;
   const int sl = kXcds * (b / per_phase) + b % kXcds;
   const int q = (b % per_phase) / kXcds;
-  const int t0 = spart[sl * (X.nbs + 1) + q], t1 = spart[sl * (X.nbs + 1) + q + 1];
-  // the source block as a buffer: 32-bit offsets, reads past its end return 0
+  const int* up = spart + (size_t)sl * (X.nbs * X.upb + 1) + (q * NWV + wv) * NPS + g;
+  const int sA = up[0], sB = up[1];
+  // group state: next record, end of its range, current segment (end, slot)
+  // and the following one, prefetched
+  int rec = 0, rend = 0, ci = sA, cend = -1, cslot = 0, nend = -1, nslot = 0;
+  if (sA < sB) {
+    const int4 d0 = segs[sA];
+    rec = d0.y;
+    cend = d0.z;
+    cslot = d0.w;
+    rend = segs[sB - 1].z;
+    if (sA + 1 < sB) {
+      const int4 d1 = segs[sA + 1];
+      nend = d1.z;
+      nslot = d1.w;
+    }
+  }
+  int steps = rend - rec;
+#pragma unroll
+  for (int o = LPR; o < 64; o <<= 1) steps = max(steps, __shfl_xor(steps, o, 64));
+  steps = __builtin_amdgcn_readfirstlane(steps);
   const double *xbase = ISA ? gzcol(G, k - 1) : gwvec(G, k + 1);
   const int xbytes = X.cols * RS * (int)sizeof(double);
   const __amdgpu_buffer_rsrc_t xr =
       __builtin_amdgcn_make_buffer_rsrc(const_cast<double *>(xbase), (short)0, xbytes, 0x00020000);
   const int loff = j2 * (int)sizeof(double);
-  for (int t = t0 + wv; t < t1; t += NWV) {
-    const int4 sg = segs[t];
-    const int end = sg.z;
-    double ax[U], ay[U];
+  double sx = 0.0, sy = 0.0;
+  // records of the next chunk are loaded one chunk ahead; a group whose range
+  // has ended reads record li (valid, value masked)
+  XNz zn = nz[rec < rend ? rec + li : li];             // < rend + LPR <= nnz + kXPad
+  for (int c0 = 0; c0 < steps; c0 += LPR) {
+    const int cr = rec + c0;
+    const XNz z = zn;
+    zn = nz[cr + LPR < rend ? cr + LPR + li : li];
+    const int zo = z.off;
+    const int zl = __double2loint(z.v), zh = __double2hiint(z.v);
 #pragma unroll
-    for (int u = 0; u < U; ++u) ax[u] = ay[u] = 0.0;
-    for (int cb = sg.y; cb < end; cb += 64) {
-      // one coalesced load of 64 records; past the segment's end they belong to
-      // the next segment or the padding (valid offsets, values masked below)
-      const XNz z = nz[cb + rl];               // < end + 64 <= nnz + kXPad
-      const int zo = z.off;
-      const int zl = __double2loint(z.v), zh = __double2hiint(z.v);
-      const int rem = end - cb;
+    for (int i0 = 0; i0 < LPR; i0 += U) {
+      if (c0 + i0 < steps) {
+        int off[U];
+        double v[U];
+        double2 xv[U];
 #pragma unroll
-      for (int i0 = 0; i0 < NSTEP; i0 += U) {
-        if (i0 * NPS < rem) {
+        for (int u = 0; u < U; ++u) {
+          const int i = i0 + u;
+          off[u] = group_bcast<LPR>(zo, i);
+          const double vv = __hiloint2double(group_bcast<LPR>(zh, i), group_bcast<LPR>(zl, i));
+          v[u] = cr + i < rend ? vv : 0.0;
+        }
 #pragma unroll
-          for (int u = 0; u < U; ++u) {
-            const int i = i0 + u;
-            int off, vl, vh;
-            if (BC) {
-              off = row_bcast_i(zo, i);
-              vl = row_bcast_i(zl, i);
-              vh = row_bcast_i(zh, i);
-            } else {
-              const int src = (i * NPS + g) * 4;
-              off = __builtin_amdgcn_ds_bpermute(src, zo);
-              vl = __builtin_amdgcn_ds_bpermute(src, zl);
-              vh = __builtin_amdgcn_ds_bpermute(src, zh);
-            }
-            const double v = (i * NPS + g < rem) ? __hiloint2double(vh, vl) : 0.0;
-            const auto raw = __builtin_amdgcn_raw_buffer_load_b128(xr, off + loff, 0, 0);
-            double2 xv;
-            __builtin_memcpy(&xv, &raw, sizeof xv);
-            ax[u] += v * xv.x;
-            ay[u] += v * xv.y;
+        for (int u = 0; u < U; ++u) {
+          const auto raw = __builtin_amdgcn_raw_buffer_load_b128(xr, off[u] + loff, 0, 0);
+          __builtin_memcpy(&xv[u], &raw, sizeof(double2));
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          sx += v[u] * xv[u].x;
+          sy += v[u] * xv[u].y;
+        }
+        // segments are padded to whole blocks: at most one ends here, after
+        // the block's last step
+        if (cr + i0 + U == cend) {
+          *reinterpret_cast<double2 *>(X.part + (size_t)cslot * RS + j2) = make_double2(sx, sy);
+          sx = sy = 0.0;
+          ++ci;
+          cend = nend;
+          cslot = nslot;
+          nend = -1;
+          if (ci + 1 < sB) {
+            const int4 d = segs[ci + 1];
+            nend = d.z;
+            nslot = d.w;
           }
         }
       }
     }
-    double sx = (ax[0] + ax[1]) + (ax[2] + ax[3]);
-    double sy = (ay[0] + ay[1]) + (ay[2] + ay[3]);
-#pragma unroll
-    for (int o = LPR; o < 64; o <<= 1) {
-      sx += __shfl_xor(sx, o, 64);
-      sy += __shfl_xor(sy, o, 64);
-    }
-    if (g == 0) *reinterpret_cast<double2 *>(X.part + (size_t)sg.w * RS + j2) = make_double2(sx, sy);
   }
 }
 
@@ -341,10 +369,16 @@ __global__ void __launch_bounds__(kWG) k_gcombine(Grp G, int k) {
   const size_t e1 = (size_t)i1 * RS;
   for (size_t e = (size_t)i0 * RS + threadIdx.x; e < e1; e += kWG) {
     const int i = (int)(e / RS);
-    double sum = 0.0;
     const double *pr = X.part + (size_t)X.crp[i] * RS + j;
     const int np = X.crp[i + 1] - X.crp[i];
-    for (int t = 0; t < np; ++t) sum += pr[(size_t)t * RS];
+    double sum = 0.0;
+    for (int t = 0; t < np; t += 4) {      // four independent loads, summed in slice order
+      const double p0 = pr[(size_t)t * RS];
+      const double p1 = t + 1 < np ? pr[(size_t)(t + 1) * RS] : 0.0;
+      const double p2 = t + 2 < np ? pr[(size_t)(t + 2) * RS] : 0.0;
+      const double p3 = t + 3 < np ? pr[(size_t)(t + 3) * RS] : 0.0;
+      sum = (((sum + p0) + p1) + p2) + p3;
+    }
     const double y = sum * scale;
     if (on) yout[e] = y;
 #pragma unroll
@@ -391,7 +425,7 @@ __global__ void k_xs_count(const int *rp, const int *ci, int rows, int NS, const
 // and the row-major slot of its partial
 __global__ void k_xs_fill1(const int *rp, const int *ci, int rows, int NS, const int *cb,
                            const int *touch, const int *crp, int *slot, int *seglen, int *segsrc,
-                           int *segrow) {
+                           int *segrow, int *segcnt) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= rows) return;
   int s = -1, t = crp[i], beg = 0, id = 0;
@@ -400,7 +434,8 @@ __global__ void k_xs_fill1(const int *rp, const int *ci, int rows, int NS, const
     const int sc = e < e1 ? slice_of(cb, NS, ci[e], s < 0 ? 0 : s) : -2;
     if (sc != s) {
       if (s >= 0) {
-        seglen[id] = e - beg;
+        seglen[id] = (e - beg + kSegAlign - 1) / kSegAlign * kSegAlign;
+        segcnt[id] = e - beg;
         segsrc[id] = beg;
         segrow[id] = i;
         slot[id] = t++;
@@ -416,22 +451,22 @@ __global__ void k_xs_fill1(const int *rp, const int *ci, int rows, int NS, const
 
 // per segment: descriptor and the slice-major copy of its nonzeros
 __global__ void k_xs_fill2(const int *ci, const double *va, int nseg, const int *pos,
-                           const int *segsrc, const int *segrow, const int *slot, int RS,
-                           int4 *seg, XNz *xnz) {
+                           const int *segsrc, const int *segrow, const int *segcnt,
+                           const int *slot, int RS, int4 *seg, XNz *xnz) {
   const int id = blockIdx.x * blockDim.x + threadIdx.x;
   if (id >= nseg) return;
-  const int p0 = pos[id], len = pos[id + 1] - p0, src = segsrc[id];
+  const int p0 = pos[id], len = pos[id + 1] - p0, cnt = segcnt[id], src = segsrc[id];
   seg[id] = make_int4(segrow[id], p0, p0 + len, slot[id]);
   for (int e = 0; e < len; ++e) {
     XNz z;
-    z.v = va[src + e];
-    z.off = ci[src + e] * RS * (int)sizeof(double);
+    z.v = e < cnt ? va[src + e] : 0.0;
+    z.off = e < cnt ? ci[src + e] * RS * (int)sizeof(double) : kXPadOff;
     z.pad = 0;
     xnz[p0 + e] = z;
   }
 }
 
-// nonzero-balanced segment ranges of the nbs workgroups of each slice
+// nonzero-balanced segment ranges of the nbs work units of each slice
 __global__ void k_xs_part(const int *touch, int rows, int NS, int nseg, const int *pos, int nbs,
                           int *spart) {
   const int id = blockIdx.x * blockDim.x + threadIdx.x;
@@ -457,15 +492,15 @@ void launch_xs_count(const int *rp, const int *ci, int rows, int NS, const int *
 }
 void launch_xs_fill1(const int *rp, const int *ci, int rows, int NS, const int *cb,
                      const int *touch, const int *crp, int *slot, int *seglen, int *segsrc,
-                     int *segrow, hipStream_t st) {
+                     int *segrow, int *segcnt, hipStream_t st) {
   hipLaunchKernelGGL(k_xs_fill1, dim3((rows + 255) / 256), dim3(256), 0, st, rp, ci, rows, NS, cb,
-                     touch, crp, slot, seglen, segsrc, segrow);
+                     touch, crp, slot, seglen, segsrc, segrow, segcnt);
 }
 void launch_xs_fill2(const int *ci, const double *va, int nseg, const int *pos, const int *segsrc,
-                     const int *segrow, const int *slot, int RS, int4 *seg, XNz *xnz,
-                     hipStream_t st) {
+                     const int *segrow, const int *segcnt, const int *slot, int RS, int4 *seg,
+                     XNz *xnz, hipStream_t st) {
   hipLaunchKernelGGL(k_xs_fill2, dim3((nseg + 255) / 256), dim3(256), 0, st, ci, va, nseg, pos,
-                     segsrc, segrow, slot, RS, seg, xnz);
+                     segsrc, segrow, segcnt, slot, RS, seg, xnz);
 }
 void launch_xs_part(const int *touch, int rows, int NS, int nseg, const int *pos, int nbs,
                     int *spart, hipStream_t st) {
@@ -621,6 +656,9 @@ void launch_group_stage(const Grp &G, int stage, int k, hipStream_t st) {
     default: launch_group_rs<64>(G, stage, k, st); break;
   }
 }
+
+// lane groups (work units) of one sliced-SpMM workgroup
+int gspmm_x_units_per_block(int RS) { return (kGWG / 64) * (64 / (RS / 2)); }
 
 // resident sliced-SpMM workgroups per CU for interleave width RS
 int gspmm_x_blocks_per_cu(int RS) {
