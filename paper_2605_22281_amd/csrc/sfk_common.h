@@ -56,7 +56,7 @@ __device__ __forceinline__ int producers(const Dev &D, int stage) {
 // Totals of the Q partial sums that the previous stage left, in a fixed order
 // (every workgroup obtains identical values).
 template <int NT>
-__device__ void consume(const Dev &D, int stage, int Q, double *lds_w, double *tot) {
+__device__ __forceinline__ void consume(const Dev &D, int stage, int Q, double *lds_w, double *tot) {
   const double *p = part_of(D, stage);
   const int np = producers(D, stage);
   double acc[kMaxQ];
@@ -71,7 +71,7 @@ __device__ void consume(const Dev &D, int stage, int Q, double *lds_w, double *t
 }
 
 template <int NT>
-__device__ void produce(const Dev &D, int stage, int wid, int Q, const double (&acc)[kMaxQ],
+__device__ __forceinline__ void produce(const Dev &D, int stage, int wid, int Q, const double (&acc)[kMaxQ],
                         double *lds_w, double *blk) {
   block_sum<NT>(acc, Q, lds_w, blk);
   if (threadIdx.x < Q) part_of(D, stage)[(size_t)threadIdx.x * D.nwmax + wid] = blk[threadIdx.x];
