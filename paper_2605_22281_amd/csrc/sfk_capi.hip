@@ -45,6 +45,7 @@ int gspmm_blocks_per_cu(int RS);
 int gspmm_x_blocks_per_cu(int RS);
 int gspmm_x_units_per_block(int RS);
 void launch_scan(int *a, int len, hipStream_t st);
+void launch_collect_halt(const Launch &L, int k, int *out, hipStream_t st);
 void launch_xs_count(const int *rp, const int *ci, int rows, int NS, const int *cb, int *touch,
                      int *rowcnt, int *err, hipStream_t st);
 void launch_xs_fill1(const int *rp, const int *ci, int rows, int NS, const int *cb,
@@ -84,6 +85,12 @@ struct sfk_ctx {
   void *hdr = nullptr;              // device: instance descriptors and block maps
   Launch L{};
   Scal *h_scal = nullptr;           // pinned copies of the device scalars
+  // early exit of long iterate() calls: the run state of every instance is
+  // copied back after each batch of iterations (side stream, pinned memory)
+  static constexpr int kChkSlots = 2;
+  int *d_halt = nullptr;            // device, kChkSlots * ninst
+  int *h_halt = nullptr;            // pinned, kChkSlots * ninst
+  hipEvent_t ev_chk[kChkSlots] = {};
   int k_iter = 0;                   // lockstep iterations launched
   int maxitmax = 0;
   bool sketch_after_C = false;      // an sFLSMR instance sketches B w_{k+1}
@@ -673,6 +680,11 @@ static sfk_status build_launch(sfk_ctx *c) {
 
 static sfk_status create_streams(sfk_ctx *c, int nb) {
   HIPCHK(c, hipHostMalloc((void **)&c->h_scal, sizeof(Scal) * nb, hipHostMallocDefault));
+  HIPCHK(c, hipHostMalloc((void **)&c->h_halt, sizeof(int) * sfk_ctx::kChkSlots * nb,
+                          hipHostMallocDefault));
+  HIPCHK(c, hipMalloc((void **)&c->d_halt, sizeof(int) * sfk_ctx::kChkSlots * nb));
+  for (int i = 0; i < sfk_ctx::kChkSlots; ++i)
+    HIPCHK(c, hipEventCreateWithFlags(&c->ev_chk[i], hipEventDisableTiming));
   HIPCHK(c, hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking));
   for (int i = 0; i < sfk_ctx::kRing; ++i) {
     HIPCHK(c, hipEventCreateWithFlags(&c->ev_main[i], hipEventDisableTiming));
@@ -713,6 +725,10 @@ static void release(sfk_ctx *c) {
     if (c->ev_ls[i]) hipEventDestroy(c->ev_ls[i]);
   }
   for (hipEvent_t e : c->ev_pool) hipEventDestroy(e);
+  for (int i = 0; i < sfk_ctx::kChkSlots; ++i)
+    if (c->ev_chk[i]) hipEventDestroy(c->ev_chk[i]);
+  if (c->d_halt) hipFree(c->d_halt);
+  if (c->h_halt) hipHostFree(c->h_halt);
   if (c->side) hipStreamDestroy(c->side);
   for (auto &I : c->inst)
     if (I.owns_ws && I.ws) hipFree(I.ws);
@@ -767,13 +783,11 @@ extern "C" sfk_status sfk_init_batch(sfk_ctx **out, int32_t nb, const sfk_csr *A
   }
   const int cus = device_cus();
   if (cus <= 0) return fail(nullptr, SFK_EDEVICE, "no HIP device available");
-  // one wave of SpMV workgroups over the whole batch, shared by nonzero count
-  const int G = cus * std::max(1, spmv_blocks_per_cu());
-  double tot = 0.0;
-  for (int i = 0; i < nb; ++i) {
-    const int64_t nz = std::max(A[i].nnz, (B && B[i].rows > 0) ? B[i].nnz : A[i].nnz);
-    tot += (double)nz;
-  }
+  // Every instance gets the row partition it would have on its own: while all
+  // instances are live the grid is oversubscribed and the hardware balances
+  // it; once some have stopped (their workgroups exit at once), the ones still
+  // running keep the whole device.
+  const int bpc = spmv_blocks_per_cu();
   sfk_ctx *c = new sfk_ctx();
   c->stream = static_cast<hipStream_t>(stream);
   c->inst.resize(nb);
@@ -781,9 +795,7 @@ extern "C" sfk_status sfk_init_batch(sfk_ctx **out, int32_t nb, const sfk_csr *A
   for (int i = 0; i < nb && s == SFK_OK; ++i) {
     c->inst[i].p = p[i];
     const sfk_csr *Bi = (B && B[i].rows > 0) ? &B[i] : nullptr;
-    const int64_t nz = std::max(A[i].nnz, Bi ? Bi->nnz : A[i].nnz);
-    int nws = (int)std::lround(G * (double)nz / std::max(tot, 1.0));
-    nws = std::max(1, std::min(nws, default_nws(&A[i], Bi, &p[i], cus, spmv_blocks_per_cu())));
+    const int nws = default_nws(&A[i], Bi, &p[i], cus, bpc);
     s = setup_instance(c, c->inst[i], &A[i], Bi, b[i], nullptr, 0, cus, nws);
     if (s != SFK_OK) c->err = "instance " + std::to_string(i) + ": " + c->err;
   }
@@ -1073,11 +1085,39 @@ extern "C" sfk_status sfk_iterate(sfk_ctx *c, int32_t k, int32_t *iters_done_hos
   const int room = c->maxitmax - c->k_iter;
   if (k > room) return fail(c, SFK_ESTATE, "capacity maxit = %d exhausted (done %d, asked %d)",
                             c->maxitmax, c->k_iter, k);
+  // Iterations are enqueued in batches.  After each batch the side stream
+  // (which runs the least-squares updates that set the stop flags) copies the
+  // run state of every instance to pinned memory; the host runs at most two
+  // batches ahead of the device and stops enqueueing once every instance has
+  // halted, so a run that stops early does not pay for the rest of k.
   const int k0 = c->k_iter;
-  for (int i = 1; i <= k; ++i) enqueue_iteration(c, k0 + i);
-  if (k > 0) HIPCHK(c, hipStreamWaitEvent(c->stream, c->ev_ls[(k0 + k) % sfk_ctx::kRing], 0));
+  constexpr int kBatch = 4;
+  int enq = 0, nbatch = 0;
+  bool all_done = false;
+  while (enq < k && !all_done) {
+    const int n = std::min(kBatch, k - enq);
+    for (int i = 1; i <= n; ++i) enqueue_iteration(c, k0 + enq + i);
+    enq += n;
+    const int slot = nbatch % sfk_ctx::kChkSlots;
+    int *dh = c->d_halt + (size_t)slot * nb;
+    int *hh = c->h_halt + (size_t)slot * nb;
+    if (nbatch >= sfk_ctx::kChkSlots) {
+      // the slot's previous batch: wait for it (the device still has the batch
+      // enqueued since then) and look at its flags
+      HIPCHK(c, hipEventSynchronize(c->ev_chk[slot]));
+      all_done = true;
+      for (int i = 0; i < nb; ++i) all_done = all_done && hh[i] != 0;
+    }
+    if (!all_done && enq < k) {
+      launch_collect_halt(c->L, k0 + enq, dh, c->side);
+      HIPCHK(c, hipMemcpyAsync(hh, dh, sizeof(int) * nb, hipMemcpyDeviceToHost, c->side));
+      HIPCHK(c, hipEventRecord(c->ev_chk[slot], c->side));
+    }
+    ++nbatch;
+  }
+  if (enq > 0) HIPCHK(c, hipStreamWaitEvent(c->stream, c->ev_ls[(k0 + enq) % sfk_ctx::kRing], 0));
   HIPCHK(c, hipGetLastError());
-  c->k_iter = k0 + k;
+  c->k_iter = k0 + enq;
   sfk_status s = read_scal(c);
   if (s != SFK_OK) return s;
   collect_stage_times(c);

@@ -933,6 +933,17 @@ __global__ void __launch_bounds__(64) k_init_rhs(Dev D) {
   if (lane == 0) sc->rhsnorm = sqrt(r2);
 }
 
+// run state of every instance after iteration k: 1 if no further iteration can
+// change it (stopped, broken down, or past its capacity)
+__global__ void k_collect_halt(const Dev *__restrict__ devs, int n, int k, int *out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const Dev &D = devs[i];
+  const Scal *sc = D.sc;
+  const int done = ld_flag(&sc->k_done);
+  out[i] = (ld_flag(&sc->halt) != 0 || ld_flag(&sc->klimit) <= done || k >= D.maxit) ? 1 : 0;
+}
+
 // ---------------------------------------------------------------------------
 // launch helpers (host side)
 // ---------------------------------------------------------------------------
@@ -1012,6 +1023,10 @@ void launch_init_b(const Dev &D, double eta, double noise, double tol_user, int 
 }
 void launch_init_rhs(const Dev &D, hipStream_t st) {
   hipLaunchKernelGGL(k_init_rhs, dim3(1), dim3(64), 0, st, D);
+}
+void launch_collect_halt(const Launch &L, int k, int *out, hipStream_t st) {
+  hipLaunchKernelGGL(k_collect_halt, dim3((L.ninst + 255) / 256), dim3(256), 0, st, L.devs, L.ninst,
+                     k, out);
 }
 void launch_scan(int *a, int len, hipStream_t st) {
   hipLaunchKernelGGL(k_scan_single, dim3(1), dim3(1024), 0, st, a, len);
