@@ -215,7 +215,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--workload", default="ct256_unmatched", choices=sorted(WORKLOADS))
     ap.add_argument("--driver", default="auto", choices=["auto", "multi", "persistent"])
-    ap.add_argument("--vw", type=int, default=0, help="SpMV variant (0 = CSR-stream)")
+    ap.add_argument("--vw", type=int, default=-2,
+                    help="SpMV kernel: -2 automatic, 0 CSR-stream, 1 SELL-64, 8..64 lanes per row")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-iters", type=int, default=40)
     ap.add_argument("--copy-calibration", action="store_true")
@@ -274,6 +275,9 @@ def main():
 
     # same work again with HIP events around every stage kernel (library stream)
     ctx = sfk.init(A, B, b, p)
+    names = {0: "CSR-stream", 1: "SELL-64", 8: "8 lanes/row", 16: "16 lanes/row",
+             32: "32 lanes/row", 64: "wave/row"}
+    spmv_kernel = {op: names.get(v, str(v)) for op, v in zip(("A", "B"), sfk.spmv_variant(ctx))}
     sfk.set_timing(ctx, True)
     sfk.iterate(ctx, K)
     times = sfk.stage_times(ctx)
@@ -316,7 +320,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": cfg["desc"], "m": P.m, "n": P.n, "nnz_A": nnzA, "nnz_B": nnzB,
                    "method": cfg["method"], "sketch": cfg["sketch"], "s": cfg["s"], "ell": ell,
-                   "driver": args.driver, "spmv_variant": args.vw},
+                   "driver": args.driver, "spmv_kernel": spmv_kernel},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "bytes_per_launch": per_launch[dom], "avg_launch_ms": stage_avg[dom]},

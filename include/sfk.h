@@ -90,14 +90,18 @@ typedef struct {
   double tol;          /* relative tolerance of the sketched stop test when the
                           discrepancy stop is off; 0 runs to maxit */
   int32_t driver;      /* sfk_driver */
-  int32_t vw;          /* SpMV variant: 0 = CSR-stream chunks, 8/16/32/64 = lanes per
+  int32_t vw;          /* SpMV kernel: -2 = automatic (SELL-64 for rows of >= 32
+                          nonzeros on average, else CSR-stream; the default),
+                          0 = CSR-stream chunks, 1 = SELL-64 copy built at init
+                          (64-row slices stored column-major), 8/16/32/64 = lanes per
                           row, -1 = lanes per row chosen from the mean row length */
   int32_t wg_per_cu;   /* data-parallel workgroups per CU; 0 = automatic */
   int32_t reserved[5];
 } sfk_params;
 
 /* Fills *p with defaults: sFLSQR, ell = 2, maxit = 50, sparse-sign s = 101, zeta = 8,
- * seed 0, tau identity, eps 1e-3, eta 1.01, no discrepancy stop, tol 0, AUTO. */
+ * seed 0, tau identity, eps 1e-3, eta 1.01, no discrepancy stop, tol 0, AUTO,
+ * vw -2 (automatic SpMV kernel). */
 void sfk_params_default(sfk_params *p);
 
 /* Host-only check of dimensions and parameters (no device access).  A and B
@@ -248,6 +252,12 @@ sfk_status sfk_set_timing(sfk_ctx *ctx, int32_t on);
 /* Accumulated kernel time per stage (ms_host[SFK_NUM_STAGES]) and number of
  * timed launches (count_host[SFK_NUM_STAGES]) since sfk_set_timing. */
 sfk_status sfk_stage_times(sfk_ctx *ctx, double *ms_host, int32_t *count_host);
+
+/* SpMV kernel in use for A and for B: 0 CSR-stream, 1 SELL-64, 64 a wave per
+ * row with the whole row in flight, 8/16/32 lanes per row; -2 for right-hand
+ * sides sharing A and B (column-sliced products).  A batch runs one kernel for
+ * all instances: instance 0's, or CSR-stream when the instances differ. */
+sfk_status sfk_spmv_variant(const sfk_ctx *ctx, int32_t *vwA_host, int32_t *vwB_host);
 
 /* Library and device description (static string). */
 const char *sfk_version(void);

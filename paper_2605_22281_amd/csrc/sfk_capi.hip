@@ -45,6 +45,10 @@ int gspmm_blocks_per_cu(int RS);
 int gspmm_x_blocks_per_cu(int RS);
 int gspmm_x_units_per_block(int RS);
 void launch_scan(int *a, int len, hipStream_t st);
+void launch_sell_len(const int *rp, int rows, int nsl, int *slen, hipStream_t st);
+void launch_spmv_core(const Dev &D, bool isa, int vw, const double *x, double *y, hipStream_t st);
+void launch_sell_fill(const int *rp, const int *ci, const double *va, int rows, const int *soff,
+                      const int *slen, int *scol, double *sval, hipStream_t st);
 void launch_collect_halt(const Launch &L, int k, int *out, hipStream_t st);
 void launch_xs_count(const int *rp, const int *ci, int rows, int NS, const int *cb, int *touch,
                      int *rowcnt, int *err, hipStream_t st);
@@ -229,6 +233,7 @@ extern "C" void sfk_params_default(sfk_params *p) {
   p->noise_norm = 0.0;
   p->tol = 0.0;
   p->driver = SFK_DRIVER_AUTO;
+  p->vw = -2;
 }
 
 static int64_t next_pow2(int64_t d) {
@@ -284,8 +289,9 @@ static sfk_status validate(sfk_ctx *c, const sfk_csr *A, const sfk_csr *B, const
     return fail(c, SFK_EINVAL, "noise_norm must be finite >= 0");
   if (!(p->tol >= 0.0) || !std::isfinite(p->tol)) return fail(c, SFK_EINVAL, "tol must be finite >= 0");
   if (p->driver < 0 || p->driver > 2) return fail(c, SFK_EINVAL, "unknown driver %d", p->driver);
-  if (p->vw != 0 && p->vw != -1 && p->vw != 8 && p->vw != 16 && p->vw != 32 && p->vw != 64)
-    return fail(c, SFK_EINVAL, "vw must be -1, 0, 8, 16, 32 or 64");
+  if (p->vw != -2 && p->vw != -1 && p->vw != 0 && p->vw != 1 && p->vw != 8 && p->vw != 16 &&
+      p->vw != 32 && p->vw != 64)
+    return fail(c, SFK_EINVAL, "vw must be -2, -1, 0, 1, 8, 16, 32 or 64");
   if (p->wg_per_cu < 0 || p->wg_per_cu > 64) return fail(c, SFK_EINVAL, "wg_per_cu out of range");
   return SFK_OK;
 }
@@ -320,11 +326,12 @@ struct Plan {
   size_t total;
 };
 
+// SpMV kernel codes: 0 CSR-stream, 1 SELL-64, 8/16/32/64 lanes per row
 static int pick_vw(int64_t nnz, int64_t rows, int user) {
-  if (user > 0) return user;
-  if (user == 0) return 0;     // CSR-stream
-  // user < 0: row-parallel with a width from the mean row length
   const double avg = rows > 0 ? (double)nnz / (double)rows : 0.0;
+  if (user >= 0) return user;
+  if (user == -2) return avg >= 32 ? -2 : 0;  // automatic: timed at init for long rows
+  // user == -1: row-parallel with a width from the mean row length
   if (avg >= 96) return 64;
   if (avg >= 40) return 32;
   if (avg >= 16) return 16;
@@ -453,6 +460,52 @@ static sfk_status read_scal(sfk_ctx *c) {
   return SFK_OK;
 }
 
+// SELL-64 copy of one operator (rows x cols CSR on the device), memory owned by
+// the context.  *ok = false when padding would grow the copy beyond 1.5x the
+// nonzeros (rows of very uneven length in one slice) or past 32-bit indices;
+// the CSR-stream kernel is used instead.
+static sfk_status build_sell(sfk_ctx *c, const int *rp, const int *ci, const double *va, int rows,
+                             int64_t nnz, int *nsl_out, const int **soff_out,
+                             const int **slen_out, const int **scol_out,
+                             const double **sval_out, bool *ok) {
+  // (the allocations are the last one or two entries of c->xmem)
+  hipStream_t st = c->stream;
+  *ok = false;
+  const int nsl = (rows + kSellC - 1) / kSellC;
+  void *meta = nullptr;
+  HIPCHK(c, hipMalloc(&meta, sizeof(int) * (2 * (size_t)nsl + 1)));
+  c->xmem.push_back(meta);
+  int *slen = static_cast<int *>(meta), *soff = slen + nsl;
+  launch_sell_len(rp, rows, nsl, slen, st);
+  std::vector<int> h(nsl);
+  HIPCHK(c, hipMemcpyAsync(h.data(), slen, sizeof(int) * nsl, hipMemcpyDeviceToHost, st));
+  HIPCHK(c, hipStreamSynchronize(st));
+  std::vector<int> hoff(nsl + 1);
+  int64_t tot = 0;
+  for (int q = 0; q < nsl; ++q) {
+    hoff[q] = (int)std::min<int64_t>(tot, (1ll << 31) - 1);
+    tot += (int64_t)h[q] * kSellC;
+  }
+  if (tot >= (1ll << 31) || (double)tot > 1.5 * (double)nnz + 64.0 * kSellC * kSellPad) return SFK_OK;
+  hoff[nsl] = (int)tot;
+  HIPCHK(c, hipMemcpyAsync(soff, hoff.data(), sizeof(int) * (nsl + 1), hipMemcpyHostToDevice, st));
+  void *mem = nullptr;
+  HIPCHK(c, hipMalloc(&mem, (size_t)std::max<int64_t>(tot, 1) * (sizeof(int) + sizeof(double))));
+  c->xmem.push_back(mem);
+  double *sval = static_cast<double *>(mem);
+  int *scol = reinterpret_cast<int *>(sval + std::max<int64_t>(tot, 1));
+  launch_sell_fill(rp, ci, va, rows, soff, slen, scol, sval, st);
+  HIPCHK(c, hipGetLastError());
+  HIPCHK(c, hipStreamSynchronize(st));
+  *nsl_out = nsl;
+  *soff_out = soff;
+  *slen_out = slen;
+  *scol_out = scol;
+  *sval_out = sval;
+  *ok = true;
+  return SFK_OK;
+}
+
 // Builds the instance's sketch from its seed and computes beta = ||b||, w~_1 = b
 // (Algorithm 1 / 2, first line).
 static sfk_status setup_sketch_and_b(sfk_ctx *c, Inst &I, hipStream_t st) {
@@ -526,6 +579,8 @@ static sfk_status setup_instance(sfk_ctx *c, Inst &I, const sfk_csr *A, const sf
   D.nws = P.nw;
   D.nwv = P.nw;
   D.vs = 1;
+  D.vwA = P.vwA;
+  D.vwB = P.vwB;
   D.nwmax = P.nwmax;
   D.nsg = p.sketch == SFK_SK_SPARSE_SIGN ? (p.s * 64 + kWG - 1) / kWG
         : p.sketch == SFK_SK_IDENTITY ? (p.s + kWG - 1) / kWG : 0;
@@ -601,7 +656,60 @@ static sfk_status setup_instance(sfk_ctx *c, Inst &I, const sfk_csr *A, const sf
   }
   launch_partition(D.Arp, D.m, P.nnzA, D.nws, at<int>(w, P.o_Apart), st);
   launch_partition(D.Brp, D.n, P.nnzB, D.nws, at<int>(w, P.o_Bpart), st);
-
+  // SpMV kernel per operator: an explicit choice is taken as given (SELL-64
+  // falls back to CSR-stream when its copy is refused); the automatic choice
+  // times the cores of CSR-stream, wave-per-row and SELL-64 on scratch vectors
+  // and keeps the fastest.
+  for (int op = 0; op < 2; ++op) {
+    const bool isa = op == 0;
+    int &vw = isa ? D.vwA : D.vwB;
+    if (vw != 1 && vw != -2) continue;
+    const bool tune = vw == -2;
+    const size_t mark = c->xmem.size();
+    bool ok = false;
+    sfk_status e = isa ? build_sell(c, D.Arp, D.Aci, D.Ava, D.m, P.nnzA, &D.Ansl, &D.Asoff,
+                                    &D.Aslen, &D.Ascol, &D.Asval, &ok)
+                       : build_sell(c, D.Brp, D.Bci, D.Bva, D.n, P.nnzB, &D.Bnsl, &D.Bsoff,
+                                    &D.Bslen, &D.Bscol, &D.Bsval, &ok);
+    if (e != SFK_OK) return e;
+    if (!tune) {
+      vw = ok ? 1 : 0;
+      continue;
+    }
+    // scratch (all zeros at this point): A reads Z ((maxit + 1) n >= n entries)
+    // and writes the raw A-product buffer (2 m); B reads the W ring
+    // ((ell + 2) m >= m) and writes the raw B-product buffer (>= 2 n)
+    const double *x = isa ? D.Z : D.W;
+    double *y = isa ? D.wraw : D.zraw;
+    const int cand[3] = {0, 64, 1};
+    float best = 1e30f;
+    int pick = 0;
+    hipEvent_t e0, e1;
+    HIPCHK(c, hipEventCreate(&e0));
+    HIPCHK(c, hipEventCreate(&e1));
+    for (int q = 0; q < 3; ++q) {
+      if (cand[q] == 1 && !ok) continue;
+      launch_spmv_core(D, isa, cand[q], x, y, st);          // warm-up
+      HIPCHK(c, hipEventRecord(e0, st));
+      for (int rep = 0; rep < 4; ++rep) launch_spmv_core(D, isa, cand[q], x, y, st);
+      HIPCHK(c, hipEventRecord(e1, st));
+      HIPCHK(c, hipEventSynchronize(e1));
+      float ms = 0.f;
+      HIPCHK(c, hipEventElapsedTime(&ms, e0, e1));
+      if (ms < best) { best = ms; pick = cand[q]; }
+    }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    HIPCHK(c, hipGetLastError());
+    vw = pick;
+    if (pick != 1) {          // the SELL copy lost (or was refused): release it
+      HIPCHK(c, hipStreamSynchronize(st));
+      while (c->xmem.size() > mark) {
+        hipFree(c->xmem.back());
+        c->xmem.pop_back();
+      }
+    }
+  }
   return setup_sketch_and_b(c, I, st);
 }
 // Uploads the instance descriptors and the block maps of every stage type.
@@ -673,6 +781,14 @@ static sfk_status build_launch(sfk_ctx *c) {
   L.smax = smax;
   L.maxitmax = maxitmax;
   L.tau = c->any_rew ? 1 : 0;
+  // one launch serves every instance, so all run one SpMV kernel: instance 0's
+  // when every instance has its data, else CSR-stream (valid for all)
+  L.vwA = c->inst[0].D.vwA;
+  L.vwB = c->inst[0].D.vwB;
+  for (int i = 1; i < nb; ++i) {
+    if (c->inst[i].D.vwA != L.vwA) L.vwA = 0;
+    if (c->inst[i].D.vwB != L.vwB) L.vwB = 0;
+  }
   c->maxitmax = maxitmax;
   c->grp.devs = L.devs;
   return SFK_OK;
@@ -1309,6 +1425,13 @@ extern "C" sfk_status sfk_coefficients(sfk_ctx *c, double *H_host, double *T_hos
     if (T_host) HIPCHK(c, hipMemcpy(T_host + (size_t)j * k, c->inst[0].D.T + (size_t)j * ld,
                                     sizeof(double) * k, hipMemcpyDeviceToHost));
   }
+  return SFK_OK;
+}
+
+extern "C" sfk_status sfk_spmv_variant(const sfk_ctx *c, int32_t *vwA_host, int32_t *vwB_host) {
+  if (!c) return fail(nullptr, SFK_EINVAL, "NULL context");
+  if (vwA_host) *vwA_host = c->multi ? -2 : c->L.vwA;
+  if (vwB_host) *vwB_host = c->multi ? -2 : c->L.vwB;
   return SFK_OK;
 }
 

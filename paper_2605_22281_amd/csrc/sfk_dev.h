@@ -16,6 +16,8 @@ constexpr int kRowsLDS = 2048;             // SpMV results kept in LDS for the e
 constexpr int kMaxQ = kMaxEll + 2;         // partial sums per workgroup and stage
 constexpr int kSrhtL = 2048;               // SRHT block length staged in LDS
 constexpr double kBreakdownTol = 1e-14;    // relative breakdown threshold
+constexpr int kSellC = 64;                 // rows per slice of the SELL copy (one per lane)
+constexpr int kSellPad = 4;                // slice lengths padded to a multiple of this
 
 // Partial-sum buffers, one per producing stage.
 enum Stage { kStageA = 0, kStageB = 1, kStageC = 2, kStageD = 3, kStageMisc = 4, kNumPart = 5 };
@@ -61,6 +63,12 @@ struct Dev {
   const int *Brp, *Bci; const double *Bva;
   const double *b;
   const int *Apart, *Bpart;    // nnz-balanced row ranges, nws + 1 entries each
+  // SELL-64 copies (SpMV variant 1): slice s holds rows 64 s .. 64 s + 63
+  // column-major, entry j of row 64 s + i at soff[s] + 64 j + i (padding:
+  // value 0, column 0); slen[s] is a multiple of kSellPad
+  int Ansl, Bnsl;
+  const int *Asoff, *Aslen, *Ascol; const double *Asval;
+  const int *Bsoff, *Bslen, *Bscol; const double *Bsval;
   // vectors
   double *W;          // (ell + 2) * m, unnormalised w~_j
   double *P;          // (ell + 1) * n, unnormalised p~_j (unused when tau = I)

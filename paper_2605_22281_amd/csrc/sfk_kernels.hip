@@ -130,12 +130,114 @@ __device__ void spmv_stream(const int *rp, const int *ci, const double *va, cons
 }
 
 // ---------------------------------------------------------------------------
+// Wave per row for long rows: a row of up to 64 * kRowSlots nonzeros is read
+// in one shot (all value and column loads issued, then all gathers), so a row
+// costs two dependent memory round trips and no barriers; longer rows loop.
+// ---------------------------------------------------------------------------
+constexpr int kRowSlots = 8;
+
+__device__ void spmv_rows64(const int *__restrict__ rp, const int *__restrict__ ci,
+                            const double *__restrict__ va, const double *__restrict__ xin,
+                            double *yout, double *ybuf, int r0, int r1, double scale) {
+  constexpr int NWV = kSpmvWG / 64;
+  const int lane = threadIdx.x & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  for (int r = r0 + wv; r < r1; r += NWV) {
+    const int e0 = rp[r], e1 = rp[r + 1];
+    double a0 = 0.0, a1 = 0.0;
+    for (int base = e0; base < e1; base += 64 * kRowSlots) {
+      double v[kRowSlots];
+      int c[kRowSlots];
+#pragma unroll
+      for (int u = 0; u < kRowSlots; ++u) {
+        const int e = base + u * 64 + lane;
+        const bool ok = e < e1;
+        v[u] = ok ? __builtin_nontemporal_load(va + e) : 0.0;
+        c[u] = ok ? __builtin_nontemporal_load(ci + e) : 0;
+      }
+      double xv[kRowSlots];
+#pragma unroll
+      for (int u = 0; u < kRowSlots; ++u) xv[u] = (base + u * 64 < e1) ? xin[c[u]] : 0.0;
+#pragma unroll
+      for (int u = 0; u < kRowSlots; u += 2) {
+        a0 += v[u] * xv[u];
+        a1 += v[u + 1] * xv[u + 1];
+      }
+    }
+    double sum = wave_sum(a0 + a1);
+    if (lane == 0) {
+      const double yr = sum * scale;
+      yout[r] = yr;
+      if (r - r0 < kRowsLDS) ybuf[r - r0] = yr;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// SELL-64: the workgroup takes a contiguous range of slices; for each slice the
+// 16 waves split its steps (lane i always on row 64 s + i), so at every step
+// the 64 lanes read entry j of 64 neighbouring rows: coalesced value/column
+// loads, and gathers that for neighbouring rows of a projection operator fall
+// on few cache lines.  The 16 partial sums of a row are added in LDS in wave
+// order.  Rows [r0, r1) of the workgroup are returned for the epilogue.
+// ---------------------------------------------------------------------------
+__device__ void spmv_sell(const int *__restrict__ soff, const int *__restrict__ slen,
+                          const int *__restrict__ scol, const double *__restrict__ sval,
+                          const double *__restrict__ xin, double *yout, double *ybuf, int s0,
+                          int s1, int rows, double scale, double *lds_part) {
+  constexpr int NWV = kSpmvWG / 64;
+  const int lane = threadIdx.x & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int r0 = s0 * kSellC;
+  for (int sl = s0; sl < s1; ++sl) {
+    const int len = slen[sl];
+    const int base = soff[sl];
+    // this wave's steps, a multiple of kSellPad
+    const int per = ((len + NWV - 1) / NWV + kSellPad - 1) / kSellPad * kSellPad;
+    const int j0 = min(len, wv * per), j1 = min(len, j0 + per);
+    double a0 = 0.0, a1 = 0.0;
+    for (int j = j0; j < j1; j += kSellPad) {
+      double v[kSellPad];
+      int c[kSellPad];
+#pragma unroll
+      for (int u = 0; u < kSellPad; ++u) {
+        const int e = base + (j + u) * kSellC + lane;
+        v[u] = __builtin_nontemporal_load(sval + e);
+        c[u] = __builtin_nontemporal_load(scol + e);
+      }
+      double xv[kSellPad];
+#pragma unroll
+      for (int u = 0; u < kSellPad; ++u) xv[u] = xin[c[u]];
+#pragma unroll
+      for (int u = 0; u < kSellPad; u += 2) {
+        a0 += v[u] * xv[u];
+        a1 += v[u + 1] * xv[u + 1];
+      }
+    }
+    lds_part[wv * kSellC + lane] = a0 + a1;
+    __syncthreads();
+    if (wv == 0) {
+      double sum = 0.0;
+      for (int w = 0; w < NWV; ++w) sum += lds_part[w * kSellC + lane];
+      const int r = sl * kSellC + lane;
+      if (r < rows) {
+        const double yr = sum * scale;
+        yout[r] = yr;
+        if (r - r0 < kRowsLDS) ybuf[r - r0] = yr;
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------
 // A(k) / C(k): CSR SpMV; the window dot products run as a coalesced epilogue
 // over the workgroup's rows (results staged in LDS).
 //   ISA = true : consumes D(k-1) (||p~_k||, Gram), w = sigp_k * A z~_k
 //   ISA = false: consumes B(k) (||w~_{k+1}||, Gram), z = sigw_{k+1} * B w~_{k+1}
-// VW = 0: CSR-stream (spmv_stream); VW > 0: VW lanes cooperate on a row, four
-// independent loads per lane in flight.
+// VW = 0: CSR-stream (spmv_stream); VW = 1: SELL-64 copy (spmv_sell); VW = 64:
+// a wave per row, the whole row in flight (spmv_rows64); VW = 8..32: VW lanes
+// cooperate on a row, four independent loads per lane in flight.
 // ---------------------------------------------------------------------------
 template <int VW, bool ISA>
 __global__ void __launch_bounds__(kSpmvWG, 8) k_spmv(const Dev *__restrict__ devs,
@@ -180,9 +282,26 @@ __global__ void __launch_bounds__(kSpmvWG, 8) k_spmv(const Dev *__restrict__ dev
   double *yout = ISA ? wrawk(D, k) : zrawk(D, k);
   const double scale = s_scale;
 
-  const int r0 = part[wid], r1 = part[wid + 1];
-  if (VW == 0) {
+  int r0, r1;
+  if (VW == 1) {
+    // SELL-64: the workgroup's rows are its slice range
+    const int nsl = ISA ? D.Ansl : D.Bnsl;
+    const int rows = ISA ? D.m : D.n;
+    const int s0 = (int)((long long)wid * nsl / D.nws), s1 = (int)((long long)(wid + 1) * nsl / D.nws);
+    r0 = min(rows, s0 * kSellC);
+    r1 = min(rows, s1 * kSellC);
+    __shared__ double lds_part[(kSpmvWG / 64) * kSellC];
+    spmv_sell(ISA ? D.Asoff : D.Bsoff, ISA ? D.Aslen : D.Bslen, ISA ? D.Ascol : D.Bscol,
+              ISA ? D.Asval : D.Bsval, xin, yout, ybuf, s0, s1, rows, scale, lds_part);
+  } else {
+    r0 = part[wid];
+    r1 = part[wid + 1];
+  }
+  if (VW == 1) {
+  } else if (VW == 0) {
     spmv_stream(rp, ci, va, xin, yout, ybuf, r0, r1, scale);
+  } else if (VW == 64) {
+    spmv_rows64(rp, ci, va, xin, yout, ybuf, r0, r1, scale);
   } else {
     constexpr int VWL = VW == 0 ? 64 : VW;
     const int grp = threadIdx.x / VWL, lane = threadIdx.x % VWL;
@@ -240,6 +359,33 @@ __global__ void __launch_bounds__(kSpmvWG, 8) k_spmv(const Dev *__restrict__ dev
   for (int q = 0; q < kMaxQ; ++q) v[q] = (q < nwin) ? acc[q] : (q == nwin ? acc[kMaxEll + 1] : 0.0);
   __shared__ double blk[kMaxQ];
   produce<NT>(D, ISA ? kStageA : kStageC, wid, nwin + 1, v, lds_w, blk);
+}
+
+// ---------------------------------------------------------------------------
+// y = Op x with one SpMV kernel's core only (no scaling, reductions or
+// epilogue): what the initialisation times to choose the kernel per operator.
+// ---------------------------------------------------------------------------
+template <int VW, bool ISA>
+__global__ void __launch_bounds__(kSpmvWG, 8) k_spmv_core(Dev D, const double *__restrict__ xin,
+                                                         double *yout) {
+  __shared__ double ybuf[kRowsLDS];
+  const int wid = blockIdx.x;
+  const int *rp = ISA ? D.Arp : D.Brp;
+  const int *ci = ISA ? D.Aci : D.Bci;
+  const double *va = ISA ? D.Ava : D.Bva;
+  const int *part = ISA ? D.Apart : D.Bpart;
+  if (VW == 1) {
+    const int nsl = ISA ? D.Ansl : D.Bnsl;
+    const int rows = ISA ? D.m : D.n;
+    const int s0 = (int)((long long)wid * nsl / D.nws), s1 = (int)((long long)(wid + 1) * nsl / D.nws);
+    __shared__ double lds_part[(kSpmvWG / 64) * kSellC];
+    spmv_sell(ISA ? D.Asoff : D.Bsoff, ISA ? D.Aslen : D.Bslen, ISA ? D.Ascol : D.Bscol,
+              ISA ? D.Asval : D.Bsval, xin, yout, ybuf, s0, s1, rows, 1.0, lds_part);
+  } else if (VW == 64) {
+    spmv_rows64(rp, ci, va, xin, yout, ybuf, part[wid], part[wid + 1], 1.0);
+  } else {
+    spmv_stream(rp, ci, va, xin, yout, ybuf, part[wid], part[wid + 1], 1.0);
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -933,6 +1079,30 @@ __global__ void __launch_bounds__(64) k_init_rhs(Dev D) {
   if (lane == 0) sc->rhsnorm = sqrt(r2);
 }
 
+// SELL-64 build: slen[s] = longest row of slice s, padded to kSellPad
+__global__ void k_sell_len(const int *rp, int rows, int nsl, int *slen) {
+  const int sl = blockIdx.x * blockDim.x + threadIdx.x;
+  if (sl >= nsl) return;
+  int mx = 0;
+  for (int r = sl * kSellC; r < min(rows, (sl + 1) * kSellC); ++r) mx = max(mx, rp[r + 1] - rp[r]);
+  slen[sl] = (mx + kSellPad - 1) / kSellPad * kSellPad;
+}
+
+// one thread per row: its entries at soff[s] + 64 j + i, padding after them
+__global__ void k_sell_fill(const int *rp, const int *ci, const double *va, int rows,
+                            const int *soff, const int *slen, int *scol, double *sval) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= rows) return;
+  const int sl = r / kSellC, i = r % kSellC;
+  const int e0 = rp[r], len = rp[r + 1] - e0, L = slen[sl];
+  const size_t base = (size_t)soff[sl] + i;
+  for (int j = 0; j < L; ++j) {
+    const bool in = j < len;
+    scol[base + (size_t)j * kSellC] = in ? ci[e0 + j] : 0;
+    sval[base + (size_t)j * kSellC] = in ? va[e0 + j] : 0.0;
+  }
+}
+
 // run state of every instance after iteration k: 1 if no further iteration can
 // change it (stopped, broken down, or past its capacity)
 __global__ void k_collect_halt(const Dev *__restrict__ devs, int n, int k, int *out) {
@@ -957,6 +1127,7 @@ static void launch_spmv_vw(const Launch &L, int k, int vw, hipStream_t st) {
     case 16: hipLaunchKernelGGL((k_spmv<16, ISA>), g, b, 0, st, L.devs, map, k); break;
     case 32: hipLaunchKernelGGL((k_spmv<32, ISA>), g, b, 0, st, L.devs, map, k); break;
     case 64: hipLaunchKernelGGL((k_spmv<64, ISA>), g, b, 0, st, L.devs, map, k); break;
+    case 1: hipLaunchKernelGGL((k_spmv<1, ISA>), g, b, 0, st, L.devs, map, k); break;
     default: hipLaunchKernelGGL((k_spmv<0, ISA>), g, b, 0, st, L.devs, map, k); break;
   }
 }
@@ -1027,6 +1198,28 @@ void launch_init_rhs(const Dev &D, hipStream_t st) {
 void launch_collect_halt(const Launch &L, int k, int *out, hipStream_t st) {
   hipLaunchKernelGGL(k_collect_halt, dim3((L.ninst + 255) / 256), dim3(256), 0, st, L.devs, L.ninst,
                      k, out);
+}
+// one launch of the core of SpMV kernel vw (0, 1 or 64) for A (isa) or B
+void launch_spmv_core(const Dev &D, bool isa, int vw, const double *x, double *y, hipStream_t st) {
+  const dim3 g(D.nws), b(kSpmvWG);
+  if (isa) {
+    if (vw == 1) hipLaunchKernelGGL((k_spmv_core<1, true>), g, b, 0, st, D, x, y);
+    else if (vw == 64) hipLaunchKernelGGL((k_spmv_core<64, true>), g, b, 0, st, D, x, y);
+    else hipLaunchKernelGGL((k_spmv_core<0, true>), g, b, 0, st, D, x, y);
+  } else {
+    if (vw == 1) hipLaunchKernelGGL((k_spmv_core<1, false>), g, b, 0, st, D, x, y);
+    else if (vw == 64) hipLaunchKernelGGL((k_spmv_core<64, false>), g, b, 0, st, D, x, y);
+    else hipLaunchKernelGGL((k_spmv_core<0, false>), g, b, 0, st, D, x, y);
+  }
+}
+
+void launch_sell_len(const int *rp, int rows, int nsl, int *slen, hipStream_t st) {
+  hipLaunchKernelGGL(k_sell_len, dim3((nsl + 255) / 256), dim3(256), 0, st, rp, rows, nsl, slen);
+}
+void launch_sell_fill(const int *rp, const int *ci, const double *va, int rows, const int *soff,
+                      const int *slen, int *scol, double *sval, hipStream_t st) {
+  hipLaunchKernelGGL(k_sell_fill, dim3((rows + 255) / 256), dim3(256), 0, st, rp, ci, va, rows,
+                     soff, slen, scol, sval);
 }
 void launch_scan(int *a, int len, hipStream_t st) {
   hipLaunchKernelGGL(k_scan_single, dim3(1), dim3(1024), 0, st, a, len);

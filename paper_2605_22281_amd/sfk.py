@@ -94,6 +94,7 @@ def lib() -> ctypes.CDLL:
         "sfk_instance_true_residual": (I32, [P, I32, PD]),
         "sfk_init_multi": (I32, [ctypes.POINTER(P), PCSR, PCSR, P, I32, PPAR, P]),
         "sfk_stage_times": (I32, [P, PD, PI32]),
+        "sfk_spmv_variant": (I32, [P, PI32, PI32]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -110,7 +111,7 @@ def exported_symbols() -> list[str]:
             "sfk_coefficients", "sfk_version", "sfk_set_timing", "sfk_stage_times",
             "sfk_init_batch", "sfk_batch_size", "sfk_instance_status", "sfk_instance_solution",
             "sfk_instance_residual_norms", "sfk_instance_true_residual", "sfk_init_multi",
-            "sfk_instance_solution_at"]
+            "sfk_instance_solution_at", "sfk_spmv_variant"]
 
 
 def _check(status: int, ctx=None):
@@ -121,7 +122,7 @@ def _check(status: int, ctx=None):
 
 def params(method="sflsqr", *, ell=2, maxit=50, sketch="sparse_sign", s=101, zeta=8, seed=0,
            instance=0, tau="identity", eps=1e-3, eta=1.01, noise_norm=0.0, tol=0.0,
-           driver="auto", vw=0, wg_per_cu=0) -> Params:
+           driver="auto", vw=-2, wg_per_cu=0) -> Params:
     p = Params()
     lib().sfk_params_default(ctypes.byref(p))
     p.method = _METHODS[method] if isinstance(method, str) else int(method)
@@ -414,6 +415,13 @@ def instance_residual_norms(ctx, i: int, cap: int) -> tuple[np.ndarray, float]:
     _check(lib().sfk_instance_residual_norms(ctx.handle, i, buf, max(1, cap), ctypes.byref(cnt),
                                              ctypes.byref(rn)), ctx.handle)
     return np.array(buf[: min(cnt.value, cap)]), rn.value
+
+
+def spmv_variant(ctx) -> tuple[int, int]:
+    """(variant for A, variant for B) actually launched (see sfk_spmv_variant)."""
+    a, b = ctypes.c_int32(), ctypes.c_int32()
+    _check(lib().sfk_spmv_variant(ctx.handle, ctypes.byref(a), ctypes.byref(b)), ctx.handle)
+    return a.value, b.value
 
 
 def version() -> str:

@@ -23,7 +23,7 @@ def rel(a, b):
 
 
 def gpu_run(P, method, kind, s, maxit, *, ell=2, tau="identity", eps=1e-3, zeta=8, seed=3001,
-            tol=0.0, noise=0.0, eta=1.01, stepwise=True, driver="auto", vw=0):
+            tol=0.0, noise=0.0, eta=1.01, stepwise=True, driver="auto", vw=-2):
     """Runs the GPU solver; returns (ctx, X (n x k), rho, rhs_norm, status)."""
     import torch
     from paper_2605_22281_amd import sfk

@@ -107,13 +107,36 @@ def test_parity_ragged_random(method):
     compare(X, rho, orc, 10, label=f"ragged/{method}")
 
 
-@pytest.mark.parametrize("vw", [0, -1, 8, 16, 32, 64])
+@pytest.mark.parametrize("vw", [-2, 0, 1, -1, 8, 16, 32, 64])
 def test_parity_all_row_widths(ct24_sparse, vw):
+    from paper_2605_22281_amd import sfk
     say(f"case: ct24 sparse vw={vw}")
-    _, X, rho, _, _ = gpu_run(ct24_sparse, "sflsqr", "sparse_sign", 60, 8, tau="reweight_l1",
-                              eps=1e-3, vw=vw)
+    ctx, X, rho, _, _ = gpu_run(ct24_sparse, "sflsqr", "sparse_sign", 60, 8, tau="reweight_l1",
+                                eps=1e-3, vw=vw)
+    va, vb = sfk.spmv_variant(ctx)
+    if vw >= 0:
+        assert (va, vb) == (vw, vw)            # the requested kernel is the one that ran
+    elif vw == -1:
+        assert va in (8, 16, 32, 64) and vb in (8, 16, 32, 64)
+    else:
+        assert va in (0, 1) and vb in (0, 1)
     orc = oracle_run(ct24_sparse, "sflsqr", "sparse_sign", 60, 8, tau="reweight_l1", eps=1e-3)
     compare(X, rho, orc, 8, label=f"vw{vw}")
+
+
+@pytest.mark.parametrize("vw", [0, 1, 64])
+def test_parity_long_and_empty_rows(vw):
+    # rows of up to 675 (A) and 1376 (B) nonzeros, i.e. several 512-nonzero
+    # passes of the wave-per-row kernel, 125 empty rows, and the largest window
+    # (ell = 8: with the full window the run stays reproducible in float64,
+    # two summation orders of the oracle agree to 2e-13 through k = 9)
+    from paper_2605_22281_amd import sfk
+    P = inputs.random_sparse_problem(2000, 900, 0.7, seed=23, unmatched=True)
+    say(f"case: long rows 2000x900 nnz={P.A.nnz} vw={vw}")
+    ctx, X, rho, _, _ = gpu_run(P, "sflsmr", "sparse_sign", 120, 9, ell=8, vw=vw)
+    assert sfk.spmv_variant(ctx) == (vw, vw)
+    orc = oracle_run(P, "sflsmr", "sparse_sign", 120, 9, ell=8)
+    compare(X, rho, orc, 9, label=f"long rows vw{vw}")
 
 
 def test_identity_sketch_is_flsqr_type():
