@@ -94,7 +94,9 @@ typedef struct {
                           nonzeros on average, else CSR-stream; the default),
                           0 = CSR-stream chunks, 1 = SELL-64 copy built at init
                           (64-row slices stored column-major), 8/16/32/64 = lanes per
-                          row, -1 = lanes per row chosen from the mean row length */
+                          row, -1 = lanes per row chosen from the mean row length.
+                          Right-hand sides sharing A and B (sfk_init_multi): -2 or 0
+                          = column-sliced products, any other value = row kernel */
   int32_t wg_per_cu;   /* data-parallel workgroups per CU; 0 = automatic */
   int32_t reserved[5];
 } sfk_params;
@@ -254,8 +256,8 @@ sfk_status sfk_set_timing(sfk_ctx *ctx, int32_t on);
 sfk_status sfk_stage_times(sfk_ctx *ctx, double *ms_host, int32_t *count_host);
 
 /* SpMV kernel in use for A and for B: 0 CSR-stream, 1 SELL-64, 64 a wave per
- * row with the whole row in flight, 8/16/32 lanes per row; -2 for right-hand
- * sides sharing A and B (column-sliced products).  A batch runs one kernel for
+ * row with the whole row in flight, 8/16/32 lanes per row; for right-hand
+ * sides sharing A and B -2 (column-sliced products) or -3 (row kernel).  A batch runs one kernel for
  * all instances: instance 0's, or CSR-stream when the instances differ. */
 sfk_status sfk_spmv_variant(const sfk_ctx *ctx, int32_t *vwA_host, int32_t *vwB_host);
 

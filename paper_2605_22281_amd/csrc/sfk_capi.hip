@@ -1148,9 +1148,9 @@ extern "C" sfk_status sfk_init_multi(sfk_ctx **out, const sfk_csr *A, const sfk_
     return SFK_OK;
   };
   if (s == SFK_OK) s = setup_group();
-  // sliced products unless the row kernel is asked for (vw != 0) or an operator
-  // cannot be sliced
-  if (s == SFK_OK && p0.vw == 0) {
+  // sliced products (vw automatic or 0) unless the row kernel is asked for
+  // (any other vw) or an operator cannot be sliced
+  if (s == SFK_OK && (p0.vw == 0 || p0.vw == -2)) {
     bool oka = false, okb = false;
     s = build_xop(c, G.xa, G.Arp, G.Aci, G.Ava, (int)m, (int)n, nnzA, RS, cus, &oka);
     if (s == SFK_OK && oka) s = build_xop(c, G.xb, G.Brp, G.Bci, G.Bva, (int)n, (int)m, nnzB, RS, cus, &okb);
@@ -1430,8 +1430,9 @@ extern "C" sfk_status sfk_coefficients(sfk_ctx *c, double *H_host, double *T_hos
 
 extern "C" sfk_status sfk_spmv_variant(const sfk_ctx *c, int32_t *vwA_host, int32_t *vwB_host) {
   if (!c) return fail(nullptr, SFK_EINVAL, "NULL context");
-  if (vwA_host) *vwA_host = c->multi ? -2 : c->L.vwA;
-  if (vwB_host) *vwB_host = c->multi ? -2 : c->L.vwB;
+  const int g = c->grp.sliced ? -2 : -3;
+  if (vwA_host) *vwA_host = c->multi ? g : c->L.vwA;
+  if (vwB_host) *vwB_host = c->multi ? g : c->L.vwB;
   return SFK_OK;
 }
 

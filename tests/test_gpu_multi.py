@@ -218,14 +218,15 @@ def test_shared_operator_row_kernel_matches_sliced():
     B = sfk.to_device_csr(P.B)
     bb = torch.from_numpy(np.ascontiguousarray(b)).cuda()
     xs = {}
-    for vw in (0, -1):
+    for vw in (-2, -1):
         ps = [sfk.params("sflsmr", maxit=MAXIT, sketch="sparse_sign", s=90, seed=300 + r, vw=vw)
               for r in range(R)]
         ctx = sfk.init_multi(A, B, bb, ps)
         sfk.iterate(ctx, MAXIT)
+        assert sfk.spmv_variant(ctx) == ((-2, -2) if vw == -2 else (-3, -3))
         xs[vw] = [sfk.instance_solution(ctx, r, P.n).cpu().numpy() for r in range(R)]
     for r in range(R):
         S = sketches.SparseSign(P.n, 90, 8, 300 + r)
         orc = fgk.sketched_flexible(P.A, b[r], S, method="sflsmr", B=P.B, maxit=MAXIT, ell=2)
-        assert rel(xs[0][r], orc.x) <= 1e-8 and rel(xs[-1][r], orc.x) <= 1e-8, r
-        assert rel(xs[0][r], xs[-1][r]) <= 1e-10, r
+        assert rel(xs[-2][r], orc.x) <= 1e-8 and rel(xs[-1][r], orc.x) <= 1e-8, r
+        assert rel(xs[-2][r], xs[-1][r]) <= 1e-10, r
