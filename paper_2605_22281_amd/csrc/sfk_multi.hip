@@ -23,6 +23,7 @@
 namespace sfk {
 
 constexpr int kGWG = 512;   // threads per SpMM workgroup
+constexpr int kStreamU = 2; // elements per thread in flight in the streaming kernels
 
 __device__ __forceinline__ double *gwvec(const Grp &G, int j) {
   return G.W + (size_t)(j % (G.ell + 2)) * G.m * G.RS;
@@ -342,7 +343,7 @@ __global__ void __launch_bounds__(kGWG) k_gspmm_x(Grp G, const int4 *__restrict_
   }
 }
 
-template <int RS, bool ISA>
+template <int RS, bool ISA, int NW>
 __global__ void __launch_bounds__(kWG) k_gcombine(Grp G, int k) {
   __shared__ int s_any;
   __shared__ double red[(kWG / 64) * RS];
@@ -357,9 +358,9 @@ __global__ void __launch_bounds__(kWG) k_gcombine(Grp G, int k) {
   int j0, nwin;
   if (ISA) { j0 = max(1, k - G.ell); nwin = k - j0 + 1; }
   else { j0 = max(1, k + 1 - G.ell); nwin = k >= j0 ? k - j0 + 1 : 0; }
-  const double *win[kMaxEll + 1];
+  const double *win[NW];
 #pragma unroll
-  for (int q = 0; q < kMaxEll + 1; ++q)
+  for (int q = 0; q < NW; ++q)
     win[q] = (q < nwin) ? (ISA ? gwvec(G, j0 + q) : gpvec(G, j0 + q)) : nullptr;
   double acc[kMaxQ];
 #pragma unroll
@@ -367,28 +368,52 @@ __global__ void __launch_bounds__(kWG) k_gcombine(Grp G, int k) {
   int i0, i1;
   chunk_range(rows, G.nwv, wid, i0, i1);
   const size_t e1 = (size_t)i1 * RS;
-  for (size_t e = (size_t)i0 * RS + threadIdx.x; e < e1; e += kWG) {
-    const int i = (int)(e / RS);
-    const double *pr = X.part + (size_t)X.crp[i] * RS + j;
-    const int np = X.crp[i + 1] - X.crp[i];
-    double sum = 0.0;
-    for (int t = 0; t < np; t += 4) {      // four independent loads, summed in slice order
-      const double p0 = pr[(size_t)t * RS];
-      const double p1 = t + 1 < np ? pr[(size_t)(t + 1) * RS] : 0.0;
-      const double p2 = t + 2 < np ? pr[(size_t)(t + 2) * RS] : 0.0;
-      const double p3 = t + 3 < np ? pr[(size_t)(t + 3) * RS] : 0.0;
-      sum = (((sum + p0) + p1) + p2) + p3;
-    }
-    const double y = sum * scale;
-    if (on) yout[e] = y;
+  for (size_t e0 = (size_t)i0 * RS + threadIdx.x; e0 < e1; e0 += kStreamU * kWG) {
+    int pb[kStreamU], np[kStreamU];
 #pragma unroll
-    for (int q = 0; q < kMaxEll + 1; ++q)
-      if (q < nwin) acc[q] += win[q][e] * y;
-    acc[kMaxEll + 1] += y * y;
+    for (int u = 0; u < kStreamU; ++u) {
+      const size_t e = e0 + (size_t)u * kWG;
+      pb[u] = 0;
+      np[u] = 0;
+      if (e < e1) {
+        const int i = (int)(e / RS);
+        pb[u] = X.crp[i];
+        np[u] = X.crp[i + 1] - pb[u];
+      }
+    }
+    int npm = 0;
+#pragma unroll
+    for (int u = 0; u < kStreamU; ++u) npm = max(npm, np[u]);
+    double sum[kStreamU];
+#pragma unroll
+    for (int u = 0; u < kStreamU; ++u) sum[u] = 0.0;
+    for (int t = 0; t < npm; t += 4) {      // the partials of a row, summed in slice order
+      double p[kStreamU][4];
+#pragma unroll
+      for (int u = 0; u < kStreamU; ++u)
+#pragma unroll
+        for (int tt = 0; tt < 4; ++tt)
+          p[u][tt] = t + tt < np[u] ? X.part[((size_t)pb[u] + t + tt) * RS + j] : 0.0;
+#pragma unroll
+      for (int u = 0; u < kStreamU; ++u)
+        if (t < np[u]) sum[u] = (((sum[u] + p[u][0]) + p[u][1]) + p[u][2]) + p[u][3];
+    }
+#pragma unroll
+    for (int u = 0; u < kStreamU; ++u) {
+      const size_t e = e0 + (size_t)u * kWG;
+      if (e < e1) {
+        const double y = sum[u] * scale;
+        if (on) yout[e] = y;
+#pragma unroll
+        for (int q = 0; q < NW; ++q)
+          if (q < nwin) acc[q] += win[q][e] * y;
+        acc[NW] += y * y;
+      }
+    }
   }
   double v[kMaxQ];
 #pragma unroll
-  for (int q = 0; q < kMaxQ; ++q) v[q] = (q < nwin) ? acc[q] : (q == nwin ? acc[kMaxEll + 1] : 0.0);
+  for (int q = 0; q < kMaxQ; ++q) v[q] = (q < nwin) ? acc[q] : (q == nwin ? acc[NW] : 0.0);
   produce_rhs<RS, kWG>(G, ISA ? kStageA : kStageC, wid, nwin + 1, v, red);
 }
 
@@ -514,7 +539,7 @@ void launch_xs_part(const int *touch, int rows, int NS, int nseg, const int *pos
 // ||w~_{k+1}||^2 and the Gram entries <w~_{k+1}, w~_j>.  Thread t always works
 // on right-hand side t % RS (kWG is a multiple of RS).
 // ---------------------------------------------------------------------------
-template <int RS>
+template <int RS, int NW>
 __global__ void __launch_bounds__(kWG) k_gwupdate(Grp G, int k) {
   __shared__ int s_any;
   __shared__ double red[(kWG / 64) * RS];
@@ -523,10 +548,10 @@ __global__ void __launch_bounds__(kWG) k_gwupdate(Grp G, int k) {
   const bool on = j < G.R && G.act[j] != 0;
   const int wid = blockIdx.x;
   const int j0 = max(1, k - G.ell), nwin = k - j0 + 1;
-  const double *win[kMaxEll + 1];
-  double cf[kMaxEll + 1];
+  const double *win[NW];
+  double cf[NW];
 #pragma unroll
-  for (int q = 0; q < kMaxEll + 1; ++q) {
+  for (int q = 0; q < NW; ++q) {
     win[q] = (q < nwin) ? gwvec(G, j0 + q) : nullptr;
     cf[q] = (q < nwin) ? G.coef[(size_t)j * kCoefStride + q] : 0.0;
   }
@@ -537,18 +562,39 @@ __global__ void __launch_bounds__(kWG) k_gwupdate(Grp G, int k) {
   double acc[kMaxQ];
 #pragma unroll
   for (int q = 0; q < kMaxQ; ++q) acc[q] = 0.0;
+  // kStreamU elements per thread at a time, all loads issued before use; the
+  // sums accumulate in element order
   const size_t e1 = (size_t)i1 * RS;
-  for (size_t e = (size_t)i0 * RS + threadIdx.x; e < e1; e += kWG) {
-    double v = wr[e];
-    double wj[kMaxEll + 1];
+  for (size_t e0 = (size_t)i0 * RS + threadIdx.x; e0 < e1; e0 += kStreamU * kWG) {
+    double v[kStreamU], wj[kStreamU][NW];
 #pragma unroll
-    for (int q = 0; q < kMaxEll + 1; ++q)
-      if (q < nwin) { wj[q] = win[q][e]; v -= cf[q] * wj[q]; }
-    if (on) out[e] = v;
-    acc[0] += v * v;
+    for (int u = 0; u < kStreamU; ++u) {
+      const size_t e = e0 + (size_t)u * kWG;
+      v[u] = 0.0;
 #pragma unroll
-    for (int q = 0; q < kMaxEll + 1; ++q)
-      if (q < nwin) acc[1 + q] += v * wj[q];
+      for (int q = 0; q < NW; ++q) wj[u][q] = 0.0;
+      if (e < e1) {
+        v[u] = wr[e];
+#pragma unroll
+        for (int q = 0; q < NW; ++q)
+          if (q < nwin) wj[u][q] = win[q][e];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < kStreamU; ++u) {
+      const size_t e = e0 + (size_t)u * kWG;
+      if (e < e1) {
+        double vv = v[u];
+#pragma unroll
+        for (int q = 0; q < NW; ++q)
+          if (q < nwin) vv -= cf[q] * wj[u][q];
+        if (on) out[e] = vv;
+        acc[0] += vv * vv;
+#pragma unroll
+        for (int q = 0; q < NW; ++q)
+          if (q < nwin) acc[1 + q] += vv * wj[u][q];
+      }
+    }
   }
   produce_rhs<RS, kWG>(G, kStageB, wid, nwin + 1, acc, red);
 }
@@ -557,7 +603,7 @@ __global__ void __launch_bounds__(kWG) k_gwupdate(Grp G, int k) {
 // D(k): p~_{k+1} = z - sum_j t_j,k+1 p~_j sigp_j, z~_{k+1} = tau(p~_{k+1}), with
 // ||p~_{k+1}||^2 and the Gram entries.  The reweighting forms x_k on the fly.
 // ---------------------------------------------------------------------------
-template <int RS>
+template <int RS, int NW>
 __global__ void __launch_bounds__(kWG) k_gpupdate(Grp G, int k) {
   __shared__ int s_any;
   __shared__ double red[(kWG / 64) * RS];
@@ -567,10 +613,10 @@ __global__ void __launch_bounds__(kWG) k_gpupdate(Grp G, int k) {
   const int wid = blockIdx.x;
   const int j0 = max(1, k + 1 - G.ell);
   const int nwin = k >= j0 ? k - j0 + 1 : 0;
-  const double *win[kMaxEll + 1];
-  double cf[kMaxEll + 1];
+  const double *win[NW];
+  double cf[NW];
 #pragma unroll
-  for (int q = 0; q < kMaxEll + 1; ++q) {
+  for (int q = 0; q < NW; ++q) {
     win[q] = (q < nwin) ? gpvec(G, j0 + q) : nullptr;
     cf[q] = (q < nwin) ? G.coef[(size_t)j * kCoefStride + q] : 0.0;
   }
@@ -586,25 +632,44 @@ __global__ void __launch_bounds__(kWG) k_gpupdate(Grp G, int k) {
 #pragma unroll
   for (int q = 0; q < kMaxQ; ++q) acc[q] = 0.0;
   const size_t e1 = (size_t)i1 * RS;
-  for (size_t e = (size_t)i0 * RS + threadIdx.x; e < e1; e += kWG) {
-    double v = zr[e];
-    double pj[kMaxEll + 1];
+  for (size_t e0 = (size_t)i0 * RS + threadIdx.x; e0 < e1; e0 += kStreamU * kWG) {
+    double v[kStreamU], pj[kStreamU][NW];
 #pragma unroll
-    for (int q = 0; q < kMaxEll + 1; ++q)
-      if (q < nwin) { pj[q] = win[q][e]; v -= cf[q] * pj[q]; }
-    if (on) pout[e] = v;
-    if (rew) {
-      double xi = 0.0;
-      for (int jj = 0; jj < k; ++jj) xi += G.gx[(size_t)jj * RS + j] * G.Z[(size_t)jj * colstride + e];
-      if (on) {
-        G.x[e] = xi;
-        zout[e] = sqrt(sqrt(xi * xi + eps2)) * v;
+    for (int u = 0; u < kStreamU; ++u) {
+      const size_t e = e0 + (size_t)u * kWG;
+      v[u] = 0.0;
+#pragma unroll
+      for (int q = 0; q < NW; ++q) pj[u][q] = 0.0;
+      if (e < e1) {
+        v[u] = zr[e];
+#pragma unroll
+        for (int q = 0; q < NW; ++q)
+          if (q < nwin) pj[u][q] = win[q][e];
       }
     }
-    acc[0] += v * v;
 #pragma unroll
-    for (int q = 0; q < kMaxEll + 1; ++q)
-      if (q < nwin) acc[1 + q] += v * pj[q];
+    for (int u = 0; u < kStreamU; ++u) {
+      const size_t e = e0 + (size_t)u * kWG;
+      if (e < e1) {
+        double vv = v[u];
+#pragma unroll
+        for (int q = 0; q < NW; ++q)
+          if (q < nwin) vv -= cf[q] * pj[u][q];
+        if (on) pout[e] = vv;
+        if (rew) {
+          double xi = 0.0;
+          for (int jj = 0; jj < k; ++jj) xi += G.gx[(size_t)jj * RS + j] * G.Z[(size_t)jj * colstride + e];
+          if (on) {
+            G.x[e] = xi;
+            zout[e] = sqrt(sqrt(xi * xi + eps2)) * vv;
+          }
+        }
+        acc[0] += vv * vv;
+#pragma unroll
+        for (int q = 0; q < NW; ++q)
+          if (q < nwin) acc[1 + q] += vv * pj[u][q];
+      }
+    }
   }
   produce_rhs<RS, kWG>(G, kStageD, wid, nwin + 1, acc, red);
 }
@@ -618,7 +683,10 @@ static void launch_product(const Grp &G, int k, hipStream_t st) {
     const XOp &X = ISA ? G.xa : G.xb;
     hipLaunchKernelGGL((k_gspmm_x<RS, ISA>), dim3(X.NS * X.nbs), dim3(kGWG), 0, st, G, X.seg,
                        X.spart, X.nz, k);
-    hipLaunchKernelGGL((k_gcombine<RS, ISA>), dim3(G.nwv), dim3(kWG), 0, st, G, k);
+    if (G.ell <= 2)
+      hipLaunchKernelGGL((k_gcombine<RS, ISA, 3>), dim3(G.nwv), dim3(kWG), 0, st, G, k);
+    else
+      hipLaunchKernelGGL((k_gcombine<RS, ISA, kMaxEll + 1>), dim3(G.nwv), dim3(kWG), 0, st, G, k);
   } else {
     hipLaunchKernelGGL((k_gspmm<RS, ISA>), dim3(G.nws), dim3(kGWG), 0, st, G, k);
   }
@@ -634,7 +702,10 @@ static void launch_group_rs(const Grp &G, int stage, int k, hipStream_t st) {
       break;
     case kStageB:
       hipLaunchKernelGGL(k_gfinish<kStageB>, fin, fb, 0, st, G, k);
-      hipLaunchKernelGGL(k_gwupdate<RS>, dim3(G.nwv), dim3(kWG), 0, st, G, k);
+      if (G.ell <= 2)
+        hipLaunchKernelGGL((k_gwupdate<RS, 3>), dim3(G.nwv), dim3(kWG), 0, st, G, k);
+      else
+        hipLaunchKernelGGL((k_gwupdate<RS, kMaxEll + 1>), dim3(G.nwv), dim3(kWG), 0, st, G, k);
       break;
     case kStageC:
       hipLaunchKernelGGL(k_gfinish<kStageC>, fin, fb, 0, st, G, k);
@@ -642,7 +713,10 @@ static void launch_group_rs(const Grp &G, int stage, int k, hipStream_t st) {
       break;
     default:
       hipLaunchKernelGGL(k_gfinish<kStageD>, fin, fb, 0, st, G, k);
-      hipLaunchKernelGGL(k_gpupdate<RS>, dim3(G.nwv), dim3(kWG), 0, st, G, k);
+      if (G.ell <= 2)
+        hipLaunchKernelGGL((k_gpupdate<RS, 3>), dim3(G.nwv), dim3(kWG), 0, st, G, k);
+      else
+        hipLaunchKernelGGL((k_gpupdate<RS, kMaxEll + 1>), dim3(G.nwv), dim3(kWG), 0, st, G, k);
       break;
   }
 }
