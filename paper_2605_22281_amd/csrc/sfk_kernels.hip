@@ -555,25 +555,83 @@ __global__ void __launch_bounds__(kWG) k_srht_blocks(const Dev *__restrict__ dev
   const int L = 1 << D.log2L;
   const int b = bm.y;
   const int base = b * L;
-  for (int i = threadIdx.x; i < L; i += kWG) {
-    const int g = base + i;
-    double val = 0.0;
-    if (g < D.d_sk) {
-      const unsigned long long w = D.srht_d[g >> 6];
-      const double vg = v[(size_t)g * vs];
-      val = ((w >> (g & 63)) & 1ull) ? -vg : vg;
+  if (L == kSrhtL) {
+    // Thread t holds elements t + kWG j: the butterfly stages h = 1..32 pair
+    // lanes of one wave (shuffles), h = 64 and 128 pair the four waves (one
+    // exchange through LDS), h = 256..1024 pair a thread's own elements.  The
+    // stages run in increasing h with the same additions as the loop below.
+    constexpr int E = kSrhtL / kWG;
+    static_assert(E == 8 && kWG == 256, "block layout");
+    const int t = threadIdx.x;
+    double x[E];
+#pragma unroll
+    for (int j = 0; j < E; ++j) {
+      const int g = base + t + kWG * j;
+      double val = 0.0;
+      if (g < D.d_sk) {
+        const unsigned long long w = D.srht_d[g >> 6];
+        const double vg = v[(size_t)g * vs];
+        val = ((w >> (g & 63)) & 1ull) ? -vg : vg;
+      }
+      x[j] = val;
     }
-    u[i] = val;
-  }
-  __syncthreads();
-  for (int h = 1; h < L; h <<= 1) {
-    for (int p = threadIdx.x; p < (L >> 1); p += kWG) {
-      const int i = (p / h) * 2 * h + (p % h);
-      const double a = u[i], c = u[i + h];
-      u[i] = a + c;
-      u[i + h] = a - c;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+      const bool hi = (t & d) != 0;
+#pragma unroll
+      for (int j = 0; j < E; ++j) {
+        const double o = __shfl_xor(x[j], d, 64);
+        x[j] = hi ? o - x[j] : x[j] + o;
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < E; ++j) u[t + kWG * j] = x[j];
+    __syncthreads();
+    {
+      const int q = (t >> 6) & 3, i0 = t & ~192;
+#pragma unroll
+      for (int j = 0; j < E; ++j) {
+        const int i = i0 + kWG * j;
+        const double a0 = u[i], a1 = u[i + 64], a2 = u[i + 128], a3 = u[i + 192];
+        const double b0 = a0 + a1, b1 = a0 - a1, b2 = a2 + a3, b3 = a2 - a3;
+        x[j] = q == 0 ? b0 + b2 : q == 1 ? b1 + b3 : q == 2 ? b0 - b2 : b1 - b3;
+      }
+    }
+#pragma unroll
+    for (int h = 1; h < E; h <<= 1) {
+#pragma unroll
+      for (int j = 0; j < E; ++j) {
+        if (j & h) continue;
+        const double a = x[j], c = x[j + h];
+        x[j] = a + c;
+        x[j + h] = a - c;
+      }
     }
     __syncthreads();
+#pragma unroll
+    for (int j = 0; j < E; ++j) u[t + kWG * j] = x[j];
+    __syncthreads();
+  } else {
+    for (int i = threadIdx.x; i < L; i += kWG) {
+      const int g = base + i;
+      double val = 0.0;
+      if (g < D.d_sk) {
+        const unsigned long long w = D.srht_d[g >> 6];
+        const double vg = v[(size_t)g * vs];
+        val = ((w >> (g & 63)) & 1ull) ? -vg : vg;
+      }
+      u[i] = val;
+    }
+    __syncthreads();
+    for (int h = 1; h < L; h <<= 1) {
+      for (int p = threadIdx.x; p < (L >> 1); p += kWG) {
+        const int i = (p / h) * 2 * h + (p % h);
+        const double a = u[i], c = u[i + h];
+        u[i] = a + c;
+        u[i + h] = a - c;
+      }
+      __syncthreads();
+    }
   }
   for (int i = threadIdx.x; i < D.s; i += kWG)
     D.srht_part[(size_t)b * D.s + i] = u[D.srht_rows[i] & (L - 1)];
@@ -589,10 +647,15 @@ __global__ void __launch_bounds__(kWG) k_srht_combine(const Dev *__restrict__ de
   if (i >= D.s) return;
   double *dst = sketch_out(D, k);
   const int hi = D.srht_rows[i] >> D.log2L;
+  // eight block partials in flight, added in block order
   double acc = 0.0;
-  for (int b = 0; b < D.nblk; ++b) {
-    const double p = D.srht_part[(size_t)b * D.s + i];
-    acc += (__popc(hi & b) & 1) ? -p : p;
+  for (int b0 = 0; b0 < D.nblk; b0 += 8) {
+    double p[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) p[u] = b0 + u < D.nblk ? D.srht_part[(size_t)(b0 + u) * D.s + i] : 0.0;
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+      if (b0 + u < D.nblk) acc += (__popc(hi & (b0 + u)) & 1) ? -p[u] : p[u];
   }
   dst[i] = acc * D.sk_scale;
 }
