@@ -92,7 +92,16 @@ def _timed_iterate(sfk, torch, ctx, k):
     return time.perf_counter() - t0, done
 
 
-def multi_rhs_bench(P, cfg, A, B, R: int, K: int):
+def _order_tensor(order: str, P):
+    """The order of the unknowns passed to the library (sfk_params.perm)."""
+    import torch
+    from paper_2605_22281_amd import inputs
+    if order == "natural":
+        return None
+    return torch.from_numpy(inputs.tile_order(P.N, int(order[len("tiles"):]))).cuda()
+
+
+def multi_rhs_bench(P, cfg, A, B, R: int, K: int, order: str = "natural"):
     """R right-hand sides sharing A and B in one context vs a loop of R plain
     solves, K iterations each (init outside the timed regions)."""
     import numpy as np
@@ -100,8 +109,10 @@ def multi_rhs_bench(P, cfg, A, B, R: int, K: int):
     from paper_2605_22281_amd import inputs, sfk
     b, xt, _ = inputs.multi_rhs(P, R, seed=21)
     bb = torch.from_numpy(np.ascontiguousarray(b)).cuda()
+    pt = _order_tensor(order, P)
     ps = [sfk.params(cfg["method"], ell=2, maxit=K, sketch=cfg["sketch"], s=cfg["s"],
-                     zeta=cfg["zeta"], seed=3100 + r, tau=cfg["tau"], eps=1e-3) for r in range(R)]
+                     zeta=cfg["zeta"], seed=3100 + r, tau=cfg["tau"], eps=1e-3, perm=pt)
+          for r in range(R)]
     warm = sfk.init_multi(A, B, bb, ps)
     sfk.iterate(warm, min(K, 10))
     sfk.destroy(warm)
@@ -143,7 +154,7 @@ def multi_rhs_bench(P, cfg, A, B, R: int, K: int):
             "stage_avg_ms": {k: (v[0] / v[1] if v[1] else 0.0) for k, v in times.items()}}
 
 
-def hetero_bench(count: int = 32, maxit: int = 100):
+def hetero_bench(count: int = 32, maxit: int = 100, order: str = "natural"):
     """Independent instances of uneven sizes in one context vs a plain loop."""
     import numpy as np
     import torch
@@ -151,8 +162,10 @@ def hetero_bench(count: int = 32, maxit: int = 100):
     probs = inputs.batch_instances(count)
     As = [sfk.to_device_csr(P.A) for P in probs]       # separate device copies
     bs = [torch.from_numpy(np.ascontiguousarray(P.b)).cuda() for P in probs]
+    perms = [_order_tensor(order, P) for P in probs]
     ps = [sfk.params("sflsqr", ell=2, maxit=maxit, sketch="sparse_sign", s=201, zeta=8,
-                     seed=5000 + i, noise_norm=P.noise_norm, eta=1.01) for i, P in enumerate(probs)]
+                     seed=5000 + i, noise_norm=P.noise_norm, eta=1.01, perm=perms[i])
+          for i, P in enumerate(probs)]
     warm = sfk.init_batch(As, None, bs, ps)
     sfk.iterate(warm, 5)
     sfk.destroy(warm)
@@ -222,6 +235,10 @@ def main():
     ap.add_argument("--copy-calibration", action="store_true")
     ap.add_argument("--batched", default="all", choices=["all", "multi", "hetero", "none"])
     ap.add_argument("--rhs", type=int, default=32)
+    ap.add_argument("--order", default="tiles4", choices=["natural", "tiles4", "tiles8"],
+                    help="order of the unknowns passed to the library: the image's row-major "
+                         "pixels, or 4x4 / 8x8 pixel tiles (results are in row-major order "
+                         "either way)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -253,7 +270,7 @@ def main():
     maxit = max(K, W, 1)
     p = sfk.params(cfg["method"], ell=2, maxit=maxit, sketch=cfg["sketch"], s=cfg["s"],
                    zeta=cfg["zeta"], seed=3000 + 2, tau=cfg["tau"], eps=1e-3, driver=args.driver,
-                   vw=args.vw)
+                   vw=args.vw, perm=_order_tensor(args.order, P))
 
     if W > 0:
         log(f"bench: warmup {W} iterations")
@@ -320,7 +337,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": cfg["desc"], "m": P.m, "n": P.n, "nnz_A": nnzA, "nnz_B": nnzB,
                    "method": cfg["method"], "sketch": cfg["sketch"], "s": cfg["s"], "ell": ell,
-                   "driver": args.driver, "spmv_kernel": spmv_kernel},
+                   "driver": args.driver, "spmv_kernel": spmv_kernel, "order": args.order},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "bytes_per_launch": per_launch[dom], "avg_launch_ms": stage_avg[dom]},
@@ -329,13 +346,13 @@ def main():
     }
     if args.batched in ("all", "multi"):
         log(f"bench: shared operator, {args.rhs} right-hand sides x {K} iterations, and plain loop")
-        mr = multi_rhs_bench(P, cfg, A, B, args.rhs, K)
+        mr = multi_rhs_bench(P, cfg, A, B, args.rhs, K, args.order)
         out["batched_multi_rhs"] = mr
         out["batched_plain_speedup"] = mr["speedup"]
         log(f"bench: shared operator speedup {mr['speedup']:.2f}x")
     if args.batched in ("all", "hetero"):
         log("bench: heterogeneous batch of 32 instances, and plain loop")
-        hb = hetero_bench()
+        hb = hetero_bench(order=args.order)
         out["batched_heterogeneous"] = hb
         log(f"bench: heterogeneous speedup {hb['speedup']:.2f}x")
     if not args.no_cpu_baseline:

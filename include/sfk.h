@@ -90,15 +90,31 @@ typedef struct {
   double tol;          /* relative tolerance of the sketched stop test when the
                           discrepancy stop is off; 0 runs to maxit */
   int32_t driver;      /* sfk_driver */
-  int32_t vw;          /* SpMV kernel: -2 = automatic (SELL-64 for rows of >= 32
-                          nonzeros on average, else CSR-stream; the default),
-                          0 = CSR-stream chunks, 1 = SELL-64 copy built at init
-                          (64-row slices stored column-major), 8/16/32/64 = lanes per
-                          row, -1 = lanes per row chosen from the mean row length.
-                          Right-hand sides sharing A and B (sfk_init_multi): -2 or 0
-                          = column-sliced products, any other value = row kernel */
+  int32_t vw;          /* SpMV kernel: -2 = automatic (the default: CSR-stream,
+                          a wave per row and SELL-64 are timed at init on each
+                          operator and the fastest is kept), 0 = CSR-stream chunks,
+                          1 = SELL-64 copy built at init (64-row slices stored
+                          column-major), 8/16/32/64 = lanes per row, -1 = lanes per
+                          row chosen from the mean row length.  Right-hand sides
+                          sharing A and B (sfk_init_multi): -2 or 0 = column-sliced
+                          products, any other value = row kernel */
   int32_t wg_per_cu;   /* data-parallel workgroups per CU; 0 = automatic */
-  int32_t reserved[5];
+  int32_t reserved0;
+  const int32_t *perm; /* optional order of the n unknowns: a device array of n
+                          distinct values in [0, n), or NULL (identity).  Unknown j
+                          is stored at position perm[j] inside the library: columns
+                          of A and rows of B are renumbered at init (into copies the
+                          context owns; the caller's arrays are not modified) and
+                          sketches of n-vectors (sFLSMR) read through perm, so the
+                          iterates are those of the caller's numbering up to the
+                          summation order of the products; solutions and residuals
+                          are returned in the caller's order.  An order that keeps
+                          unknowns read by the same rows close together (e.g. 4 x 4
+                          pixel tiles of an image) makes the gathers of the products
+                          touch fewer cache lines.  With perm, rows of A must have at
+                          most 4096 entries (SFK_EINVAL otherwise).  Must stay valid
+                          until sfk_init returns. */
+  int32_t reserved[2];
 } sfk_params;
 
 /* Fills *p with defaults: sFLSQR, ell = 2, maxit = 50, sparse-sign s = 101, zeta = 8,

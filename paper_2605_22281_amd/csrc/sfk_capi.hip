@@ -38,6 +38,11 @@ void launch_transpose(const int *rp, const int *ci, const double *va, int rows, 
                       int *bci, double *bva, int *cursor, int *err, hipStream_t st);
 void launch_sketch_build(const Dev &D, uint64_t key0, uint64_t key1, uint64_t key1_rows,
                          int *scratch, int *err, hipStream_t st);
+void launch_perm_check(const int *perm, int n, int *cnt, int *pinv, int *err, hipStream_t st);
+void launch_relabel_cols(const int *rp, const int *ci, const double *va, int rows, int nnz,
+                         const int *perm, int *oci, double *ova, int *err, hipStream_t st);
+void launch_perm_rows(const int *rp, const int *ci, const double *va, int rows, const int *perm,
+                      int *orp, int *oci, double *ova, hipStream_t st);
 void launch_solution(const Dev &D, int kk, const double *yv, double *x, hipStream_t st);
 void launch_true_residual(const Dev &D, const double *x, double *out, hipStream_t st);
 void launch_group_stage(const Grp &G, int stage, int k, hipStream_t st);
@@ -76,6 +81,8 @@ struct Inst {
   double *d_scalar = nullptr;     // one double of scratch (true residual)
   double *d_ytmp = nullptr;       // maxit
   int *chunk_scratch = nullptr;   // sparse-sign build scratch
+  const int *user_aci = nullptr;  // the caller's A columns/values when the products
+  const double *user_ava = nullptr;  // run on a renumbered copy (true residual)
   int k_done = 0, stopped = 0, breakdown = 0, halted = 0;
   double rhsnorm = 0.0;
 };
@@ -102,7 +109,9 @@ struct sfk_ctx {
   bool multi = false;               // right-hand sides sharing A and B (stages via grp)
   Grp grp{};
   void *gws = nullptr;              // workspace of the shared arrays
-  std::vector<void *> xmem;         // sliced copies of A and B
+  std::vector<void *> xmem;         // sliced / SELL / renumbered copies of A and B
+  const int *gperm = nullptr;       // shared operators: the group's order of the
+  const int *gpinv = nullptr;       // unknowns and its inverse (NULL: identity)
   std::string err;
   // optional per-stage timing with HIP events
   bool timing = false;
@@ -533,6 +542,69 @@ static sfk_status setup_sketch_and_b(sfk_ctx *c, Inst &I, hipStream_t st) {
 // if needed, the row partitions and the sketch, and computes beta = ||b||.
 // grp != NULL: right-hand side r of a shared-operator group whose shared
 // arrays (vectors, partitions, B) are already set up.
+// Copies of the operators in the caller's order of the unknowns
+// (sfk_params.perm): A' has column j renamed perm[j] (each row re-sorted by
+// column), B' (when B is given) has row i moved to row perm[i]; also a copy of
+// perm (read by the sketches of n-vectors) and its inverse (the solution
+// output).  Memory owned by the context.  *bci is left NULL when B is NULL.
+static sfk_status relabel(sfk_ctx *c, const int *perm, const sfk_csr *A, const sfk_csr *B,
+                          int *err, const int **perm_copy, const int **pinv, const int **aci,
+                          const double **ava, const int **brp, const int **bci,
+                          const double **bva) {
+  hipStream_t st = c->stream;
+  const int m = (int)A->rows, n = (int)A->cols;
+  auto alloc = [&](void **q, size_t bytes) -> sfk_status {
+    HIPCHK(c, hipMalloc(q, std::max<size_t>(bytes, 256)));
+    c->xmem.push_back(*q);
+    return SFK_OK;
+  };
+  void *pc = nullptr, *pi = nullptr, *cnt = nullptr;
+  sfk_status e = alloc(&pc, sizeof(int) * (size_t)n);
+  if (e == SFK_OK) e = alloc(&pi, sizeof(int) * (size_t)n);
+  if (e == SFK_OK) e = alloc(&cnt, sizeof(int) * (size_t)n);   // released below
+  if (e != SFK_OK) return e;
+  HIPCHK(c, hipMemcpyAsync(pc, perm, sizeof(int) * (size_t)n, hipMemcpyDeviceToDevice, st));
+  HIPCHK(c, hipMemsetAsync(cnt, 0, sizeof(int) * (size_t)n, st));
+  HIPCHK(c, hipMemsetAsync(err, 0, sizeof(int), st));
+  launch_perm_check(static_cast<int *>(pc), n, static_cast<int *>(cnt), static_cast<int *>(pi), err,
+                    st);
+  int herr = 0;
+  HIPCHK(c, hipMemcpyAsync(&herr, err, sizeof(int), hipMemcpyDeviceToHost, st));
+  HIPCHK(c, hipStreamSynchronize(st));
+  hipFree(cnt);
+  c->xmem.pop_back();
+  if (herr) return fail(c, SFK_EINVAL, "perm must hold each of 0..n-1 exactly once");
+  void *ca = nullptr, *va = nullptr;
+  e = alloc(&ca, sizeof(int) * (size_t)A->nnz);
+  if (e == SFK_OK) e = alloc(&va, sizeof(double) * (size_t)A->nnz);
+  if (e != SFK_OK) return e;
+  launch_relabel_cols(A->rowptr, A->colind, A->val, m, (int)A->nnz, static_cast<int *>(pc),
+                      static_cast<int *>(ca), static_cast<double *>(va), err, st);
+  HIPCHK(c, hipGetLastError());
+  HIPCHK(c, hipMemcpyAsync(&herr, err, sizeof(int), hipMemcpyDeviceToHost, st));
+  HIPCHK(c, hipStreamSynchronize(st));
+  if (herr) return fail(c, SFK_EINVAL, "with perm, rows of A may have at most 4096 entries");
+  *perm_copy = static_cast<const int *>(pc);
+  *pinv = static_cast<const int *>(pi);
+  *aci = static_cast<const int *>(ca);
+  *ava = static_cast<const double *>(va);
+  *bci = nullptr;
+  if (B) {
+    void *rb = nullptr, *cb = nullptr, *vb = nullptr;
+    e = alloc(&rb, sizeof(int) * ((size_t)n + 1));
+    if (e == SFK_OK) e = alloc(&cb, sizeof(int) * (size_t)B->nnz);
+    if (e == SFK_OK) e = alloc(&vb, sizeof(double) * (size_t)B->nnz);
+    if (e != SFK_OK) return e;
+    launch_perm_rows(B->rowptr, B->colind, B->val, n, static_cast<int *>(pc), static_cast<int *>(rb),
+                     static_cast<int *>(cb), static_cast<double *>(vb), st);
+    HIPCHK(c, hipGetLastError());
+    *brp = static_cast<const int *>(rb);
+    *bci = static_cast<const int *>(cb);
+    *bva = static_cast<const double *>(vb);
+  }
+  return SFK_OK;
+}
+
 static sfk_status setup_instance(sfk_ctx *c, Inst &I, const sfk_csr *A, const sfk_csr *B,
                                  const double *b, void *workspace, size_t ws_bytes, int cus,
                                  int nws, const Grp *grp = nullptr, int r = 0) {
@@ -623,6 +695,8 @@ static sfk_status setup_instance(sfk_ctx *c, Inst &I, const sfk_csr *A, const sf
   I.chunk_scratch = at<int>(w, P.o_chunk);
 
   if (grp) {
+    D.skperm = p.method == SFK_SFLSMR ? c->gperm : nullptr;
+    D.pinv = c->gpinv;
     D.vs = grp->RS;
     D.W = grp->W + r;
     D.P = grp->P + r;
@@ -646,11 +720,24 @@ static sfk_status setup_instance(sfk_ctx *c, Inst &I, const sfk_csr *A, const sf
   HIPCHK(c, hipStreamSynchronize(st));
   if (herr) return fail(c, SFK_EINVAL, "invalid CSR structure (code %d): row pointers must rise "
                         "from 0 to nnz and column indices lie in range", herr);
+  if (p.perm) {
+    const int *pc = nullptr, *pinv = nullptr, *aci = nullptr, *brp = nullptr, *bci = nullptr;
+    const double *ava = nullptr, *bva = nullptr;
+    sfk_status e = relabel(c, p.perm, A, B, I.d_err, &pc, &pinv, &aci, &ava, &brp, &bci, &bva);
+    if (e != SFK_OK) return e;
+    I.user_aci = A->colind;
+    I.user_ava = A->val;
+    D.Aci = aci;
+    D.Ava = ava;
+    if (B) { D.Brp = brp; D.Bci = bci; D.Bva = bva; }
+    D.skperm = p.method == SFK_SFLSMR ? pc : nullptr;
+    D.pinv = pinv;
+  }
   if (!B) {
     int *brp = at<int>(w, P.o_brp);
     int *bci = at<int>(w, P.o_bci);
     double *bva = at<double>(w, P.o_bva);
-    launch_transpose(A->rowptr, A->colind, A->val, D.m, D.n, brp, bci, bva, at<int>(w, P.o_cursor),
+    launch_transpose(D.Arp, D.Aci, D.Ava, D.m, D.n, brp, bci, bva, at<int>(w, P.o_cursor),
                      I.d_err, st);
     D.Brp = brp; D.Bci = bci; D.Bva = bva;
   }
@@ -938,6 +1025,7 @@ static sfk_status same_params(const sfk_params &a, const sfk_params &b, int r) {
   else if (a.sketch == SFK_SK_SPARSE_SIGN && a.zeta != b.zeta) what = "zeta";
   else if (a.tau != b.tau) what = "tau";
   else if (a.tau == SFK_TAU_REWEIGHT_L1 && a.eps != b.eps) what = "eps";
+  else if (a.perm != b.perm) what = "perm";
   if (what)
     return fail(nullptr, SFK_EINVAL, "right-hand side %d: '%s' differs from right-hand side 0 "
                 "(right-hand sides sharing A and B may differ only in seed, instance, eta, "
@@ -1130,11 +1218,19 @@ extern "C" sfk_status sfk_init_multi(sfk_ctx **out, const sfk_csr *A, const sfk_
     HIPCHK(c, hipStreamSynchronize(st));
     if (herr) return fail(c, SFK_EINVAL, "invalid CSR structure (code %d): row pointers must rise "
                           "from 0 to nnz and column indices lie in range", herr);
+    if (p0.perm) {
+      const int *brp = nullptr, *bci = nullptr;
+      const double *bva = nullptr;
+      sfk_status e = relabel(c, p0.perm, A, B, err, &c->gperm, &c->gpinv, &G.Aci, &G.Ava, &brp, &bci,
+                             &bva);
+      if (e != SFK_OK) return e;
+      if (B) { G.Brp = brp; G.Bci = bci; G.Bva = bva; }
+    }
     if (!B) {
       int *brp = at<int>(w, o_brp);
       int *bci = at<int>(w, o_bci);
       double *bva = at<double>(w, o_bva);
-      launch_transpose(A->rowptr, A->colind, A->val, (int)m, (int)n, brp, bci, bva,
+      launch_transpose(G.Arp, G.Aci, G.Ava, (int)m, (int)n, brp, bci, bva,
                        at<int>(w, o_cursor), err, st);
       G.Brp = brp; G.Bci = bci; G.Bva = bva;
       HIPCHK(c, hipMemcpyAsync(&herr, err, sizeof(int), hipMemcpyDeviceToHost, st));
@@ -1336,7 +1432,10 @@ static sfk_status true_residual_impl(sfk_ctx *c, Inst &I, double *out_host) {
   double *xtmp = I.D.x;
   sfk_status s = solution_impl(c, I, I.k_done, xtmp);
   if (s != SFK_OK) return s;
-  launch_true_residual(I.D, xtmp, I.d_scalar, c->stream);
+  // x is in the caller's order: the residual uses the caller's A
+  Dev D = I.D;
+  if (I.user_aci) { D.Aci = I.user_aci; D.Ava = I.user_ava; }
+  launch_true_residual(D, xtmp, I.d_scalar, c->stream);
   HIPCHK(c, hipGetLastError());
   HIPCHK(c, hipMemcpyAsync(out_host, I.d_scalar, sizeof(double), hipMemcpyDeviceToHost, c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));

@@ -63,6 +63,11 @@ struct Dev {
   const int *Brp, *Bci; const double *Bva;
   const double *b;
   const int *Apart, *Bpart;    // nnz-balanced row ranges, nws + 1 entries each
+  // caller's order of the unknowns (sfk_params.perm): unknown j at position
+  // perm[j]; skperm = perm when the sketched vectors are n-vectors (sFLSMR),
+  // pinv the inverse (solutions are written back in the caller's order); both
+  // NULL without a perm
+  const int *skperm, *pinv;
   // SELL-64 copies (SpMV variant 1): slice s holds rows 64 s .. 64 s + 63
   // column-major, entry j of row 64 s + i at soff[s] + 64 j + i (padding:
   // value 0, column 0); slen[s] is a multiple of kSellPad

@@ -522,7 +522,7 @@ __global__ void __launch_bounds__(kWG) k_sketch_gather(const Dev *__restrict__ d
   double *dst = sketch_out(D, k);
   if (D.sketch == 2) {
     const int i = bm.y * kWG + threadIdx.x;
-    if (i < D.s) dst[i] = v[(size_t)i * vs];
+    if (i < D.s) dst[i] = v[(size_t)(D.skperm ? D.skperm[i] : i) * vs];
     return;
   }
   const int wave = (bm.y * kWG + threadIdx.x) >> 6;
@@ -570,7 +570,7 @@ __global__ void __launch_bounds__(kWG) k_srht_blocks(const Dev *__restrict__ dev
       double val = 0.0;
       if (g < D.d_sk) {
         const unsigned long long w = D.srht_d[g >> 6];
-        const double vg = v[(size_t)g * vs];
+        const double vg = v[(size_t)(D.skperm ? D.skperm[g] : g) * vs];
         val = ((w >> (g & 63)) & 1ull) ? -vg : vg;
       }
       x[j] = val;
@@ -617,7 +617,7 @@ __global__ void __launch_bounds__(kWG) k_srht_blocks(const Dev *__restrict__ dev
       double val = 0.0;
       if (g < D.d_sk) {
         const unsigned long long w = D.srht_d[g >> 6];
-        const double vg = v[(size_t)g * vs];
+        const double vg = v[(size_t)(D.skperm ? D.skperm[g] : g) * vs];
         val = ((w >> (g & 63)) & 1ull) ? -vg : vg;
       }
       u[i] = val;
@@ -886,7 +886,7 @@ __global__ void __launch_bounds__(kWG) k_solution(Dev D, int kk, const double *y
   if (i >= D.n) return;
   double xi = 0.0;
   for (int j = 0; j < kk; ++j) xi += cf[j] * zcol(D, j)[(size_t)i * D.vs];
-  x[i] = xi;
+  x[D.pinv ? D.pinv[i] : i] = xi;
 }
 
 // ||b - A x||^2: partials over the nnz-balanced row ranges, then one workgroup
@@ -918,6 +918,49 @@ __global__ void __launch_bounds__(kWG) k_finish_misc(Dev D, double *out) {
 // initialisation kernels
 // ---------------------------------------------------------------------------
 // CSR structure check: row pointers monotone from 0 to nnz, columns in range.
+// ---------------------------------------------------------------------------
+// Caller's order of the unknowns (initialisation only).  perm must hold each
+// of 0..n-1 once; pinv is its inverse.
+// ---------------------------------------------------------------------------
+__global__ void k_perm_check(const int *perm, int n, int *cnt, int *pinv, int *err) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= n) return;
+  const int v = perm[j];
+  if (v < 0 || v >= n) {
+    atomicOr(err, 8);
+    return;
+  }
+  if (atomicAdd(cnt + v, 1) != 0) atomicOr(err, 8);
+  else pinv[v] = j;
+}
+// A' = A with column j renamed perm[j] (rows keep their entries, re-sorted
+// afterwards by k_tr_sort)
+__global__ void k_relabel_cols(const int *ci, const double *va, int nnz, const int *perm, int *oci,
+                               double *ova) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= nnz) return;
+  oci[e] = perm[ci[e]];
+  ova[e] = va[e];
+}
+// B' = B with row i moved to row perm[i]: lengths (then an exclusive scan of
+// [len_0, ..., len_{n-1}, 0]), then one wave copies each row
+__global__ void k_perm_rowlen(const int *rp, int rows, const int *perm, int *orp) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < rows) orp[perm[i]] = rp[i + 1] - rp[i];
+  if (i == rows) orp[rows] = 0;
+}
+__global__ void k_perm_rows(const int *rp, const int *ci, const double *va, int rows,
+                            const int *perm, const int *orp, int *oci, double *ova) {
+  const int i = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const int lane = threadIdx.x & 63;
+  if (i >= rows) return;
+  const int e0 = rp[i], len = rp[i + 1] - e0, d0 = orp[perm[i]];
+  for (int t = lane; t < len; t += 64) {
+    oci[d0 + t] = ci[e0 + t];
+    ova[d0 + t] = va[e0 + t];
+  }
+}
+
 __global__ void k_csr_check(const int *rp, const int *ci, int rows, int cols, long long nnz,
                             int *err) {
   const int r = blockIdx.x * blockDim.x + threadIdx.x;
@@ -1068,7 +1111,7 @@ __global__ void __launch_bounds__(64) k_ss_fill(Dev D, const int *chunk_off) {
     for (int t = 0; t < D.zeta; ++t) {
       const int code = D.sk_code[(size_t)j * D.zeta + t];
       const int pos = cur[code >> 1]++;
-      D.sk_ent[pos] = (int)((unsigned)j | ((unsigned)(code & 1) << 31));
+      D.sk_ent[pos] = (int)((unsigned)(D.skperm ? D.skperm[j] : j) | ((unsigned)(code & 1) << 31));
     }
 }
 
@@ -1307,6 +1350,25 @@ void launch_transpose(const int *rp, const int *ci, const double *va, int rows, 
   hipLaunchKernelGGL(k_tr_fill, dim3((rows + 255) / 256), dim3(256), 0, st, rp, ci, va, rows,
                      cursor, bci, bva);
   hipLaunchKernelGGL(k_tr_sort, dim3(cols), dim3(256), 0, st, brp, bci, bva, cols, err);
+}
+void launch_perm_check(const int *perm, int n, int *cnt, int *pinv, int *err, hipStream_t st) {
+  hipLaunchKernelGGL(k_perm_check, dim3((n + 255) / 256), dim3(256), 0, st, perm, n, cnt, pinv, err);
+}
+// A' columns renamed and each row re-sorted (err bit 4: a row longer than 4096)
+void launch_relabel_cols(const int *rp, const int *ci, const double *va, int rows, int nnz,
+                         const int *perm, int *oci, double *ova, int *err, hipStream_t st) {
+  if (nnz > 0)
+    hipLaunchKernelGGL(k_relabel_cols, dim3((nnz + 255) / 256), dim3(256), 0, st, ci, va, nnz, perm,
+                       oci, ova);
+  if (rows > 0) hipLaunchKernelGGL(k_tr_sort, dim3(rows), dim3(256), 0, st, rp, oci, ova, rows, err);
+}
+void launch_perm_rows(const int *rp, const int *ci, const double *va, int rows, const int *perm,
+                      int *orp, int *oci, double *ova, hipStream_t st) {
+  hipLaunchKernelGGL(k_perm_rowlen, dim3((rows + 1 + 255) / 256), dim3(256), 0, st, rp, rows, perm, orp);
+  hipLaunchKernelGGL(k_scan_single, dim3(1), dim3(1024), 0, st, orp, rows + 1);
+  if (rows > 0)
+    hipLaunchKernelGGL(k_perm_rows, dim3((rows + 3) / 4), dim3(256), 0, st, rp, ci, va, rows, perm, orp,
+                       oci, ova);
 }
 void launch_sketch_build(const Dev &D, uint64_t key0, uint64_t key1, uint64_t key1_rows,
                          int *scratch, int *err, hipStream_t st) {

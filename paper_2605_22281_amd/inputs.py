@@ -276,6 +276,19 @@ def workload(name: str) -> Problem:
     return ct_problem(name=name, **kw)
 
 
+def tile_order(N: int, tile: int = 4) -> np.ndarray:
+    """An order of the N*N pixels (row-major index j) in tile x tile blocks:
+    pixel j goes to position perm[j]; blocks follow each other row-major and
+    pixels inside a block row-major (blocks at the edges may be partial).  Rays
+    crossing a block then read few consecutive positions in any direction."""
+    r, c = np.divmod(np.arange(N * N, dtype=np.int64), N)
+    key = ((r // tile) * ((N + tile - 1) // tile) + c // tile) * (tile * tile) + (r % tile) * tile + c % tile
+    order = np.argsort(key, kind="stable")          # position -> pixel
+    perm = np.empty(N * N, dtype=np.int32)
+    perm[order] = np.arange(N * N, dtype=np.int32)  # pixel -> position
+    return perm
+
+
 def batch_instances(count: int = 32, sides=(128, 192, 256, 384), seed: int = 4,
                     max_side: int | None = None) -> list[Problem]:
     """Heterogeneous batch: sides drawn uniformly, own phantom, noise U[0.5%, 3%].

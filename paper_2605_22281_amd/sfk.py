@@ -50,7 +50,8 @@ class Params(ctypes.Structure):
                 ("seed", ctypes.c_uint64), ("instance", ctypes.c_int32), ("tau", ctypes.c_int32),
                 ("eps", ctypes.c_double), ("eta", ctypes.c_double), ("noise_norm", ctypes.c_double),
                 ("tol", ctypes.c_double), ("driver", ctypes.c_int32), ("vw", ctypes.c_int32),
-                ("wg_per_cu", ctypes.c_int32), ("reserved", ctypes.c_int32 * 5)]
+                ("wg_per_cu", ctypes.c_int32), ("reserved0", ctypes.c_int32),
+                ("perm", ctypes.c_void_p), ("reserved", ctypes.c_int32 * 2)]
 
 
 _lib = None
@@ -122,7 +123,10 @@ def _check(status: int, ctx=None):
 
 def params(method="sflsqr", *, ell=2, maxit=50, sketch="sparse_sign", s=101, zeta=8, seed=0,
            instance=0, tau="identity", eps=1e-3, eta=1.01, noise_norm=0.0, tol=0.0,
-           driver="auto", vw=-2, wg_per_cu=0) -> Params:
+           driver="auto", vw=-2, wg_per_cu=0, perm=None) -> Params:
+    """perm: optional order of the unknowns, a torch.int32 device tensor of n
+    distinct values in [0, n) (unknown j stored at position perm[j] inside the
+    library; results come back in the caller's order)."""
     p = Params()
     lib().sfk_params_default(ctypes.byref(p))
     p.method = _METHODS[method] if isinstance(method, str) else int(method)
@@ -135,6 +139,12 @@ def params(method="sflsqr", *, ell=2, maxit=50, sketch="sparse_sign", s=101, zet
     p.eps, p.eta, p.noise_norm, p.tol = eps, eta, noise_norm, tol
     p.driver = _DRIVERS[driver] if isinstance(driver, str) else int(driver)
     p.vw, p.wg_per_cu = vw, wg_per_cu
+    if perm is not None:
+        import torch
+        if perm.dtype != torch.int32 or not perm.is_cuda or not perm.is_contiguous():
+            raise ValueError("perm must be a contiguous torch.int32 device tensor")
+        p.perm = perm.data_ptr()
+        p._perm = perm           # kept alive with the parameters (copied at init)
     return p
 
 

@@ -23,15 +23,17 @@ def rel(a, b):
 
 
 def gpu_run(P, method, kind, s, maxit, *, ell=2, tau="identity", eps=1e-3, zeta=8, seed=3001,
-            tol=0.0, noise=0.0, eta=1.01, stepwise=True, driver="auto", vw=-2):
-    """Runs the GPU solver; returns (ctx, X (n x k), rho, rhs_norm, status)."""
+            tol=0.0, noise=0.0, eta=1.01, stepwise=True, driver="auto", vw=-2, perm=None):
+    """Runs the GPU solver; returns (ctx, X (n x k), rho, rhs_norm, status).
+    perm: optional order of the unknowns (numpy int32, n entries)."""
     import torch
     from paper_2605_22281_amd import sfk
     A = sfk.to_device_csr(P.A)
     B = sfk.to_device_csr(P.B) if P.B is not None else None
     b = torch.from_numpy(np.ascontiguousarray(P.b)).cuda()
+    pt = torch.from_numpy(np.ascontiguousarray(perm, dtype=np.int32)).cuda() if perm is not None else None
     p = sfk.params(method, ell=ell, maxit=maxit, sketch=kind, s=s, zeta=zeta, seed=seed, tau=tau,
-                   eps=eps, tol=tol, noise_norm=noise, eta=eta, driver=driver, vw=vw)
+                   eps=eps, tol=tol, noise_norm=noise, eta=eta, driver=driver, vw=vw, perm=pt)
     ctx = sfk.init(A, B, b, p)
     X = []
     st = sfk.OK

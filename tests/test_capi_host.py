@@ -35,11 +35,30 @@ def test_every_declared_symbol_is_exported():
         assert hasattr(L, d)
 
 
-def test_params_layout_matches_header():
-    # sfk_params: 6 int32, uint64 seed, 2 int32, 4 double, 3 int32, 5 int32 reserved
+def test_params_layout_matches_header(tmp_path):
+    # sfk_params: 6 int32, uint64 seed, 2 int32, 4 double, 4 int32, perm pointer, 2 int32
     assert ctypes.sizeof(sfk.Params) == 104
     assert sfk.Params.seed.offset == 24 and sfk.Params.eps.offset == 40
     assert ctypes.sizeof(sfk.CSR) == 48
+    # the C compiler's layout of the header agrees field by field
+    fields = [f[0] for f in sfk.Params._fields_]
+    src = tmp_path / "layout.c"
+    src.write_text('#include <stdio.h>\n#include <stddef.h>\n#include "sfk.h"\nint main(void) {\n'
+                   '  printf("%zu\\n", sizeof(sfk_params));\n'
+                   + "".join(f'  printf("%zu\\n", offsetof(sfk_params, {f}));\n' for f in fields)
+                   + "  return 0;\n}\n")
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    got = [int(v) for v in subprocess.run([str(exe)], capture_output=True, text=True,
+                                          check=True).stdout.split()]
+    assert got[0] == ctypes.sizeof(sfk.Params)
+    assert got[1:] == [getattr(sfk.Params, f).offset for f in fields]
+
+
+def test_params_perm_requires_int32_device_tensor():
+    import torch
+    with pytest.raises(ValueError):
+        sfk.params(perm=torch.arange(4, dtype=torch.int32))      # host tensor
 
 
 def test_defaults():

@@ -92,3 +92,22 @@ def test_random_sparse_problem_has_empty_rows():
     lens = np.diff(P.A.indptr)
     assert (lens == 0).any()
     assert sp.issparse(P.B) and P.B.shape == (40, 100)
+
+
+def test_tile_order_is_a_permutation_grouping_blocks():
+    for N, T in ((8, 4), (10, 4), (24, 4), (16, 8)):
+        perm = inputs.tile_order(N, T)
+        assert perm.dtype == np.int32 and sorted(perm.tolist()) == list(range(N * N))
+        # the pixels of one full block occupy T*T consecutive positions
+        r0, c0 = T, 0
+        block = [(r0 + i) * N + c0 + j for i in range(T) for j in range(T)]
+        pos = np.sort(perm[block])
+        assert pos[-1] - pos[0] == T * T - 1
+    # renumbering the columns of a projector leaves each row's dot product unchanged
+    P = inputs.small_ct(12, 10)
+    perm = inputs.tile_order(12, 4)
+    x = np.random.default_rng(0).standard_normal(P.n)
+    xp = np.empty_like(x)
+    xp[perm] = x
+    Ap = sp.csr_matrix((P.A.data, perm[P.A.indices], P.A.indptr), shape=P.A.shape)
+    assert np.allclose(Ap @ xp, P.A @ x, rtol=1e-14, atol=1e-14)
