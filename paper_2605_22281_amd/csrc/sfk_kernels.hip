@@ -1194,13 +1194,15 @@ __global__ void k_sell_len(const int *rp, int rows, int nsl, int *slen) {
   slen[sl] = (mx + kSellPad - 1) / kSellPad * kSellPad;
 }
 
-// one thread per row: its entries at soff[s] + 64 j + i, padding after them
-__global__ void k_sell_fill(const int *rp, const int *ci, const double *va, int rows,
+// one thread per slice lane, the lanes of the last slice past the final row
+// included (the SpMV loads every lane of a slice): row entries at
+// soff[s] + 64 j + i, then padding (value 0, column 0) up to the slice length
+__global__ void k_sell_fill(const int *rp, const int *ci, const double *va, int rows, int nsl,
                             const int *soff, const int *slen, int *scol, double *sval) {
   const int r = blockIdx.x * blockDim.x + threadIdx.x;
-  if (r >= rows) return;
+  if (r >= nsl * kSellC) return;
   const int sl = r / kSellC, i = r % kSellC;
-  const int e0 = rp[r], len = rp[r + 1] - e0, L = slen[sl];
+  const int e0 = r < rows ? rp[r] : 0, len = r < rows ? rp[r + 1] - e0 : 0, L = slen[sl];
   const size_t base = (size_t)soff[sl] + i;
   for (int j = 0; j < L; ++j) {
     const bool in = j < len;
@@ -1324,8 +1326,10 @@ void launch_sell_len(const int *rp, int rows, int nsl, int *slen, hipStream_t st
 }
 void launch_sell_fill(const int *rp, const int *ci, const double *va, int rows, const int *soff,
                       const int *slen, int *scol, double *sval, hipStream_t st) {
-  hipLaunchKernelGGL(k_sell_fill, dim3((rows + 255) / 256), dim3(256), 0, st, rp, ci, va, rows,
-                     soff, slen, scol, sval);
+  const int nsl = (rows + kSellC - 1) / kSellC;
+  if (nsl > 0)
+    hipLaunchKernelGGL(k_sell_fill, dim3((nsl * kSellC + 255) / 256), dim3(256), 0, st, rp, ci, va,
+                       rows, nsl, soff, slen, scol, sval);
 }
 void launch_scan(int *a, int len, hipStream_t st) {
   hipLaunchKernelGGL(k_scan_single, dim3(1), dim3(1024), 0, st, a, len);
