@@ -106,6 +106,7 @@ struct sfk_ctx {
   int maxitmax = 0;
   bool sketch_after_C = false;      // an sFLSMR instance sketches B w_{k+1}
   bool any_rew = false;
+  int pending_side = -1;            // iteration whose sketch/LS waits for the next A stage
   bool multi = false;               // right-hand sides sharing A and B (stages via grp)
   Grp grp{};
   void *gws = nullptr;              // workspace of the shared arrays
@@ -171,34 +172,56 @@ static void run_stage(sfk_ctx *c, int stage, int k, hipStream_t st) {
   }
 }
 
-static void enqueue_iteration(sfk_ctx *c, int k) {
+// Sketch and least-squares update of iteration j on the side stream, after
+// what the main stream has been given so far.
+static void enqueue_side(sfk_ctx *c, int j) {
   const Launch &L = c->L;
   hipStream_t st = c->stream, sd = c->side;
-  const int r = k % sfk_ctx::kRing;
+  const int r = j % sfk_ctx::kRing;
+  hipEventRecord(c->ev_main[r], st);
+  hipStreamWaitEvent(sd, c->ev_main[r], 0);
+  int t = stage_begin(c, SFK_STAGE_SKETCH, sd);
+  launch_sketch(L, j, sd);
+  stage_end(c, t, sd);
+  hipEventRecord(c->ev_sk[r], sd);
+  t = stage_begin(c, SFK_STAGE_LS, sd);
+  launch_ls(L, j, sd);
+  stage_end(c, t, sd);
+  hipEventRecord(c->ev_ls[r], sd);
+}
+
+static void flush_side(sfk_ctx *c) {
+  if (c->pending_side >= 0) enqueue_side(c, c->pending_side);
+  c->pending_side = -1;
+}
+
+// One iteration.  The sketch of iteration k reads a raw product slot that the
+// product of iteration k + 2 overwrites, so it may start as late as one
+// iteration after its input exists: without the reweighting (which makes D(k)
+// wait for LS(k)) it goes out after the next sparse product, where its
+// workgroups run beside a light vector stage instead of taking CU slots from
+// a product's workgroups: sFLSQR after C(k), sFLSMR after A(k + 1).
+static void enqueue_iteration(sfk_ctx *c, int k) {
+  hipStream_t st = c->stream;
+  const bool late = !c->any_rew;
   if (k >= 3) hipStreamWaitEvent(st, c->ev_sk[(k - 2) % sfk_ctx::kRing], 0);
   int t = stage_begin(c, SFK_STAGE_SPMV_A, st);
   run_stage(c, kStageA, k, st);
   stage_end(c, t, st);
+  flush_side(c);
   t = stage_begin(c, SFK_STAGE_W_UPDATE, st);
   run_stage(c, kStageB, k, st);
   stage_end(c, t, st);
-  if (!c->sketch_after_C) hipEventRecord(c->ev_main[r], st);
+  if (!c->sketch_after_C && !late) enqueue_side(c, k);
   t = stage_begin(c, SFK_STAGE_SPMV_B, st);
   run_stage(c, kStageC, k, st);
   stage_end(c, t, st);
-  if (c->sketch_after_C) hipEventRecord(c->ev_main[r], st);
-
-  hipStreamWaitEvent(sd, c->ev_main[r], 0);
-  t = stage_begin(c, SFK_STAGE_SKETCH, sd);
-  launch_sketch(L, k, sd);
-  stage_end(c, t, sd);
-  hipEventRecord(c->ev_sk[r], sd);
-  t = stage_begin(c, SFK_STAGE_LS, sd);
-  launch_ls(L, k, sd);
-  stage_end(c, t, sd);
-  hipEventRecord(c->ev_ls[r], sd);
-
-  if (c->any_rew) hipStreamWaitEvent(st, c->ev_ls[r], 0);
+  if (!c->sketch_after_C && late) enqueue_side(c, k);
+  if (c->sketch_after_C) {
+    if (late) c->pending_side = k;
+    else enqueue_side(c, k);
+  }
+  if (c->any_rew) hipStreamWaitEvent(st, c->ev_ls[k % sfk_ctx::kRing], 0);
   t = stage_begin(c, SFK_STAGE_P_UPDATE, st);
   run_stage(c, kStageD, k, st);
   stage_end(c, t, st);
@@ -1327,6 +1350,7 @@ extern "C" sfk_status sfk_iterate(sfk_ctx *c, int32_t k, int32_t *iters_done_hos
     }
     ++nbatch;
   }
+  flush_side(c);
   if (enq > 0) HIPCHK(c, hipStreamWaitEvent(c->stream, c->ev_ls[(k0 + enq) % sfk_ctx::kRing], 0));
   HIPCHK(c, hipGetLastError());
   c->k_iter = k0 + enq;

@@ -33,16 +33,26 @@ def _horizon_compare(X, rho, orc, spread, kmax, label):
     return horizon
 
 
-def test_ct256_unmatched_sflsmr_srht():
-    """256^2 CT, 180 x 363, unmatched pixel-driven B, sFLSMR, SRHT s = 400, 200 steps."""
+@pytest.fixture(scope="module")
+def ct256():
     P = inputs.workload("ct256_unmatched")
-    say(f"case: ct256 sFLSMR SRHT full size m={P.m} n={P.n}")
+    orc, spread = rounding_spread(P, "sflsmr", "srht", 400, 40, seed=3002)
+    return P, orc, spread
+
+
+@pytest.mark.parametrize("order", ["natural", "tiles4"])
+def test_ct256_unmatched_sflsmr_srht(ct256, order):
+    """256^2 CT, 180 x 363, unmatched pixel-driven B, sFLSMR, SRHT s = 400, 200 steps,
+    in the image's row-major order and in the 4 x 4 tile order bench.py passes."""
+    P, orc, spread = ct256
+    say(f"case: ct256 sFLSMR SRHT full size m={P.m} n={P.n} order={order}")
     kcmp = 40
-    ctx, X, rho, rn, st = gpu_run(P, "sflsmr", "srht", 400, 200, seed=3002, stepwise=False)
+    perm = inputs.tile_order(P.N, 4) if order == "tiles4" else None
+    ctx, X, rho, rn, st = gpu_run(P, "sflsmr", "srht", 400, 200, seed=3002, stepwise=False,
+                                  perm=perm)
     assert X.shape[1] == 200
-    orc, spread = rounding_spread(P, "sflsmr", "srht", 400, kcmp, seed=3002)
     assert abs(rn - orc.rhs_norm) <= 1e-12 * orc.rhs_norm
-    horizon = _horizon_compare(X, rho, orc, spread, kcmp, "ct256")
+    horizon = _horizon_compare(X, rho, orc, spread, kcmp, f"ct256 {order}")
     assert horizon >= 10
     # properties at any size: the minimised objective over nested subspaces does
     # not increase; everything finite
