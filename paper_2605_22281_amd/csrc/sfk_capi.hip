@@ -91,7 +91,7 @@ struct sfk_ctx {
   std::vector<Inst> inst;
   hipStream_t stream = nullptr;
   hipStream_t side = nullptr;       // sketch + least-squares stream (default priority)
-  static constexpr int kRing = 4;   // iterations of synchronisation events kept
+  static constexpr int kRing = kRawSlots;   // iterations of synchronisation events kept
   hipEvent_t ev_main[kRing] = {}, ev_sk[kRing] = {}, ev_ls[kRing] = {};
   void *hdr = nullptr;              // device: instance descriptors and block maps
   Launch L{};
@@ -106,7 +106,7 @@ struct sfk_ctx {
   int maxitmax = 0;
   bool sketch_after_C = false;      // an sFLSMR instance sketches B w_{k+1}
   bool any_rew = false;
-  int pending_side = -1;            // iteration whose sketch/LS waits for the next A stage
+  int pending_side[2] = {-1, -1};   // iterations whose sketch/LS wait for the next flush point
   bool multi = false;               // right-hand sides sharing A and B (stages via grp)
   Grp grp{};
   void *gws = nullptr;              // workspace of the shared arrays
@@ -172,54 +172,69 @@ static void run_stage(sfk_ctx *c, int stage, int k, hipStream_t st) {
   }
 }
 
-// Sketch and least-squares update of iteration j on the side stream, after
-// what the main stream has been given so far.
-static void enqueue_side(sfk_ctx *c, int j) {
+// Sketches and least-squares updates of iterations js[0..n) (in order) on the
+// side stream, after what the main stream has been given so far (one event).
+static void enqueue_side(sfk_ctx *c, const int *js, int n) {
   const Launch &L = c->L;
   hipStream_t st = c->stream, sd = c->side;
-  const int r = j % sfk_ctx::kRing;
-  hipEventRecord(c->ev_main[r], st);
-  hipStreamWaitEvent(sd, c->ev_main[r], 0);
-  int t = stage_begin(c, SFK_STAGE_SKETCH, sd);
-  launch_sketch(L, j, sd);
-  stage_end(c, t, sd);
-  hipEventRecord(c->ev_sk[r], sd);
-  t = stage_begin(c, SFK_STAGE_LS, sd);
-  launch_ls(L, j, sd);
-  stage_end(c, t, sd);
-  hipEventRecord(c->ev_ls[r], sd);
+  const int r0 = js[0] % sfk_ctx::kRing;
+  hipEventRecord(c->ev_main[r0], st);
+  hipStreamWaitEvent(sd, c->ev_main[r0], 0);
+  for (int i = 0; i < n; ++i) {
+    const int j = js[i], r = j % sfk_ctx::kRing;
+    int t = stage_begin(c, SFK_STAGE_SKETCH, sd);
+    launch_sketch(L, j, sd);
+    stage_end(c, t, sd);
+    hipEventRecord(c->ev_sk[r], sd);
+    t = stage_begin(c, SFK_STAGE_LS, sd);
+    launch_ls(L, j, sd);
+    stage_end(c, t, sd);
+    hipEventRecord(c->ev_ls[r], sd);
+  }
 }
 
 static void flush_side(sfk_ctx *c) {
-  if (c->pending_side >= 0) enqueue_side(c, c->pending_side);
-  c->pending_side = -1;
+  int n = 0;
+  while (n < 2 && c->pending_side[n] >= 0) ++n;
+  if (n > 0) enqueue_side(c, c->pending_side, n);
+  c->pending_side[0] = c->pending_side[1] = -1;
 }
 
-// One iteration.  The sketch of iteration k reads a raw product slot that the
-// product of iteration k + 2 overwrites, so it may start as late as one
-// iteration after its input exists: without the reweighting (which makes D(k)
-// wait for LS(k)) it goes out after the next sparse product, where its
-// workgroups run beside a light vector stage instead of taking CU slots from
-// a product's workgroups: sFLSQR after C(k), sFLSMR after A(k + 1).
+static void defer_side(sfk_ctx *c, int k) {
+  if (c->pending_side[0] < 0) c->pending_side[0] = k;
+  else c->pending_side[1] = k;
+}
+
+// One iteration.  The sketch of iteration k reads raw product slot
+// k % kRawSlots, rewritten by iteration k + kRawSlots; the main stream waits
+// for the side stream once every four iterations (before A(k), k = 0 mod 4:
+// for the sketch of iteration k - 5, and with it every earlier one), and the
+// sketches go out in pairs after a sparse product, where their workgroups run
+// beside a light vector stage instead of taking CU slots from a product's:
+// sFLSQR after C(k), sFLSMR after A(k) (sketches k - 2 and k - 1), k even.
+// The reweighting needs LS(k) before D(k): then each sketch goes out as soon
+// as its input exists.
 static void enqueue_iteration(sfk_ctx *c, int k) {
+  static_assert(sfk_ctx::kRing >= 8 && kRawSlots >= 8, "side-stream lag");
   hipStream_t st = c->stream;
   const bool late = !c->any_rew;
-  if (k >= 3) hipStreamWaitEvent(st, c->ev_sk[(k - 2) % sfk_ctx::kRing], 0);
+  if (k >= 8 && k % 4 == 0) hipStreamWaitEvent(st, c->ev_sk[(k - 5) % sfk_ctx::kRing], 0);
   int t = stage_begin(c, SFK_STAGE_SPMV_A, st);
   run_stage(c, kStageA, k, st);
   stage_end(c, t, st);
-  flush_side(c);
+  if (late && c->sketch_after_C && k % 2 == 0) flush_side(c);
   t = stage_begin(c, SFK_STAGE_W_UPDATE, st);
   run_stage(c, kStageB, k, st);
   stage_end(c, t, st);
-  if (!c->sketch_after_C && !late) enqueue_side(c, k);
+  if (!late && !c->sketch_after_C) enqueue_side(c, &k, 1);
   t = stage_begin(c, SFK_STAGE_SPMV_B, st);
   run_stage(c, kStageC, k, st);
   stage_end(c, t, st);
-  if (!c->sketch_after_C && late) enqueue_side(c, k);
-  if (c->sketch_after_C) {
-    if (late) c->pending_side = k;
-    else enqueue_side(c, k);
+  if (late) {
+    defer_side(c, k);
+    if (!c->sketch_after_C && k % 2 == 0) flush_side(c);
+  } else if (c->sketch_after_C) {
+    enqueue_side(c, &k, 1);
   }
   if (c->any_rew) hipStreamWaitEvent(st, c->ev_ls[k % sfk_ctx::kRing], 0);
   t = stage_begin(c, SFK_STAGE_P_UPDATE, st);
@@ -420,8 +435,8 @@ static Plan make_plan(const sfk_csr *A, const sfk_csr *B, const sfk_params *p, i
   P.o_W = L_.take<double>(vm * (ell + 2) * m + 1);
   P.o_P = L_.take<double>(p->tau == SFK_TAU_REWEIGHT_L1 ? vm * (ell + 1) * n + 1 : 1);
   P.o_Z = L_.take<double>(vm * (mi + 1) * n + 1);      // z~_1 .. z~_{maxit+1}
-  P.o_wraw = L_.take<double>(vm * 2 * m + 1);
-  P.o_zraw = L_.take<double>(vm * 2 * std::max<int64_t>(n, (P.N + 1) / 2 + 1) + 1);
+  P.o_wraw = L_.take<double>(vm * kRawSlots * m + 1);
+  P.o_zraw = L_.take<double>(vm * kRawSlots * std::max<int64_t>(n, (P.N + 1) / 2 + 1) + 1);
   P.o_x = L_.take<double>(n);
   P.o_Apart = L_.take<int>(vm * (nw_alloc + 1) + 1);
   P.o_Bpart = L_.take<int>(vm * (nw_alloc + 1) + 1);
@@ -1190,8 +1205,8 @@ extern "C" sfk_status sfk_init_multi(sfk_ctx **out, const sfk_csr *A, const sfk_
   const size_t o_W = L_.take<double>((ell + 2) * m * RS);
   const size_t o_P = L_.take<double>(p0.tau == SFK_TAU_REWEIGHT_L1 ? (ell + 1) * n * RS : 1);
   const size_t o_Z = L_.take<double>((mi + 1) * n * RS);
-  const size_t o_wraw = L_.take<double>(2 * m * RS);
-  const size_t o_zraw = L_.take<double>(2 * std::max<int64_t>(n, (N + 1) / 2 + 1) * RS);
+  const size_t o_wraw = L_.take<double>(kRawSlots * m * RS);
+  const size_t o_zraw = L_.take<double>(kRawSlots * std::max<int64_t>(n, (N + 1) / 2 + 1) * RS);
   const size_t o_x = L_.take<double>(p0.tau == SFK_TAU_REWEIGHT_L1 ? n * RS : 1);
   const size_t o_Apart = L_.take<int>(nw + 1);
   const size_t o_Bpart = L_.take<int>(nw + 1);

@@ -14,6 +14,8 @@ constexpr int kWG = 256;                   // threads per vector-stage workgroup
 constexpr int kSpmvWG = 1024;              // threads per SpMV workgroup
 constexpr int kRowsLDS = 2048;             // SpMV results kept in LDS for the epilogue
 constexpr int kMaxQ = kMaxEll + 2;         // partial sums per workgroup and stage
+constexpr int kRawSlots = 8;   // raw products kept (the sketch of iteration k reads
+                                // slot k % kRawSlots until iteration k + kRawSlots)
 constexpr int kSrhtL = 2048;               // SRHT block length staged in LDS
 constexpr double kBreakdownTol = 1e-14;    // relative breakdown threshold
 constexpr int kSellC = 64;                 // rows per slice of the SELL copy (one per lane)
@@ -78,8 +80,8 @@ struct Dev {
   double *W;          // (ell + 2) * m, unnormalised w~_j
   double *P;          // (ell + 1) * n, unnormalised p~_j (unused when tau = I)
   double *Z;          // (maxit + 1) * n, z~_j (column j-1)
-  double *wraw;       // 2 * m, A z_k in slot k & 1
-  double *zraw;       // 2 * n, B w_{k+1} in slot k & 1
+  double *wraw;       // kRawSlots * m, A z_k in slot k % kRawSlots
+  double *zraw;       // kRawSlots * n, B w_{k+1} in slot k % kRawSlots
   double *x;          // n, current iterate (reweighting) / scratch
   // sketch
   int *sk_rp;         // s + 1   (sparse-sign, transposed: entries per sketch row)
@@ -164,8 +166,8 @@ struct Grp {
   double *W;          // (ell + 2) slots of m * RS
   double *P;          // (ell + 1) slots of n * RS (reweighting only)
   double *Z;          // (maxit + 1) columns of n * RS
-  double *wraw;       // 2 * m * RS
-  double *zraw;       // 2 * n * RS (at least)
+  double *wraw;       // kRawSlots * m * RS
+  double *zraw;       // kRawSlots * n * RS (at least)
   double *x;          // n * RS, x_k for the reweighting
   double *coef;       // RS * kCoefStride: coefficients of the stage about to run
   int *act;           // RS: 1 if the right-hand side takes part in that stage
@@ -178,8 +180,8 @@ struct Grp {
 __device__ __forceinline__ int wslot(const Dev &D, int j) { return j % (D.ell + 2); }
 __device__ __forceinline__ int pslot(const Dev &D, int j) { return j % (D.ell + 1); }
 // vectors of one instance; element i of each is at [i * D.vs]
-__device__ __forceinline__ double *wrawk(const Dev &D, int k) { return D.wraw + (size_t)(k & 1) * D.m * D.vs; }
-__device__ __forceinline__ double *zrawk(const Dev &D, int k) { return D.zraw + (size_t)(k & 1) * D.n * D.vs; }
+__device__ __forceinline__ double *wrawk(const Dev &D, int k) { return D.wraw + (size_t)(k & (kRawSlots - 1)) * D.m * D.vs; }
+__device__ __forceinline__ double *zrawk(const Dev &D, int k) { return D.zraw + (size_t)(k & (kRawSlots - 1)) * D.n * D.vs; }
 __device__ __forceinline__ double *wvec(const Dev &D, int j) { return D.W + (size_t)wslot(D, j) * D.m * D.vs; }
 __device__ __forceinline__ double *zcol(const Dev &D, int j) { return D.Z + (size_t)j * D.n * D.vs; }
 __device__ __forceinline__ double *pvec(const Dev &D, int j) {

@@ -154,7 +154,7 @@ __global__ void __launch_bounds__(kGWG) k_gspmm(Grp G, int k) {
   const double *va = ISA ? G.Ava : G.Bva;
   const int *part = ISA ? G.Apart : G.Bpart;
   const double *xin = (ISA ? gzcol(G, k - 1) : gwvec(G, k + 1)) + j;
-  double *yout = ISA ? G.wraw + (size_t)(k & 1) * G.m * RS : G.zraw + (size_t)(k & 1) * G.n * RS;
+  double *yout = ISA ? G.wraw + (size_t)(k & (kRawSlots - 1)) * G.m * RS : G.zraw + (size_t)(k & (kRawSlots - 1)) * G.n * RS;
   int j0, nwin;
   if (ISA) { j0 = max(1, k - G.ell); nwin = k - j0 + 1; }
   else { j0 = max(1, k + 1 - G.ell); nwin = k >= j0 ? k - j0 + 1 : 0; }
@@ -354,7 +354,7 @@ __global__ void __launch_bounds__(kWG) k_gcombine(Grp G, int k) {
   const double scale = G.coef[(size_t)j * kCoefStride];
   const int wid = blockIdx.x;
   const int rows = ISA ? G.m : G.n;
-  double *yout = ISA ? G.wraw + (size_t)(k & 1) * G.m * RS : G.zraw + (size_t)(k & 1) * G.n * RS;
+  double *yout = ISA ? G.wraw + (size_t)(k & (kRawSlots - 1)) * G.m * RS : G.zraw + (size_t)(k & (kRawSlots - 1)) * G.n * RS;
   int j0, nwin;
   if (ISA) { j0 = max(1, k - G.ell); nwin = k - j0 + 1; }
   else { j0 = max(1, k + 1 - G.ell); nwin = k >= j0 ? k - j0 + 1 : 0; }
@@ -555,7 +555,7 @@ __global__ void __launch_bounds__(kWG) k_gwupdate(Grp G, int k) {
     win[q] = (q < nwin) ? gwvec(G, j0 + q) : nullptr;
     cf[q] = (q < nwin) ? G.coef[(size_t)j * kCoefStride + q] : 0.0;
   }
-  const double *wr = G.wraw + (size_t)(k & 1) * G.m * RS;
+  const double *wr = G.wraw + (size_t)(k & (kRawSlots - 1)) * G.m * RS;
   double *out = gwvec(G, k + 1);
   int i0, i1;
   chunk_range(G.m, G.nwv, wid, i0, i1);
@@ -621,7 +621,7 @@ __global__ void __launch_bounds__(kWG) k_gpupdate(Grp G, int k) {
     cf[q] = (q < nwin) ? G.coef[(size_t)j * kCoefStride + q] : 0.0;
   }
   const bool rew = G.tau == 1;
-  const double *zr = G.zraw + (size_t)(k & 1) * G.n * RS;
+  const double *zr = G.zraw + (size_t)(k & (kRawSlots - 1)) * G.n * RS;
   double *zout = gzcol(G, k);
   double *pout = rew ? G.P + (size_t)((k + 1) % (G.ell + 1)) * G.n * RS : zout;
   const double eps2 = G.eps * G.eps;
