@@ -288,12 +288,14 @@ def main():
     log(f"bench: timed {done} iterations in {elapsed * 1e3:.2f} ms")
     if done != K:
         raise SystemExit(f"run ended after {done} of {K} iterations (status {st})")
-    sfk.destroy(ctx)
-
-    # same work again with HIP events around every stage kernel (library stream)
-    ctx = sfk.init(A, B, b, p)
     names = {0: "CSR-stream", 1: "SELL-64", 8: "8 lanes/row", 16: "16 lanes/row",
              32: "32 lanes/row", 64: "wave/row"}
+    timed_kernel = {op: names.get(v, str(v)) for op, v in zip(("A", "B"), sfk.spmv_variant(ctx))}
+    sfk.destroy(ctx)
+
+    # same work again with HIP events around every stage kernel (library stream);
+    # each init chooses its SpMV kernels by timing them, so both choices are kept
+    ctx = sfk.init(A, B, b, p)
     spmv_kernel = {op: names.get(v, str(v)) for op, v in zip(("A", "B"), sfk.spmv_variant(ctx))}
     sfk.set_timing(ctx, True)
     sfk.iterate(ctx, K)
@@ -315,7 +317,12 @@ def main():
     if os.path.exists(tr_file):
         try:
             tr = json.load(open(tr_file))
-            if tr.get("source_hash") == source_hash() and tr.get("workload") == args.workload:
+            # counters taken on the same kernel sources, workload, order of the
+            # unknowns and SpMV variant as this run
+            op = "A" if dom == "spmv_A" else "B"
+            if (tr.get("source_hash") == source_hash() and tr.get("workload") == args.workload
+                    and tr.get("order") == args.order
+                    and tr.get("variant", {}).get(dom) == spmv_kernel[op]):
                 traffic = tr.get("bytes_per_launch", {}).get(dom)
         except (OSError, ValueError):
             traffic = None
@@ -337,8 +344,10 @@ def main():
         "data": "synthetic",
         "config": {"workload": cfg["desc"], "m": P.m, "n": P.n, "nnz_A": nnzA, "nnz_B": nnzB,
                    "method": cfg["method"], "sketch": cfg["sketch"], "s": cfg["s"], "ell": ell,
-                   "driver": args.driver, "spmv_kernel": spmv_kernel, "order": args.order},
-        "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
+                   "driver": args.driver, "spmv_kernel": timed_kernel, "order": args.order},
+        "roofline": {"bound": "hbm", "kernel": dom,
+                     "variant": spmv_kernel["A" if dom == "spmv_A" else "B"],
+                     "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "bytes_per_launch": per_launch[dom], "avg_launch_ms": stage_avg[dom]},
         "iteration_GBps": iter_bytes / (ms_per_step * 1e-3) / 1e9,
