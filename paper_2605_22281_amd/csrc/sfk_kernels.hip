@@ -50,7 +50,11 @@ __device__ __forceinline__ void philox4x64_10(uint64_t c[4], uint64_t k0, uint64
 // kPerThread (value, column) pairs at once, gathers x, and leaves the products
 // in LDS; then one wave per row sums the row's segment of the chunk.  A row
 // that continues into the next chunk carries its partial sum.  The next
-// chunk's values and columns are loaded while the current one is reduced.
+// chunk's values and columns are loaded while the current one is reduced,
+// with ordinary (temporal) loads: an operator of up to ~200 MB of nonzeros can
+// then stay in the 256 MB last-level cache between iterations (measured on
+// the 256^2 projector: 70 us per product against 77 us with non-temporal
+// loads, while the larger back-projector keeps streaming through SELL-64).
 // y[r] = scale * sum_e val[e] x[col[e]]; also kept in ybuf for rows < kRowsLDS.
 // ---------------------------------------------------------------------------
 constexpr int kPerThread = 4;
@@ -73,7 +77,7 @@ __device__ void spmv_stream(const int *rp, const int *ci, const double *va, cons
 #pragma unroll
   for (int j = 0; j < kPerThread; ++j) {
     const int e = E0 + j * NT + tid;
-    if (e < E1) { vv[j] = __builtin_nontemporal_load(va + e); cc[j] = __builtin_nontemporal_load(ci + e); }
+    if (e < E1) { vv[j] = va[e]; cc[j] = ci[e]; }
     else { vv[j] = 0.0; cc[j] = -1; }
   }
   for (int cs = E0; cs < E1; cs += kChunk) {
@@ -84,7 +88,7 @@ __device__ void spmv_stream(const int *rp, const int *ci, const double *va, cons
 #pragma unroll
     for (int j = 0; j < kPerThread; ++j) {
       const int e = cs + kChunk + j * NT + tid;
-      if (e < E1) { vv[j] = __builtin_nontemporal_load(va + e); cc[j] = __builtin_nontemporal_load(ci + e); }
+      if (e < E1) { vv[j] = va[e]; cc[j] = ci[e]; }
       else { vv[j] = 0.0; cc[j] = -1; }
     }
     for (;;) {
