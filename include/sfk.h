@@ -96,8 +96,11 @@ typedef struct {
                           1 = SELL-64 copy built at init (64-row slices stored
                           column-major), 8/16/32/64 = lanes per row, -1 = lanes per
                           row chosen from the mean row length.  Right-hand sides
-                          sharing A and B (sfk_init_multi): -2 or 0 = column-sliced
-                          products, any other value = row kernel */
+                          sharing A and B (sfk_init_multi): column-sliced products
+                          with the block rows gathered from L2 (0), staged through
+                          LDS in units of nearby rows (2, where a unit's rows fit),
+                          or staged where the plan reuses each staged row at least
+                          3 times on average (-2); any other value = row kernel */
   int32_t wg_per_cu;   /* data-parallel workgroups per CU; 0 = automatic */
   int32_t reserved0;
   const int32_t *perm; /* optional order of the n unknowns: a device array of n
@@ -273,7 +276,8 @@ sfk_status sfk_stage_times(sfk_ctx *ctx, double *ms_host, int32_t *count_host);
 
 /* SpMV kernel in use for A and for B: 0 CSR-stream, 1 SELL-64, 64 a wave per
  * row with the whole row in flight, 8/16/32 lanes per row; for right-hand
- * sides sharing A and B -2 (column-sliced products) or -3 (row kernel).  A batch runs one kernel for
+ * sides sharing A and B -2 (column-sliced products gathering from L2), -4 (column-sliced
+ * products staged through LDS) or -3 (row kernel).  A batch runs one kernel for
  * all instances: instance 0's, or CSR-stream when the instances differ. */
 sfk_status sfk_spmv_variant(const sfk_ctx *ctx, int32_t *vwA_host, int32_t *vwB_host);
 

@@ -18,6 +18,7 @@
 
 #include "sfk.h"
 #include "sfk_dev.h"
+#include "sfk_units.h"
 
 namespace sfk {
 void launch_stage_A(const Launch &L, int k, hipStream_t st);
@@ -49,6 +50,7 @@ void launch_group_stage(const Grp &G, int stage, int k, hipStream_t st);
 int gspmm_blocks_per_cu(int RS);
 int gspmm_x_blocks_per_cu(int RS);
 int gspmm_x_units_per_block(int RS);
+int gspmm_l_blocks_per_cu(int RS);
 void launch_scan(int *a, int len, hipStream_t st);
 void launch_sell_len(const int *rp, int rows, int nsl, int *slen, hipStream_t st);
 void launch_spmv_core(const Dev &D, bool isa, int vw, const double *x, double *y, hipStream_t st);
@@ -289,7 +291,8 @@ static int64_t next_pow2(int64_t d) {
   return N;
 }
 
-static sfk_status validate(sfk_ctx *c, const sfk_csr *A, const sfk_csr *B, const sfk_params *p) {
+static sfk_status validate(sfk_ctx *c, const sfk_csr *A, const sfk_csr *B, const sfk_params *p,
+                           bool multi = false) {
   if (!A || !p) return fail(c, SFK_EINVAL, "A and params must not be NULL");
   const int64_t m = A->rows, n = A->cols;
   if (m < 1 || n < 1 || m >= (1ll << 30) || n >= (1ll << 30))
@@ -337,8 +340,10 @@ static sfk_status validate(sfk_ctx *c, const sfk_csr *A, const sfk_csr *B, const
   if (!(p->tol >= 0.0) || !std::isfinite(p->tol)) return fail(c, SFK_EINVAL, "tol must be finite >= 0");
   if (p->driver < 0 || p->driver > 2) return fail(c, SFK_EINVAL, "unknown driver %d", p->driver);
   if (p->vw != -2 && p->vw != -1 && p->vw != 0 && p->vw != 1 && p->vw != 8 && p->vw != 16 &&
-      p->vw != 32 && p->vw != 64)
-    return fail(c, SFK_EINVAL, "vw must be -2, -1, 0, 1, 8, 16, 32 or 64");
+      p->vw != 32 && p->vw != 64 && !(multi && p->vw == 2))
+    return fail(c, SFK_EINVAL, multi ? "vw must be -2, -1, 0, 1, 2, 8, 16, 32 or 64"
+                                     : "vw must be -2, -1, 0, 1, 8, 16, 32 or 64 (2 only for "
+                                       "right-hand sides sharing A and B)");
   if (p->wg_per_cu < 0 || p->wg_per_cu > 64) return fail(c, SFK_EINVAL, "wg_per_cu out of range");
   return SFK_OK;
 }
@@ -1071,13 +1076,89 @@ static sfk_status same_params(const sfk_params &a, const sfk_params &b, int r) {
   return SFK_OK;
 }
 
+// Automatic choice of the LDS-staged product: at least this many nonzeros per
+// staged source row.
+constexpr double kLdsMinReuse = 3.0;
+// Work of staging one source row, in records (one L2 read and one LDS write
+// of the row against one LDS read of it per record), for the workgroup split.
+constexpr int kStageWeight = 2;
+
+// Plans the LDS-staged units of a sliced operator on the host (sfk_units.h)
+// and, when taken (mode 2, or mode 1 with at least kLdsMinReuse nonzeros per
+// staged row), rewrites the record offsets and uploads the unit tables.
+// Leaves X on the gathers (SFK_OK) when a segment reads more source rows than
+// a staged block holds.  touch: the scanned slice-major segment ids.
+static sfk_status plan_lds(sfk_ctx *c, XOp &X, const int *touch, int RS, int cus, int mode,
+                           int64_t nrec) {
+  hipStream_t st = c->stream;
+  const int rowbytes = RS * (int)sizeof(double);
+  const int cap = kLdsRows / rowbytes;
+  const int nbw = std::max(1, cus * gspmm_l_blocks_per_cu(RS) / kXcds);
+  const int ng = gspmm_x_units_per_block(RS);
+  std::vector<int32_t> sbeg(X.NS + 1), seg(4 * (size_t)X.nseg);
+  std::vector<XNz> nz((size_t)nrec);
+  for (int q = 0; q < X.NS; ++q)
+    HIPCHK(c, hipMemcpyAsync(&sbeg[q], touch + (size_t)q * X.rows, sizeof(int),
+                             hipMemcpyDeviceToHost, st));
+  sbeg[X.NS] = X.nseg;
+  HIPCHK(c, hipMemcpyAsync(seg.data(), X.seg, sizeof(int4) * (size_t)X.nseg, hipMemcpyDeviceToHost, st));
+  HIPCHK(c, hipMemcpyAsync(nz.data(), X.nz, sizeof(XNz) * (size_t)nrec, hipMemcpyDeviceToHost, st));
+  HIPCHK(c, hipStreamSynchronize(st));
+  std::vector<int32_t> off((size_t)nrec);
+  for (int64_t e = 0; e < nrec; ++e) off[e] = nz[e].off;
+  UnitPlan P;
+  if (!plan_units(X.NS, sbeg.data(), seg.data(), off.data(), nrec, X.cols, rowbytes, kXPadOff,
+                  cap, kLdsRecs, ng, nbw, kStageWeight, P))
+    return SFK_OK;
+  if (mode == 1 && (double)P.nonzeros < kLdsMinReuse * (double)P.staged) return SFK_OK;
+  for (int64_t e = 0; e < nrec; ++e) {
+    nz[e].off = P.off[e];
+    nz[e].pad = P.endslot[e];
+  }
+  // device tables: every unit's records at a fixed stride of kLdsRecs (then
+  // padding), per unit and lane group the record range inside that block
+  const size_t nunit = P.unit.size() / 4;
+  std::vector<int32_t> meta, grp;
+  unit_tables(P, seg.data(), ng, meta, grp);
+  std::vector<XNz> urec(nunit * (size_t)kLdsRecs, XNz{0.0, kLdsRows, -1});
+  for (size_t u = 0; u < nunit; ++u) {
+    if (meta[2 * u + 1] > kLdsRecs) return fail(c, SFK_EDEVICE, "staged unit larger than planned");
+    std::copy(nz.begin() + meta[2 * u], nz.begin() + meta[2 * u] + meta[2 * u + 1],
+              urec.begin() + u * (size_t)kLdsRecs);
+  }
+  Layout L;
+  const size_t o_rec = L.take<XNz>(std::max<size_t>(urec.size(), 1));
+  const size_t o_stage = L.take<int>(std::max<size_t>(P.stage.size(), 1));
+  const size_t o_grp = L.take<int2>(std::max<size_t>(grp.size() / 2, 1));
+  const size_t o_upart = L.take<int>(P.upart.size());
+  void *mem = nullptr;
+  HIPCHK(c, hipMalloc(&mem, L.off));
+  c->xmem.push_back(mem);
+  HIPCHK(c, hipMemcpyAsync(at<XNz>(mem, o_rec), urec.data(), sizeof(XNz) * urec.size(),
+                           hipMemcpyHostToDevice, st));
+  HIPCHK(c, hipMemcpyAsync(at<int>(mem, o_stage), P.stage.data(), sizeof(int32_t) * P.stage.size(),
+                           hipMemcpyHostToDevice, st));
+  HIPCHK(c, hipMemcpyAsync(at<int2>(mem, o_grp), grp.data(), sizeof(int32_t) * grp.size(),
+                           hipMemcpyHostToDevice, st));
+  HIPCHK(c, hipMemcpyAsync(at<int>(mem, o_upart), P.upart.data(), sizeof(int32_t) * P.upart.size(),
+                           hipMemcpyHostToDevice, st));
+  HIPCHK(c, hipStreamSynchronize(st));
+  X.nbw = nbw;
+  X.urec = at<XNz>(mem, o_rec);
+  X.stage = at<int>(mem, o_stage);
+  X.ugrp = at<int2>(mem, o_grp);
+  X.upart = at<int>(mem, o_upart);
+  return SFK_OK;
+}
+
 // Column-sliced copy of one operator (rows x cols CSR on the device) for the
 // shared-operator products: slices of at most ~2 MB of source-block rows each,
 // a multiple of kXcds of them, nbs workgroups per slice.  *ok = false (and
 // SFK_OK) when the operator cannot be sliced (columns not increasing within a
 // row, or index ranges beyond 32-bit offsets): the row kernel is used instead.
 static sfk_status build_xop(sfk_ctx *c, XOp &X, const int *rp, const int *ci, const double *va,
-                            int rows, int cols, int64_t nnz, int RS, int cus, bool *ok) {
+                            int rows, int cols, int64_t nnz, int RS, int cus, int lds_mode,
+                            bool *ok) {
   hipStream_t st = c->stream;
   *ok = false;
   const int64_t cps = std::max<int64_t>(1, (int64_t)(2 << 20) / (RS * (int64_t)sizeof(double)));
@@ -1162,7 +1243,9 @@ static sfk_status build_xop(sfk_ctx *c, XOp &X, const int *rp, const int *ci, co
   X.nz = at<XNz>(mem, o_nz);
   X.crp = crp;
   X.part = at<double>(mem, o_part);
+  X.urec = nullptr;
   *ok = true;
+  if (lds_mode) return plan_lds(c, X, touch, RS, cus, lds_mode, (int64_t)nzpad + kXPad);
   return SFK_OK;
 }
 
@@ -1174,7 +1257,7 @@ extern "C" sfk_status sfk_init_multi(sfk_ctx **out, const sfk_csr *A, const sfk_
   if (R < 1 || R > kMaxRhs) return fail(nullptr, SFK_EINVAL, "R = %d not in [1, %d]", R, kMaxRhs);
   if (!A || !b_block || !p) return fail(nullptr, SFK_EINVAL, "A, b_block and params must not be NULL");
   for (int r = 0; r < R; ++r) {
-    sfk_status s = validate(nullptr, A, B, &p[r]);
+    sfk_status s = validate(nullptr, A, B, &p[r], true);
     if (s != SFK_OK) {
       g_err = "right-hand side " + std::to_string(r) + ": " + g_err;
       return s;
@@ -1282,12 +1365,15 @@ extern "C" sfk_status sfk_init_multi(sfk_ctx **out, const sfk_csr *A, const sfk_
     return SFK_OK;
   };
   if (s == SFK_OK) s = setup_group();
-  // sliced products (vw automatic or 0) unless the row kernel is asked for
-  // (any other vw) or an operator cannot be sliced
-  if (s == SFK_OK && (p0.vw == 0 || p0.vw == -2)) {
+  // sliced products (vw automatic, 0 or 2) unless the row kernel is asked for
+  // (any other vw) or an operator cannot be sliced; LDS-staged units where
+  // they pay (vw automatic), never (0) or wherever they fit (2)
+  if (s == SFK_OK && (p0.vw == 0 || p0.vw == -2 || p0.vw == 2)) {
     bool oka = false, okb = false;
-    s = build_xop(c, G.xa, G.Arp, G.Aci, G.Ava, (int)m, (int)n, nnzA, RS, cus, &oka);
-    if (s == SFK_OK && oka) s = build_xop(c, G.xb, G.Brp, G.Bci, G.Bva, (int)n, (int)m, nnzB, RS, cus, &okb);
+    const int lds = p0.vw == -2 ? 1 : p0.vw == 2 ? 2 : 0;
+    s = build_xop(c, G.xa, G.Arp, G.Aci, G.Ava, (int)m, (int)n, nnzA, RS, cus, lds, &oka);
+    if (s == SFK_OK && oka)
+      s = build_xop(c, G.xb, G.Brp, G.Bci, G.Bva, (int)n, (int)m, nnzB, RS, cus, lds, &okb);
     G.sliced = (oka && okb) ? 1 : 0;
   }
   for (int r = 0; r < R && s == SFK_OK; ++r) {
@@ -1568,9 +1654,10 @@ extern "C" sfk_status sfk_coefficients(sfk_ctx *c, double *H_host, double *T_hos
 
 extern "C" sfk_status sfk_spmv_variant(const sfk_ctx *c, int32_t *vwA_host, int32_t *vwB_host) {
   if (!c) return fail(nullptr, SFK_EINVAL, "NULL context");
-  const int g = c->grp.sliced ? -2 : -3;
-  if (vwA_host) *vwA_host = c->multi ? g : c->L.vwA;
-  if (vwB_host) *vwB_host = c->multi ? g : c->L.vwB;
+  const Grp &G = c->grp;
+  const int ga = !G.sliced ? -3 : G.xa.urec ? -4 : -2, gb = !G.sliced ? -3 : G.xb.urec ? -4 : -2;
+  if (vwA_host) *vwA_host = c->multi ? ga : c->L.vwA;
+  if (vwB_host) *vwB_host = c->multi ? gb : c->L.vwB;
   return SFK_OK;
 }
 

@@ -129,6 +129,8 @@ constexpr int kXPad = 256;                 // tail padding of the sliced nonzero
 constexpr int kXcds = 8;                   // L2 domains; workgroup b runs on domain b % 8
 constexpr int kSegAlign = 4;               // segments of the sliced copy padded to this many nonzeros
 constexpr int kXPadOff = 0x7fffff00;       // offset of a padding nonzero: past any source block
+constexpr int kLdsRows = 98304;            // bytes of staged source rows per unit (LDS)
+constexpr int kLdsRecs = 3584;             // records per unit (LDS)
 
 // Column-sliced copy of one operator for the shared-operator products.  The
 // columns are cut into NS ranges (a multiple of kXcds, each small enough that
@@ -138,7 +140,9 @@ constexpr int kXPadOff = 0x7fffff00;       // offset of a padding nonzero: past 
 // row of RS sums in a row-major slot (the partials of row i are slots
 // crp[i] .. crp[i + 1] - 1, in slice order); a combine pass adds them.
 // one nonzero of the sliced copy: value and byte offset of its source row in
-// the interleaved block (column * RS * 8)
+// the interleaved block (column * RS * 8); for the LDS-staged products the
+// offset is into the unit's staged block and `pad` is the segment's partial
+// slot on a segment's last record (-1 elsewhere)
 struct alignas(16) XNz {
   double v;
   int off;
@@ -154,6 +158,14 @@ struct XOp {
   const XNz *nz;        // nnz + kXPad (padding: value 0, offset 0)
   const int *crp;       // rows + 1
   double *part;         // nseg * RS, slot-major
+  // LDS-staged units (urec != nullptr; record offsets are byte offsets inside
+  // the unit's staged block, kLdsRows for padding)
+  int nbw;              // workgroups per slice
+  const XNz *urec;      // kLdsRecs per unit: the unit's records, then padding (value 0,
+                        // offset kLdsRows, slot -1)
+  const int *stage;     // kLdsRows / (8 RS) per unit: source rows of the staged block, -1 after
+  const int2 *ugrp;     // per unit and lane group: record range relative to the unit's first
+  const int *upart;     // NS * (nbw + 1): unit range of each workgroup of a slice
 };
 
 struct Grp {

@@ -217,7 +217,7 @@ __global__ void __launch_bounds__(kGWG) k_gspmm(Grp G, int k) {
 // VALU op); ds_bpermute reads any lane (the address is the source lane * 4).
 template <int I>
 __device__ __forceinline__ int row_bcast(int x) {
-  return __builtin_amdgcn_update_dpp(0, x, 0x150 + I, 0xf, 0xf, false);
+  return __builtin_amdgcn_mov_dpp(x, 0x150 + I, 0xf, 0xf, true);
 }
 __device__ __forceinline__ int row_bcast_i(int x, int i) {
   switch (i) {   // i is a compile-time constant at every call site after unrolling
@@ -336,6 +336,170 @@ __global__ void __launch_bounds__(kGWG) k_gspmm_x(Grp G, const int4 *__restrict_
             const int4 d = segs[ci + 1];
             nend = d.z;
             nslot = d.w;
+          }
+        }
+      }
+    }
+  }
+}
+
+// LDS-staged variant of k_gspmm_x for operators whose nearby rows read the
+// same source rows.  A unit is a run of consecutive segments of one slice
+// whose nonzeros read at most kLdsRows bytes of distinct source rows and hold
+// at most kLdsRecs records (planned at init).  The workgroup copies the unit's
+// source rows, its records and the record range of each lane group into LDS,
+// then each lane group streams its range as in k_gspmm_x with every read from
+// LDS: a record's offset is into the staged block (padding records: the zero
+// row after it), and a segment's last record carries the segment's partial
+// slot.  All global reads of the next unit (rows, records, ranges) are issued
+// when the current unit's compute starts and land in registers, so the compute
+// loop itself reads no global memory.  Partial slots and the summation order
+// inside a segment are those of k_gspmm_x.
+template <int RS, bool ISA>
+__global__ void __launch_bounds__(kGWG, 2) k_gspmm_l(Grp G, int k) {
+  constexpr int LPR = RS / 2;          // lanes per group = records per chunk
+  constexpr int NPS = 64 / LPR;        // groups per wave
+  constexpr int NWV = kGWG / 64;
+  constexpr int NG = NWV * NPS;        // groups per workgroup
+  constexpr int U = 4;                 // records per block (segments are padded to U)
+  constexpr int NB = LPR >= 2 * U ? 2 : 1;   // blocks per batch of LDS reads
+  constexpr int CAP = kLdsRows / (RS * 8);   // staged rows per unit
+  constexpr int XE = kLdsRows / 16;    // double2 slots of the staged block
+  constexpr int SPT = (XE + kGWG - 1) / kGWG;
+  constexpr int RPT = (kLdsRecs + kGWG - 1) / kGWG;
+  static_assert(LPR % (NB * U) == 0 && U == kSegAlign && kLdsRows % (8 * 64) == 0 && NG <= kGWG,
+                "chunk layout");
+  __shared__ double2 xs[XE + LPR];     // staged block, then a row of zeros
+  __shared__ XNz zs[kLdsRecs];         // the unit's records
+  __shared__ int2 gs[NG];              // record range of each lane group
+  __shared__ int s_any;
+  if (!any_active(G, &s_any)) return;
+  const XOp &X = ISA ? G.xa : G.xb;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int g = lane / LPR, li = lane % LPR;
+  const int j2 = li * 2;
+  const int gid = wv * NPS + g;
+  if (tid < LPR) xs[XE + tid] = make_double2(0.0, 0.0);
+  const int per_phase = kXcds * X.nbw;
+  const int b = blockIdx.x;
+  const int sl = kXcds * (b / per_phase) + b % kXcds;
+  const int q = (b % per_phase) / kXcds;
+  const int *up = X.upart + (size_t)sl * (X.nbw + 1) + q;
+  const int u0 = up[0], u1 = up[1];
+  if (u0 >= u1) return;
+  const double2 *xg = reinterpret_cast<const double2 *>(ISA ? gzcol(G, k - 1) : gwvec(G, k + 1));
+  // registers of the unit about to be written to LDS: block slot t = tid +
+  // i kGWG (pair t % LPR of staged row t / LPR), record tid + i kGWG, and
+  // the range of group tid
+  int sidx[SPT];                       // source rows of a later unit's slots, -1 past its rows
+  double bx[SPT], by[SPT];
+  unsigned vmask = 0;                  // bit i: slot i holds a staged row
+  double rv[RPT];                      // records: value, offset, partial slot
+  int ro[RPT], rs[RPT];
+  int2 gg = make_int2(0, 0);
+  auto load_idx = [&](int u) {
+#pragma unroll
+    for (int i = 0; i < SPT; ++i) {
+      const int t = tid + i * kGWG;
+      sidx[i] = t < CAP * LPR ? X.stage[(size_t)u * CAP + t / LPR] : -1;
+    }
+  };
+  auto load_unit = [&](int u) {        // uses sidx of unit u
+    vmask = 0;
+#pragma unroll
+    for (int i = 0; i < SPT; ++i) {
+      const int t = tid + i * kGWG;
+      double2 v = make_double2(0.0, 0.0);
+      if (sidx[i] >= 0) {
+        v = xg[(size_t)sidx[i] * LPR + t % LPR];
+        vmask |= 1u << i;
+      }
+      bx[i] = v.x;
+      by[i] = v.y;
+    }
+#pragma unroll
+    for (int i = 0; i < RPT; ++i) {
+      const int t = tid + i * kGWG;
+      XNz z{0.0, kLdsRows, -1};
+      if (t < kLdsRecs) z = X.urec[(size_t)u * kLdsRecs + t];
+      rv[i] = z.v;
+      ro[i] = z.off;
+      rs[i] = z.pad;
+    }
+    if (tid < NG) gg = X.ugrp[(size_t)u * NG + tid];
+  };
+  load_idx(u0);
+  load_unit(u0);
+  if (u0 + 1 < u1) load_idx(u0 + 1);
+  for (int u = u0; u < u1; ++u) {
+    __syncthreads();                   // every wave is done with the previous unit
+    // every global read issued so far is needed now (vmcnt 0; expcnt and
+    // lgkmcnt left alone): stating it here spares the reads of the next unit
+    // waits that only the loop's merged counts would ask for
+    __builtin_amdgcn_s_waitcnt(0x0F70);
+#pragma unroll
+    for (int i = 0; i < SPT; ++i)
+      if (vmask & (1u << i)) xs[tid + i * kGWG] = make_double2(bx[i], by[i]);
+#pragma unroll
+    for (int i = 0; i < RPT; ++i)
+      if (tid + i * kGWG < kLdsRecs) zs[tid + i * kGWG] = XNz{rv[i], ro[i], rs[i]};
+    if (tid < NG) gs[tid] = gg;
+    __syncthreads();
+    if (u + 1 < u1) {                  // the next unit, and the row list after it
+      load_unit(u + 1);
+      if (u + 2 < u1) load_idx(u + 2);
+    }
+    const int2 gr = gs[gid];
+    const int rec = gr.x, rend = gr.y;   // a whole number of blocks of U records
+    int steps = rend - rec;
+#pragma unroll
+    for (int o = LPR; o < 64; o <<= 1) steps = max(steps, __shfl_xor(steps, o, 64));
+    steps = __builtin_amdgcn_readfirstlane(steps);
+    double sx = 0.0, sy = 0.0;
+    for (int c0 = 0; c0 < steps; c0 += LPR) {
+      const int cr = rec + c0;
+      const XNz z = zs[min(cr + li, kLdsRecs - 1)];
+      const int zo = z.off, ze = z.pad;
+      const int zl = __double2loint(z.v), zh = __double2hiint(z.v);
+      // batches of NB blocks of U records (never more than the group's LPR
+      // records of the chunk): all LDS reads of a batch are issued before its
+      // products; a block past the group's range reads the zero row with
+      // value 0 (blocks lie wholly inside or outside the range)
+#pragma unroll
+      for (int b0 = 0; b0 < LPR; b0 += NB * U) {
+        if (c0 + b0 < steps) {
+          unsigned off[NB * U];
+          double v[NB * U];
+          double2 xv[NB * U];
+          bool live[NB];
+#pragma unroll
+          for (int h = 0; h < NB; ++h) live[h] = cr + b0 + h * U < rend;
+#pragma unroll
+          for (int uu = 0; uu < NB * U; ++uu) {
+            const int i = b0 + uu;
+            const unsigned o = (unsigned)group_bcast<LPR>(zo, i);
+            const double vv = __hiloint2double(group_bcast<LPR>(zh, i), group_bcast<LPR>(zl, i));
+            off[uu] = (live[uu / U] ? min(o, (unsigned)kLdsRows) : (unsigned)kLdsRows) + li * 16;
+            v[uu] = live[uu / U] ? vv : 0.0;
+          }
+#pragma unroll
+          for (int uu = 0; uu < NB * U; ++uu)
+            xv[uu] = *reinterpret_cast<const double2 *>(reinterpret_cast<const char *>(xs) + off[uu]);
+#pragma unroll
+          for (int h = 0; h < NB; ++h) {
+#pragma unroll
+            for (int uu = h * U; uu < h * U + U; ++uu) {
+              sx += v[uu] * xv[uu].x;
+              sy += v[uu] * xv[uu].y;
+            }
+            // slot if a segment ends with this block
+            const int es = group_bcast<LPR>(ze, b0 + h * U + U - 1);
+            if (live[h] && es >= 0) {
+              *reinterpret_cast<double2 *>(X.part + (size_t)es * RS + j2) = make_double2(sx, sy);
+              sx = sy = 0.0;
+            }
           }
         }
       }
@@ -681,8 +845,11 @@ template <int RS, bool ISA>
 static void launch_product(const Grp &G, int k, hipStream_t st) {
   if (G.sliced) {
     const XOp &X = ISA ? G.xa : G.xb;
-    hipLaunchKernelGGL((k_gspmm_x<RS, ISA>), dim3(X.NS * X.nbs), dim3(kGWG), 0, st, G, X.seg,
-                       X.spart, X.nz, k);
+    if (X.urec)
+      hipLaunchKernelGGL((k_gspmm_l<RS, ISA>), dim3(X.NS * X.nbw), dim3(kGWG), 0, st, G, k);
+    else
+      hipLaunchKernelGGL((k_gspmm_x<RS, ISA>), dim3(X.NS * X.nbs), dim3(kGWG), 0, st, G, X.seg,
+                         X.spart, X.nz, k);
     if (G.ell <= 2)
       hipLaunchKernelGGL((k_gcombine<RS, ISA, 3>), dim3(G.nwv), dim3(kWG), 0, st, G, k);
     else
@@ -743,6 +910,19 @@ int gspmm_x_blocks_per_cu(int RS) {
     case 16: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_gspmm_x<16, true>, kGWG, 0); break;
     case 32: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_gspmm_x<32, true>, kGWG, 0); break;
     default: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_gspmm_x<64, true>, kGWG, 0); break;
+  }
+  return (e == hipSuccess && nb > 0) ? nb : 1;
+}
+
+// resident LDS-staged SpMM workgroups per CU for interleave width RS
+int gspmm_l_blocks_per_cu(int RS) {
+  int nb = 0;
+  hipError_t e;
+  switch (RS) {
+    case 8: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_gspmm_l<8, true>, kGWG, 0); break;
+    case 16: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_gspmm_l<16, true>, kGWG, 0); break;
+    case 32: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_gspmm_l<32, true>, kGWG, 0); break;
+    default: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_gspmm_l<64, true>, kGWG, 0); break;
   }
   return (e == hipSuccess && nb > 0) ? nb : 1;
 }

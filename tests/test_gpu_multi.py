@@ -16,14 +16,15 @@ pytestmark = pytest.mark.gpu
 
 MAXIT = 12
 
-# (label, side, method, sketch, s, tau, R, unmatched B, stop test)
+# (label, side, method, sketch, s, tau, R, unmatched B, stop test, vw); vw 2 stages
+# the products through LDS (interleave widths 8, 16, 64 and 32 below), 0 gathers
 CASES = [
-    ("sflsqr-sparse_sign-R5-discrepancy", 24, "sflsqr", "sparse_sign", 90, "identity", 5, False, True),
-    ("sflsmr-srht-R9-unmatched-tol", 20, "sflsmr", "srht", 80, "identity", 9, True, True),
-    ("sflsqr-reweight-R4", 24, "sflsqr", "sparse_sign", 90, "reweight_l1", 4, False, False),
-    ("sflsqr-countsketch-R33-discrepancy", 16, "sflsqr", "countsketch", 60, "identity", 33, False, True),
-    ("sflsmr-reweight-R32-unmatched", 20, "sflsmr", "sparse_sign", 80, "reweight_l1", 32, True, False),
-    ("sflsqr-srht-R1", 16, "sflsqr", "srht", 50, "identity", 1, False, False),
+    ("sflsqr-sparse_sign-R5-discrepancy", 24, "sflsqr", "sparse_sign", 90, "identity", 5, False, True, 2),
+    ("sflsmr-srht-R9-unmatched-tol", 20, "sflsmr", "srht", 80, "identity", 9, True, True, 2),
+    ("sflsqr-reweight-R4", 24, "sflsqr", "sparse_sign", 90, "reweight_l1", 4, False, False, 0),
+    ("sflsqr-countsketch-R33-discrepancy", 16, "sflsqr", "countsketch", 60, "identity", 33, False, True, 2),
+    ("sflsmr-reweight-R32-unmatched", 20, "sflsmr", "sparse_sign", 80, "reweight_l1", 32, True, False, 2),
+    ("sflsqr-srht-R1", 16, "sflsqr", "srht", 50, "identity", 1, False, False, 0),
 ]
 
 
@@ -33,7 +34,7 @@ def _problem(side, unmatched, idx):
                              unmatched=unmatched)
 
 
-def _rhs_params(method, kind, s, tau, R, stop, dn, bnorm):
+def _rhs_params(method, kind, s, tau, R, stop, dn, bnorm, vw=-2):
     """Per right-hand side: seed, discrepancy noise (sFLSQR) or tolerance (sFLSMR),
     chosen so that the right-hand sides stop at different iterations."""
     from paper_2605_22281_amd import sfk
@@ -49,7 +50,7 @@ def _rhs_params(method, kind, s, tau, R, stop, dn, bnorm):
         else:
             tols.append(0.0)
         ps.append(sfk.params(method, maxit=MAXIT, sketch=kind, s=s, seed=9000 + 7 * r, tau=tau,
-                             eps=1e-2, noise_norm=noise, eta=1.01, tol=tol))
+                             eps=1e-2, noise_norm=noise, eta=1.01, tol=tol, vw=vw))
     return ps, tols
 
 
@@ -64,18 +65,19 @@ def _oracle(P, b, method, kind, s, tau, seed, tol):
 @pytest.mark.parametrize("case", CASES, ids=[c[0] for c in CASES])
 def test_shared_operator_rhs_match_oracle_and_plain(case):
     from paper_2605_22281_amd import sfk
-    label, side, method, kind, s, tau, R, unmatched, stop = case
+    label, side, method, kind, s, tau, R, unmatched, stop, vw = case
     say("case:", label)
     P = _problem(side, unmatched, CASES.index(case))
     levels = [0.02 + 0.02 * (r % 5) for r in range(R)]   # 2% .. 10%
     b, xt, dn = inputs.multi_rhs(P, R, seed=11, noise=levels)
     bnorm = np.linalg.norm(b, axis=1)
-    ps, tols = _rhs_params(method, kind, s, tau, R, stop, dn, bnorm)
+    ps, tols = _rhs_params(method, kind, s, tau, R, stop, dn, bnorm, vw)
     A = sfk.to_device_csr(P.A)
     B = sfk.to_device_csr(P.B) if P.B is not None else None
     bb = torch.from_numpy(np.ascontiguousarray(b)).cuda()
     ctx = sfk.init_multi(A, B, bb, ps)
     assert sfk.lib().sfk_batch_size(ctx.handle) == R
+    assert sfk.spmv_variant(ctx) == ((-4, -4) if vw == 2 else (-2, -2))
     done, all_stopped, st = sfk.iterate(ctx, MAXIT)
     assert done == MAXIT
     ks = []
@@ -207,8 +209,9 @@ def test_shared_operator_ct256_32_rhs():
 
 
 def test_shared_operator_row_kernel_matches_sliced():
-    """The row kernel on the caller's CSR arrays (vw != 0) and the column-sliced
-    products give the same iterates (both checked against the oracle)."""
+    """The row kernel on the caller's CSR arrays (vw = -1), the column-sliced
+    products gathering from L2 (vw = 0) or staged through LDS (vw = 2) and the
+    automatic choice give the same iterates (all checked against the oracle)."""
     from paper_2605_22281_amd import sfk
     say("case: shared operator, row kernel vs sliced products")
     P = _problem(24, True, 92)
@@ -218,15 +221,66 @@ def test_shared_operator_row_kernel_matches_sliced():
     B = sfk.to_device_csr(P.B)
     bb = torch.from_numpy(np.ascontiguousarray(b)).cuda()
     xs = {}
-    for vw in (-2, -1):
+    expect = {0: (-2, -2), 2: (-4, -4), -1: (-3, -3)}
+    for vw in (-2, 0, 2, -1):
         ps = [sfk.params("sflsmr", maxit=MAXIT, sketch="sparse_sign", s=90, seed=300 + r, vw=vw)
               for r in range(R)]
         ctx = sfk.init_multi(A, B, bb, ps)
         sfk.iterate(ctx, MAXIT)
-        assert sfk.spmv_variant(ctx) == ((-2, -2) if vw == -2 else (-3, -3))
+        kern = sfk.spmv_variant(ctx)
+        say(f"vw {vw}: kernels {kern}")
+        assert kern == expect[vw] if vw in expect else set(kern) <= {-2, -4}
         xs[vw] = [sfk.instance_solution(ctx, r, P.n).cpu().numpy() for r in range(R)]
     for r in range(R):
         S = sketches.SparseSign(P.n, 90, 8, 300 + r)
         orc = fgk.sketched_flexible(P.A, b[r], S, method="sflsmr", B=P.B, maxit=MAXIT, ell=2)
-        assert rel(xs[-2][r], orc.x) <= 1e-8 and rel(xs[-1][r], orc.x) <= 1e-8, r
-        assert rel(xs[-2][r], xs[-1][r]) <= 1e-10, r
+        for vw in xs:
+            assert rel(xs[vw][r], orc.x) <= 1e-8, (vw, r)
+            assert rel(xs[vw][r], xs[-1][r]) <= 1e-10, (vw, r)
+    # same partial slots and summation order inside a segment: staged and gathered agree
+    for r in range(R):
+        assert rel(xs[2][r], xs[0][r]) <= 1e-13, r
+
+
+def test_shared_operator_ct256_staged_products():
+    """256^2 CT in 4 x 4 pixel-tile order, 32 right-hand sides: the automatic
+    choice stages B's products through LDS; every right-hand side matches the
+    run that gathers from L2, and right-hand side 0 the oracle through its
+    reproducible horizon."""
+    from paper_2605_22281_amd import sfk
+    P = inputs.workload("ct256_unmatched")
+    R, K = 32, 12
+    say(f"case: ct256 shared operator, tile order, staged vs gathered products, {R} right-hand sides")
+    b, xt, dn = inputs.multi_rhs(P, R, seed=21)
+    A = sfk.to_device_csr(P.A)
+    B = sfk.to_device_csr(P.B)
+    bb = torch.from_numpy(np.ascontiguousarray(b)).cuda()
+    perm = torch.from_numpy(inputs.tile_order(P.N, 4)).cuda()
+    xs, rhos = {}, {}
+    for vw in (-2, 0):
+        ps = [sfk.params("sflsmr", maxit=K, sketch="srht", s=400, seed=3100 + r, vw=vw, perm=perm)
+              for r in range(R)]
+        ctx = sfk.init_multi(A, B, bb, ps)
+        kern = sfk.spmv_variant(ctx)
+        say(f"vw {vw}: kernels {kern}")
+        assert kern[1] == (-4 if vw == -2 else -2)
+        done, _, _ = sfk.iterate(ctx, K)
+        assert done == K
+        xs[vw] = [sfk.instance_solution(ctx, r, P.n).cpu().numpy() for r in range(R)]
+        rhos[vw] = sfk.instance_residual_norms(ctx, 0, K)[0]
+        sfk.destroy(ctx)
+    worst = max(rel(xs[-2][r], xs[0][r]) for r in range(R))
+    say(f"staged vs gathered at k = {K}: worst rel {worst:.2e}")
+    assert worst <= 1e-10
+    Pr = inputs.Problem(A=P.A, B=P.B, b=b[0], x_true=xt[0], noise_norm=float(dn[0]), N=P.N,
+                        n_angles=P.n_angles, n_det=P.n_det)
+    orc, spread = rounding_spread(Pr, "sflsmr", "srht", 400, K, seed=3100)
+    horizon = 0
+    for k in range(K):
+        tol = max(1e-8, 1e3 * spread[k])
+        er = abs(rhos[-2][k] - orc.rho[k]) / orc.rho[k]
+        assert er <= tol, (k, er, tol)
+        if tol == 1e-8:
+            horizon = k + 1
+    say(f"ct256 staged rhs 0: rho parity 1e-8 through k = {horizon}")
+    assert horizon >= 10
