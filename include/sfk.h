@@ -100,7 +100,7 @@ typedef struct {
                           with the block rows gathered from L2 (0), staged through
                           LDS in units of nearby rows (2, where a unit's rows fit),
                           or staged where the plan reuses each staged row at least
-                          3 times on average (-2); any other value = row kernel */
+                          5 times on average (-2); any other value = row kernel */
   int32_t wg_per_cu;   /* data-parallel workgroups per CU; 0 = automatic */
   int32_t reserved0;
   const int32_t *perm; /* optional order of the n unknowns: a device array of n

@@ -1078,7 +1078,7 @@ static sfk_status same_params(const sfk_params &a, const sfk_params &b, int r) {
 
 // Automatic choice of the LDS-staged product: at least this many nonzeros per
 // staged source row.
-constexpr double kLdsMinReuse = 3.0;
+constexpr double kLdsMinReuse = 5.0;
 // Work of staging one source row, in records (one L2 read and one LDS write
 // of the row against one LDS read of it per record), for the workgroup split.
 constexpr int kStageWeight = 2;
@@ -1108,7 +1108,7 @@ static sfk_status plan_lds(sfk_ctx *c, XOp &X, const int *touch, int RS, int cus
   for (int64_t e = 0; e < nrec; ++e) off[e] = nz[e].off;
   UnitPlan P;
   if (!plan_units(X.NS, sbeg.data(), seg.data(), off.data(), nrec, X.cols, rowbytes, kXPadOff,
-                  cap, kLdsRecs, ng, nbw, kStageWeight, P))
+                  cap, kLdsRecs - kSegAlign, ng, nbw, kStageWeight, P))
     return SFK_OK;
   if (mode == 1 && (double)P.nonzeros < kLdsMinReuse * (double)P.staged) return SFK_OK;
   for (int64_t e = 0; e < nrec; ++e) {
@@ -1122,7 +1122,8 @@ static sfk_status plan_lds(sfk_ctx *c, XOp &X, const int *touch, int RS, int cus
   unit_tables(P, seg.data(), ng, meta, grp);
   std::vector<XNz> urec(nunit * (size_t)kLdsRecs, XNz{0.0, kLdsRows, -1});
   for (size_t u = 0; u < nunit; ++u) {
-    if (meta[2 * u + 1] > kLdsRecs) return fail(c, SFK_EDEVICE, "staged unit larger than planned");
+    if (meta[2 * u + 1] > kLdsRecs - kSegAlign)
+      return fail(c, SFK_EDEVICE, "staged unit larger than planned");
     std::copy(nz.begin() + meta[2 * u], nz.begin() + meta[2 * u] + meta[2 * u + 1],
               urec.begin() + u * (size_t)kLdsRecs);
   }

@@ -348,10 +348,12 @@ __global__ void __launch_bounds__(kGWG) k_gspmm_x(Grp G, const int4 *__restrict_
 // whose nonzeros read at most kLdsRows bytes of distinct source rows and hold
 // at most kLdsRecs records (planned at init).  The workgroup copies the unit's
 // source rows, its records and the record range of each lane group into LDS,
-// then each lane group streams its range as in k_gspmm_x with every read from
-// LDS: a record's offset is into the staged block (padding records: the zero
-// row after it), and a segment's last record carries the segment's partial
-// slot.  All global reads of the next unit (rows, records, ranges) are issued
+// then each lane group streams its range with every read from LDS: all lanes
+// of a group read the current records themselves (no cross-lane broadcast), a
+// record's offset is into the staged block (padding records: the zero row
+// after it), and a segment's last record carries the segment's partial slot.
+// The last kSegAlign record slots of a unit hold padding, read by blocks past a
+// group's range.  All global reads of the next unit (rows, records, ranges) are issued
 // when the current unit's compute starts and land in registers, so the compute
 // loop itself reads no global memory.  Partial slots and the summation order
 // inside a segment are those of k_gspmm_x.
@@ -362,13 +364,12 @@ __global__ void __launch_bounds__(kGWG, 2) k_gspmm_l(Grp G, int k) {
   constexpr int NWV = kGWG / 64;
   constexpr int NG = NWV * NPS;        // groups per workgroup
   constexpr int U = 4;                 // records per block (segments are padded to U)
-  constexpr int NB = LPR >= 2 * U ? 2 : 1;   // blocks per batch of LDS reads
+  constexpr int NB = 2;                // blocks per batch of LDS reads
   constexpr int CAP = kLdsRows / (RS * 8);   // staged rows per unit
   constexpr int XE = kLdsRows / 16;    // double2 slots of the staged block
   constexpr int SPT = (XE + kGWG - 1) / kGWG;
   constexpr int RPT = (kLdsRecs + kGWG - 1) / kGWG;
-  static_assert(LPR % (NB * U) == 0 && U == kSegAlign && kLdsRows % (8 * 64) == 0 && NG <= kGWG,
-                "chunk layout");
+  static_assert(U == kSegAlign && kLdsRows % (8 * 64) == 0 && NG <= kGWG, "block layout");
   __shared__ double2 xs[XE + LPR];     // staged block, then a row of zeros
   __shared__ XNz zs[kLdsRecs];         // the unit's records
   __shared__ int2 gs[NG];              // record range of each lane group
@@ -458,49 +459,35 @@ __global__ void __launch_bounds__(kGWG, 2) k_gspmm_l(Grp G, int k) {
     for (int o = LPR; o < 64; o <<= 1) steps = max(steps, __shfl_xor(steps, o, 64));
     steps = __builtin_amdgcn_readfirstlane(steps);
     double sx = 0.0, sy = 0.0;
-    for (int c0 = 0; c0 < steps; c0 += LPR) {
-      const int cr = rec + c0;
-      const XNz z = zs[min(cr + li, kLdsRecs - 1)];
-      const int zo = z.off, ze = z.pad;
-      const int zl = __double2loint(z.v), zh = __double2hiint(z.v);
-      // batches of NB blocks of U records (never more than the group's LPR
-      // records of the chunk): all LDS reads of a batch are issued before its
-      // products; a block past the group's range reads the zero row with
-      // value 0 (blocks lie wholly inside or outside the range)
+    // batches of NB blocks of U records; every lane of a group reads the
+    // block's records itself (one address per group), and a block past the
+    // group's range reads the padding records at the end of the unit's block
+    for (int c0 = 0; c0 < steps; c0 += NB * U) {
+      int base[NB];
 #pragma unroll
-      for (int b0 = 0; b0 < LPR; b0 += NB * U) {
-        if (c0 + b0 < steps) {
-          unsigned off[NB * U];
-          double v[NB * U];
-          double2 xv[NB * U];
-          bool live[NB];
+      for (int h = 0; h < NB; ++h) {
+        const int r = rec + c0 + h * U;
+        base[h] = r < rend ? r : kLdsRecs - U;
+      }
+      XNz zz[NB * U];
 #pragma unroll
-          for (int h = 0; h < NB; ++h) live[h] = cr + b0 + h * U < rend;
+      for (int uu = 0; uu < NB * U; ++uu) zz[uu] = zs[base[uu / U] + uu % U];
+      double2 xv[NB * U];
 #pragma unroll
-          for (int uu = 0; uu < NB * U; ++uu) {
-            const int i = b0 + uu;
-            const unsigned o = (unsigned)group_bcast<LPR>(zo, i);
-            const double vv = __hiloint2double(group_bcast<LPR>(zh, i), group_bcast<LPR>(zl, i));
-            off[uu] = (live[uu / U] ? min(o, (unsigned)kLdsRows) : (unsigned)kLdsRows) + li * 16;
-            v[uu] = live[uu / U] ? vv : 0.0;
-          }
+      for (int uu = 0; uu < NB * U; ++uu)
+        xv[uu] = *reinterpret_cast<const double2 *>(reinterpret_cast<const char *>(xs) +
+                                                     min((unsigned)zz[uu].off, (unsigned)kLdsRows) + li * 16);
 #pragma unroll
-          for (int uu = 0; uu < NB * U; ++uu)
-            xv[uu] = *reinterpret_cast<const double2 *>(reinterpret_cast<const char *>(xs) + off[uu]);
+      for (int h = 0; h < NB; ++h) {
 #pragma unroll
-          for (int h = 0; h < NB; ++h) {
-#pragma unroll
-            for (int uu = h * U; uu < h * U + U; ++uu) {
-              sx += v[uu] * xv[uu].x;
-              sy += v[uu] * xv[uu].y;
-            }
-            // slot if a segment ends with this block
-            const int es = group_bcast<LPR>(ze, b0 + h * U + U - 1);
-            if (live[h] && es >= 0) {
-              *reinterpret_cast<double2 *>(X.part + (size_t)es * RS + j2) = make_double2(sx, sy);
-              sx = sy = 0.0;
-            }
-          }
+        for (int uu = h * U; uu < h * U + U; ++uu) {
+          sx += zz[uu].v * xv[uu].x;
+          sy += zz[uu].v * xv[uu].y;
+        }
+        const int es = zz[h * U + U - 1].pad;   // slot if a segment ends with this block
+        if (es >= 0) {
+          *reinterpret_cast<double2 *>(X.part + (size_t)es * RS + j2) = make_double2(sx, sy);
+          sx = sy = 0.0;
         }
       }
     }
