@@ -76,6 +76,10 @@ struct Dev {
   int Ansl, Bnsl;
   const int *Asoff, *Aslen, *Ascol; const double *Asval;
   const int *Bsoff, *Bslen, *Bscol; const double *Bsval;
+  // 16-bit copies of the column indices of an operator with at most 65536
+  // columns (read by CSR-stream and SELL-64 instead of the 32-bit arrays), or
+  // nullptr
+  const uint16_t *Aci16, *Bci16, *Ascol16, *Bscol16;
   // vectors
   double *W;          // (ell + 2) * m, unnormalised w~_j
   double *P;          // (ell + 1) * n, unnormalised p~_j (unused when tau = I)

@@ -61,8 +61,9 @@ constexpr int kPerThread = 4;
 constexpr int kChunk = kSpmvWG * kPerThread;
 constexpr int kRowWin = 1024;   // row pointers staged per pass
 
-__device__ void spmv_stream(const int *rp, const int *ci, const double *va, const double *xin,
-                            double *yout, double *ybuf, int r0, int r1, double scale) {
+__device__ void spmv_stream(const int *rp, const int *ci, const uint16_t *c16, const double *va,
+                            const double *xin, double *yout, double *ybuf, int r0, int r1,
+                            double scale) {
   constexpr int NT = kSpmvWG;
   __shared__ double prod[kChunk];
   __shared__ int rps[kRowWin + 1];
@@ -77,7 +78,7 @@ __device__ void spmv_stream(const int *rp, const int *ci, const double *va, cons
 #pragma unroll
   for (int j = 0; j < kPerThread; ++j) {
     const int e = E0 + j * NT + tid;
-    if (e < E1) { vv[j] = va[e]; cc[j] = ci[e]; }
+    if (e < E1) { vv[j] = va[e]; cc[j] = c16 ? (int)c16[e] : ci[e]; }
     else { vv[j] = 0.0; cc[j] = -1; }
   }
   for (int cs = E0; cs < E1; cs += kChunk) {
@@ -88,7 +89,7 @@ __device__ void spmv_stream(const int *rp, const int *ci, const double *va, cons
 #pragma unroll
     for (int j = 0; j < kPerThread; ++j) {
       const int e = cs + kChunk + j * NT + tid;
-      if (e < E1) { vv[j] = va[e]; cc[j] = ci[e]; }
+      if (e < E1) { vv[j] = va[e]; cc[j] = c16 ? (int)c16[e] : ci[e]; }
       else { vv[j] = 0.0; cc[j] = -1; }
     }
     for (;;) {
@@ -186,7 +187,8 @@ __device__ void spmv_rows64(const int *__restrict__ rp, const int *__restrict__ 
 // order.  Rows [r0, r1) of the workgroup are returned for the epilogue.
 // ---------------------------------------------------------------------------
 __device__ void spmv_sell(const int *__restrict__ soff, const int *__restrict__ slen,
-                          const int *__restrict__ scol, const double *__restrict__ sval,
+                          const int *__restrict__ scol, const uint16_t *__restrict__ scol16,
+                          const double *__restrict__ sval,
                           const double *__restrict__ xin, double *yout, double *ybuf, int s0,
                           int s1, int rows, double scale, double *lds_part) {
   constexpr int NWV = kSpmvWG / 64;
@@ -207,7 +209,7 @@ __device__ void spmv_sell(const int *__restrict__ soff, const int *__restrict__ 
       for (int u = 0; u < kSellPad; ++u) {
         const int e = base + (j + u) * kSellC + lane;
         v[u] = __builtin_nontemporal_load(sval + e);
-        c[u] = __builtin_nontemporal_load(scol + e);
+        c[u] = scol16 ? (int)__builtin_nontemporal_load(scol16 + e) : __builtin_nontemporal_load(scol + e);
       }
       double xv[kSellPad];
 #pragma unroll
@@ -296,14 +298,15 @@ __global__ void __launch_bounds__(kSpmvWG, 8) k_spmv(const Dev *__restrict__ dev
     r1 = min(rows, s1 * kSellC);
     __shared__ double lds_part[(kSpmvWG / 64) * kSellC];
     spmv_sell(ISA ? D.Asoff : D.Bsoff, ISA ? D.Aslen : D.Bslen, ISA ? D.Ascol : D.Bscol,
-              ISA ? D.Asval : D.Bsval, xin, yout, ybuf, s0, s1, rows, scale, lds_part);
+              ISA ? D.Ascol16 : D.Bscol16, ISA ? D.Asval : D.Bsval, xin, yout, ybuf, s0, s1,
+              rows, scale, lds_part);
   } else {
     r0 = part[wid];
     r1 = part[wid + 1];
   }
   if (VW == 1) {
   } else if (VW == 0) {
-    spmv_stream(rp, ci, va, xin, yout, ybuf, r0, r1, scale);
+    spmv_stream(rp, ci, ISA ? D.Aci16 : D.Bci16, va, xin, yout, ybuf, r0, r1, scale);
   } else if (VW == 64) {
     spmv_rows64(rp, ci, va, xin, yout, ybuf, r0, r1, scale);
   } else {
@@ -384,11 +387,12 @@ __global__ void __launch_bounds__(kSpmvWG, 8) k_spmv_core(Dev D, const double *_
     const int s0 = (int)((long long)wid * nsl / D.nws), s1 = (int)((long long)(wid + 1) * nsl / D.nws);
     __shared__ double lds_part[(kSpmvWG / 64) * kSellC];
     spmv_sell(ISA ? D.Asoff : D.Bsoff, ISA ? D.Aslen : D.Bslen, ISA ? D.Ascol : D.Bscol,
-              ISA ? D.Asval : D.Bsval, xin, yout, ybuf, s0, s1, rows, 1.0, lds_part);
+              ISA ? D.Ascol16 : D.Bscol16, ISA ? D.Asval : D.Bsval, xin, yout, ybuf, s0, s1,
+              rows, 1.0, lds_part);
   } else if (VW == 64) {
     spmv_rows64(rp, ci, va, xin, yout, ybuf, part[wid], part[wid + 1], 1.0);
   } else {
-    spmv_stream(rp, ci, va, xin, yout, ybuf, part[wid], part[wid + 1], 1.0);
+    spmv_stream(rp, ci, ISA ? D.Aci16 : D.Bci16, va, xin, yout, ybuf, part[wid], part[wid + 1], 1.0);
   }
 }
 
@@ -1325,6 +1329,17 @@ void launch_spmv_core(const Dev &D, bool isa, int vw, const double *x, double *y
   }
 }
 
+// 16-bit copy of column indices known to lie in [0, 65536)
+__global__ void k_to_u16(const int *in, uint16_t *out, long long n) {
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+       i += (long long)gridDim.x * blockDim.x)
+    out[i] = (uint16_t)in[i];
+}
+void launch_to_u16(const int *in, uint16_t *out, long long n, hipStream_t st) {
+  if (n > 0)
+    hipLaunchKernelGGL(k_to_u16, dim3((unsigned)std::min<long long>((n + 255) / 256, 65536)),
+                       dim3(256), 0, st, in, out, n);
+}
 void launch_sell_len(const int *rp, int rows, int nsl, int *slen, hipStream_t st) {
   hipLaunchKernelGGL(k_sell_len, dim3((nsl + 255) / 256), dim3(256), 0, st, rp, rows, nsl, slen);
 }

@@ -139,6 +139,19 @@ def test_parity_long_and_empty_rows(vw):
     compare(X, rho, orc, 9, label=f"long rows vw{vw}")
 
 
+@pytest.mark.parametrize("vw", [0, 1])
+def test_parity_wide_operator_32bit_columns(vw):
+    # A with 70000 columns keeps 32-bit column indices in CSR-stream and
+    # SELL-64; B (3000 columns) reads the 16-bit copies
+    from paper_2605_22281_amd import sfk
+    P = inputs.random_sparse_problem(3000, 70000, 0.0008, seed=29, unmatched=True)
+    say(f"case: wide 3000x70000 nnz={P.A.nnz} vw={vw}")
+    ctx, X, rho, _, _ = gpu_run(P, "sflsqr", "sparse_sign", 120, 8, vw=vw)
+    assert sfk.spmv_variant(ctx)[0] == vw
+    orc = oracle_run(P, "sflsqr", "sparse_sign", 120, 8)
+    compare(X, rho, orc, 8, label=f"wide vw{vw}")
+
+
 def test_identity_sketch_is_flsqr_type():
     # S = I (s = m): sFLSQR minimises the true residual over range(Z_k)
     P = inputs.small_ct(12, 10, n_det=17, unmatched=True)
