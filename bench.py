@@ -66,11 +66,20 @@ def source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def spmv_bytes(nnz: int, rows: int, cols: int, out_len: int, window: int) -> int:
+def spmv_bytes(nnz: int, rows: int, cols: int, out_len: int, window: int,
+               idx_bytes: int = 4) -> int:
     """Algorithmic bytes of one CSR SpMV launch with the fused window dots:
-    12 B per nonzero (value + column), 4 B per row pointer, the gathered vector
-    once, the output once, and the window vectors once."""
-    return 12 * nnz + 4 * (rows + 1) + 8 * cols + 8 * out_len + 8 * out_len * window
+    8 B per nonzero value plus its column index (idx_bytes: 2 where the kernel
+    reads the 16-bit copy), 4 B per row pointer, the gathered vector once, the
+    output once, and the window vectors once."""
+    return ((8 + idx_bytes) * nnz + 4 * (rows + 1) + 8 * cols + 8 * out_len
+            + 8 * out_len * window)
+
+
+def index_bytes(cols: int, kernel: str) -> int:
+    """Bytes per column index read by the SpMV kernel: CSR-stream and SELL-64
+    read 16-bit copies of operators with at most 65536 columns."""
+    return 2 if cols <= 65536 and kernel in ("CSR-stream", "SELL-64") else 4
 
 
 def copy_calibration(nbytes: int = 1 << 30):
@@ -306,8 +315,8 @@ def main():
     nnzB = P.B.nnz if P.B is not None else P.A.nnz
     ell = 2
     per_launch = {
-        "spmv_A": spmv_bytes(nnzA, P.m, P.n, P.m, ell + 1),
-        "spmv_B": spmv_bytes(nnzB, P.n, P.m, P.n, ell),
+        "spmv_A": spmv_bytes(nnzA, P.m, P.n, P.m, ell + 1, index_bytes(P.n, spmv_kernel["A"])),
+        "spmv_B": spmv_bytes(nnzB, P.n, P.m, P.n, ell, index_bytes(P.m, spmv_kernel["B"])),
     }
     stage_avg = {k: (v[0] / v[1] if v[1] else 0.0) for k, v in times.items()}
     dom = max(("spmv_A", "spmv_B"), key=lambda s: times[s][0])
