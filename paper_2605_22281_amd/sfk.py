@@ -126,7 +126,12 @@ def params(method="sflsqr", *, ell=2, maxit=50, sketch="sparse_sign", s=101, zet
            driver="auto", vw=-2, wg_per_cu=0, perm=None) -> Params:
     """perm: optional order of the unknowns, a torch.int32 device tensor of n
     distinct values in [0, n) (unknown j stored at position perm[j] inside the
-    library; results come back in the caller's order)."""
+    library; results come back in the caller's order).
+    vw: SpMV kernel, as sfk_params.vw: -2 automatic (timed at init), 0
+    CSR-stream, 1 SELL-64, 8/16/32/64 lanes per row, -1 lanes from the mean row
+    length; for right-hand sides sharing A and B (init_multi) -2 automatic, 0
+    column-sliced L2 gathers, 2 LDS-staged units, any other value the row
+    kernel."""
     p = Params()
     lib().sfk_params_default(ctypes.byref(p))
     p.method = _METHODS[method] if isinstance(method, str) else int(method)
