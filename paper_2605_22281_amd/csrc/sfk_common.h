@@ -19,7 +19,32 @@ __device__ __forceinline__ double group_sum(double v) {
   return v;
 }
 
-__device__ __forceinline__ double wave_sum(double v) { return group_sum<64>(v); }
+// A double moved across lanes by a DPP pattern (both 32-bit halves).
+template <int CTRL>
+__device__ __forceinline__ double dpp_double(double v) {
+  const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), CTRL, 0xf, 0xf, true);
+  const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), CTRL, 0xf, 0xf, true);
+  return __hiloint2double(hi, lo);
+}
+
+// Sum over the 64 lanes of a wave (every lane active), the same in every lane.
+// Within each row of 16 lanes: pairs (xor 1), quads (xor 2), then the mirror
+// images in the half row and the row, after which all 16 lanes hold the row's
+// sum; the four row sums are read by lane and added as (r0 + r1) + (r2 + r3).
+// No LDS traffic (cross-lane permutes through the LDS unit cost a round trip
+// per stage).
+__device__ __forceinline__ double wave_sum(double v) {
+  v += dpp_double<0xB1>(v);    // quad_perm [1, 0, 3, 2]
+  v += dpp_double<0x4E>(v);    // quad_perm [2, 3, 0, 1]
+  v += dpp_double<0x141>(v);   // row_half_mirror
+  v += dpp_double<0x140>(v);   // row_mirror
+  const int lo = __double2loint(v), hi = __double2hiint(v);
+  const double r0 = __hiloint2double(__builtin_amdgcn_readlane(hi, 0), __builtin_amdgcn_readlane(lo, 0));
+  const double r1 = __hiloint2double(__builtin_amdgcn_readlane(hi, 16), __builtin_amdgcn_readlane(lo, 16));
+  const double r2 = __hiloint2double(__builtin_amdgcn_readlane(hi, 32), __builtin_amdgcn_readlane(lo, 32));
+  const double r3 = __hiloint2double(__builtin_amdgcn_readlane(hi, 48), __builtin_amdgcn_readlane(lo, 48));
+  return (r0 + r1) + (r2 + r3);
+}
 
 // Sum of Q per-thread values over a workgroup of NT threads, result in out[0..Q)
 // (LDS, visible to all threads on return).  lds_w holds kMaxQ * NT / 64 doubles.
