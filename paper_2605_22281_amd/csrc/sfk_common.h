@@ -27,6 +27,12 @@ __device__ __forceinline__ double dpp_double(double v) {
   return __hiloint2double(hi, lo);
 }
 
+// The double held by lane `src` (uniform across the wave), in every lane.
+__device__ __forceinline__ double lane_double(double v, int src) {
+  return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), src),
+                          __builtin_amdgcn_readlane(__double2loint(v), src));
+}
+
 // Sum over the 64 lanes of a wave (every lane active), the same in every lane.
 // Within each row of 16 lanes: pairs (xor 1), quads (xor 2), then the mirror
 // images in the half row and the row, after which all 16 lanes hold the row's

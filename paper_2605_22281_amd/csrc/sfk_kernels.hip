@@ -701,7 +701,7 @@ __device__ void backsub_wave(const Dev &D, int j, double *yout, double *cbuf) {
 #pragma unroll
         for (int e = 0; e < ER; ++e)
           if (lane + 64 * e == i) dl = col[p][e];
-        const double rii = __shfl(dl, i & 63, 64);
+        const double rii = lane_double(dl, i & 63);
         const double yi = cbuf[i] / rii;
         if (lane == 0) yout[i] = yi;
 #pragma unroll
@@ -817,7 +817,7 @@ __global__ void __launch_bounds__(64) k_ls(const Dev *__restrict__ devs, int k) 
     if (i == nsel) alpha_l = a[e];
     if (i > nsel && i < s) x2 += a[e] * a[e];
   }
-  const double alpha = __shfl(alpha_l, nsel & 63, 64);
+  const double alpha = lane_double(alpha_l, nsel & 63);
   x2 = wave_sum(x2);
   double beta, tau, scl;
   if (x2 == 0.0) {
@@ -863,7 +863,7 @@ __global__ void __launch_bounds__(64) k_ls(const Dev *__restrict__ devs, int k) 
     if (i == nsel) ck_l = cv[e];
     if (i > nsel && i < s) r2 += cv[e] * cv[e];
   }
-  const double ck = __shfl(ck_l, nsel & 63, 64);
+  const double ck = lane_double(ck_l, nsel & 63);
   const double rho = sqrt(wave_sum(r2));
   __syncthreads();
 
