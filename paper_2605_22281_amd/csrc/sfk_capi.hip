@@ -704,7 +704,7 @@ static sfk_status setup_instance(sfk_ctx *c, Inst &I, const sfk_csr *A, const sf
   D.vwA = P.vwA;
   D.vwB = P.vwB;
   D.nwmax = P.nwmax;
-  D.nsg = p.sketch == SFK_SK_SPARSE_SIGN ? (p.s * 64 + kWG - 1) / kWG
+  D.nsg = p.sketch == SFK_SK_SPARSE_SIGN ? p.s                       // a workgroup per sketch row
         : p.sketch == SFK_SK_IDENTITY ? (p.s + kWG - 1) / kWG : 0;
   D.eps = p.eps;
   D.sk_scale = p.sketch == SFK_SK_SPARSE_SIGN ? 1.0 / std::sqrt((double)p.zeta)

@@ -533,19 +533,33 @@ __global__ void __launch_bounds__(kWG) k_sketch_gather(const Dev *__restrict__ d
     if (i < D.s) dst[i] = v[(size_t)(D.skperm ? D.skperm[i] : i) * vs];
     return;
   }
-  const int wave = (bm.y * kWG + threadIdx.x) >> 6;
-  const int lane = threadIdx.x & 63;
-  const int nwaves = (D.nsg * kWG) >> 6;
-  for (int r = wave; r < D.s; r += nwaves) {
-    const int e0 = D.sk_rp[r], e1 = D.sk_rp[r + 1];
-    double acc = 0.0;
-    for (int e = e0 + lane; e < e1; e += 64) {
-      const int code = D.sk_ent[e];
-      const double val = v[(size_t)(code & 0x7fffffff) * vs];
-      acc += code < 0 ? -val : val;
-    }
-    acc = wave_sum(acc);
-    if (lane == 0) dst[r] = acc * D.sk_scale;
+  // sparse-sign: workgroup bm.y sums sketch row bm.y; its threads split the
+  // row's entries (four gathers in flight each), then the wave sums are added
+  // in wave order
+  __shared__ double s_part[kWG / 64];
+  const int r = bm.y;
+  if (r >= D.s) return;
+  const int e0 = D.sk_rp[r], e1 = D.sk_rp[r + 1];
+  double acc = 0.0;
+  for (int e = e0 + threadIdx.x; e < e1; e += 4 * kWG) {
+    int code[4];
+    double val[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) code[u] = e + u * kWG < e1 ? D.sk_ent[e + u * kWG] : 0;
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+      val[u] = e + u * kWG < e1 ? v[(size_t)(code[u] & 0x7fffffff) * vs] : 0.0;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) acc += code[u] < 0 ? -val[u] : val[u];
+  }
+  acc = wave_sum(acc);
+  if ((threadIdx.x & 63) == 0) s_part[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+#pragma unroll
+    for (int w = 0; w < kWG / 64; ++w) t += s_part[w];
+    dst[r] = t * D.sk_scale;
   }
 }
 
