@@ -9,6 +9,19 @@
 
 namespace sfk {
 
+// A pointer into device (global) memory.  A plain pointer read out of a Dev
+// record may address any memory as far as the compiler knows, so its loads and
+// stores become flat instructions, which also count against the LDS/scalar
+// wait counter: every wait for an LDS value then waits for all memory loads in
+// flight as well.  Through gptr they become global instructions.
+template <class T>
+using gptr = T __attribute__((address_space(1))) *;
+
+template <class T>
+__device__ __forceinline__ gptr<T> gmem(T *p) {
+  return (gptr<T>)p;
+}
+
 // ---------------------------------------------------------------------------
 // reductions
 // ---------------------------------------------------------------------------
@@ -88,7 +101,7 @@ __device__ __forceinline__ int producers(const Dev &D, int stage) {
 // (every workgroup obtains identical values).
 template <int NT>
 __device__ __forceinline__ void consume(const Dev &D, int stage, int Q, double *lds_w, double *tot) {
-  const double *p = part_of(D, stage);
+  const gptr<const double> p = gmem(part_of(D, stage));
   const int np = producers(D, stage);
   double acc[kMaxQ];
 #pragma unroll
@@ -105,7 +118,7 @@ template <int NT>
 __device__ __forceinline__ void produce(const Dev &D, int stage, int wid, int Q, const double (&acc)[kMaxQ],
                         double *lds_w, double *blk) {
   block_sum<NT>(acc, Q, lds_w, blk);
-  if (threadIdx.x < Q) part_of(D, stage)[(size_t)threadIdx.x * D.nwmax + wid] = blk[threadIdx.x];
+  if (threadIdx.x < Q) gmem(part_of(D, stage))[(size_t)threadIdx.x * D.nwmax + wid] = blk[threadIdx.x];
 }
 
 __device__ __forceinline__ int ld_flag(const int *p) {

@@ -61,9 +61,9 @@ constexpr int kPerThread = 4;
 constexpr int kChunk = kSpmvWG * kPerThread;
 constexpr int kRowWin = 1024;   // row pointers staged per pass
 
-__device__ void spmv_stream(const int *rp, const int *ci, const uint16_t *c16, const double *va,
-                            const double *xin, double *yout, double *ybuf, int r0, int r1,
-                            double scale) {
+__device__ void spmv_stream(gptr<const int> rp, gptr<const int> ci, gptr<const uint16_t> c16,
+                            gptr<const double> va, gptr<const double> xin, gptr<double> yout,
+                            double *ybuf, int r0, int r1, double scale) {
   constexpr int NT = kSpmvWG;
   __shared__ double prod[kChunk];
   __shared__ int rps[kRowWin + 1];
@@ -141,9 +141,9 @@ __device__ void spmv_stream(const int *rp, const int *ci, const uint16_t *c16, c
 // ---------------------------------------------------------------------------
 constexpr int kRowSlots = 8;
 
-__device__ void spmv_rows64(const int *__restrict__ rp, const int *__restrict__ ci,
-                            const double *__restrict__ va, const double *__restrict__ xin,
-                            double *yout, double *ybuf, int r0, int r1, double scale) {
+__device__ void spmv_rows64(gptr<const int> __restrict__ rp, gptr<const int> __restrict__ ci,
+                            gptr<const double> __restrict__ va, gptr<const double> __restrict__ xin,
+                            gptr<double> yout, double *ybuf, int r0, int r1, double scale) {
   constexpr int NWV = kSpmvWG / 64;
   const int lane = threadIdx.x & 63;
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -186,11 +186,11 @@ __device__ void spmv_rows64(const int *__restrict__ rp, const int *__restrict__ 
 // on few cache lines.  The 16 partial sums of a row are added in LDS in wave
 // order.  Rows [r0, r1) of the workgroup are returned for the epilogue.
 // ---------------------------------------------------------------------------
-__device__ void spmv_sell(const int *__restrict__ soff, const int *__restrict__ slen,
-                          const int *__restrict__ scol, const uint16_t *__restrict__ scol16,
-                          const double *__restrict__ sval,
-                          const double *__restrict__ xin, double *yout, double *ybuf, int s0,
-                          int s1, int rows, double scale, double *lds_part) {
+__device__ void spmv_sell(gptr<const int> __restrict__ soff, gptr<const int> __restrict__ slen,
+                          gptr<const int> __restrict__ scol, gptr<const uint16_t> __restrict__ scol16,
+                          gptr<const double> __restrict__ sval, gptr<const double> __restrict__ xin,
+                          gptr<double> yout, double *ybuf, int s0, int s1, int rows, double scale,
+                          double *lds_part) {
   constexpr int NWV = kSpmvWG / 64;
   const int lane = threadIdx.x & 63;
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -280,12 +280,12 @@ __global__ void __launch_bounds__(kSpmvWG, 8) k_spmv(const Dev *__restrict__ dev
     __syncthreads();
   }
 
-  const int *rp = ISA ? D.Arp : D.Brp;
-  const int *ci = ISA ? D.Aci : D.Bci;
-  const double *va = ISA ? D.Ava : D.Bva;
-  const int *part = ISA ? D.Apart : D.Bpart;
-  const double *xin = ISA ? D.Z + (size_t)(k - 1) * D.n : wvec(D, k + 1);
-  double *yout = ISA ? wrawk(D, k) : zrawk(D, k);
+  const gptr<const int> rp = gmem(ISA ? D.Arp : D.Brp);
+  const gptr<const int> ci = gmem(ISA ? D.Aci : D.Bci);
+  const gptr<const double> va = gmem(ISA ? D.Ava : D.Bva);
+  const gptr<const int> part = gmem(ISA ? D.Apart : D.Bpart);
+  const gptr<const double> xin = gmem(ISA ? D.Z + (size_t)(k - 1) * D.n : wvec(D, k + 1));
+  const gptr<double> yout = gmem(ISA ? wrawk(D, k) : zrawk(D, k));
   const double scale = s_scale;
 
   int r0, r1;
@@ -297,16 +297,16 @@ __global__ void __launch_bounds__(kSpmvWG, 8) k_spmv(const Dev *__restrict__ dev
     r0 = min(rows, s0 * kSellC);
     r1 = min(rows, s1 * kSellC);
     __shared__ double lds_part[(kSpmvWG / 64) * kSellC];
-    spmv_sell(ISA ? D.Asoff : D.Bsoff, ISA ? D.Aslen : D.Bslen, ISA ? D.Ascol : D.Bscol,
-              ISA ? D.Ascol16 : D.Bscol16, ISA ? D.Asval : D.Bsval, xin, yout, ybuf, s0, s1,
-              rows, scale, lds_part);
+    spmv_sell(gmem(ISA ? D.Asoff : D.Bsoff), gmem(ISA ? D.Aslen : D.Bslen),
+              gmem(ISA ? D.Ascol : D.Bscol), gmem(ISA ? D.Ascol16 : D.Bscol16),
+              gmem(ISA ? D.Asval : D.Bsval), xin, yout, ybuf, s0, s1, rows, scale, lds_part);
   } else {
     r0 = part[wid];
     r1 = part[wid + 1];
   }
   if (VW == 1) {
   } else if (VW == 0) {
-    spmv_stream(rp, ci, ISA ? D.Aci16 : D.Bci16, va, xin, yout, ybuf, r0, r1, scale);
+    spmv_stream(rp, ci, gmem(ISA ? D.Aci16 : D.Bci16), va, xin, yout, ybuf, r0, r1, scale);
   } else if (VW == 64) {
     spmv_rows64(rp, ci, va, xin, yout, ybuf, r0, r1, scale);
   } else {
@@ -347,10 +347,10 @@ __global__ void __launch_bounds__(kSpmvWG, 8) k_spmv(const Dev *__restrict__ dev
   int j0, nwin;
   if (ISA) { j0 = wwin0(D, k); nwin = k - j0 + 1; }
   else { j0 = pwin0(D, k); nwin = k >= j0 ? k - j0 + 1 : 0; }
-  const double *win[kMaxEll + 1];
+  gptr<const double> win[kMaxEll + 1];
 #pragma unroll
   for (int q = 0; q < kMaxEll + 1; ++q)
-    win[q] = (q < nwin) ? (ISA ? wvec(D, j0 + q) : pvec(D, j0 + q)) : nullptr;
+    win[q] = (q < nwin) ? gmem(ISA ? wvec(D, j0 + q) : pvec(D, j0 + q)) : nullptr;
   double acc[kMaxQ];
 #pragma unroll
   for (int q = 0; q < kMaxQ; ++q) acc[q] = 0.0;
@@ -377,22 +377,24 @@ __global__ void __launch_bounds__(kSpmvWG, 8) k_spmv_core(Dev D, const double *_
                                                          double *yout) {
   __shared__ double ybuf[kRowsLDS];
   const int wid = blockIdx.x;
-  const int *rp = ISA ? D.Arp : D.Brp;
-  const int *ci = ISA ? D.Aci : D.Bci;
-  const double *va = ISA ? D.Ava : D.Bva;
-  const int *part = ISA ? D.Apart : D.Bpart;
+  const gptr<const int> rp = gmem(ISA ? D.Arp : D.Brp);
+  const gptr<const int> ci = gmem(ISA ? D.Aci : D.Bci);
+  const gptr<const double> va = gmem(ISA ? D.Ava : D.Bva);
+  const gptr<const int> part = gmem(ISA ? D.Apart : D.Bpart);
+  const gptr<const double> xg = gmem(xin);
+  const gptr<double> yg = gmem(yout);
   if (VW == 1) {
     const int nsl = ISA ? D.Ansl : D.Bnsl;
     const int rows = ISA ? D.m : D.n;
     const int s0 = (int)((long long)wid * nsl / D.nws), s1 = (int)((long long)(wid + 1) * nsl / D.nws);
     __shared__ double lds_part[(kSpmvWG / 64) * kSellC];
-    spmv_sell(ISA ? D.Asoff : D.Bsoff, ISA ? D.Aslen : D.Bslen, ISA ? D.Ascol : D.Bscol,
-              ISA ? D.Ascol16 : D.Bscol16, ISA ? D.Asval : D.Bsval, xin, yout, ybuf, s0, s1,
-              rows, 1.0, lds_part);
+    spmv_sell(gmem(ISA ? D.Asoff : D.Bsoff), gmem(ISA ? D.Aslen : D.Bslen),
+              gmem(ISA ? D.Ascol : D.Bscol), gmem(ISA ? D.Ascol16 : D.Bscol16),
+              gmem(ISA ? D.Asval : D.Bsval), xg, yg, ybuf, s0, s1, rows, 1.0, lds_part);
   } else if (VW == 64) {
-    spmv_rows64(rp, ci, va, xin, yout, ybuf, part[wid], part[wid + 1], 1.0);
+    spmv_rows64(rp, ci, va, xg, yg, ybuf, part[wid], part[wid + 1], 1.0);
   } else {
-    spmv_stream(rp, ci, ISA ? D.Aci16 : D.Bci16, va, xin, yout, ybuf, part[wid], part[wid + 1], 1.0);
+    spmv_stream(rp, ci, gmem(ISA ? D.Aci16 : D.Bci16), va, xg, yg, ybuf, part[wid], part[wid + 1], 1.0);
   }
 }
 
@@ -413,15 +415,15 @@ __global__ void __launch_bounds__(kWG) k_wupdate(const Dev *__restrict__ devs,
   consume<kWG>(D, kStageA, nwin + 1, lds_w, tot);
   if (threadIdx.x == 0) finish_w_coeffs(D, k, tot, s_cf, wid == 0);
   __syncthreads();
-  const double *win[kMaxEll + 1];
+  gptr<const double> win[kMaxEll + 1];
   double cf[kMaxEll + 1];
 #pragma unroll
   for (int q = 0; q < kMaxEll + 1; ++q) {
-    win[q] = (q < nwin) ? wvec(D, j0 + q) : nullptr;
+    win[q] = (q < nwin) ? gmem(wvec(D, j0 + q)) : nullptr;
     cf[q] = (q < nwin) ? s_cf[q] : 0.0;
   }
-  const double *wr = wrawk(D, k);
-  double *out = wvec(D, k + 1);
+  const gptr<const double> wr = gmem(wrawk(D, k));
+  const gptr<double> out = gmem(wvec(D, k + 1));
   int i0, i1;
   chunk_range(D.m, D.nwv, wid, i0, i1);
   double acc[kMaxQ];
@@ -466,16 +468,18 @@ __global__ void __launch_bounds__(kWG) k_pupdate(const Dev *__restrict__ devs,
   if (rew)
     for (int j = threadIdx.x; j < k; j += kWG) coefx[j] = D.sigp[j + 1] * D.y[j];
   __syncthreads();
-  const double *win[kMaxEll + 1];
+  gptr<const double> win[kMaxEll + 1];
   double cf[kMaxEll + 1];
 #pragma unroll
   for (int q = 0; q < kMaxEll + 1; ++q) {
-    win[q] = (q < nwin) ? pvec(D, j0 + q) : nullptr;
+    win[q] = (q < nwin) ? gmem(pvec(D, j0 + q)) : nullptr;
     cf[q] = (q < nwin) ? s_cf[q] : 0.0;
   }
-  const double *zr = zrawk(D, k);
-  double *zout = D.Z + (size_t)k * D.n;
-  double *pout = rew ? D.P + (size_t)pslot(D, k + 1) * D.n : zout;
+  const gptr<const double> zr = gmem(zrawk(D, k));
+  const gptr<double> zout = gmem(D.Z + (size_t)k * D.n);
+  const gptr<double> pout = rew ? gmem(D.P + (size_t)pslot(D, k + 1) * D.n) : zout;
+  const gptr<const double> Zg = gmem(D.Z);
+  const gptr<double> xg = gmem(D.x);
   const double eps2 = D.eps * D.eps;
   int i0, i1;
   chunk_range(D.n, D.nwv, wid, i0, i1);
@@ -491,8 +495,8 @@ __global__ void __launch_bounds__(kWG) k_pupdate(const Dev *__restrict__ devs,
     pout[i] = v;
     if (rew) {
       double xi = 0.0;
-      for (int j = 0; j < k; ++j) xi += coefx[j] * D.Z[(size_t)j * D.n + i];
-      D.x[i] = xi;
+      for (int j = 0; j < k; ++j) xi += coefx[j] * Zg[(size_t)j * D.n + i];
+      xg[i] = xi;
       zout[i] = sqrt(sqrt(xi * xi + eps2)) * v;
     }
     acc[0] += v * v;
@@ -526,8 +530,8 @@ __global__ void __launch_bounds__(kWG) k_sketch_gather(const Dev *__restrict__ d
   const Dev &D = devs[bm.x];
   if (k > 0 && skip_iter(D, k)) return;
   int vs;
-  const double *v = sketch_in(D, k, vs);
-  double *dst = sketch_out(D, k);
+  const gptr<const double> v = gmem(sketch_in(D, k, vs));
+  const gptr<double> dst = gmem(sketch_out(D, k));
   if (D.sketch == 2) {
     const int i = bm.y * kWG + threadIdx.x;
     if (i < D.s) dst[i] = v[(size_t)(D.skperm ? D.skperm[i] : i) * vs];
@@ -540,12 +544,13 @@ __global__ void __launch_bounds__(kWG) k_sketch_gather(const Dev *__restrict__ d
   const int r = bm.y;
   if (r >= D.s) return;
   const int e0 = D.sk_rp[r], e1 = D.sk_rp[r + 1];
+  const gptr<const int> ent = gmem(D.sk_ent);
   double acc = 0.0;
   for (int e = e0 + threadIdx.x; e < e1; e += 4 * kWG) {
     int code[4];
     double val[4];
 #pragma unroll
-    for (int u = 0; u < 4; ++u) code[u] = e + u * kWG < e1 ? D.sk_ent[e + u * kWG] : 0;
+    for (int u = 0; u < 4; ++u) code[u] = e + u * kWG < e1 ? ent[e + u * kWG] : 0;
 #pragma unroll
     for (int u = 0; u < 4; ++u)
       val[u] = e + u * kWG < e1 ? v[(size_t)(code[u] & 0x7fffffff) * vs] : 0.0;
@@ -573,7 +578,9 @@ __global__ void __launch_bounds__(kWG) k_srht_blocks(const Dev *__restrict__ dev
   if (k > 0 && skip_iter(D, k)) return;
   __shared__ double u[kSrhtL];
   int vs;
-  const double *v = sketch_in(D, k, vs);
+  const gptr<const double> v = gmem(sketch_in(D, k, vs));
+  const gptr<const unsigned long long> dbits = gmem(D.srht_d);
+  const gptr<const int> skperm = gmem(D.skperm);
   const int L = 1 << D.log2L;
   const int b = bm.y;
   const int base = b * L;
@@ -591,8 +598,8 @@ __global__ void __launch_bounds__(kWG) k_srht_blocks(const Dev *__restrict__ dev
       const int g = base + t + kWG * j;
       double val = 0.0;
       if (g < D.d_sk) {
-        const unsigned long long w = D.srht_d[g >> 6];
-        const double vg = v[(size_t)(D.skperm ? D.skperm[g] : g) * vs];
+        const unsigned long long w = dbits[g >> 6];
+        const double vg = v[(size_t)(skperm ? skperm[g] : g) * vs];
         val = ((w >> (g & 63)) & 1ull) ? -vg : vg;
       }
       x[j] = val;
@@ -638,8 +645,8 @@ __global__ void __launch_bounds__(kWG) k_srht_blocks(const Dev *__restrict__ dev
       const int g = base + i;
       double val = 0.0;
       if (g < D.d_sk) {
-        const unsigned long long w = D.srht_d[g >> 6];
-        const double vg = v[(size_t)(D.skperm ? D.skperm[g] : g) * vs];
+        const unsigned long long w = dbits[g >> 6];
+        const double vg = v[(size_t)(skperm ? skperm[g] : g) * vs];
         val = ((w >> (g & 63)) & 1ull) ? -vg : vg;
       }
       u[i] = val;
@@ -656,7 +663,7 @@ __global__ void __launch_bounds__(kWG) k_srht_blocks(const Dev *__restrict__ dev
     }
   }
   for (int i = threadIdx.x; i < D.s; i += kWG)
-    D.srht_part[(size_t)b * D.s + i] = u[D.srht_rows[i] & (L - 1)];
+    gmem(D.srht_part)[(size_t)b * D.s + i] = u[gmem(D.srht_rows)[i] & (L - 1)];
 }
 
 // SRHT, stage 2: dst_i = (1/sqrt(s)) sum_b (-1)^popcount((rows_i >> log2L) & b) part[b][i]
@@ -667,14 +674,15 @@ __global__ void __launch_bounds__(kWG) k_srht_combine(const Dev *__restrict__ de
   if (k > 0 && skip_iter(D, k)) return;
   const int i = bm.y * kWG + threadIdx.x;
   if (i >= D.s) return;
-  double *dst = sketch_out(D, k);
+  const gptr<double> dst = gmem(sketch_out(D, k));
+  const gptr<const double> part = gmem(D.srht_part);
   const int hi = D.srht_rows[i] >> D.log2L;
   // eight block partials in flight, added in block order
   double acc = 0.0;
   for (int b0 = 0; b0 < D.nblk; b0 += 8) {
     double p[8];
 #pragma unroll
-    for (int u = 0; u < 8; ++u) p[u] = b0 + u < D.nblk ? D.srht_part[(size_t)(b0 + u) * D.s + i] : 0.0;
+    for (int u = 0; u < 8; ++u) p[u] = b0 + u < D.nblk ? part[(size_t)(b0 + u) * D.s + i] : 0.0;
 #pragma unroll
     for (int u = 0; u < 8; ++u)
       if (b0 + u < D.nblk) acc += (__popc(hi & (b0 + u)) & 1) ? -p[u] : p[u];
@@ -693,7 +701,7 @@ template <int ER>
 __device__ void backsub_wave(const Dev &D, int j, double *yout, double *cbuf) {
   const int lane = threadIdx.x;
   const int ld = D.maxit;
-  const double *R = D.R;
+  const gptr<const double> R = gmem(D.R);
   for (int t = lane; t < j; t += 64) cbuf[t] = D.c[t];
   __syncthreads();
   double col[kBsPF][ER];
@@ -766,7 +774,7 @@ __global__ void __launch_bounds__(64) k_ls(const Dev *__restrict__ devs, int k) 
 #pragma unroll
   for (int e = 0; e < E; ++e) a[e] = 0.0;
   if (D.method == 0) {
-    const double *col = D.SK + (size_t)(k - 1) * s;
+    const gptr<const double> col = gmem(D.SK) + (size_t)(k - 1) * s;
 #pragma unroll
     for (int e = 0; e < E; ++e) {
       const int i = lane + 64 * e;
@@ -776,7 +784,7 @@ __global__ void __launch_bounds__(64) k_ls(const Dev *__restrict__ devs, int k) 
     const int j0 = max(1, k - D.ell);
     for (int j = j0; j <= k + 1; ++j) {
       const double hj = D.H[(size_t)(k - 1) * ldh + (j - 1)];
-      const double *col = D.SK + (size_t)(j - 1) * s;
+      const gptr<const double> col = gmem(D.SK) + (size_t)(j - 1) * s;
 #pragma unroll
       for (int e = 0; e < E; ++e) {
         const int i = lane + 64 * e;
@@ -792,7 +800,7 @@ __global__ void __launch_bounds__(64) k_ls(const Dev *__restrict__ devs, int k) 
 #pragma unroll
   for (int p = 0; p < PF; ++p) {
     if (p < nsel) {
-      const double *vp = D.V + (size_t)p * s;
+      const gptr<const double> vp = gmem(D.V) + (size_t)p * s;
 #pragma unroll
       for (int e = 0; e < E; ++e) {
         const int i = lane + 64 * e;
@@ -812,7 +820,7 @@ __global__ void __launch_bounds__(64) k_ls(const Dev *__restrict__ devs, int k) 
 #pragma unroll
         for (int e = 0; e < E; ++e) a[e] -= g * vb[p][e];
         if (jj + PF < nsel) {
-          const double *vp = D.V + (size_t)(jj + PF) * s;
+          const gptr<const double> vp = gmem(D.V) + (size_t)(jj + PF) * s;
 #pragma unroll
           for (int e = 0; e < E; ++e) {
             const int i = lane + 64 * e;
