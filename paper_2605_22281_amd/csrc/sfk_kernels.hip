@@ -795,38 +795,38 @@ __global__ void __launch_bounds__(64) k_ls(const Dev *__restrict__ devs, int k) 
   for (int t = lane; t < nsel; t += 64) s_tau[t] = D.tauv[t];
   __syncthreads();
 
-  // apply H_1 ... H_{k-1} (register ring prefetch of the reflectors)
-  double vb[PF][E];
-#pragma unroll
-  for (int p = 0; p < PF; ++p) {
-    if (p < nsel) {
-      const gptr<const double> vp = gmem(D.V) + (size_t)p * s;
-#pragma unroll
-      for (int e = 0; e < E; ++e) {
-        const int i = lane + 64 * e;
-        vb[p][e] = i < s ? vp[i] : 0.0;
-      }
-    }
-  }
-  for (int j = 0; j < nsel; j += PF) {
+  // apply H_1 ... H_{k-1}.  The reflectors pass through a register ring PF
+  // rows ahead.  Their loads are unconditional (row clamped to the last
+  // reflector, entry to the last sketch row), so that no branch join makes the
+  // compiler wait for them; entries past s meet a zero coefficient instead
+  // (a is zero there, and stays so).
+  if (nsel > 0) {
+    const gptr<const double> Vg = gmem(D.V);
+    double vb[PF][E];
 #pragma unroll
     for (int p = 0; p < PF; ++p) {
-      const int jj = j + p;
-      if (jj < nsel) {
-        double d = 0.0;
+      const gptr<const double> vp = Vg + (size_t)min(p, nsel - 1) * s;
 #pragma unroll
-        for (int e = 0; e < E; ++e) d += vb[p][e] * a[e];
-        const double g = s_tau[jj] * wave_sum(d);
+      for (int e = 0; e < E; ++e) vb[p][e] = vp[min(lane + 64 * e, s - 1)];
+    }
+    for (int j = 0; j < nsel; j += PF) {
 #pragma unroll
-        for (int e = 0; e < E; ++e) a[e] -= g * vb[p][e];
-        if (jj + PF < nsel) {
-          const gptr<const double> vp = gmem(D.V) + (size_t)(jj + PF) * s;
+      for (int p = 0; p < PF; ++p) {
+        const int jj = j + p;
+        if (jj < nsel) {
+          double d = 0.0;
 #pragma unroll
-          for (int e = 0; e < E; ++e) {
-            const int i = lane + 64 * e;
-            vb[p][e] = i < s ? vp[i] : 0.0;
-          }
+          for (int e = 0; e < E; ++e) d += vb[p][e] * a[e];
+          const double g = s_tau[jj] * wave_sum(d);
+#pragma unroll
+          for (int e = 0; e < E; ++e) a[e] -= (lane + 64 * e < s ? g : 0.0) * vb[p][e];
         }
+        // keep the refill after the use: hoisted above it, the loads would be
+        // counted ahead of the older rows still in flight (in-order counter)
+        __builtin_amdgcn_sched_barrier(0);
+        const gptr<const double> vp = Vg + (size_t)min(jj + PF, nsel - 1) * s;
+#pragma unroll
+        for (int e = 0; e < E; ++e) vb[p][e] = vp[min(lane + 64 * e, s - 1)];
       }
     }
   }
