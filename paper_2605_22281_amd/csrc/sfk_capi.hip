@@ -196,6 +196,23 @@ static void enqueue_side(sfk_ctx *c, const int *js, int n) {
   }
 }
 
+// Sketch of iteration k on the main stream, then its least-squares update on
+// the side stream (the reweighting, where D(k) needs LS(k)).
+static void sketch_main_ls_side(sfk_ctx *c, int k) {
+  const Launch &L = c->L;
+  hipStream_t st = c->stream, sd = c->side;
+  const int r = k % sfk_ctx::kRing;
+  int t = stage_begin(c, SFK_STAGE_SKETCH, st);
+  launch_sketch(L, k, st);
+  stage_end(c, t, st);
+  hipEventRecord(c->ev_sk[r], st);
+  hipStreamWaitEvent(sd, c->ev_sk[r], 0);
+  t = stage_begin(c, SFK_STAGE_LS, sd);
+  launch_ls(L, k, sd);
+  stage_end(c, t, sd);
+  hipEventRecord(c->ev_ls[r], sd);
+}
+
 static void flush_side(sfk_ctx *c) {
   int n = 0;
   while (n < 2 && c->pending_side[n] >= 0) ++n;
@@ -215,8 +232,10 @@ static void defer_side(sfk_ctx *c, int k) {
 // sketches go out in pairs after a sparse product, where their workgroups run
 // beside a light vector stage instead of taking CU slots from a product's:
 // sFLSQR after C(k), sFLSMR after A(k) (sketches k - 2 and k - 1), k even.
-// The reweighting needs LS(k) before D(k): then each sketch goes out as soon
-// as its input exists.
+// The reweighting needs LS(k) before D(k): then each sketch runs on the main
+// stream as soon as its input exists (a sketch beside a sparse product is
+// slowed about tenfold, ~5 -> ~50 us for a sparse-sign sketch, and D(k) would
+// wait for it), and only the least-squares update goes to the side stream.
 static void enqueue_iteration(sfk_ctx *c, int k) {
   static_assert(sfk_ctx::kRing >= 8 && kRawSlots >= 8, "side-stream lag");
   hipStream_t st = c->stream;
@@ -226,10 +245,10 @@ static void enqueue_iteration(sfk_ctx *c, int k) {
   run_stage(c, kStageA, k, st);
   stage_end(c, t, st);
   if (late && c->sketch_after_C && k % 2 == 0) flush_side(c);
+  if (!late && !c->sketch_after_C) sketch_main_ls_side(c, k);
   t = stage_begin(c, SFK_STAGE_W_UPDATE, st);
   run_stage(c, kStageB, k, st);
   stage_end(c, t, st);
-  if (!late && !c->sketch_after_C) enqueue_side(c, &k, 1);
   t = stage_begin(c, SFK_STAGE_SPMV_B, st);
   run_stage(c, kStageC, k, st);
   stage_end(c, t, st);
@@ -237,7 +256,7 @@ static void enqueue_iteration(sfk_ctx *c, int k) {
     defer_side(c, k);
     if (!c->sketch_after_C && k % 2 == 0) flush_side(c);
   } else if (c->sketch_after_C) {
-    enqueue_side(c, &k, 1);
+    sketch_main_ls_side(c, k);
   }
   if (c->any_rew) hipStreamWaitEvent(st, c->ev_ls[k % sfk_ctx::kRing], 0);
   t = stage_begin(c, SFK_STAGE_P_UPDATE, st);

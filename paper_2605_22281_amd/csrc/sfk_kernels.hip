@@ -522,7 +522,7 @@ __device__ __forceinline__ double *sketch_out(const Dev &D, int k) {
   return D.method == 0 ? D.SK + (size_t)(k - 1) * D.s : D.SK + (size_t)k * D.s;
 }
 
-// sparse-sign: one wave per sketch row, over the row's (column, sign) entries
+// sparse-sign: a workgroup per sketch row, over the row's (column, sign) entries
 // in increasing column order; identity: copy.
 __global__ void __launch_bounds__(kWG) k_sketch_gather(const Dev *__restrict__ devs,
                                                       const int2 *__restrict__ map, int k) {
