@@ -6,6 +6,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "sfk_sell.h"
+
 namespace sfk {
 
 constexpr int kMaxEll = 8;                 // orthogonalisation window limit
@@ -18,8 +20,6 @@ constexpr int kRawSlots = 8;   // raw products kept (the sketch of iteration k r
                                 // slot k % kRawSlots until iteration k + kRawSlots)
 constexpr int kSrhtL = 2048;               // SRHT block length staged in LDS
 constexpr double kBreakdownTol = 1e-14;    // relative breakdown threshold
-constexpr int kSellC = 64;                 // rows per slice of the SELL copy (one per lane)
-constexpr int kSellPad = 4;                // slice lengths padded to a multiple of this
 
 // Partial-sum buffers, one per producing stage.
 enum Stage { kStageA = 0, kStageB = 1, kStageC = 2, kStageD = 3, kStageMisc = 4, kNumPart = 5 };

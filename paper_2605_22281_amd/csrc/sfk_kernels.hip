@@ -198,16 +198,15 @@ __device__ void spmv_sell(gptr<const int> __restrict__ soff, gptr<const int> __r
   for (int sl = s0; sl < s1; ++sl) {
     const int len = slen[sl];
     const int base = soff[sl];
-    // this wave's steps, a multiple of kSellPad
-    const int per = ((len + NWV - 1) / NWV + kSellPad - 1) / kSellPad * kSellPad;
-    const int j0 = min(len, wv * per), j1 = min(len, j0 + per);
+    int j0, j1;   // this wave's steps, a multiple of kSellPad
+    sell_wave_steps(len, NWV, wv, j0, j1);
     double a0 = 0.0, a1 = 0.0;
     for (int j = j0; j < j1; j += kSellPad) {
       double v[kSellPad];
       int c[kSellPad];
 #pragma unroll
       for (int u = 0; u < kSellPad; ++u) {
-        const int e = base + (j + u) * kSellC + lane;
+        const size_t e = sell_at(base, j + u, lane);
         v[u] = __builtin_nontemporal_load(sval + e);
         c[u] = scol16 ? (int)__builtin_nontemporal_load(scol16 + e) : __builtin_nontemporal_load(scol + e);
       }
@@ -1219,9 +1218,7 @@ __global__ void __launch_bounds__(64) k_init_rhs(Dev D) {
 __global__ void k_sell_len(const int *rp, int rows, int nsl, int *slen) {
   const int sl = blockIdx.x * blockDim.x + threadIdx.x;
   if (sl >= nsl) return;
-  int mx = 0;
-  for (int r = sl * kSellC; r < min(rows, (sl + 1) * kSellC); ++r) mx = max(mx, rp[r + 1] - rp[r]);
-  slen[sl] = (mx + kSellPad - 1) / kSellPad * kSellPad;
+  slen[sl] = sell_len(rp, rows, sl);
 }
 
 // one thread per slice lane, the lanes of the last slice past the final row
@@ -1229,16 +1226,9 @@ __global__ void k_sell_len(const int *rp, int rows, int nsl, int *slen) {
 // soff[s] + 64 j + i, then padding (value 0, column 0) up to the slice length
 __global__ void k_sell_fill(const int *rp, const int *ci, const double *va, int rows, int nsl,
                             const int *soff, const int *slen, int *scol, double *sval) {
-  const int r = blockIdx.x * blockDim.x + threadIdx.x;
-  if (r >= nsl * kSellC) return;
-  const int sl = r / kSellC, i = r % kSellC;
-  const int e0 = r < rows ? rp[r] : 0, len = r < rows ? rp[r + 1] - e0 : 0, L = slen[sl];
-  const size_t base = (size_t)soff[sl] + i;
-  for (int j = 0; j < L; ++j) {
-    const bool in = j < len;
-    scol[base + (size_t)j * kSellC] = in ? ci[e0 + j] : 0;
-    sval[base + (size_t)j * kSellC] = in ? va[e0 + j] : 0.0;
-  }
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= nsl * kSellC) return;
+  sell_fill_lane(t, rows, rp, ci, va, soff, slen, scol, sval);
 }
 
 // run state of every instance after iteration k: 1 if no further iteration can
