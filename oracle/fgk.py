@@ -27,6 +27,9 @@ notes):
     the minimised objective ||s - [S A^T W, S z] H y_k|| < tol * ||s|| (the
     listing's test drops the last column and H); with a discrepancy target the
     tolerance is tol = eta * delta_e / ||b||;
+  * alternatively (true_tol > 0) the discrepancy principle on the true residual
+    as eq. (discrP) writes it: stop at the first k with ||b - A x_k|| <= true_tol
+    (= eta * delta_e), the sketched test then being off;
   * breakdown when t_kk <= 1e-14 * ||z before projection|| (basis cannot grow:
     return x_{k-1}) or h_{k+1,k} <= 1e-14 * ||A z_k|| (x_k is still formed with
     the new column, then the run stops);
@@ -86,13 +89,16 @@ def tau_apply(tau: str, p: np.ndarray, x_prev: np.ndarray, eps: float) -> np.nda
 def sketched_flexible(A, b, sketch, *, method: str = "sflsqr", B=None, maxit: int = 50,
                       ell: int = 2, tau: str = "identity", eps: float = 1e-3,
                       tol: float = 0.0, orth_against: str = "P", m: int | None = None,
-                      n: int | None = None) -> Result:
+                      n: int | None = None, true_tol: float = 0.0) -> Result:
     """sFLSQR (Algorithm 1) or sFLSMR (Algorithm 2), step by step.
 
     A, B: matrices (dense or scipy sparse) or callables; B None means A^T.
     sketch: object with .apply(v) -> S v (S acts on m-vectors for sFLSQR and on
     n-vectors for sFLSMR).
+    true_tol: > 0 stops on ||b - A x_k|| <= true_tol instead of the sketched test.
     """
+    if true_tol > 0.0 and tol > 0.0:
+        raise ValueError("one stop test at a time: tol (sketched) or true_tol")
     if method not in ("sflsqr", "sflsmr"):
         raise ValueError(method)
     Av = _matvec(A)
@@ -197,6 +203,9 @@ def sketched_flexible(A, b, sketch, *, method: str = "sflsqr", B=None, maxit: in
             breakdown = True
             break
         if tol > 0.0 and rho < tol * rhs_norm:
+            stopped = True
+            break
+        if true_tol > 0.0 and rtrue[-1] <= true_tol:
             stopped = True
             break
 
