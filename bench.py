@@ -1,25 +1,34 @@
 #!/usr/bin/env python3
 """Throughput of the sketched flexible Golub-Kahan iteration on one MI355X.
 
-Workload (default): 256 x 256 image (n = 65536), 180 angles x 363 bins
-(m = 65340), exact ray/pixel intersection lengths A, unmatched pixel-driven
-back-projector B, ellipse phantom, 2% noise; sFLSMR with an SRHT sketch of
-s = 400 rows, 200 iterations, FP64.  One step = one iteration of the method
-(forward projection, truncated Gram-Schmidt, sketch, small sketched least
-squares, back-projection, flexible preconditioner).  Inputs are resident in HBM
-before the timed region; the context set-up (init) is outside it.
+Workload (default, the headline): sFLSQR with l1 reweighting on a 512 x 512
+image (n = 262144), 360 angles x 725 bins (m = 261000), exact ray/pixel
+intersection lengths A (1.2e8 nonzeros), B = A^T built on the device, sparse
+phantom (2% of the pixels), 1% noise, sparse-sign sketch s = 600 (zeta = 8),
+eps = 1e-3, FP64.  One step = one iteration of the method (forward projection,
+truncated Gram-Schmidt, sketch, small sketched least squares, back-projection,
+flexible preconditioner with the x assembly).  --steps K times the first K
+iterations of a fresh context; the whole 300-iteration run is timed as well
+(`full_run`, where the least-squares and x-assembly costs have grown with k).
+Inputs are resident in HBM before every timed region; context set-up (init)
+is outside them.
 
-Batched throughput, reported beside the plain figure (same JSON line):
-  * shared operator: R = 32 right-hand sides of the default workload's A and B
-    (own phantom, own SRHT seed each) in one context, against a loop of 32
-    plain solves on the same GPU; both run the same number of iterations, and
-    every right-hand side's x_10 must agree with its plain run to 1e-8 relative;
-  * heterogeneous: 32 independent instances, image side drawn from
-    {128, 192, 256, 384} (angles 0.7 side, bins ceil(sqrt(2) side)), own
-    ellipse phantom and noise U[0.5%, 3%], sFLSQR with B = A^T built on the
-    device, sparse-sign s = 201, zeta = 8, up to 100 iterations with the
-    discrepancy principle per instance, against a plain loop over the same 32.
-Set-up (init) is outside every timed region.
+Beside the headline, in the same JSON line:
+  * `workloads`: the 64^2 sFLSQR workload (50 iterations, and its discrepancy
+    run) and the 256^2 unmatched sFLSMR workload (SRHT s = 400), each with its
+    stage times and the roofline of its dominant product;
+  * shared operator (`batched_multi_rhs`): R = 32 right-hand sides of the
+    256^2 workload's A and B (own phantom, own SRHT seed each) in one context,
+    against a loop of 32 plain solves on the same GPU; both run the same
+    number of iterations, and every right-hand side's x_10 must agree with
+    its plain run to 1e-8 relative;
+  * heterogeneous (`batched_heterogeneous`): 32 independent instances, image
+    side drawn from {128, 192, 256, 384} (angles 0.7 side, bins
+    ceil(sqrt(2) side)), own ellipse phantom and noise U[0.5%, 3%], sFLSQR with
+    B = A^T built on the device, sparse-sign s = 201, zeta = 8, up to 100
+    iterations with the discrepancy principle per instance, against a plain
+    loop over the same 32;
+  * `cpu_baseline`: the oracle on the headline workload, first iterations.
 
 Prints one JSON line.  --gpus N with N > 1 is refused: this build runs on one
 GPU.
@@ -41,13 +50,15 @@ HBM_PEAK_GBS = 8000.0
 
 WORKLOADS = {
     "ct256_unmatched": dict(method="sflsmr", sketch="srht", s=400, zeta=8, iters=200, tau="identity",
+                            seed=3002,
                             desc="256^2 CT (180 angles x 363 bins), unmatched pixel-driven B, "
                                  "sFLSMR, SRHT s=400, 200 iterations"),
     "ct64": dict(method="sflsqr", sketch="sparse_sign", s=200, zeta=8, iters=50, tau="identity",
+                 seed=3001,
                  desc="64^2 CT (90 angles x 91 bins), B = A^T, sFLSQR, sparse-sign s=200 zeta=8, "
                       "50 iterations"),
     "ct512_sparse": dict(method="sflsqr", sketch="sparse_sign", s=600, zeta=8, iters=300,
-                         tau="reweight_l1",
+                         tau="reweight_l1", seed=3003,
                          desc="512^2 CT (360 angles x 725 bins), B = A^T, sFLSQR with l1 "
                               "reweighting eps=1e-3, sparse-sign s=600 zeta=8, 300 iterations"),
 }
@@ -209,7 +220,7 @@ def cpu_baseline(P, cfg, sample_iters: int):
     except Exception:
         blas_threads = os.cpu_count() or 1
     d = P.m if cfg["method"] == "sflsqr" else P.n
-    S = sketches.make(cfg["sketch"], d, cfg["s"], 3000 + 2, zeta=cfg["zeta"])
+    S = sketches.make(cfg["sketch"], d, cfg["s"], cfg["seed"], zeta=cfg["zeta"])
     B = P.B
     t0 = time.perf_counter()
     fgk.sketched_flexible(P.A, P.b, S, method=cfg["method"], B=B, maxit=sample_iters, ell=2,
@@ -230,19 +241,133 @@ def cpu_baseline(P, cfg, sample_iters: int):
                       f"{blas_threads} threads; {model}, {os.cpu_count()} logical CPUs)"}
 
 
+KERNEL_NAMES = {0: "CSR-stream", 1: "SELL-64", 8: "8 lanes/row", 16: "16 lanes/row",
+                32: "32 lanes/row", 64: "wave/row"}
+
+
+def _load(name):
+    import torch
+    from paper_2605_22281_amd import inputs, sfk
+    log(f"bench: generating {name}")
+    t = time.perf_counter()
+    P = inputs.workload(name)
+    log(f"bench: {name}: m={P.m} n={P.n} nnzA={P.A.nnz} "
+        f"nnzB={(P.B.nnz if P.B is not None else P.A.nnz)} ({time.perf_counter() - t:.1f} s)")
+    dev = torch.device("cuda:0")
+    A = sfk.to_device_csr(P.A, dev)
+    B = sfk.to_device_csr(P.B, dev) if P.B is not None else None
+    b = torch.from_numpy(P.b).to(dev)
+    return P, A, B, b
+
+
+def run_plain(name, P, A, B, b, K, W, args, full_run=False, noise=False):
+    """Plain single-instance throughput: W untimed warm-up iterations on a
+    throw-away context, K timed iterations of a fresh context, then the same K
+    iterations once more with HIP events around every stage kernel (same SpMV
+    kernels as the timed run: the automatic choice is repeated by vw/vw_b) for
+    the stage averages and the roofline of the dominant product.  full_run:
+    also the workload's whole iteration count, timed on a fresh context.
+    noise: the discrepancy principle (eta = 1.01) instead of a fixed count."""
+    import torch
+    from paper_2605_22281_amd import sfk
+    cfg = WORKLOADS[name]
+    iters = cfg["iters"]
+    maxit = max(K, W, iters if (full_run or noise) else 1)
+    kw = dict(ell=2, maxit=maxit, sketch=cfg["sketch"], s=cfg["s"], zeta=cfg["zeta"],
+              seed=cfg["seed"], tau=cfg["tau"], eps=1e-3, driver=args.driver,
+              perm=_order_tensor(args.order, P))
+    if noise:
+        kw.update(noise_norm=P.noise_norm, eta=1.01)
+    p = sfk.params(cfg["method"], vw=args.vw, **kw)
+    if W > 0:
+        ctx = sfk.init(A, B, b, p)
+        sfk.iterate(ctx, W)
+        sfk.destroy(ctx)
+    ctx = sfk.init(A, B, b, p)
+    va, vb = sfk.spmv_variant(ctx)
+    elapsed, done = _timed_iterate(sfk, torch, ctx, K if not noise else iters)
+    sfk.destroy(ctx)
+    log(f"bench: {name}: timed {done} iterations in {elapsed * 1e3:.2f} ms")
+    if not noise and done != K:
+        raise SystemExit(f"{name}: run ended after {done} of {K} iterations")
+    res = {"workload": cfg["desc"], "m": P.m, "n": P.n, "nnz_A": int(P.A.nnz),
+           "nnz_B": int(P.B.nnz if P.B is not None else P.A.nnz), "method": cfg["method"],
+           "sketch": cfg["sketch"], "s": cfg["s"], "iterations_timed": done,
+           "iterations_per_s": done / elapsed, "ms_per_step": elapsed * 1e3 / max(done, 1),
+           "spmv_kernel": {"A": KERNEL_NAMES.get(va, str(va)), "B": KERNEL_NAMES.get(vb, str(vb))}}
+    if noise:
+        res["stopped_at"] = done
+        return res
+    if full_run and iters > K:
+        ctx = sfk.init(A, B, b, sfk.params(cfg["method"], vw=va, vw_b=vb, **kw))
+        et, dn = _timed_iterate(sfk, torch, ctx, iters)
+        sfk.destroy(ctx)
+        res["full_run"] = {"iterations": dn, "iterations_per_s": dn / et,
+                           "ms_per_step": et * 1e3 / dn}
+        log(f"bench: {name}: full run {dn} iterations, {dn / et:.1f} it/s")
+    ctx = sfk.init(A, B, b, sfk.params(cfg["method"], vw=va, vw_b=vb, **kw))
+    assert sfk.spmv_variant(ctx) == (va, vb)
+    sfk.set_timing(ctx, True)
+    sfk.iterate(ctx, K)
+    times = sfk.stage_times(ctx)
+    sfk.destroy(ctx)
+    ell = 2
+    kA, kB = res["spmv_kernel"]["A"], res["spmv_kernel"]["B"]
+    per_launch = {
+        "spmv_A": spmv_bytes(P.A.nnz, P.m, P.n, P.m, ell + 1, index_bytes(P.n, kA)),
+        "spmv_B": spmv_bytes(res["nnz_B"], P.n, P.m, P.n, ell, index_bytes(P.m, kB)),
+    }
+    stage_avg = {k: (v[0] / v[1] if v[1] else 0.0) for k, v in times.items()}
+    dom = max(("spmv_A", "spmv_B"), key=lambda q: times[q][0])
+    achieved = per_launch[dom] / (stage_avg[dom] * 1e-3) / 1e9
+    variant = kA if dom == "spmv_A" else kB
+    traffic = None
+    tr_file = os.path.join(ROOT, "profiles", "traffic.json")
+    if os.path.exists(tr_file):
+        try:
+            entries = json.load(open(tr_file))
+            entries = entries if isinstance(entries, list) else [entries]
+            for tr in entries:
+                # counters taken on the same kernel sources, workload, order of the
+                # unknowns and SpMV variant as this run
+                if (tr.get("source_hash") == source_hash() and tr.get("workload") == name
+                        and tr.get("order") == args.order
+                        and tr.get("variant", {}).get(dom) == variant):
+                    traffic = tr.get("bytes_per_launch", {}).get(dom)
+        except (OSError, ValueError):
+            traffic = None
+    # the whole iteration: both products' algorithmic bytes, the vector stages
+    # (window reads, update writes), and the x assembly of the reweighting
+    # (8 n (k - 1) bytes at step k, averaged over the timed steps)
+    xbytes = 8 * P.n * (K - 1) / 2 if cfg["tau"] == "reweight_l1" else 0
+    iter_bytes = (per_launch["spmv_A"] + per_launch["spmv_B"]
+                  + 8 * (P.m * (ell + 3) + P.n * (ell + 3)) + xbytes)
+    res["roofline"] = {"bound": "hbm", "kernel": dom, "variant": variant, "achieved": achieved,
+                       "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                       "traffic": traffic, "bytes_per_launch": per_launch[dom],
+                       "avg_launch_ms": stage_avg[dom]}
+    res["iteration_GBps"] = iter_bytes / (res["ms_per_step"] * 1e-3) / 1e9
+    res["iteration_frac"] = res["iteration_GBps"] / HBM_PEAK_GBS
+    res["stage_avg_ms"] = stage_avg
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=None)
-    ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--workload", default="ct256_unmatched", choices=sorted(WORKLOADS))
-    ap.add_argument("--driver", default="auto", choices=["auto", "multi", "persistent"])
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", default="ct512_sparse", choices=sorted(WORKLOADS))
+    ap.add_argument("--driver", default="auto", choices=["auto", "multi", "graph"])
     ap.add_argument("--vw", type=int, default=-2,
                     help="SpMV kernel: -2 automatic, 0 CSR-stream, 1 SELL-64, 8..64 lanes per row")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample-iters", type=int, default=40)
+    ap.add_argument("--cpu-sample-iters", type=int, default=None)
     ap.add_argument("--copy-calibration", action="store_true")
     ap.add_argument("--batched", default="all", choices=["all", "multi", "hetero", "none"])
+    ap.add_argument("--extras", default="all", choices=["all", "none"],
+                    help="the other plain workloads beside the headline")
+    ap.add_argument("--no-full-run", action="store_true")
     ap.add_argument("--rhs", type=int, default=32)
     ap.add_argument("--order", default="tiles4", choices=["natural", "tiles4", "tiles8"],
                     help="order of the unknowns passed to the library: the image's row-major "
@@ -258,113 +383,70 @@ def main():
         copy_calibration()
         return
 
-    import numpy as np
     import torch
-    from paper_2605_22281_amd import inputs, sfk
 
-    cfg = WORKLOADS[args.workload]
+    name = args.workload
+    cfg = WORKLOADS[name]
     K = args.steps if args.steps is not None else cfg["iters"]
     if K < 1 or K >= cfg["s"]:
         raise SystemExit(f"--steps must be in [1, {cfg['s'] - 1}] for this workload")
     W = args.warmup
-    log(f"bench: generating {args.workload}")
-    t = time.perf_counter()
-    P = inputs.workload(args.workload)
-    log(f"bench: m={P.m} n={P.n} nnzA={P.A.nnz} nnzB={(P.B.nnz if P.B is not None else P.A.nnz)} "
-        f"({time.perf_counter() - t:.1f} s)")
-    dev = torch.device("cuda:0")
-    A = sfk.to_device_csr(P.A, dev)
-    B = sfk.to_device_csr(P.B, dev) if P.B is not None else None
-    b = torch.from_numpy(P.b).to(dev)
-    maxit = max(K, W, 1)
-    p = sfk.params(cfg["method"], ell=2, maxit=maxit, sketch=cfg["sketch"], s=cfg["s"],
-                   zeta=cfg["zeta"], seed=3000 + 2, tau=cfg["tau"], eps=1e-3, driver=args.driver,
-                   vw=args.vw, perm=_order_tensor(args.order, P))
-
-    if W > 0:
-        log(f"bench: warmup {W} iterations")
-        ctx = sfk.init(A, B, b, p)
-        sfk.iterate(ctx, W)
-        sfk.destroy(ctx)
-
-    # timed region: K iterations of a fresh context (init outside)
-    ctx = sfk.init(A, B, b, p)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    done, stopped, st = sfk.iterate(ctx, K)
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    log(f"bench: timed {done} iterations in {elapsed * 1e3:.2f} ms")
-    if done != K:
-        raise SystemExit(f"run ended after {done} of {K} iterations (status {st})")
-    names = {0: "CSR-stream", 1: "SELL-64", 8: "8 lanes/row", 16: "16 lanes/row",
-             32: "32 lanes/row", 64: "wave/row"}
-    timed_kernel = {op: names.get(v, str(v)) for op, v in zip(("A", "B"), sfk.spmv_variant(ctx))}
-    sfk.destroy(ctx)
-
-    # same work again with HIP events around every stage kernel (library stream);
-    # each init chooses its SpMV kernels by timing them, so both choices are kept
-    ctx = sfk.init(A, B, b, p)
-    spmv_kernel = {op: names.get(v, str(v)) for op, v in zip(("A", "B"), sfk.spmv_variant(ctx))}
-    sfk.set_timing(ctx, True)
-    sfk.iterate(ctx, K)
-    times = sfk.stage_times(ctx)
-    sfk.destroy(ctx)
-
-    nnzA = P.A.nnz
-    nnzB = P.B.nnz if P.B is not None else P.A.nnz
-    ell = 2
-    per_launch = {
-        "spmv_A": spmv_bytes(nnzA, P.m, P.n, P.m, ell + 1, index_bytes(P.n, spmv_kernel["A"])),
-        "spmv_B": spmv_bytes(nnzB, P.n, P.m, P.n, ell, index_bytes(P.m, spmv_kernel["B"])),
-    }
-    stage_avg = {k: (v[0] / v[1] if v[1] else 0.0) for k, v in times.items()}
-    dom = max(("spmv_A", "spmv_B"), key=lambda s: times[s][0])
-    achieved = per_launch[dom] / (stage_avg[dom] * 1e-3) / 1e9
-    traffic = None
-    tr_file = os.path.join(ROOT, "profiles", "traffic.json")
-    if os.path.exists(tr_file):
-        try:
-            tr = json.load(open(tr_file))
-            # counters taken on the same kernel sources, workload, order of the
-            # unknowns and SpMV variant as this run
-            op = "A" if dom == "spmv_A" else "B"
-            if (tr.get("source_hash") == source_hash() and tr.get("workload") == args.workload
-                    and tr.get("order") == args.order
-                    and tr.get("variant", {}).get(dom) == spmv_kernel[op]):
-                traffic = tr.get("bytes_per_launch", {}).get(dom)
-        except (OSError, ValueError):
-            traffic = None
-
-    ms_per_step = elapsed * 1e3 / K
-    iter_bytes = per_launch["spmv_A"] + per_launch["spmv_B"] + 8 * (P.m * (ell + 3) + P.n * (ell + 3))
+    P, A, B, b = _load(name)
+    head = run_plain(name, P, A, B, b, K, W, args, full_run=not args.no_full_run)
     out = {
         "metric": METRIC,
-        "value": K / elapsed,
+        "value": head["iterations_per_s"],
         "unit": "iterations/s",
         "n_gpus": 1,
         "steps": K,
         "warmup": W,
-        "ms_per_step": ms_per_step,
+        "ms_per_step": head["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": cfg["desc"], "m": P.m, "n": P.n, "nnz_A": nnzA, "nnz_B": nnzB,
-                   "method": cfg["method"], "sketch": cfg["sketch"], "s": cfg["s"], "ell": ell,
-                   "driver": args.driver, "spmv_kernel": timed_kernel, "order": args.order},
-        "roofline": {"bound": "hbm", "kernel": dom,
-                     "variant": spmv_kernel["A" if dom == "spmv_A" else "B"],
-                     "achieved": achieved, "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "bytes_per_launch": per_launch[dom], "avg_launch_ms": stage_avg[dom]},
-        "iteration_GBps": iter_bytes / (ms_per_step * 1e-3) / 1e9,
-        "stage_avg_ms": stage_avg,
+        "config": {"workload": cfg["desc"] + f" (timed: iterations 1..{K} of a fresh context)",
+                   "m": P.m, "n": P.n, "nnz_A": head["nnz_A"], "nnz_B": head["nnz_B"],
+                   "method": cfg["method"], "sketch": cfg["sketch"], "s": cfg["s"], "ell": 2,
+                   "driver": args.driver, "spmv_kernel": head["spmv_kernel"], "order": args.order},
+        "roofline": head["roofline"],
+        "iteration_GBps": head["iteration_GBps"],
+        "iteration_frac": head["iteration_frac"],
+        "stage_avg_ms": head["stage_avg_ms"],
     }
+    if "full_run" in head:
+        out["full_run"] = head["full_run"]
+    if not args.no_cpu_baseline:
+        si = args.cpu_sample_iters or (12 if name == "ct512_sparse" else 40)
+        log(f"bench: oracle baseline, {si} iterations")
+        out["cpu_baseline"] = cpu_baseline(P, cfg, si)
+    del A, B, b
+    torch.cuda.empty_cache()
+    others = [q for q in ("ct64", "ct256_unmatched", "ct512_sparse") if q != name]
+    extras = {}
+    keep = None
+    for q in (others if args.extras == "all" else []):
+        Pq, Aq, Bq, bq = _load(q)
+        Kq = min(WORKLOADS[q]["iters"], WORKLOADS[q]["s"] - 1)
+        extras[q] = run_plain(q, Pq, Aq, Bq, bq, Kq, W, args)
+        if q == "ct64":
+            extras[q]["discrepancy_run"] = run_plain(q, Pq, Aq, Bq, bq, Kq, 0, args, noise=True)
+        if q == "ct256_unmatched":
+            keep = (Pq, Aq, Bq)
+        else:
+            del Aq, Bq, bq
+    if extras:
+        out["workloads"] = extras
     if args.batched in ("all", "multi"):
-        log(f"bench: shared operator, {args.rhs} right-hand sides x {K} iterations, and plain loop")
-        mr = multi_rhs_bench(P, cfg, A, B, args.rhs, K, args.order)
+        q = "ct256_unmatched"
+        if keep is None:
+            Pq, Aq, Bq, _ = _load(q)
+        else:
+            Pq, Aq, Bq = keep
+        Kq = min(K, WORKLOADS[q]["s"] - 1)
+        log(f"bench: shared operator, {args.rhs} right-hand sides x {Kq} iterations, and plain loop")
+        mr = multi_rhs_bench(Pq, WORKLOADS[q], Aq, Bq, args.rhs, Kq, args.order)
         out["batched_multi_rhs"] = mr
         out["batched_plain_speedup"] = mr["speedup"]
         log(f"bench: shared operator speedup {mr['speedup']:.2f}x")
@@ -373,9 +455,6 @@ def main():
         hb = hetero_bench(order=args.order)
         out["batched_heterogeneous"] = hb
         log(f"bench: heterogeneous speedup {hb['speedup']:.2f}x")
-    if not args.no_cpu_baseline:
-        log(f"bench: oracle baseline, {args.cpu_sample_iters} iterations")
-        out["cpu_baseline"] = cpu_baseline(P, cfg, args.cpu_sample_iters)
     print(json.dumps(out))
 
 

@@ -62,9 +62,29 @@ typedef enum { SFK_SK_SPARSE_SIGN = 0, SFK_SK_SRHT = 1, SFK_SK_IDENTITY = 2 } sf
  * REWEIGHT_L1: z_k = (x_{k-1}^2 + eps^2)^(1/4) * p_k elementwise, x_0 = 0. */
 typedef enum { SFK_TAU_IDENTITY = 0, SFK_TAU_REWEIGHT_L1 = 1 } sfk_tau;
 
-/* Iteration driver: AUTO picks PERSISTENT when the device supports cooperative
- * launch, else MULTI (one kernel per pipeline stage). */
-typedef enum { SFK_DRIVER_AUTO = 0, SFK_DRIVER_MULTI = 1, SFK_DRIVER_PERSISTENT = 2 } sfk_driver;
+/* Iteration driver.  MULTI: every stage kernel of every iteration is launched
+ * on the context's stream (and a second stream for the sketch and the small
+ * least-squares update).  GRAPH: the same launches, captured once per batch of
+ * iterations into a HIP graph that is launched as one unit (the host submits one
+ * graph per batch instead of every kernel).  AUTO = MULTI.  Both give identical
+ * results. */
+typedef enum { SFK_DRIVER_AUTO = 0, SFK_DRIVER_MULTI = 1, SFK_DRIVER_GRAPH = 2 } sfk_driver;
+
+/* Residual histories (sfk_residual_norms):
+ *   SKETCHED:        rho_j, the minimised sketched objective of the small
+ *                    least-squares problem (eq. (sFLSQR) / (sFLSMR)), which the
+ *                    stop test of Algorithm 1 / 2 reads;
+ *   TRUE_RECURRENCE: || beta e_1 - H_{j+1,j} y_j ||, the residual in the
+ *                    coordinates of the basis W_{j+1} (eq. (FGK) gives
+ *                    b - A x_j = W_{j+1} (beta e_1 - H_{j+1,j} y_j)); it equals
+ *                    ||b - A x_j|| when the columns of W_{j+1} are orthonormal
+ *                    (a window covering the whole basis) and estimates it with a
+ *                    truncated window;
+ *   TRUE_EXPLICIT:   ||b - A x_j||, the residual of the discrepancy principle
+ *                    (eq. (discrP)): recorded every iteration when
+ *                    sfk_params.resid >= 1, else computed when asked (one
+ *                    solution assembly and one product per iterate). */
+typedef enum { SFK_RES_SKETCHED = 0, SFK_RES_TRUE_RECURRENCE = 1, SFK_RES_TRUE_EXPLICIT = 2 } sfk_res_kind;
 
 /* CSR matrix, device arrays: rowptr[rows + 1], colind[nnz], val[nnz]. */
 typedef struct {
@@ -101,8 +121,27 @@ typedef struct {
                           LDS in units of nearby rows (2, where a unit's rows fit),
                           or staged where the plan reuses each staged row at least
                           5 times on average (-2); any other value = row kernel */
+  int32_t vw_b;        /* SpMV kernel of B, coded as vw, when vw_split = 1 (vw then
+                          applies to A only); e.g. to repeat the kernels an earlier
+                          automatic choice made (sfk_spmv_variant) */
+  int32_t vw_split;    /* 0: vw applies to A and B; 1: vw to A, vw_b to B */
   int32_t wg_per_cu;   /* data-parallel workgroups per CU; 0 = automatic */
-  int32_t reserved0;
+  int32_t resid;       /* explicit true residual ||b - A x_k|| (eq. (discrP)):
+                          0 = not computed during the iteration (sfk_residual_norms
+                          computes it on request); 1 = recorded every iteration
+                          (x_k assembled and one extra product A x_k per
+                          iteration, on the side stream); 2 = recorded and used as
+                          the stop test instead of the sketched one: stop at the
+                          first k with ||b - A x_k|| <= eta * noise_norm (or
+                          <= tol * ||b|| when noise_norm is 0), the discrepancy
+                          principle as eq. (discrP) states it */
+  int32_t copies;      /* 0: sfk_init may allocate device copies of A and B beyond
+                          the workspace (SELL-64, 16-bit column indices, the
+                          renumbered operators of perm; sfk_memory reports their
+                          size); 1: it may not: CSR-stream or row kernels on the
+                          caller's arrays (and the transpose in the workspace),
+                          SFK_EINVAL with perm or vw = 1 */
+  int32_t reserved;    /* must be 0 */
   const int32_t *perm; /* optional order of the n unknowns: a device array of n
                           distinct values in [0, n), or NULL (identity).  Unknown j
                           is stored at position perm[j] inside the library: columns
@@ -117,7 +156,6 @@ typedef struct {
                           touch fewer cache lines.  With perm, rows of A must have at
                           most 4096 entries (SFK_EINVAL otherwise).  Must stay valid
                           until sfk_init returns. */
-  int32_t reserved[2];
 } sfk_params;
 
 /* Fills *p with defaults: sFLSQR, ell = 2, maxit = 50, sparse-sign s = 101, zeta = 8,
@@ -163,15 +201,30 @@ sfk_status sfk_solution(sfk_ctx *ctx, double *x);
 /* x_j = Z_j y_j for 1 <= j <= current k (y_j from the stored factorisation). */
 sfk_status sfk_solution_at(sfk_ctx *ctx, int32_t j, double *x);
 
-/* Per-iteration minimised sketched objective rho_j = min_y ||S(A Z_j y - b)||
- * (sFLSQR) or ||S(B A Z_j y - B b)|| (sFLSMR), j = 1..k: copies min(k, cap)
- * values to out_host, *count_host = k.  *rhs_norm_host (may be NULL) receives
- * ||S b|| (resp. ||S B b||), the scale of the stop test. */
-sfk_status sfk_residual_norms(sfk_ctx *ctx, double *out_host, int32_t cap, int32_t *count_host,
-                              double *rhs_norm_host);
+/* Residual history of kind `kind` (sfk_res_kind) for j = 1..k, k = iterations
+ * done: copies min(k, cap) values to out_host, *count_host = k.
+ *   SFK_RES_SKETCHED: rho_j = min_y ||S(A Z_j y - b)|| (sFLSQR) or
+ *     ||S(B A Z_j y - B b)|| (sFLSMR).
+ *   SFK_RES_TRUE_RECURRENCE: ||beta e_1 - H_{j+1,j} y_j|| (host arithmetic on the
+ *     stored coefficients and y_j).
+ *   SFK_RES_TRUE_EXPLICIT: ||b - A x_j||; recorded values when sfk_params.resid
+ *     >= 1, else each x_j is assembled and multiplied on the device when asked.
+ * *rhs_norm_host (may be NULL) receives the scale of the matching stop test:
+ * ||S b|| (resp. ||S B b||) for SKETCHED, ||b|| for the two true kinds.
+ * SFK_EINVAL for an unknown kind or out_host NULL with cap > 0 and k > 0. */
+sfk_status sfk_residual_norms(sfk_ctx *ctx, int32_t kind, double *out_host, int32_t cap,
+                              int32_t *count_host, double *rhs_norm_host);
 
 /* Explicit true residual ||b - A x_k|| of the current iterate (one extra SpMV). */
 sfk_status sfk_true_residual(sfk_ctx *ctx, double *out_host);
+
+/* Device memory of the context, in bytes: *workspace_host = the workspace
+ * (borrowed from the caller or allocated by sfk_init), *library_host = what
+ * sfk_init allocated besides it (copies of the operators: SELL-64, 16-bit column
+ * indices, renumbered operators, column-sliced copies of shared operators;
+ * descriptors and block maps; the halt flags).  sfk_params.copies = 1 keeps the
+ * copies out.  Either pointer may be NULL. */
+sfk_status sfk_memory(const sfk_ctx *ctx, size_t *workspace_host, size_t *library_host);
 
 /* Frees the context and the workspace it allocated.  NULL is a no-op. */
 sfk_status sfk_destroy(sfk_ctx *ctx);
@@ -231,9 +284,9 @@ sfk_status sfk_instance_solution(sfk_ctx *ctx, int32_t i, double *x);
 /* x_j of instance i for 0 <= j <= its k (see sfk_solution_at). */
 sfk_status sfk_instance_solution_at(sfk_ctx *ctx, int32_t i, int32_t j, double *x);
 
-/* rho_1..rho_k of instance i (see sfk_residual_norms). */
-sfk_status sfk_instance_residual_norms(sfk_ctx *ctx, int32_t i, double *out_host, int32_t cap,
-                                       int32_t *count_host, double *rhs_norm_host);
+/* Residual history of instance i (see sfk_residual_norms). */
+sfk_status sfk_instance_residual_norms(sfk_ctx *ctx, int32_t i, int32_t kind, double *out_host,
+                                       int32_t cap, int32_t *count_host, double *rhs_norm_host);
 
 /* ||b_i - A_i x_k|| of instance i at its own k (see sfk_true_residual). */
 sfk_status sfk_instance_true_residual(sfk_ctx *ctx, int32_t i, double *out_host);
@@ -251,6 +304,15 @@ sfk_status sfk_sketch_srht(sfk_ctx *ctx, int32_t *rows_host, int8_t *neg_host, i
 /* Recurrence coefficients of eq. (FGK) for the first k steps: H_host
  * ((k+1) x k, column-major) and T_host (k x k, column-major). */
 sfk_status sfk_coefficients(sfk_ctx *ctx, double *H_host, double *T_host, int32_t k);
+
+/* Basis vector of eq. (FGK) of instance i after k iterations (a live run, not
+ * stopped): kind 0 = w_j (unit m-vector; kept for k - ell <= j <= k + 1),
+ * kind 1 = p_j (unit n-vector before tau; kept for every j <= k when tau is the
+ * identity, for k + 1 - ell <= j <= k with the reweighting), kind 2 =
+ * z_j = tau(p_j) (n-vector, kept for 1 <= j <= k).  n-vectors are written in
+ * the caller's order of the unknowns.  out: device vector of m or n doubles.
+ * SFK_ESTATE when the vector is not kept or the run has halted. */
+sfk_status sfk_basis_vector(sfk_ctx *ctx, int32_t i, int32_t kind, int32_t j, double *out);
 
 /* ---- timing ---------------------------------------------------------------- */
 

@@ -46,6 +46,11 @@ void launch_perm_rows(const int *rp, const int *ci, const double *va, int rows, 
                       int *orp, int *oci, double *ova, hipStream_t st);
 void launch_solution(const Dev &D, int kk, const double *yv, double *x, hipStream_t st);
 void launch_true_residual(const Dev &D, const double *x, double *out, hipStream_t st);
+void launch_true_iter(const Dev &D, int k, hipStream_t st);
+void launch_zero_bytes(void *p, size_t n, hipStream_t st);
+void launch_iota_map(int2 *map, int count, hipStream_t st);
+void launch_export_vec(const double *src, int vs, int len, const double *scale, const int *pinv,
+                       double *out, hipStream_t st);
 void launch_group_stage(const Grp &G, int stage, int k, hipStream_t st);
 int gspmm_blocks_per_cu(int RS);
 int gspmm_x_blocks_per_cu(int RS);
@@ -97,6 +102,7 @@ struct sfk_ctx {
   static constexpr int kRing = kRawSlots;   // iterations of synchronisation events kept
   hipEvent_t ev_main[kRing] = {}, ev_sk[kRing] = {}, ev_ls[kRing] = {};
   void *hdr = nullptr;              // device: instance descriptors and block maps
+  size_t hdr_bytes = 0, gws_bytes = 0;
   Launch L{};
   Scal *h_scal = nullptr;           // pinned copies of the device scalars
   // early exit of long iterate() calls: the run state of every instance is
@@ -106,17 +112,28 @@ struct sfk_ctx {
   int *h_halt = nullptr;            // pinned, kChkSlots * ninst
   hipEvent_t ev_chk[kChkSlots] = {};
   int k_iter = 0;                   // lockstep iterations launched
+  // events of iterations below ev_from were recorded inside a graph capture
+  // (or belong to a finished graph): no stream waits on them
+  int ev_from = 0;
+  bool graph = false;               // driver GRAPH
+  hipGraphExec_t gexec = nullptr;   // executable graph of the last batch (updated per batch)
+  hipEvent_t ev_join = nullptr;     // joins the side stream into a captured batch
+  hipStream_t gstream = nullptr;    // capture stream (the caller's may be the legacy
+  hipEvent_t ev_fork = nullptr;     // default stream, which cannot be captured), ordered
+  hipEvent_t ev_done = nullptr;     // after and before the caller's by these events
   int maxitmax = 0;
   bool sketch_after_C = false;      // an sFLSMR instance sketches B w_{k+1}
   bool any_rew = false;
+  int resid = 0;                    // per-iteration true residual (single instance)
+  size_t lib_bytes = 0;             // device memory allocated besides the workspaces
   int pending_side[2] = {-1, -1};   // iterations whose sketch/LS wait for the next flush point
   bool multi = false;               // right-hand sides sharing A and B (stages via grp)
   Grp grp{};
   void *gws = nullptr;              // workspace of the shared arrays
-  std::vector<void *> xmem;         // sliced / SELL / renumbered copies of A and B
+  std::vector<std::pair<void *, size_t>> xmem;  // sliced / SELL / renumbered copies of A and B
   const int *gperm = nullptr;       // shared operators: the group's order of the
   const int *gpinv = nullptr;       // unknowns and its inverse (NULL: identity)
-  std::string err;
+  char err[512] = {};               // last error (fixed storage: reporting allocates nothing)
   // optional per-stage timing with HIP events
   bool timing = false;
   std::vector<hipEvent_t> ev_pool;
@@ -124,6 +141,19 @@ struct sfk_ctx {
   double stage_ms[SFK_NUM_STAGES] = {};
   int stage_count[SFK_NUM_STAGES] = {};
 };
+
+// Device memory owned by the context besides the workspaces (released in
+// order by lib_pop, all at sfk_destroy).
+static hipError_t lib_malloc(sfk_ctx *c, void **q, size_t bytes) {
+  hipError_t e = hipMalloc(q, bytes);
+  if (e == hipSuccess) c->xmem.push_back({*q, bytes});
+  return e;
+}
+
+static void lib_pop(sfk_ctx *c) {
+  hipFree(c->xmem.back().first);
+  c->xmem.pop_back();
+}
 
 // records the start event of a timed stage; returns its pool index or -1
 static int stage_begin(sfk_ctx *c, int stage, hipStream_t st) {
@@ -192,6 +222,7 @@ static void enqueue_side(sfk_ctx *c, const int *js, int n) {
     t = stage_begin(c, SFK_STAGE_LS, sd);
     launch_ls(L, j, sd);
     stage_end(c, t, sd);
+    if (c->resid) launch_true_iter(c->inst[0].D, j, sd);
     hipEventRecord(c->ev_ls[r], sd);
   }
 }
@@ -210,6 +241,7 @@ static void sketch_main_ls_side(sfk_ctx *c, int k) {
   t = stage_begin(c, SFK_STAGE_LS, sd);
   launch_ls(L, k, sd);
   stage_end(c, t, sd);
+  if (c->resid) launch_true_iter(c->inst[0].D, k, sd);
   hipEventRecord(c->ev_ls[r], sd);
 }
 
@@ -240,7 +272,8 @@ static void enqueue_iteration(sfk_ctx *c, int k) {
   static_assert(sfk_ctx::kRing >= 8 && kRawSlots >= 8, "side-stream lag");
   hipStream_t st = c->stream;
   const bool late = !c->any_rew;
-  if (k >= 8 && k % 4 == 0) hipStreamWaitEvent(st, c->ev_sk[(k - 5) % sfk_ctx::kRing], 0);
+  if (k >= 8 && k % 4 == 0 && k - 5 >= c->ev_from)
+    hipStreamWaitEvent(st, c->ev_sk[(k - 5) % sfk_ctx::kRing], 0);
   int t = stage_begin(c, SFK_STAGE_SPMV_A, st);
   run_stage(c, kStageA, k, st);
   stage_end(c, t, st);
@@ -264,7 +297,59 @@ static void enqueue_iteration(sfk_ctx *c, int k) {
   stage_end(c, t, st);
 }
 
-static thread_local std::string g_err;
+// Iterations k0 .. k0 + n - 1 captured from the two streams into one HIP
+// graph (the side stream forks from and joins back into the capture), then
+// launched on the context's stream.  Kernel arguments depend on k, so each
+// batch is captured anew; the executable graph is updated in place when the
+// topology allows it, else instantiated again.  Work of earlier batches is
+// complete before a graph launch starts (stream order), so waits on events of
+// earlier batches are dropped (ev_from).
+static hipError_t enqueue_graph_batch(sfk_ctx *c, int k0, int n) {
+  hipStream_t user = c->stream, st = c->gstream;
+  hipError_t e = hipEventRecord(c->ev_fork, user);
+  if (e == hipSuccess) e = hipStreamWaitEvent(st, c->ev_fork, 0);
+  if (e != hipSuccess) return e;
+  c->ev_from = k0;
+  e = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal);
+  if (e != hipSuccess) return e;
+  c->stream = st;                       // the stage sequence runs on the capture stream
+  for (int i = 0; i < n; ++i) enqueue_iteration(c, k0 + i);
+  flush_side(c);
+  hipEventRecord(c->ev_join, c->side);
+  hipStreamWaitEvent(st, c->ev_join, 0);
+  c->stream = user;
+  hipGraph_t g = nullptr;
+  e = hipStreamEndCapture(st, &g);
+  if (e != hipSuccess) return e;
+  if (c->gexec) {
+    hipGraphNode_t bad = nullptr;
+    hipGraphExecUpdateResult res;
+    if (hipGraphExecUpdate(c->gexec, g, &bad, &res) != hipSuccess || res != hipGraphExecUpdateSuccess) {
+      (void)hipGetLastError();
+      hipGraphExecDestroy(c->gexec);
+      c->gexec = nullptr;
+    }
+  }
+  if (!c->gexec) e = hipGraphInstantiate(&c->gexec, g, nullptr, nullptr, 0);
+  hipGraphDestroy(g);
+  if (e != hipSuccess) return e;
+  e = hipGraphLaunch(c->gexec, st);
+  if (e == hipSuccess) e = hipEventRecord(c->ev_done, st);
+  if (e == hipSuccess) e = hipStreamWaitEvent(user, c->ev_done, 0);
+  c->ev_from = k0 + n;
+  return e;
+}
+
+static thread_local char g_err[512];
+
+static void set_err(char *dst, const char *src) { std::snprintf(dst, 512, "%s", src); }
+
+// prefixes the error of a context (or the thread's) with "<what> <i>: "
+static void prefix_err(char *dst, const char *what, int i) {
+  char tmp[512];
+  std::snprintf(tmp, sizeof tmp, "%s %d: %s", what, i, dst);
+  set_err(dst, tmp);
+}
 
 static sfk_status fail(sfk_ctx *c, sfk_status st, const char *fmt, ...) {
   char buf[512];
@@ -272,7 +357,7 @@ static sfk_status fail(sfk_ctx *c, sfk_status st, const char *fmt, ...) {
   va_start(ap, fmt);
   vsnprintf(buf, sizeof buf, fmt, ap);
   va_end(ap);
-  if (c) c->err = buf; else g_err = buf;
+  set_err(c ? c->err : g_err, buf);
   return st;
 }
 
@@ -359,11 +444,23 @@ static sfk_status validate(sfk_ctx *c, const sfk_csr *A, const sfk_csr *B, const
     return fail(c, SFK_EINVAL, "noise_norm must be finite >= 0");
   if (!(p->tol >= 0.0) || !std::isfinite(p->tol)) return fail(c, SFK_EINVAL, "tol must be finite >= 0");
   if (p->driver < 0 || p->driver > 2) return fail(c, SFK_EINVAL, "unknown driver %d", p->driver);
-  if (p->vw != -2 && p->vw != -1 && p->vw != 0 && p->vw != 1 && p->vw != 8 && p->vw != 16 &&
-      p->vw != 32 && p->vw != 64 && !(multi && p->vw == 2))
+  auto vw_ok = [&](int v) {
+    return v == -2 || v == -1 || v == 0 || v == 1 || v == 8 || v == 16 || v == 32 || v == 64 ||
+           (multi && v == 2);
+  };
+  if (!vw_ok(p->vw) || (p->vw_split && !vw_ok(p->vw_b)))
     return fail(c, SFK_EINVAL, multi ? "vw must be -2, -1, 0, 1, 2, 8, 16, 32 or 64"
                                      : "vw must be -2, -1, 0, 1, 8, 16, 32 or 64 (2 only for "
                                        "right-hand sides sharing A and B)");
+  if (p->vw_split != 0 && p->vw_split != 1) return fail(c, SFK_EINVAL, "vw_split must be 0 or 1");
+  if (p->resid < 0 || p->resid > 2) return fail(c, SFK_EINVAL, "resid must be 0, 1 or 2");
+  if (p->copies != 0 && p->copies != 1) return fail(c, SFK_EINVAL, "copies must be 0 or 1");
+  if (p->reserved != 0) return fail(c, SFK_EINVAL, "reserved must be 0");
+  if (p->copies && (p->perm || p->vw == 1 || (p->vw_split && p->vw_b == 1)))
+    return fail(c, SFK_EINVAL, "copies = 1 excludes perm and the SELL-64 kernel (vw = 1)");
+  if (p->method == SFK_SFLSMR && p->noise_norm > 0.0 && p->resid != 2)
+    return fail(c, SFK_EINVAL, "the sketched discrepancy test is defined for sFLSQR; for sFLSMR "
+                "set resid = 2 (stop on ||b - A x_k|| <= eta * noise_norm)");
   if (p->wg_per_cu < 0 || p->wg_per_cu > 64) return fail(c, SFK_EINVAL, "wg_per_cu out of range");
   return SFK_OK;
 }
@@ -393,7 +490,7 @@ struct Plan {
   size_t o_sc, o_err, o_scalar, o_part, o_sigw, o_sigp, o_H, o_T, o_rho;
   size_t o_W, o_P, o_Z, o_wraw, o_zraw, o_x, o_Apart, o_Bpart;
   size_t o_skcode, o_skent, o_skrp, o_chunk, o_srows, o_sd, o_spart, o_SK, o_skrhs;
-  size_t o_V, o_tauv, o_R, o_c, o_y, o_ytmp;
+  size_t o_V, o_tauv, o_R, o_c, o_y, o_ytmp, o_rtrue, o_xres;
   size_t o_brp, o_bci, o_bva, o_cursor;
   size_t total;
 };
@@ -433,7 +530,7 @@ static Plan make_plan(const sfk_csr *A, const sfk_csr *B, const sfk_params *p, i
   P.nnzB = B ? B->nnz : A->nnz;
   P.nw = nws;
   P.vwA = pick_vw(P.nnzA, P.m, p->vw);
-  P.vwB = pick_vw(P.nnzB, P.n, p->vw);
+  P.vwB = pick_vw(P.nnzB, P.n, p->vw_split ? p->vw_b : p->vw);
   P.d = (int)(p->method == SFK_SFLSQR ? P.m : P.n);
   P.N = (int)next_pow2(P.d);
   const int L = std::min(P.N, kSrhtL);
@@ -482,6 +579,8 @@ static Plan make_plan(const sfk_csr *A, const sfk_csr *B, const sfk_params *p, i
   P.o_c = L_.take<double>(s);
   P.o_y = L_.take<double>(mi);
   P.o_ytmp = L_.take<double>(mi);
+  P.o_rtrue = L_.take<double>(p->resid ? mi : 1);
+  P.o_xres = L_.take<double>(p->resid ? n : 1);
   if (P.transpose && !member) {
     P.o_brp = L_.take<int>(n + 1);
     P.o_bci = L_.take<int>(P.nnzB);
@@ -545,8 +644,7 @@ static sfk_status build_sell(sfk_ctx *c, const int *rp, const int *ci, const dou
   *ok = false;
   const int nsl = (rows + kSellC - 1) / kSellC;
   void *meta = nullptr;
-  HIPCHK(c, hipMalloc(&meta, sizeof(int) * (2 * (size_t)nsl + 1)));
-  c->xmem.push_back(meta);
+  HIPCHK(c, lib_malloc(c, &meta, sizeof(int) * (2 * (size_t)nsl + 1)));
   int *slen = static_cast<int *>(meta), *soff = slen + nsl;
   launch_sell_len(rp, rows, nsl, slen, st);
   std::vector<int> h(nsl);
@@ -565,8 +663,7 @@ static sfk_status build_sell(sfk_ctx *c, const int *rp, const int *ci, const dou
   const bool narrow = cols <= 65536;
   const size_t tot1 = (size_t)std::max<int64_t>(tot, 1);
   void *mem = nullptr;
-  HIPCHK(c, hipMalloc(&mem, tot1 * (sizeof(int) + sizeof(double) + (narrow ? sizeof(uint16_t) : 0))));
-  c->xmem.push_back(mem);
+  HIPCHK(c, lib_malloc(c, &mem, tot1 * (sizeof(int) + sizeof(double) + (narrow ? sizeof(uint16_t) : 0))));
   double *sval = static_cast<double *>(mem);
   int *scol = reinterpret_cast<int *>(sval + tot1);
   uint16_t *scol16 = narrow ? reinterpret_cast<uint16_t *>(scol + tot1) : nullptr;
@@ -623,8 +720,7 @@ static sfk_status relabel(sfk_ctx *c, const int *perm, const sfk_csr *A, const s
   hipStream_t st = c->stream;
   const int m = (int)A->rows, n = (int)A->cols;
   auto alloc = [&](void **q, size_t bytes) -> sfk_status {
-    HIPCHK(c, hipMalloc(q, std::max<size_t>(bytes, 256)));
-    c->xmem.push_back(*q);
+    HIPCHK(c, lib_malloc(c, q, std::max<size_t>(bytes, 256)));
     return SFK_OK;
   };
   void *pc = nullptr, *pi = nullptr, *cnt = nullptr;
@@ -640,8 +736,7 @@ static sfk_status relabel(sfk_ctx *c, const int *perm, const sfk_csr *A, const s
   int herr = 0;
   HIPCHK(c, hipMemcpyAsync(&herr, err, sizeof(int), hipMemcpyDeviceToHost, st));
   HIPCHK(c, hipStreamSynchronize(st));
-  hipFree(cnt);
-  c->xmem.pop_back();
+  lib_pop(c);   // cnt
   if (herr) return fail(c, SFK_EINVAL, "perm must hold each of 0..n-1 exactly once");
   void *ca = nullptr, *va = nullptr;
   e = alloc(&ca, sizeof(int) * (size_t)A->nnz);
@@ -700,7 +795,7 @@ static sfk_status setup_instance(sfk_ctx *c, Inst &I, const sfk_csr *A, const sf
   I.ws_bytes = P.total;
   void *w = I.ws;
   hipStream_t st = c->stream;
-  HIPCHK(c, hipMemsetAsync(w, 0, P.total, st));
+  launch_zero_bytes(w, P.total, st);
 
   Dev &D = I.D;
   std::memset(&D, 0, sizeof D);
@@ -714,6 +809,7 @@ static sfk_status setup_instance(sfk_ctx *c, Inst &I, const sfk_csr *A, const sf
   D.sketch = p.sketch;
   D.zeta = p.zeta;
   D.d_sk = P.d;
+  D.resid = p.resid;
   D.N = P.N;
   D.log2L = P.log2L;
   D.nblk = P.nblk;
@@ -758,6 +854,8 @@ static sfk_status setup_instance(sfk_ctx *c, Inst &I, const sfk_csr *A, const sf
   D.R = at<double>(w, P.o_R);
   D.c = at<double>(w, P.o_c);
   D.y = at<double>(w, P.o_y);
+  D.rtrue = at<double>(w, P.o_rtrue);
+  D.xres = at<double>(w, P.o_xres);
   I.d_err = at<int>(w, P.o_err);
   I.d_scalar = at<double>(w, P.o_scalar);
   I.d_ytmp = at<double>(w, P.o_ytmp);
@@ -817,10 +915,9 @@ static sfk_status setup_instance(sfk_ctx *c, Inst &I, const sfk_csr *A, const sf
   for (int op = 0; op < 2; ++op) {
     const bool isa = op == 0;
     const int64_t cols = isa ? D.n : D.m, nnz = isa ? P.nnzA : P.nnzB;
-    if (cols > 65536 || nnz <= 0) continue;
+    if (cols > 65536 || nnz <= 0 || p.copies) continue;
     void *m16 = nullptr;
-    HIPCHK(c, hipMalloc(&m16, sizeof(uint16_t) * (size_t)nnz));
-    c->xmem.push_back(m16);
+    HIPCHK(c, lib_malloc(c, &m16, sizeof(uint16_t) * (size_t)nnz));
     launch_to_u16(isa ? D.Aci : D.Bci, static_cast<uint16_t *>(m16), nnz, st);
     (isa ? D.Aci16 : D.Bci16) = static_cast<const uint16_t *>(m16);
   }
@@ -836,7 +933,8 @@ static sfk_status setup_instance(sfk_ctx *c, Inst &I, const sfk_csr *A, const sf
     const bool tune = vw == -2;
     const size_t mark = c->xmem.size();
     bool ok = false;
-    sfk_status e = isa ? build_sell(c, D.Arp, D.Aci, D.Ava, D.m, D.n, P.nnzA, &D.Ansl, &D.Asoff,
+    sfk_status e = p.copies ? SFK_OK
+                 : isa ? build_sell(c, D.Arp, D.Aci, D.Ava, D.m, D.n, P.nnzA, &D.Ansl, &D.Asoff,
                                     &D.Aslen, &D.Ascol, &D.Ascol16, &D.Asval, &ok)
                        : build_sell(c, D.Brp, D.Bci, D.Bva, D.n, D.m, P.nnzB, &D.Bnsl, &D.Bsoff,
                                     &D.Bslen, &D.Bscol, &D.Bscol16, &D.Bsval, &ok);
@@ -873,10 +971,7 @@ static sfk_status setup_instance(sfk_ctx *c, Inst &I, const sfk_csr *A, const sf
     vw = pick;
     if (pick != 1) {          // the SELL copy lost (or was refused): release it
       HIPCHK(c, hipStreamSynchronize(st));
-      while (c->xmem.size() > mark) {
-        hipFree(c->xmem.back());
-        c->xmem.pop_back();
-      }
+      while (c->xmem.size() > mark) lib_pop(c);
       if (isa) D.Ascol16 = nullptr; else D.Bscol16 = nullptr;
     }
   }
@@ -916,6 +1011,7 @@ static sfk_status build_launch(sfk_ctx *c) {
     maxitmax = std::max(maxitmax, D.maxit);
     if (D.method == SFK_SFLSMR) c->sketch_after_C = true;
     if (D.tau == SFK_TAU_REWEIGHT_L1) c->any_rew = true;
+    if (c->inst[i].p.driver == SFK_DRIVER_GRAPH) c->graph = true;
   }
   auto al = [](size_t v) { return (v + 255) / 256 * 256; };
   const size_t o_dev = 0;
@@ -926,6 +1022,7 @@ static sfk_status build_launch(sfk_ctx *c) {
   const size_t o_mc = al(o_mb + sizeof(int2) * mb.size());
   const size_t total = al(o_mc + sizeof(int2) * mc.size()) + 256;
   HIPCHK(c, hipMalloc(&c->hdr, total));
+  c->hdr_bytes = total;
   std::vector<char> h(total, 0);
   for (int i = 0; i < nb; ++i) std::memcpy(h.data() + o_dev + sizeof(Dev) * i, &c->inst[i].D, sizeof(Dev));
   auto put = [&](size_t off, const std::vector<int2> &v) {
@@ -972,6 +1069,10 @@ static sfk_status create_streams(sfk_ctx *c, int nb) {
   for (int i = 0; i < sfk_ctx::kChkSlots; ++i)
     HIPCHK(c, hipEventCreateWithFlags(&c->ev_chk[i], hipEventDisableTiming));
   HIPCHK(c, hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking));
+  HIPCHK(c, hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming));
+  HIPCHK(c, hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming));
+  HIPCHK(c, hipEventCreateWithFlags(&c->ev_done, hipEventDisableTiming));
+  HIPCHK(c, hipStreamCreateWithFlags(&c->gstream, hipStreamNonBlocking));
   for (int i = 0; i < sfk_ctx::kRing; ++i) {
     HIPCHK(c, hipEventCreateWithFlags(&c->ev_main[i], hipEventDisableTiming));
     HIPCHK(c, hipEventCreateWithFlags(&c->ev_sk[i], hipEventDisableTiming));
@@ -1013,13 +1114,21 @@ static void release(sfk_ctx *c) {
   for (hipEvent_t e : c->ev_pool) hipEventDestroy(e);
   for (int i = 0; i < sfk_ctx::kChkSlots; ++i)
     if (c->ev_chk[i]) hipEventDestroy(c->ev_chk[i]);
+  if (c->ev_join) hipEventDestroy(c->ev_join);
+  if (c->ev_fork) hipEventDestroy(c->ev_fork);
+  if (c->ev_done) hipEventDestroy(c->ev_done);
+  if (c->gexec) hipGraphExecDestroy(c->gexec);
   if (c->d_halt) hipFree(c->d_halt);
   if (c->h_halt) hipHostFree(c->h_halt);
   if (c->side) hipStreamDestroy(c->side);
+  if (c->gstream) {
+    hipStreamSynchronize(c->gstream);
+    hipStreamDestroy(c->gstream);
+  }
   for (auto &I : c->inst)
     if (I.owns_ws && I.ws) hipFree(I.ws);
   if (c->gws) hipFree(c->gws);
-  for (void *q : c->xmem) hipFree(q);
+  for (auto &q : c->xmem) hipFree(q.first);
   if (c->hdr) hipFree(c->hdr);
   if (c->h_scal) hipHostFree(c->h_scal);
   delete c;
@@ -1038,13 +1147,14 @@ extern "C" sfk_status sfk_init(sfk_ctx **out, const sfk_csr *A, const sfk_csr *B
   c->stream = static_cast<hipStream_t>(stream);
   c->inst.resize(1);
   c->inst[0].p = *p;
+  c->resid = p->resid;
   s = create_streams(c, 1);
   if (s == SFK_OK)
     s = setup_instance(c, c->inst[0], A, B, b, workspace, workspace_bytes, cus,
                        default_nws(A, B, p, cus, spmv_blocks_per_cu()));
   if (s == SFK_OK) s = init_common(c);
   if (s != SFK_OK) {
-    g_err = c->err;
+    set_err(g_err, c->err);
     release(c);
     return s;
   }
@@ -1062,8 +1172,10 @@ extern "C" sfk_status sfk_init_batch(sfk_ctx **out, int32_t nb, const sfk_csr *A
   for (int i = 0; i < nb; ++i) {
     const sfk_csr *Bi = (B && B[i].rows > 0) ? &B[i] : nullptr;
     sfk_status s = validate(nullptr, &A[i], Bi, &p[i]);
+    if (s == SFK_OK && p[i].resid != 0)
+      s = fail(nullptr, SFK_EINVAL, "resid must be 0 in a batch (single-instance contexts only)");
     if (s != SFK_OK) {
-      g_err = "instance " + std::to_string(i) + ": " + g_err;
+      prefix_err(g_err, "instance", i);
       return s;
     }
   }
@@ -1083,11 +1195,11 @@ extern "C" sfk_status sfk_init_batch(sfk_ctx **out, int32_t nb, const sfk_csr *A
     const sfk_csr *Bi = (B && B[i].rows > 0) ? &B[i] : nullptr;
     const int nws = default_nws(&A[i], Bi, &p[i], cus, bpc);
     s = setup_instance(c, c->inst[i], &A[i], Bi, b[i], nullptr, 0, cus, nws);
-    if (s != SFK_OK) c->err = "instance " + std::to_string(i) + ": " + c->err;
+    if (s != SFK_OK) prefix_err(c->err, "instance", i);
   }
   if (s == SFK_OK) s = init_common(c);
   if (s != SFK_OK) {
-    g_err = c->err;
+    set_err(g_err, c->err);
     release(c);
     return s;
   }
@@ -1109,6 +1221,7 @@ static sfk_status same_params(const sfk_params &a, const sfk_params &b, int r) {
   else if (a.tau != b.tau) what = "tau";
   else if (a.tau == SFK_TAU_REWEIGHT_L1 && a.eps != b.eps) what = "eps";
   else if (a.perm != b.perm) what = "perm";
+  else if (a.copies != b.copies) what = "copies";
   if (what)
     return fail(nullptr, SFK_EINVAL, "right-hand side %d: '%s' differs from right-hand side 0 "
                 "(right-hand sides sharing A and B may differ only in seed, instance, eta, "
@@ -1173,8 +1286,7 @@ static sfk_status plan_lds(sfk_ctx *c, XOp &X, const int *touch, int RS, int cus
   const size_t o_grp = L.take<int2>(std::max<size_t>(grp.size() / 2, 1));
   const size_t o_upart = L.take<int>(P.upart.size());
   void *mem = nullptr;
-  HIPCHK(c, hipMalloc(&mem, L.off));
-  c->xmem.push_back(mem);
+  HIPCHK(c, lib_malloc(c, &mem, L.off));
   HIPCHK(c, hipMemcpyAsync(at<XNz>(mem, o_rec), urec.data(), sizeof(XNz) * urec.size(),
                            hipMemcpyHostToDevice, st));
   HIPCHK(c, hipMemcpyAsync(at<int>(mem, o_stage), P.stage.data(), sizeof(int32_t) * P.stage.size(),
@@ -1224,8 +1336,7 @@ static sfk_status build_xop(sfk_ctx *c, XOp &X, const int *rp, const int *ci, co
     ~Guard() { if (p) hipFree(p); }
   } g1{scr};
   void *crp_mem = nullptr;
-  HIPCHK(c, hipMalloc(&crp_mem, sizeof(int) * ((size_t)rows + 1)));
-  c->xmem.push_back(crp_mem);
+  HIPCHK(c, lib_malloc(c, &crp_mem, sizeof(int) * ((size_t)rows + 1)));
   int *cb = at<int>(scr, o_cb), *touch = at<int>(scr, o_touch), *err = at<int>(scr, o_err);
   int *crp = static_cast<int *>(crp_mem);
   std::vector<int> hcb(NS + 1);
@@ -1252,8 +1363,7 @@ static sfk_status build_xop(sfk_ctx *c, XOp &X, const int *rp, const int *ci, co
   const size_t o_nz = L2.take<XNz>(nzcap);
   const size_t o_part = L2.take<double>((size_t)std::max(nseg, 1) * RS);
   void *mem = nullptr;
-  HIPCHK(c, hipMalloc(&mem, L2.off));
-  c->xmem.push_back(mem);
+  HIPCHK(c, lib_malloc(c, &mem, L2.off));
   Layout L3;
   const size_t o_len = L3.take<int>((size_t)nseg + 1);
   const size_t o_src = L3.take<int>(std::max(nseg, 1));
@@ -1299,8 +1409,11 @@ extern "C" sfk_status sfk_init_multi(sfk_ctx **out, const sfk_csr *A, const sfk_
   if (!A || !b_block || !p) return fail(nullptr, SFK_EINVAL, "A, b_block and params must not be NULL");
   for (int r = 0; r < R; ++r) {
     sfk_status s = validate(nullptr, A, B, &p[r], true);
+    if (s == SFK_OK && p[r].resid != 0)
+      s = fail(nullptr, SFK_EINVAL, "resid must be 0 for right-hand sides sharing A and B "
+               "(single-instance contexts only)");
     if (s != SFK_OK) {
-      g_err = "right-hand side " + std::to_string(r) + ": " + g_err;
+      prefix_err(g_err, "right-hand side", r);
       return s;
     }
     s = same_params(p[0], p[r], r);
@@ -1355,6 +1468,7 @@ extern "C" sfk_status sfk_init_multi(sfk_ctx **out, const sfk_csr *A, const sfk_
   Grp &G = c->grp;
   auto setup_group = [&]() -> sfk_status {
     hipError_t e = hipMalloc(&c->gws, total);
+    c->gws_bytes = total;
     if (e != hipSuccess) {
       c->gws = nullptr;
       return fail(c, SFK_ENOMEM, "hipMalloc of %zu bytes failed: %s", total, hipGetErrorString(e));
@@ -1409,7 +1523,7 @@ extern "C" sfk_status sfk_init_multi(sfk_ctx **out, const sfk_csr *A, const sfk_
   // sliced products (vw automatic, 0 or 2) unless the row kernel is asked for
   // (any other vw) or an operator cannot be sliced; LDS-staged units where
   // they pay (vw automatic), never (0) or wherever they fit (2)
-  if (s == SFK_OK && (p0.vw == 0 || p0.vw == -2 || p0.vw == 2)) {
+  if (s == SFK_OK && !p0.copies && (p0.vw == 0 || p0.vw == -2 || p0.vw == 2)) {
     bool oka = false, okb = false;
     const int lds = p0.vw == -2 ? 1 : p0.vw == 2 ? 2 : 0;
     s = build_xop(c, G.xa, G.Arp, G.Aci, G.Ava, (int)m, (int)n, nnzA, RS, cus, lds, &oka);
@@ -1420,11 +1534,11 @@ extern "C" sfk_status sfk_init_multi(sfk_ctx **out, const sfk_csr *A, const sfk_
   for (int r = 0; r < R && s == SFK_OK; ++r) {
     c->inst[r].p = p[r];
     s = setup_instance(c, c->inst[r], A, B, b_block + (size_t)r * m, nullptr, 0, cus, nw, &G, r);
-    if (s != SFK_OK) c->err = "right-hand side " + std::to_string(r) + ": " + c->err;
+    if (s != SFK_OK) prefix_err(c->err, "right-hand side", r);
   }
   if (s == SFK_OK) s = init_common(c);
   if (s != SFK_OK) {
-    g_err = c->err;
+    set_err(g_err, c->err);
     release(c);
     return s;
   }
@@ -1468,12 +1582,16 @@ extern "C" sfk_status sfk_iterate(sfk_ctx *c, int32_t k, int32_t *iters_done_hos
   // batches ahead of the device and stops enqueueing once every instance has
   // halted, so a run that stops early does not pay for the rest of k.
   const int k0 = c->k_iter;
-  constexpr int kBatch = 4;
+  // graphs are not used while the stages are timed (events between kernels)
+  const bool graph = c->graph && !c->timing;
+  const int kBatch = graph ? 8 : 4;
+  hipStream_t chk = graph ? c->stream : c->side;
   int enq = 0, nbatch = 0;
   bool all_done = false;
   while (enq < k && !all_done) {
     const int n = std::min(kBatch, k - enq);
-    for (int i = 1; i <= n; ++i) enqueue_iteration(c, k0 + enq + i);
+    if (graph) HIPCHK(c, enqueue_graph_batch(c, k0 + enq + 1, n));
+    else for (int i = 1; i <= n; ++i) enqueue_iteration(c, k0 + enq + i);
     enq += n;
     const int slot = nbatch % sfk_ctx::kChkSlots;
     int *dh = c->d_halt + (size_t)slot * nb;
@@ -1486,14 +1604,17 @@ extern "C" sfk_status sfk_iterate(sfk_ctx *c, int32_t k, int32_t *iters_done_hos
       for (int i = 0; i < nb; ++i) all_done = all_done && hh[i] != 0;
     }
     if (!all_done && enq < k) {
-      launch_collect_halt(c->L, k0 + enq, dh, c->side);
-      HIPCHK(c, hipMemcpyAsync(hh, dh, sizeof(int) * nb, hipMemcpyDeviceToHost, c->side));
-      HIPCHK(c, hipEventRecord(c->ev_chk[slot], c->side));
+      launch_collect_halt(c->L, k0 + enq, dh, chk);
+      HIPCHK(c, hipMemcpyAsync(hh, dh, sizeof(int) * nb, hipMemcpyDeviceToHost, chk));
+      HIPCHK(c, hipEventRecord(c->ev_chk[slot], chk));
     }
     ++nbatch;
   }
-  flush_side(c);
-  if (enq > 0) HIPCHK(c, hipStreamWaitEvent(c->stream, c->ev_ls[(k0 + enq) % sfk_ctx::kRing], 0));
+  if (!graph) {
+    flush_side(c);
+    if (enq > 0 && k0 + enq >= c->ev_from)
+      HIPCHK(c, hipStreamWaitEvent(c->stream, c->ev_ls[(k0 + enq) % sfk_ctx::kRing], 0));
+  }
   HIPCHK(c, hipGetLastError());
   c->k_iter = k0 + enq;
   sfk_status s = read_scal(c);
@@ -1551,31 +1672,80 @@ extern "C" sfk_status sfk_instance_solution_at(sfk_ctx *c, int32_t i, int32_t j,
   return s != SFK_OK ? s : solution_impl(c, *I, j, x);
 }
 
-static sfk_status norms_impl(sfk_ctx *c, Inst &I, double *out_host, int32_t cap,
+static sfk_status true_residual_impl(sfk_ctx *c, Inst &I, double *out_host);
+static sfk_status explicit_residual_at(sfk_ctx *c, Inst &I, int j, double *out_host);
+
+// Residual histories (sfk_res_kind) of one instance for j = 1..k_done.
+static sfk_status norms_impl(sfk_ctx *c, Inst &I, int kind, double *out_host, int32_t cap,
                              int32_t *count_host, double *rhs_norm_host) {
+  if (kind < SFK_RES_SKETCHED || kind > SFK_RES_TRUE_EXPLICIT)
+    return fail(c, SFK_EINVAL, "unknown residual kind %d", kind);
   const int n = std::min(cap, I.k_done);
-  if (n > 0) {
-    if (!out_host) return fail(c, SFK_EINVAL, "out_host must not be NULL");
-    HIPCHK(c, hipMemcpy(out_host, I.D.rho, sizeof(double) * n, hipMemcpyDeviceToHost));
+  if (n > 0 && !out_host) return fail(c, SFK_EINVAL, "out_host must not be NULL");
+  const double beta = c->h_scal[&I - &c->inst[0]].beta;
+  if (kind == SFK_RES_SKETCHED) {
+    if (n > 0) HIPCHK(c, hipMemcpy(out_host, I.D.rho, sizeof(double) * n, hipMemcpyDeviceToHost));
+    if (rhs_norm_host) *rhs_norm_host = I.rhsnorm;
+  } else if (kind == SFK_RES_TRUE_RECURRENCE) {
+    // || beta e_1 - H_{j+1,j} y_j || from the stored H column band and y_j
+    const int ldh = I.D.maxit + 1;
+    std::vector<double> H((size_t)ldh * std::max(n, 1)), y(std::max(n, 1));
+    if (n > 0)
+      HIPCHK(c, hipMemcpy(H.data(), I.D.H, sizeof(double) * (size_t)ldh * n, hipMemcpyDeviceToHost));
+    for (int j = 1; j <= n; ++j) {
+      launch_backsub(I.D, j, I.d_ytmp, c->stream);
+      HIPCHK(c, hipGetLastError());
+      HIPCHK(c, hipMemcpyAsync(y.data(), I.d_ytmp, sizeof(double) * j, hipMemcpyDeviceToHost,
+                               c->stream));
+      HIPCHK(c, hipStreamSynchronize(c->stream));
+      double r2 = 0.0;
+      for (int i = 0; i <= j; ++i) {      // row i of beta e_1 - H_{j+1,j} y
+        double v = i == 0 ? beta : 0.0;
+        for (int q = 0; q < j; ++q) v -= H[(size_t)q * ldh + i] * y[q];
+        r2 += v * v;
+      }
+      out_host[j - 1] = std::sqrt(r2);
+    }
+    if (rhs_norm_host) *rhs_norm_host = beta;
+  } else {
+    if (I.p.resid) {
+      if (n > 0) HIPCHK(c, hipMemcpy(out_host, I.D.rtrue, sizeof(double) * n, hipMemcpyDeviceToHost));
+    } else {
+      for (int j = 1; j <= n; ++j) {
+        sfk_status s = explicit_residual_at(c, I, j, out_host + (j - 1));
+        if (s != SFK_OK) return s;
+      }
+    }
+    if (rhs_norm_host) *rhs_norm_host = beta;
   }
   if (count_host) *count_host = I.k_done;
-  if (rhs_norm_host) *rhs_norm_host = I.rhsnorm;
   return SFK_OK;
 }
 
-extern "C" sfk_status sfk_residual_norms(sfk_ctx *c, double *out_host, int32_t cap,
+extern "C" sfk_status sfk_residual_norms(sfk_ctx *c, int32_t kind, double *out_host, int32_t cap,
                                          int32_t *count_host, double *rhs_norm_host) {
   Inst *I;
   sfk_status s = instance_of(c, 0, &I);
-  return s != SFK_OK ? s : norms_impl(c, *I, out_host, cap, count_host, rhs_norm_host);
+  return s != SFK_OK ? s : norms_impl(c, *I, kind, out_host, cap, count_host, rhs_norm_host);
 }
 
-extern "C" sfk_status sfk_instance_residual_norms(sfk_ctx *c, int32_t i, double *out_host,
-                                                  int32_t cap, int32_t *count_host,
-                                                  double *rhs_norm_host) {
+extern "C" sfk_status sfk_instance_residual_norms(sfk_ctx *c, int32_t i, int32_t kind,
+                                                  double *out_host, int32_t cap,
+                                                  int32_t *count_host, double *rhs_norm_host) {
   Inst *I;
   sfk_status s = instance_of(c, i, &I);
-  return s != SFK_OK ? s : norms_impl(c, *I, out_host, cap, count_host, rhs_norm_host);
+  return s != SFK_OK ? s : norms_impl(c, *I, kind, out_host, cap, count_host, rhs_norm_host);
+}
+
+extern "C" sfk_status sfk_memory(const sfk_ctx *c, size_t *workspace_host, size_t *library_host) {
+  if (!c) return fail(nullptr, SFK_EINVAL, "NULL context");
+  size_t ws = c->gws_bytes, lib = c->hdr_bytes;
+  for (const auto &I : c->inst) ws += I.ws_bytes;
+  for (const auto &q : c->xmem) lib += q.second;
+  if (c->d_halt) lib += sizeof(int) * sfk_ctx::kChkSlots * c->inst.size();
+  if (workspace_host) *workspace_host = ws;
+  if (library_host) *library_host = lib;
+  return SFK_OK;
 }
 
 extern "C" sfk_status sfk_instance_status(sfk_ctx *c, int32_t i, int32_t *iters_done_host,
@@ -1591,12 +1761,15 @@ extern "C" sfk_status sfk_instance_status(sfk_ctx *c, int32_t i, int32_t *iters_
 
 extern "C" int32_t sfk_batch_size(const sfk_ctx *c) { return c ? (int32_t)c->inst.size() : 0; }
 
-static sfk_status true_residual_impl(sfk_ctx *c, Inst &I, double *out_host) {
+// ||b - A x_j|| of instance I (x_j assembled in the caller's order, multiplied
+// by the caller's A)
+static sfk_status explicit_residual_at(sfk_ctx *c, Inst &I, int j, double *out_host) {
   if (!out_host) return fail(c, SFK_EINVAL, "NULL argument");
-  // D.x is contiguous scratch here (tau = I), holds x_k itself (reweighting,
-  // single instance) or is a right-hand side's own scratch (shared operators)
+  // D.x is scratch: the p-update of the reweighting writes x_k there but no
+  // stage reads it back; for shared operators it is a right-hand side's own
+  // contiguous n-vector
   double *xtmp = I.D.x;
-  sfk_status s = solution_impl(c, I, I.k_done, xtmp);
+  sfk_status s = solution_impl(c, I, j, xtmp);
   if (s != SFK_OK) return s;
   // x is in the caller's order: the residual uses the caller's A
   Dev D = I.D;
@@ -1606,6 +1779,10 @@ static sfk_status true_residual_impl(sfk_ctx *c, Inst &I, double *out_host) {
   HIPCHK(c, hipMemcpyAsync(out_host, I.d_scalar, sizeof(double), hipMemcpyDeviceToHost, c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
   return SFK_OK;
+}
+
+static sfk_status true_residual_impl(sfk_ctx *c, Inst &I, double *out_host) {
+  return explicit_residual_at(c, I, I.k_done, out_host);
 }
 
 extern "C" sfk_status sfk_true_residual(sfk_ctx *c, double *out_host) {
@@ -1643,8 +1820,8 @@ extern "C" sfk_status sfk_destroy(sfk_ctx *c) {
 }
 
 extern "C" const char *sfk_last_error(const sfk_ctx *c) {
-  if (c) return c->err.c_str();
-  return g_err.c_str();
+  if (c) return c->err;
+  return g_err;
 }
 
 extern "C" sfk_status sfk_sketch_sparse_sign(sfk_ctx *c, int32_t *rows_host, int8_t *neg_host) {
@@ -1690,6 +1867,41 @@ extern "C" sfk_status sfk_coefficients(sfk_ctx *c, double *H_host, double *T_hos
     if (T_host) HIPCHK(c, hipMemcpy(T_host + (size_t)j * k, c->inst[0].D.T + (size_t)j * ld,
                                     sizeof(double) * k, hipMemcpyDeviceToHost));
   }
+  return SFK_OK;
+}
+
+extern "C" sfk_status sfk_basis_vector(sfk_ctx *c, int32_t i, int32_t kind, int32_t j, double *out) {
+  Inst *I;
+  sfk_status s = instance_of(c, i, &I);
+  if (s != SFK_OK) return s;
+  if (!out) return fail(c, SFK_EINVAL, "out must not be NULL");
+  if (kind < 0 || kind > 2) return fail(c, SFK_EINVAL, "unknown basis kind %d", kind);
+  const Dev &D = I->D;
+  const int k = I->k_done;
+  if (I->halted) return fail(c, SFK_ESTATE, "basis vectors are available while the run is live");
+  const int lo = kind == 0 ? std::max(1, k + 1 - (D.ell + 1))
+               : (kind == 1 && D.tau == SFK_TAU_REWEIGHT_L1) ? std::max(1, k + 1 - D.ell) : 1;
+  // the scale of p_{k+1} (and z_{k+1}) is formed by the next iteration's first stage
+  const int hi = kind == 0 ? k + 1 : k;
+  if (j < lo || j > hi)
+    return fail(c, SFK_ESTATE, "basis vector %d not kept (available %d..%d)", j, lo, hi);
+  const double *src, *scale;
+  int len;
+  const int *pinv = nullptr;
+  if (kind == 0) {
+    src = D.W + (size_t)(j % (D.ell + 2)) * D.m * D.vs;
+    scale = D.sigw + j;
+    len = D.m;
+  } else {
+    src = (kind == 2 || D.tau != SFK_TAU_REWEIGHT_L1) ? D.Z + (size_t)(j - 1) * D.n * D.vs
+                                                      : D.P + (size_t)(j % (D.ell + 1)) * D.n * D.vs;
+    scale = D.sigp + j;
+    len = D.n;
+    pinv = D.pinv;
+  }
+  launch_export_vec(src, D.vs, len, scale, pinv, out, c->stream);
+  HIPCHK(c, hipGetLastError());
+  HIPCHK(c, hipStreamSynchronize(c->stream));
   return SFK_OK;
 }
 

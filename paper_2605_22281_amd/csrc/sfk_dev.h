@@ -22,14 +22,18 @@ constexpr int kSrhtL = 2048;               // SRHT block length staged in LDS
 constexpr double kBreakdownTol = 1e-14;    // relative breakdown threshold
 
 // Partial-sum buffers, one per producing stage.
-enum Stage { kStageA = 0, kStageB = 1, kStageC = 2, kStageD = 3, kStageMisc = 4, kNumPart = 5 };
+// kStageMisc: the true residual asked for after the run; kStageTrue: the one
+// recorded every iteration (side stream)
+enum Stage { kStageA = 0, kStageB = 1, kStageC = 2, kStageD = 3, kStageMisc = 4, kStageTrue = 5,
+             kNumPart = 6 };
 
 // Scalar state shared by the stages (device memory).  Slots: w_j lives in
 // W ring slot j % (ell + 2), p_j in P ring slot j % (ell + 1).
 struct Scal {
   double beta;        // ||b||
   double rhsnorm;     // ||S b|| (sFLSQR) or ||S B b|| (sFLSMR)
-  double tol;         // relative tolerance of the stop test (0: none)
+  double tol;         // relative tolerance of the sketched stop test (0: none)
+  double ttol;        // threshold of the true-residual stop test (Dev::resid = 2)
   double wpre;        // ||A z_k|| before orthogonalisation
   double zpre;        // ||B w_{k+1}|| before orthogonalisation
   double Gw[(kMaxEll + 2) * (kMaxEll + 2)];  // <w_i, w_j> by slot
@@ -48,6 +52,8 @@ struct Dev {
   // sizes and parameters
   int m, n, s, ell, maxit, method, tau, sketch, zeta;
   int d_sk;           // length of sketched vectors (m or n)
+  int resid;          // 0: no per-iteration true residual; 1: recorded; 2: recorded
+                      // and the stop test
   int N;              // SRHT padded length
   int log2L;          // SRHT block length log2
   int nblk;           // SRHT blocks
@@ -109,7 +115,10 @@ struct Dev {
   double *tauv;       // maxit
   double *R;          // maxit * maxit, column-major
   double *c;          // s: Q^T rhs
-  double *y;          // maxit: y_k (kept current for the reweighting)
+  double *y;          // maxit: y_k (kept current for the reweighting and resid)
+  // per-iteration true residual (resid >= 1)
+  double *rtrue;      // maxit: ||b - A x_k||
+  double *xres;       // n: x_k in the library's order of the unknowns
 };
 
 // Launch geometry of a batch of instances: the device array of instance

@@ -892,8 +892,9 @@ __global__ void __launch_bounds__(64) k_ls(const Dev *__restrict__ devs, int k) 
     if (lane == 0) { atomicOr(&sc->breakdown, 4); sc->halt = 1; }
     return;
   }
-  // the reweighting needs y_k = R_k^{-1} c[0:k] before the next basis vector
-  if (D.tau == 1) backsub_wave<ER>(D, k, D.y, s_r);
+  // the reweighting needs y_k = R_k^{-1} c[0:k] before the next basis vector,
+  // the per-iteration true residual for x_k
+  if (D.tau == 1 || D.resid) backsub_wave<ER>(D, k, D.y, s_r);
   if (lane == 0) {
     D.rho[k - 1] = rho;
     sc->k_done = k;
@@ -934,6 +935,67 @@ __global__ void __launch_bounds__(kWG) k_true_residual(Dev D, const double *x) {
     if (lane == 0) { const double rr = D.b[r] - s; acc[0] += rr * rr; }
   }
   produce<kWG>(D, kStageMisc, blockIdx.x, 1, acc, lds_w, blk);
+}
+
+// Per-iteration true residual (resid >= 1, side stream after LS(k)): runs only
+// when LS(k) completed (k_done = k); a stop at k makes every later k skip.
+__device__ __forceinline__ bool true_iter_off(const Dev &D, int k) {
+  return ld_flag(&D.sc->k_done) != k;
+}
+
+// x_k = Z_k y_k in the library's order of the unknowns
+__global__ void __launch_bounds__(kWG) k_xres(Dev D, int k) {
+  if (true_iter_off(D, k)) return;
+  extern __shared__ double cf[];
+  for (int j = threadIdx.x; j < k; j += kWG) cf[j] = D.sigp[j + 1] * D.y[j];
+  __syncthreads();
+  const gptr<const double> Zg = gmem(D.Z);
+  for (int i = blockIdx.x * kWG + threadIdx.x; i < D.n; i += gridDim.x * kWG) {
+    double xi = 0.0;
+    for (int j = 0; j < k; ++j) xi += cf[j] * Zg[(size_t)j * D.n + i];
+    D.xres[i] = xi;
+  }
+}
+
+// ||b - A x_k||^2 partials over the nnz-balanced row ranges (operator as the
+// products use it, x_k in the same order)
+__global__ void __launch_bounds__(kWG) k_true_res_iter(Dev D, int k) {
+  if (true_iter_off(D, k)) return;
+  __shared__ double lds_w[kMaxQ * (kWG / 64)];
+  __shared__ double blk[kMaxQ];
+  double acc[kMaxQ];
+#pragma unroll
+  for (int q = 0; q < kMaxQ; ++q) acc[q] = 0.0;
+  const int r0 = D.Apart[blockIdx.x], r1 = D.Apart[blockIdx.x + 1];
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const gptr<const double> x = gmem(D.xres);
+  for (int r = r0 + wv; r < r1; r += kWG / 64) {
+    double s = 0.0;
+    for (int e = D.Arp[r] + lane; e < D.Arp[r + 1]; e += 64) s += D.Ava[e] * x[D.Aci[e]];
+    s = wave_sum(s);
+    if (lane == 0) { const double rr = D.b[r] - s; acc[0] += rr * rr; }
+  }
+  produce<kWG>(D, kStageTrue, blockIdx.x, 1, acc, lds_w, blk);
+}
+
+// rtrue[k-1] = ||b - A x_k||; with resid = 2 the discrepancy principle stops
+// the run at the first k with ||b - A x_k|| <= ttol
+__global__ void __launch_bounds__(kWG) k_true_stop(Dev D, int k) {
+  if (true_iter_off(D, k)) return;
+  __shared__ double lds_w[kMaxQ * (kWG / 64)];
+  __shared__ double tot[kMaxQ];
+  // the producers of kStageTrue are the nws SpMV row ranges
+  const gptr<const double> p = gmem(part_of(D, kStageTrue));
+  double acc[kMaxQ];
+#pragma unroll
+  for (int q = 0; q < kMaxQ; ++q) acc[q] = 0.0;
+  for (int i = threadIdx.x; i < D.nws; i += kWG) acc[0] += p[i];
+  block_sum<kWG>(acc, 1, lds_w, tot);
+  if (threadIdx.x != 0) return;
+  const double r = sqrt(tot[0]);
+  D.rtrue[k - 1] = r;
+  Scal *sc = D.sc;
+  if (D.resid == 2 && r <= sc->ttol) { sc->stopped = 1; sc->halt = 1; }
 }
 
 __global__ void __launch_bounds__(kWG) k_finish_misc(Dev D, double *out) {
@@ -1195,7 +1257,10 @@ __global__ void __launch_bounds__(1024) k_init_b(Dev D, double eta, double noise
   sc->klimit = 0x7fffffff;
   if (!(beta > 0.0) || !isfinite(beta)) { sc->err |= 16; sc->halt = 1; return; }
   D.sigw[1] = 1.0 / beta;
-  sc->tol = use_disc ? eta * noise / beta : tol_user;
+  // with the true-residual stop (resid = 2) the sketched test is off and the
+  // discrepancy principle reads ||b - A x_k|| <= eta delta_e (or tol ||b||)
+  sc->ttol = noise > 0.0 ? eta * noise : tol_user * beta;
+  sc->tol = D.resid == 2 ? 0.0 : (use_disc ? eta * noise / beta : tol_user);
 }
 
 // rhs = S b (sFLSQR) or beta * S B w_1 (sFLSMR, in SK column 0); c = rhs
@@ -1424,6 +1489,52 @@ void launch_sketch_build(const Dev &D, uint64_t key0, uint64_t key1, uint64_t ke
 void launch_solution(const Dev &D, int kk, const double *yv, double *x, hipStream_t st) {
   hipLaunchKernelGGL(k_solution, dim3((D.n + kWG - 1) / kWG), dim3(kWG),
                      sizeof(double) * (size_t)max(1, kk), st, D, kk, yv, x);
+}
+// byte fill with zero (16-byte stores; the tail byte by byte)
+__global__ void k_zero_bytes(unsigned char *p, size_t n) {
+  const size_t n16 = n / 16;
+  const size_t stride = (size_t)gridDim.x * blockDim.x;
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n16; i += stride)
+    reinterpret_cast<int4 *>(p)[i] = make_int4(0, 0, 0, 0);
+  for (size_t i = n16 * 16 + blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += stride)
+    p[i] = 0;
+}
+void launch_zero_bytes(void *p, size_t n, hipStream_t st) {
+  if (n == 0) return;
+  const size_t blocks = std::min<size_t>((n / 16 + 255) / 256 + 1, 4096);
+  hipLaunchKernelGGL(k_zero_bytes, dim3((unsigned)blocks), dim3(256), 0, st,
+                     static_cast<unsigned char *>(p), n);
+}
+
+// block map of a single instance: entry w = (0, w)
+__global__ void k_iota_map(int2 *map, int count) {
+  const int w = blockIdx.x * blockDim.x + threadIdx.x;
+  if (w < count) map[w] = make_int2(0, w);
+}
+void launch_iota_map(int2 *map, int count, hipStream_t st) {
+  if (count > 0)
+    hipLaunchKernelGGL(k_iota_map, dim3((count + 255) / 256), dim3(256), 0, st, map, count);
+}
+
+// a stored basis vector times its scale (1 / the norm of the unnormalised
+// vector), written in the caller's order when pinv is given
+__global__ void k_export_vec(const double *src, int vs, int len, const double *scale,
+                             const int *pinv, double *out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= len) return;
+  out[pinv ? pinv[i] : i] = src[(size_t)i * vs] * scale[0];
+}
+void launch_export_vec(const double *src, int vs, int len, const double *scale, const int *pinv,
+                       double *out, hipStream_t st) {
+  hipLaunchKernelGGL(k_export_vec, dim3((len + 255) / 256), dim3(256), 0, st, src, vs, len, scale,
+                     pinv, out);
+}
+
+void launch_true_iter(const Dev &D, int k, hipStream_t st) {
+  const int nb = std::max(1, std::min((D.n + kWG - 1) / kWG, 2048));
+  hipLaunchKernelGGL(k_xres, dim3(nb), dim3(kWG), sizeof(double) * (size_t)max(1, k), st, D, k);
+  hipLaunchKernelGGL(k_true_res_iter, dim3(D.nws), dim3(kWG), 0, st, D, k);
+  hipLaunchKernelGGL(k_true_stop, dim3(1), dim3(kWG), 0, st, D, k);
 }
 void launch_true_residual(const Dev &D, const double *x, double *out, hipStream_t st) {
   hipLaunchKernelGGL(k_true_residual, dim3(D.nws), dim3(kWG), 0, st, D, x);

@@ -24,13 +24,16 @@ OK, EINVAL, ENOMEM, EDEVICE, BREAKDOWN, ESTATE = range(6)
 SFLSQR, SFLSMR = 0, 1
 SK_SPARSE_SIGN, SK_SRHT, SK_IDENTITY = 0, 1, 2
 TAU_IDENTITY, TAU_REWEIGHT_L1 = 0, 1
-DRIVER_AUTO, DRIVER_MULTI, DRIVER_PERSISTENT = 0, 1, 2
+DRIVER_AUTO, DRIVER_MULTI, DRIVER_GRAPH = 0, 1, 2
+RES_SKETCHED, RES_TRUE_RECURRENCE, RES_TRUE_EXPLICIT = 0, 1, 2
 
 _METHODS = {"sflsqr": SFLSQR, "sflsmr": SFLSMR}
 _SKETCHES = {"sparse_sign": SK_SPARSE_SIGN, "countsketch": SK_SPARSE_SIGN, "srht": SK_SRHT,
              "identity": SK_IDENTITY}
 _TAUS = {"identity": TAU_IDENTITY, "reweight_l1": TAU_REWEIGHT_L1}
-_DRIVERS = {"auto": DRIVER_AUTO, "multi": DRIVER_MULTI, "persistent": DRIVER_PERSISTENT}
+_DRIVERS = {"auto": DRIVER_AUTO, "multi": DRIVER_MULTI, "graph": DRIVER_GRAPH}
+_RES = {"sketched": RES_SKETCHED, "true_recurrence": RES_TRUE_RECURRENCE,
+        "true_explicit": RES_TRUE_EXPLICIT}
 
 
 class SfkError(RuntimeError):
@@ -50,8 +53,10 @@ class Params(ctypes.Structure):
                 ("seed", ctypes.c_uint64), ("instance", ctypes.c_int32), ("tau", ctypes.c_int32),
                 ("eps", ctypes.c_double), ("eta", ctypes.c_double), ("noise_norm", ctypes.c_double),
                 ("tol", ctypes.c_double), ("driver", ctypes.c_int32), ("vw", ctypes.c_int32),
-                ("wg_per_cu", ctypes.c_int32), ("reserved0", ctypes.c_int32),
-                ("perm", ctypes.c_void_p), ("reserved", ctypes.c_int32 * 2)]
+                ("vw_b", ctypes.c_int32), ("vw_split", ctypes.c_int32),
+                ("wg_per_cu", ctypes.c_int32), ("resid", ctypes.c_int32),
+                ("copies", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("perm", ctypes.c_void_p)]
 
 
 _lib = None
@@ -77,7 +82,9 @@ def lib() -> ctypes.CDLL:
         "sfk_iterate": (I32, [P, I32, PI32, PI32]),
         "sfk_solution": (I32, [P, P]),
         "sfk_solution_at": (I32, [P, I32, P]),
-        "sfk_residual_norms": (I32, [P, PD, I32, PI32, PD]),
+        "sfk_residual_norms": (I32, [P, I32, PD, I32, PI32, PD]),
+        "sfk_basis_vector": (I32, [P, I32, I32, I32, P]),
+        "sfk_memory": (I32, [P, ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(ctypes.c_size_t)]),
         "sfk_true_residual": (I32, [P, PD]),
         "sfk_destroy": (I32, [P]),
         "sfk_last_error": (ctypes.c_char_p, [P]),
@@ -91,7 +98,7 @@ def lib() -> ctypes.CDLL:
         "sfk_instance_status": (I32, [P, I32, PI32, PI32, PI32]),
         "sfk_instance_solution": (I32, [P, I32, P]),
         "sfk_instance_solution_at": (I32, [P, I32, I32, P]),
-        "sfk_instance_residual_norms": (I32, [P, I32, PD, I32, PI32, PD]),
+        "sfk_instance_residual_norms": (I32, [P, I32, I32, PD, I32, PI32, PD]),
         "sfk_instance_true_residual": (I32, [P, I32, PD]),
         "sfk_init_multi": (I32, [ctypes.POINTER(P), PCSR, PCSR, P, I32, PPAR, P]),
         "sfk_stage_times": (I32, [P, PD, PI32]),
@@ -112,7 +119,7 @@ def exported_symbols() -> list[str]:
             "sfk_coefficients", "sfk_version", "sfk_set_timing", "sfk_stage_times",
             "sfk_init_batch", "sfk_batch_size", "sfk_instance_status", "sfk_instance_solution",
             "sfk_instance_residual_norms", "sfk_instance_true_residual", "sfk_init_multi",
-            "sfk_instance_solution_at", "sfk_spmv_variant"]
+            "sfk_instance_solution_at", "sfk_spmv_variant", "sfk_memory", "sfk_basis_vector"]
 
 
 def _check(status: int, ctx=None):
@@ -123,7 +130,8 @@ def _check(status: int, ctx=None):
 
 def params(method="sflsqr", *, ell=2, maxit=50, sketch="sparse_sign", s=101, zeta=8, seed=0,
            instance=0, tau="identity", eps=1e-3, eta=1.01, noise_norm=0.0, tol=0.0,
-           driver="auto", vw=-2, wg_per_cu=0, perm=None) -> Params:
+           driver="auto", vw=-2, vw_b=None, wg_per_cu=0, resid=0, copies=0,
+           perm=None) -> Params:
     """perm: optional order of the unknowns, a torch.int32 device tensor of n
     distinct values in [0, n) (unknown j stored at position perm[j] inside the
     library; results come back in the caller's order).
@@ -131,7 +139,11 @@ def params(method="sflsqr", *, ell=2, maxit=50, sketch="sparse_sign", s=101, zet
     CSR-stream, 1 SELL-64, 8/16/32/64 lanes per row, -1 lanes from the mean row
     length; for right-hand sides sharing A and B (init_multi) -2 automatic, 0
     column-sliced L2 gathers, 2 LDS-staged units, any other value the row
-    kernel."""
+    kernel.
+    vw_b: SpMV kernel of B (coded as vw) when it differs from A's (sets
+    vw_split); resid: 0, 1 (record ||b - A x_k|| every iteration) or 2 (record
+    it and stop on it); copies: 1 forbids device copies of the operators
+    beyond the workspace."""
     p = Params()
     lib().sfk_params_default(ctypes.byref(p))
     p.method = _METHODS[method] if isinstance(method, str) else int(method)
@@ -144,6 +156,9 @@ def params(method="sflsqr", *, ell=2, maxit=50, sketch="sparse_sign", s=101, zet
     p.eps, p.eta, p.noise_norm, p.tol = eps, eta, noise_norm, tol
     p.driver = _DRIVERS[driver] if isinstance(driver, str) else int(driver)
     p.vw, p.wg_per_cu = vw, wg_per_cu
+    if vw_b is not None:
+        p.vw_b, p.vw_split = int(vw_b), 1
+    p.resid, p.copies = int(resid), int(copies)
     if perm is not None:
         import torch
         if perm.dtype != torch.int32 or not perm.is_cuda or not perm.is_contiguous():
@@ -272,15 +287,29 @@ def solution_at(ctx: Context, j: int, out=None):
     return x
 
 
-def residual_norms(ctx: Context) -> tuple[np.ndarray, float]:
-    """Per-iteration minimised sketched objective rho_1..rho_k and the rhs norm."""
+def _res_kind(kind) -> int:
+    return _RES[kind] if isinstance(kind, str) else int(kind)
+
+
+def residual_norms(ctx: Context, kind="sketched") -> tuple[np.ndarray, float]:
+    """Residual history j = 1..k of the given kind ("sketched": rho_j,
+    "true_recurrence": ||beta e_1 - H y_j||, "true_explicit": ||b - A x_j||) and
+    the scale of its stop test (||S b|| or ||S B b|| for "sketched", ||b||
+    otherwise)."""
     cap = max(1, ctx.p.maxit)
     buf = (ctypes.c_double * cap)()
     cnt = ctypes.c_int32()
     rn = ctypes.c_double()
-    _check(lib().sfk_residual_norms(ctx.handle, buf, cap, ctypes.byref(cnt), ctypes.byref(rn)),
-           ctx.handle)
+    _check(lib().sfk_residual_norms(ctx.handle, _res_kind(kind), buf, cap, ctypes.byref(cnt),
+                                    ctypes.byref(rn)), ctx.handle)
     return np.array(buf[: cnt.value]), rn.value
+
+
+def memory(ctx) -> tuple[int, int]:
+    """(workspace bytes, bytes the library allocated besides it) of a context."""
+    ws, lb = ctypes.c_size_t(), ctypes.c_size_t()
+    _check(lib().sfk_memory(ctx.handle, ctypes.byref(ws), ctypes.byref(lb)), ctx.handle)
+    return ws.value, lb.value
 
 
 def true_residual(ctx: Context) -> float:
@@ -423,13 +452,33 @@ def instance_solution_at(ctx, i: int, j: int, n: int, out=None):
     return x
 
 
-def instance_residual_norms(ctx, i: int, cap: int) -> tuple[np.ndarray, float]:
+def instance_residual_norms(ctx, i: int, cap: int, kind="sketched") -> tuple[np.ndarray, float]:
     buf = (ctypes.c_double * max(1, cap))()
     cnt = ctypes.c_int32()
     rn = ctypes.c_double()
-    _check(lib().sfk_instance_residual_norms(ctx.handle, i, buf, max(1, cap), ctypes.byref(cnt),
-                                             ctypes.byref(rn)), ctx.handle)
+    _check(lib().sfk_instance_residual_norms(ctx.handle, i, _res_kind(kind), buf, max(1, cap),
+                                             ctypes.byref(cnt), ctypes.byref(rn)), ctx.handle)
     return np.array(buf[: min(cnt.value, cap)]), rn.value
+
+
+BASIS = {"w": 0, "p": 1, "z": 2}
+
+
+def basis_vector(ctx, kind: str, j: int, i: int = 0):
+    """Basis vector w_j, p_j or z_j of instance i (see sfk_basis_vector), as a
+    CUDA float64 tensor (n-vectors in the caller's order)."""
+    import torch
+    inst_ctx = ctx
+    length = None
+    if isinstance(ctx, Context):
+        length = ctx.m if kind == "w" else ctx.n
+    else:
+        A = ctx.As[0] if len(ctx.As) == 1 else ctx.As[i]
+        length = A.rows if kind == "w" else A.cols
+    x = torch.empty(length, dtype=torch.float64, device="cuda")
+    _check(lib().sfk_basis_vector(inst_ctx.handle, int(i), BASIS[kind], int(j), x.data_ptr()),
+           inst_ctx.handle)
+    return x
 
 
 def spmv_variant(ctx) -> tuple[int, int]:
@@ -467,8 +516,8 @@ class Solver:
     def solution_at(self, j: int):
         return solution_at(self.ctx, j)
 
-    def residual_norms(self):
-        return residual_norms(self.ctx)
+    def residual_norms(self, kind="sketched"):
+        return residual_norms(self.ctx, kind)
 
     def true_residual(self):
         return true_residual(self.ctx)

@@ -36,8 +36,9 @@ def test_every_declared_symbol_is_exported():
 
 
 def test_params_layout_matches_header(tmp_path):
-    # sfk_params: 6 int32, uint64 seed, 2 int32, 4 double, 4 int32, perm pointer, 2 int32
-    assert ctypes.sizeof(sfk.Params) == 104
+    # sfk_params: 6 int32, uint64 seed, 2 int32, 4 double, 8 int32, perm pointer
+    assert ctypes.sizeof(sfk.Params) == 112
+    assert sfk.Params.perm.offset == 104
     assert sfk.Params.seed.offset == 24 and sfk.Params.eps.offset == 40
     assert ctypes.sizeof(sfk.CSR) == 48
     # the C compiler's layout of the header agrees field by field
@@ -84,12 +85,24 @@ def _A(m=200, n=80, nnz=500):
     (dict(tol=-1.0), "tol"),
     (dict(noise_norm=float("nan")), "noise"),
     (dict(vw=12), "vw"),
+    (dict(vw_b=5), "vw"),
+    (dict(resid=3), "resid"),
+    (dict(copies=1, vw=1), "copies"),
+    (dict(copies=2), "copies"),
+    (dict(driver=3), "driver"),
+    (dict(method="sflsmr", s=60, maxit=20, noise_norm=1.0), "resid = 2"),
 ])
 def test_validation_rejects(kw, frag):
     p = sfk.params(**kw)
     st, msg = sfk.validate(_A(), None, p)
     assert st == sfk.EINVAL
     assert frag in msg
+
+
+def test_validation_accepts_new_options():
+    for kw in (dict(resid=1), dict(resid=2), dict(copies=1), dict(vw=0, vw_b=64),
+               dict(driver="graph"), dict(method="sflsmr", s=60, maxit=20, noise_norm=1.0, resid=2)):
+        assert sfk.validate(_A(), None, sfk.params(**kw))[0] == sfk.OK, kw
 
 
 def test_validation_dimensions():

@@ -36,7 +36,7 @@ def _horizon_compare(X, rho, orc, spread, kmax, label):
 @pytest.fixture(scope="module")
 def ct256():
     P = inputs.workload("ct256_unmatched")
-    orc, spread = rounding_spread(P, "sflsmr", "srht", 400, 40, seed=3002)
+    orc, spread = rounding_spread(P, "sflsmr", "srht", 400, 50, seed=3002)
     return P, orc, spread
 
 
@@ -46,7 +46,7 @@ def test_ct256_unmatched_sflsmr_srht(ct256, order):
     in the image's row-major order and in the 4 x 4 tile order bench.py passes."""
     P, orc, spread = ct256
     say(f"case: ct256 sFLSMR SRHT full size m={P.m} n={P.n} order={order}")
-    kcmp = 40
+    kcmp = 50
     perm = inputs.tile_order(P.N, 4) if order == "tiles4" else None
     ctx, X, rho, rn, st = gpu_run(P, "sflsmr", "srht", 400, 200, seed=3002, stepwise=False,
                                   perm=perm)
@@ -63,10 +63,12 @@ def test_ct256_unmatched_sflsmr_srht(ct256, order):
 
 def test_ct512_sparse_reweighted_sflsqr():
     """512^2 CT, 360 x 725, B = A^T built on the device, sparse phantom, l1
-    reweighting eps = 1e-3, sparse-sign s = 600, zeta = 8 (first 20 of 300 steps)."""
+    reweighting eps = 1e-3, sparse-sign s = 600, zeta = 8 (first 50 of 300
+    steps; the reweighted basis stays well conditioned, so 1e-8 holds at every
+    compared k)."""
     P = inputs.workload("ct512_sparse")
     say(f"case: ct512 reweighted sFLSQR m={P.m} n={P.n} nnz={P.A.nnz}")
-    k = 20
+    k = 50
     _, X, rho, rn, st = gpu_run(P, "sflsqr", "sparse_sign", 600, k, tau="reweight_l1", eps=1e-3,
                                 seed=3003, stepwise=False)
     S = sketches.SparseSign(P.m, 600, 8, 3003)

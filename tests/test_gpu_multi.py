@@ -193,6 +193,21 @@ def test_shared_operator_ct256_32_rhs():
         assert rel(x, orc.x) <= max(1e-8, 1e3 * spread[K - 1]), (r, rel(x, orc.x))
         say(f"ct256 rhs {r}: rho parity 1e-8 through k = {horizon}")
         assert horizon >= 10
+    # every right-hand side against the oracle at 1e-8 through k = 10 (inside
+    # the reproducible horizon of each of them)
+    worst_o = 0.0
+    for r in range(R):
+        Pr = inputs.Problem(A=P.A, B=P.B, b=b[r], x_true=xt[r], noise_norm=float(dn[r]), N=P.N,
+                            n_angles=P.n_angles, n_det=P.n_det)
+        orc = fgk.sketched_flexible(P.A, b[r], sketches.SRHT(P.n, 400, 3100 + r), method="sflsmr",
+                                    B=P.B, maxit=10, ell=2)
+        rho, _ = sfk.instance_residual_norms(ctx, r, K)
+        x10 = sfk.instance_solution_at(ctx, r, 10, P.n).cpu().numpy()
+        er = np.max(np.abs(rho[:10] - orc.rho) / orc.rho)
+        ex = rel(x10, orc.x)
+        worst_o = max(worst_o, er, ex)
+        assert er <= 1e-8 and ex <= 1e-8, (r, er, ex)
+    say(f"ct256 32 rhs vs oracle, k <= 10: worst rel {worst_o:.2e}")
     ctx10 = sfk.init_multi(A, B, bb, [sfk.params("sflsmr", maxit=10, sketch="srht", s=400,
                                                  seed=3100 + r) for r in range(R)])
     sfk.iterate(ctx10, 10)

@@ -1,0 +1,185 @@
+"""Residual histories, the discrepancy principle on the true residual, the
+graph-captured driver and the copy-free mode, through the C ABI.
+
+The explicit residual ||b - A x_k|| is the quantity of the discrepancy
+principle (eq. (discrP)); the recurrence residual ||beta e_1 - H y_k|| is its
+expression in the basis W_{k+1} (eq. (FGK)), exact when W_{k+1} is orthonormal.
+"""
+import numpy as np
+import pytest
+
+from oracle import fgk, sketches
+from paper_2605_22281_amd import inputs
+
+from gpu_cases import compare, gpu_run, oracle_run, rel, say
+
+pytestmark = pytest.mark.gpu
+
+
+def _recurrence_residuals(orc):
+    """||beta e_1 - H_{j+1,j} y_j|| from the oracle's own coefficients."""
+    out = []
+    for j, y in enumerate(orc.Ys, start=1):
+        e1 = np.zeros(j + 1)
+        e1[0] = orc.beta
+        out.append(np.linalg.norm(e1 - orc.H[: j + 1, :j] @ y))
+    return np.array(out)
+
+
+@pytest.mark.parametrize("method,tau", [("sflsqr", "identity"), ("sflsmr", "reweight_l1")])
+def test_residual_kinds_against_oracle(method, tau):
+    from paper_2605_22281_amd import sfk
+    P = inputs.small_ct(24, 18, unmatched=True, noise=0.02)
+    say(f"case: residual kinds {method} {tau}")
+    k = 10
+    ctx, X, rho, _, _ = gpu_run(P, method, "sparse_sign", 60, k, tau=tau, eps=1e-2, stepwise=False)
+    orc = oracle_run(P, method, "sparse_sign", 60, k, tau=tau, eps=1e-2)
+    compare(X, rho, orc, k, label="kinds")
+    rs, scale_s = sfk.residual_norms(ctx, "sketched")
+    assert np.array_equal(rs, rho)
+    assert abs(scale_s - orc.rhs_norm) <= 1e-13 * orc.rhs_norm
+    re, scale_e = sfk.residual_norms(ctx, "true_explicit")
+    assert abs(scale_e - orc.beta) <= 1e-14 * orc.beta
+    assert np.max(np.abs(re - orc.res_true) / orc.res_true) <= 1e-8
+    rr, _ = sfk.residual_norms(ctx, "true_recurrence")
+    ro = _recurrence_residuals(orc)
+    assert np.max(np.abs(rr - ro) / ro) <= 1e-8
+
+
+def test_recurrence_equals_explicit_with_full_window():
+    # ell >= k: W_{k+1} orthonormal, so ||beta e_1 - H y|| = ||b - A x||
+    from paper_2605_22281_amd import sfk
+    P = inputs.small_ct(20, 16, noise=0.01)
+    say("case: full window recurrence residual")
+    ctx, *_ = gpu_run(P, "sflsqr", "sparse_sign", 60, 8, ell=8, stepwise=False)
+    re, _ = sfk.residual_norms(ctx, "true_explicit")
+    rr, _ = sfk.residual_norms(ctx, "true_recurrence")
+    assert np.max(np.abs(rr - re) / re) <= 1e-10
+
+
+@pytest.mark.parametrize("resid", [1, 2])
+def test_recorded_true_residual_ct64(resid):
+    """64^2 CT, sparse-sign s = 200: the recorded ||b - A x_k|| equals the
+    oracle's; resid = 2 stops at the first k with ||b - A x_k|| <= 1.01 delta_e
+    (the discrepancy principle as eq. (discrP) states it)."""
+    from paper_2605_22281_amd import sfk
+    P = inputs.workload("ct64")
+    say(f"case: ct64 recorded true residual resid={resid}")
+    thr = 1.01 * P.noise_norm
+    ctx, X, rho, _, st = gpu_run(P, "sflsqr", "sparse_sign", 200, 50, seed=3001, resid=resid,
+                                 noise=P.noise_norm if resid == 2 else 0.0, stepwise=False)
+    S = sketches.SparseSign(P.m, 200, 8, 3001)
+    orc = fgk.sketched_flexible(P.A, P.b, S, maxit=50, ell=2,
+                                true_tol=thr if resid == 2 else 0.0)
+    rt, _ = sfk.residual_norms(ctx, "true_explicit")
+    k = X.shape[1]
+    if resid == 2:
+        assert orc.stopped and k == orc.k, (k, orc.k)
+        assert rt[-1] <= thr and np.all(rt[:-1] > thr)
+        # the decision is not borderline
+        assert abs(orc.res_true[-1] / thr - 1) > 1e-6
+        kc = k
+    else:
+        assert k == 50
+        kc = 20                 # within the reproducible horizon of this problem
+    compare(X, rho, orc, kc, label=f"ct64 resid={resid}")
+    assert np.max(np.abs(rt[:kc] - orc.res_true[:kc]) / orc.res_true[:kc]) <= 1e-8
+    # the recorded value is the residual of the returned iterate
+    for j in (1, kc):
+        xj = sfk.solution_at(ctx, j).cpu().numpy()
+        assert abs(rt[j - 1] - np.linalg.norm(P.b - P.A @ xj)) <= 1e-10 * rt[j - 1]
+
+
+def test_sflsmr_true_residual_stop():
+    from paper_2605_22281_amd import sfk
+    P = inputs.small_ct(24, 18, unmatched=True, noise=0.05)
+    say("case: sFLSMR true-residual discrepancy stop")
+    thr = 1.01 * P.noise_norm
+    ctx, X, rho, _, st = gpu_run(P, "sflsmr", "srht", 60, 40, noise=P.noise_norm, resid=2,
+                                 stepwise=False)
+    S = sketches.SRHT(P.n, 60, 3001)
+    orc = fgk.sketched_flexible(P.A, P.b, S, method="sflsmr", B=P.B, maxit=40, ell=2,
+                                true_tol=thr)
+    assert orc.stopped and X.shape[1] == orc.k
+    compare(X, rho, orc, orc.k, label="sflsmr true stop")
+
+
+def test_recording_does_not_change_iterates():
+    from paper_2605_22281_amd import sfk
+    P = inputs.small_ct(24, 18, phantom="sparse", noise=0.01)
+    say("case: resid=1 leaves iterates bit-identical")
+    c0, X0, r0, _, _ = gpu_run(P, "sflsqr", "sparse_sign", 60, 12, tau="reweight_l1", stepwise=False)
+    c1, X1, r1, _, _ = gpu_run(P, "sflsqr", "sparse_sign", 60, 12, tau="reweight_l1", stepwise=False,
+                               resid=1)
+    assert np.array_equal(X0, X1) and np.array_equal(r0, r1)
+
+
+CASES = [
+    ("sflsqr", "sparse_sign", "identity", "ct64"),
+    ("sflsqr", "sparse_sign", "reweight_l1", "ct24"),
+    ("sflsmr", "srht", "identity", "ct24u"),
+    ("sflsmr", "srht", "reweight_l1", "ct24u"),
+]
+
+
+@pytest.mark.parametrize("method,kind,tau,prob", CASES)
+def test_graph_driver_bit_identical(method, kind, tau, prob):
+    """The graph-captured batches launch the same kernels with the same
+    arguments in the same dependency order: results are bit-identical."""
+    from paper_2605_22281_amd import sfk
+    P = {"ct64": lambda: inputs.workload("ct64"),
+         "ct24": lambda: inputs.small_ct(24, 18, phantom="sparse", noise=0.01),
+         "ct24u": lambda: inputs.small_ct(24, 18, unmatched=True, noise=0.02)}[prob]()
+    s = 200 if prob == "ct64" else 60
+    say(f"case: graph driver {method} {kind} {tau} {prob}")
+    k = 30 if prob == "ct64" else 20
+    ca, Xa, ra, _, _ = gpu_run(P, method, kind, s, k, tau=tau, eps=1e-2, stepwise=False,
+                               driver="multi")
+    cb, Xb, rb, _, _ = gpu_run(P, method, kind, s, k, tau=tau, eps=1e-2, stepwise=False,
+                               driver="graph")
+    assert np.array_equal(Xa, Xb) and np.array_equal(ra, rb)
+    # iterate calls of odd lengths (partial batches, resumed runs)
+    cc = gpu_run(P, method, kind, s, k, tau=tau, eps=1e-2, stepwise=True, driver="graph")
+    assert np.array_equal(cc[1], Xa)
+
+
+def test_graph_driver_discrepancy_stop_and_batch():
+    from paper_2605_22281_amd import sfk
+    import torch
+    P = inputs.workload("ct64")
+    say("case: graph driver ct64 discrepancy")
+    _, Xa, ra, _, _ = gpu_run(P, "sflsqr", "sparse_sign", 200, 50, noise=P.noise_norm, seed=3001,
+                              stepwise=False, driver="multi")
+    _, Xb, rb, _, _ = gpu_run(P, "sflsqr", "sparse_sign", 200, 50, noise=P.noise_norm, seed=3001,
+                              stepwise=False, driver="graph")
+    assert Xa.shape == Xb.shape and np.array_equal(Xa, Xb) and np.array_equal(ra, rb)
+    probs = [inputs.small_ct(n, 12, noise=0.02, seed_offset=40 + n) for n in (12, 16, 20)]
+    As = [sfk.to_device_csr(Q.A) for Q in probs]
+    bs = [torch.from_numpy(Q.b).cuda() for Q in probs]
+    out = {}
+    for drv in ("multi", "graph"):
+        ps = [sfk.params("sflsqr", maxit=20, s=60, seed=11 + i, noise_norm=Q.noise_norm, driver=drv)
+              for i, Q in enumerate(probs)]
+        ctx = sfk.init_batch(As, None, bs, ps)
+        sfk.iterate(ctx, 20)
+        out[drv] = [sfk.instance_solution(ctx, i, Q.n).cpu().numpy() for i, Q in enumerate(probs)]
+        out[drv + "k"] = [sfk.instance_status(ctx, i)[0] for i in range(len(probs))]
+    assert out["multik"] == out["graphk"]
+    for a, b in zip(out["multi"], out["graph"]):
+        assert np.array_equal(a, b)
+
+
+def test_copy_free_mode_and_memory_report():
+    from paper_2605_22281_amd import sfk
+    P = inputs.small_ct(24, 18, unmatched=True, noise=0.02)
+    say("case: copies=0/1 memory report")
+    c0, X0, r0, _, _ = gpu_run(P, "sflsmr", "srht", 60, 10, vw=0, stepwise=False)
+    c1, X1, r1, _, _ = gpu_run(P, "sflsmr", "srht", 60, 10, vw=0, stepwise=False, copies=1)
+    # same CSR-stream kernel; 16-bit and 32-bit column indices read the same values
+    assert np.array_equal(X0, X1) and np.array_equal(r0, r1)
+    ws0, lib0 = sfk.memory(c0)
+    ws1, lib1 = sfk.memory(c1)
+    assert ws0 == ws1 > 0
+    nnz = P.A.nnz + P.B.nnz
+    assert lib0 >= 2 * nnz                 # the 16-bit column copies
+    assert lib1 < 64 * 1024                # descriptors, block maps, halt flags only
