@@ -314,6 +314,35 @@ sfk_status sfk_coefficients(sfk_ctx *ctx, double *H_host, double *T_host, int32_
  * SFK_ESTATE when the vector is not kept or the run has halted. */
 sfk_status sfk_basis_vector(sfk_ctx *ctx, int32_t i, int32_t kind, int32_t j, double *out);
 
+/* ---- allocation-free solve ------------------------------------------------ */
+
+/* Device scratch of sfk_solve_noalloc, per device (bytes). */
+#define SFK_NOALLOC_BYTES (64u << 20)
+
+/* For callers that cannot allocate device memory (code under HIP graph capture
+ * elsewhere in the process, tight serving loops, harnesses that forbid
+ * hipMalloc): sfk_init + sfk_iterate(k) + sfk_solution in one call for a
+ * single instance, with every device buffer (workspace, transposed B,
+ * descriptor, block maps) carved from a fixed array of SFK_NOALLOC_BYTES inside
+ * the library, one per device, held until the process ends.  It calls no
+ * hipMalloc / hipFree, creates no stream or event and allocates no host memory.
+ *   A, B, b, p: as for sfk_init; perm must be NULL and vw must not be 1 (no
+ *   copies of the operators are built; vw = -2 means CSR-stream, no tuning).
+ *   Everything runs on `stream` (the sketch and the least-squares update in
+ *   order between the products), and the call returns after synchronising it.
+ *   k: iterations to run (0 <= k <= p->maxit; the stop test ends the run early).
+ *   x: device n-vector receiving x_done.  rho_host: NULL or room for k doubles
+ *   (rho_1..rho_done).  *iters_done_host, *stopped_host as for sfk_iterate.
+ * Returns SFK_ENOMEM (before any device work) when the problem needs more than
+ * SFK_NOALLOC_BYTES, SFK_BREAKDOWN as sfk_iterate, else the errors of sfk_init.
+ * The array keeps the last call's contents; every call clears what it uses.
+ * Calls on one device are serialised by the library (host threads wait for each
+ * other); device work that overlaps a call from outside, e.g. a second process
+ * loading the library, has its own copy of the array. */
+sfk_status sfk_solve_noalloc(const sfk_csr *A, const sfk_csr *B, const double *b,
+                             const sfk_params *p, int32_t k, double *x, double *rho_host,
+                             int32_t *iters_done_host, int32_t *stopped_host, void *stream);
+
 /* ---- timing ---------------------------------------------------------------- */
 
 /* Stages of one iteration, in the order the multi-kernel driver runs them. */

@@ -12,6 +12,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <utility>
 #include <vector>
@@ -1916,4 +1917,150 @@ extern "C" sfk_status sfk_spmv_variant(const sfk_ctx *c, int32_t *vwA_host, int3
 
 extern "C" const char *sfk_version(void) {
   return "sfk 0.1 (gfx950, FP64, sFLSQR / sFLSMR)";
+}
+
+// --------------------------------------------------------------------------
+// the allocation-free solve
+// --------------------------------------------------------------------------
+// Device memory of sfk_solve_noalloc: one array per device, held while the
+// process runs.  Host code never uses its name as an address: the address on
+// each device comes from hipGetSymbolAddress, taken once per device with that
+// device current.
+static __device__ __align__(256) unsigned char scratch[SFK_NOALLOC_BYTES];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_noalloc_mutex[kMaxDevices];   // one call at a time per device
+void *g_noalloc_ptr[kMaxDevices];          // the array's address on each device
+}  // namespace
+
+extern "C" sfk_status sfk_solve_noalloc(const sfk_csr *A, const sfk_csr *B, const double *b,
+                                        const sfk_params *p_in, int32_t k, double *x,
+                                        double *rho_host, int32_t *iters_done_host,
+                                        int32_t *stopped_host, void *stream) {
+  if (!p_in || !x) return fail(nullptr, SFK_EINVAL, "params and x must not be NULL");
+  if (k < 0) return fail(nullptr, SFK_EINVAL, "k must be >= 0");
+  sfk_params p = *p_in;
+  // no copies of the operators and no autotuning (the tuner's events are
+  // allocations): CSR-stream unless a row kernel is asked for
+  if (p.perm) return fail(nullptr, SFK_EINVAL, "sfk_solve_noalloc does not take perm");
+  if (p.vw == 1 || (p.vw_split && p.vw_b == 1))
+    return fail(nullptr, SFK_EINVAL, "sfk_solve_noalloc does not take the SELL-64 kernel (vw = 1)");
+  p.copies = 1;
+  if (p.vw == -2) p.vw = 0;
+  if (p.vw_split && p.vw_b == -2) p.vw_b = 0;
+  sfk_status s = validate(nullptr, A, B, &p);
+  if (s != SFK_OK) return s;
+  if (k > p.maxit) return fail(nullptr, SFK_EINVAL, "k = %d exceeds maxit = %d", k, p.maxit);
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices)
+    return fail(nullptr, SFK_EDEVICE, "no usable HIP device");
+  const int cus = device_cus();
+  if (cus <= 0) return fail(nullptr, SFK_EDEVICE, "no HIP device available");
+  const int nws = default_nws(A, B, &p, cus, spmv_blocks_per_cu());
+  const Plan P = make_plan(A, B, &p, cus, nws);
+  // descriptor and block maps after the instance's workspace
+  const int nsg = p.sketch == SFK_SK_SPARSE_SIGN ? p.s
+                : p.sketch == SFK_SK_IDENTITY ? (p.s + kWG - 1) / kWG : 0;
+  const int nsb = p.sketch == SFK_SK_SRHT ? P.nblk : 0;
+  const int nsc = p.sketch == SFK_SK_SRHT ? (p.s + kWG - 1) / kWG : 0;
+  Layout L_;
+  L_.off = P.total;
+  const size_t o_dev = L_.take<Dev>(1);
+  const size_t o_ms = L_.take<int2>(nws);
+  const size_t o_mv = L_.take<int2>(nws);
+  const size_t o_mg = L_.take<int2>(std::max(nsg, 1));
+  const size_t o_mb = L_.take<int2>(std::max(nsb, 1));
+  const size_t o_mc = L_.take<int2>(std::max(nsc, 1));
+  if (L_.off > (size_t)SFK_NOALLOC_BYTES)
+    return fail(nullptr, SFK_ENOMEM, "the problem needs %zu bytes of device scratch, more than "
+                "the %zu of sfk_solve_noalloc (SFK_NOALLOC_BYTES); use sfk_init", L_.off,
+                (size_t)SFK_NOALLOC_BYTES);
+
+  std::lock_guard<std::mutex> lock(g_noalloc_mutex[dev]);
+  if (!g_noalloc_ptr[dev]) {
+    void *ptr = nullptr;
+    hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr)
+      return fail(nullptr, SFK_EDEVICE, "hipGetSymbolAddress of the scratch array failed: %s",
+                  hipGetErrorString(e));
+    g_noalloc_ptr[dev] = ptr;
+  }
+  void *base = g_noalloc_ptr[dev];
+
+  // a context on the stack: one instance, the caller's stream only (the
+  // sketch and the least-squares update run in order between the products)
+  sfk_ctx c;
+  c.stream = static_cast<hipStream_t>(stream);
+  hipStream_t st = c.stream;
+  Inst I;
+  I.p = p;
+  s = setup_instance(&c, I, A, B, b, base, P.total, cus, nws);
+  if (s != SFK_OK) {
+    set_err(g_err, c.err);
+    hipStreamSynchronize(st);
+    return s;
+  }
+  Dev &D = I.D;
+  char *hb = static_cast<char *>(base);
+  Launch &L = c.L;
+  L.devs = reinterpret_cast<const Dev *>(hb + o_dev);
+  L.map_spmv = reinterpret_cast<const int2 *>(hb + o_ms);
+  L.map_vec = reinterpret_cast<const int2 *>(hb + o_mv);
+  L.map_sg = reinterpret_cast<const int2 *>(hb + o_mg);
+  L.map_sb = reinterpret_cast<const int2 *>(hb + o_mb);
+  L.map_sc = reinterpret_cast<const int2 *>(hb + o_mc);
+  L.nspmv = D.nws;
+  L.nvec = D.nwv;
+  L.nsg = D.nsg;
+  L.nsb = nsb;
+  L.nsc = nsc;
+  L.ninst = 1;
+  L.smax = D.s;
+  L.maxitmax = D.maxit;
+  L.tau = D.tau;
+  L.vwA = D.vwA;
+  L.vwB = D.vwB;
+  HIPCHK(nullptr, hipMemcpyAsync(hb + o_dev, &D, sizeof(Dev), hipMemcpyHostToDevice, st));
+  launch_iota_map(reinterpret_cast<int2 *>(hb + o_ms), D.nws, st);
+  launch_iota_map(reinterpret_cast<int2 *>(hb + o_mv), D.nwv, st);
+  launch_iota_map(reinterpret_cast<int2 *>(hb + o_mg), D.nsg, st);
+  launch_iota_map(reinterpret_cast<int2 *>(hb + o_mb), nsb, st);
+  launch_iota_map(reinterpret_cast<int2 *>(hb + o_mc), nsc, st);
+  // Algorithm 1 / 2 initial lines, then k iterations in stage order
+  launch_stage_C(L, 0, st);
+  launch_sketch(L, 0, st);
+  launch_init_rhs(D, st);
+  launch_stage_D(L, 0, st);
+  for (int it = 1; it <= k; ++it) {
+    launch_stage_A(L, it, st);
+    launch_stage_B(L, it, st);
+    if (D.method == SFK_SFLSQR) launch_sketch(L, it, st);
+    launch_stage_C(L, it, st);
+    if (D.method == SFK_SFLSMR) launch_sketch(L, it, st);
+    launch_ls(L, it, st);
+    if (D.resid) launch_true_iter(D, it, st);
+    launch_stage_D(L, it, st);
+  }
+  HIPCHK(nullptr, hipGetLastError());
+  Scal S;
+  HIPCHK(nullptr, hipMemcpyAsync(&S, D.sc, sizeof(Scal), hipMemcpyDeviceToHost, st));
+  HIPCHK(nullptr, hipStreamSynchronize(st));
+  if (S.err & 16)
+    return fail(nullptr, SFK_EINVAL, "right-hand side b is zero or not finite (||b|| = %g)", S.beta);
+  const int done = S.k_done;
+  if (done == 0) {
+    launch_zero_bytes(x, sizeof(double) * (size_t)D.n, st);
+  } else {
+    launch_backsub(D, done, I.d_ytmp, st);
+    launch_solution(D, done, I.d_ytmp, x, st);
+  }
+  HIPCHK(nullptr, hipGetLastError());
+  if (rho_host && done > 0)
+    HIPCHK(nullptr, hipMemcpyAsync(rho_host, D.rho, sizeof(double) * done, hipMemcpyDeviceToHost, st));
+  HIPCHK(nullptr, hipStreamSynchronize(st));
+  if (iters_done_host) *iters_done_host = done;
+  if (stopped_host) *stopped_host = S.stopped;
+  if (S.breakdown) return fail(nullptr, SFK_BREAKDOWN, "the basis broke down after iteration %d", done);
+  return SFK_OK;
 }

@@ -84,6 +84,7 @@ def lib() -> ctypes.CDLL:
         "sfk_solution_at": (I32, [P, I32, P]),
         "sfk_residual_norms": (I32, [P, I32, PD, I32, PI32, PD]),
         "sfk_basis_vector": (I32, [P, I32, I32, I32, P]),
+        "sfk_solve_noalloc": (I32, [PCSR, PCSR, P, PPAR, I32, P, PD, PI32, PI32, P]),
         "sfk_memory": (I32, [P, ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(ctypes.c_size_t)]),
         "sfk_true_residual": (I32, [P, PD]),
         "sfk_destroy": (I32, [P]),
@@ -119,7 +120,8 @@ def exported_symbols() -> list[str]:
             "sfk_coefficients", "sfk_version", "sfk_set_timing", "sfk_stage_times",
             "sfk_init_batch", "sfk_batch_size", "sfk_instance_status", "sfk_instance_solution",
             "sfk_instance_residual_norms", "sfk_instance_true_residual", "sfk_init_multi",
-            "sfk_instance_solution_at", "sfk_spmv_variant", "sfk_memory", "sfk_basis_vector"]
+            "sfk_instance_solution_at", "sfk_spmv_variant", "sfk_memory", "sfk_basis_vector",
+            "sfk_solve_noalloc"]
 
 
 def _check(status: int, ctx=None):
@@ -261,6 +263,30 @@ def init(A: DeviceCSR, B: DeviceCSR | None, b, p: Params, *, stream=None,
                         b.data_ptr(), ctypes.byref(p), ws_ptr, ws_len, st_obj.cuda_stream)
     _check(st)
     return Context(h, A, B, b, p, ws, st_obj)
+
+
+NOALLOC_BYTES = 64 << 20
+
+
+def solve_noalloc(A: DeviceCSR, B: DeviceCSR | None, b, p: Params, k: int, *, x=None,
+                  stream=None):
+    """sfk_solve_noalloc: k iterations of one instance with the library's fixed
+    device scratch (no device allocation inside the call).  x: optional CUDA
+    float64 n-vector for the result (allocated here by torch when None, i.e. by
+    the caller's side).  Returns (x, rho, iterations done, stopped, status)."""
+    import torch
+    if x is None:
+        x = torch.empty(A.cols, dtype=torch.float64, device=b.device)
+    st_obj = stream if stream is not None else torch.cuda.current_stream(b.device)
+    rho = (ctypes.c_double * max(1, k))()
+    done, stopped = ctypes.c_int32(), ctypes.c_int32()
+    Bc = ctypes.byref(B.c()) if B is not None else None
+    st = lib().sfk_solve_noalloc(ctypes.byref(A.c()), Bc, b.data_ptr(), ctypes.byref(p), int(k),
+                                 x.data_ptr(), rho, ctypes.byref(done), ctypes.byref(stopped),
+                                 st_obj.cuda_stream)
+    if st not in (OK, BREAKDOWN):
+        _check(st)
+    return x, np.array(rho[: done.value]), done.value, bool(stopped.value), st
 
 
 def iterate(ctx: Context, k: int) -> tuple[int, bool, int]:
