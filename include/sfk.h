@@ -46,7 +46,16 @@ typedef enum {
   SFK_ESTATE = 5      /* call not allowed in the context's state (e.g. k out of range) */
 } sfk_status;
 
-typedef enum { SFK_SFLSQR = 0, SFK_SFLSMR = 1 } sfk_method;
+/* Methods.  SFLSQR / SFLSMR: the sketched methods (Algorithms 1 and 2; window
+ * ell, sketch S).  FLSQR / FLSMR: the flexible methods with full
+ * orthogonalisation they are compared with (Sec. 2.2, eq. (flsqr-relations)):
+ * every new w and z orthogonalised against the whole basis (two passes of
+ * classical Gram-Schmidt), y_k = argmin ||beta e_1 - H_{k+1,k} y|| (FLSQR,
+ * eq. (FLSQR)) or argmin ||T_{k+1}(beta e_1 - H_{k+1,k} y)|| (FLSMR); sketch,
+ * s, zeta and ell are ignored, maxit <= 1024, single-instance contexts only.
+ * For FLSQR the projected residual is ||b - A x_k||, so noise_norm > 0 stops
+ * by the discrepancy principle directly. */
+typedef enum { SFK_SFLSQR = 0, SFK_SFLSMR = 1, SFK_FLSQR = 2, SFK_FLSMR = 3 } sfk_method;
 
 /* Sketch families (paper Sec. 2.7 names them; the concrete definitions and the
  * seeding are the library's, identical to the test oracle's):

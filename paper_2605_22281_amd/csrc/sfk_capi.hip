@@ -49,6 +49,11 @@ void launch_solution(const Dev &D, int kk, const double *yv, double *x, hipStrea
 void launch_true_residual(const Dev &D, const double *x, double *out, hipStream_t st);
 void launch_true_iter(const Dev &D, int k, hipStream_t st);
 void launch_zero_bytes(void *p, size_t n, hipStream_t st);
+size_t full_scratch_doubles(int maxit);
+void launch_full_init(const Dev &D, int vwB, hipStream_t st);
+void launch_full_iteration(const Dev &D, int k, int vwA, int vwB, hipStream_t st,
+                           void (*mark)(void *, int, int), void *ctx);
+void launch_full_backsub(const Dev &D, int j, double *yout, hipStream_t st);
 void launch_iota_map(int2 *map, int count, hipStream_t st);
 void launch_export_vec(const double *src, int vs, int len, const double *scale, const int *pinv,
                        double *out, hipStream_t st);
@@ -126,6 +131,8 @@ struct sfk_ctx {
   bool sketch_after_C = false;      // an sFLSMR instance sketches B w_{k+1}
   bool any_rew = false;
   int resid = 0;                    // per-iteration true residual (single instance)
+  bool full = false;                // FLSQR / FLSMR (full orthogonalisation)
+  int open_stage[SFK_NUM_STAGES] = {-1, -1, -1, -1, -1, -1};
   size_t lib_bytes = 0;             // device memory allocated besides the workspaces
   int pending_side[2] = {-1, -1};   // iterations whose sketch/LS wait for the next flush point
   bool multi = false;               // right-hand sides sharing A and B (stages via grp)
@@ -298,6 +305,19 @@ static void enqueue_iteration(sfk_ctx *c, int k) {
   stage_end(c, t, st);
 }
 
+// Stage timing of the full-orthogonalisation iteration (begin = 1 / 0).
+static void full_mark(void *ctx, int stage, int begin) {
+  sfk_ctx *c = static_cast<sfk_ctx *>(ctx);
+  if (begin) c->open_stage[stage] = stage_begin(c, stage, c->stream);
+  else stage_end(c, c->open_stage[stage], c->stream);
+}
+
+static void enqueue_full_iteration(sfk_ctx *c, int k) {
+  const Dev &D = c->inst[0].D;
+  launch_full_iteration(D, k, D.vwA, D.vwB, c->stream, c->timing ? full_mark : nullptr, c);
+  if (c->resid) launch_true_iter(D, k, c->stream);
+}
+
 // Iterations k0 .. k0 + n - 1 captured from the two streams into one HIP
 // graph (the side stream forks from and joins back into the capture), then
 // launched on the context's stream.  Kernel arguments depend on k, so each
@@ -412,8 +432,32 @@ static sfk_status validate(sfk_ctx *c, const sfk_csr *A, const sfk_csr *B, const
     if (B->nnz < 0 || B->nnz >= (1ll << 31))
       return fail(c, SFK_EINVAL, "B nnz %lld out of range", (long long)B->nnz);
   }
-  if (p->method != SFK_SFLSQR && p->method != SFK_SFLSMR)
+  if (p->method < SFK_SFLSQR || p->method > SFK_FLSMR)
     return fail(c, SFK_EINVAL, "unknown method %d", p->method);
+  if (p->method == SFK_FLSQR || p->method == SFK_FLSMR) {
+    // full orthogonalisation: no sketch, no window; one instance per context
+    if (multi) return fail(c, SFK_EINVAL, "FLSQR / FLSMR run in single-instance contexts");
+    if (p->maxit < 1 || p->maxit > 1024)
+      return fail(c, SFK_EINVAL, "maxit %d not in [1, 1024] for FLSQR / FLSMR", p->maxit);
+    if (p->tau != SFK_TAU_IDENTITY && p->tau != SFK_TAU_REWEIGHT_L1)
+      return fail(c, SFK_EINVAL, "unknown tau %d", p->tau);
+    if (p->tau == SFK_TAU_REWEIGHT_L1 && !(p->eps > 0.0 && std::isfinite(p->eps)))
+      return fail(c, SFK_EINVAL, "reweighting needs finite eps > 0");
+    if (!(p->eta >= 0.0) || !std::isfinite(p->eta)) return fail(c, SFK_EINVAL, "eta must be finite >= 0");
+    if (!(p->noise_norm >= 0.0) || !std::isfinite(p->noise_norm))
+      return fail(c, SFK_EINVAL, "noise_norm must be finite >= 0");
+    if (!(p->tol >= 0.0) || !std::isfinite(p->tol)) return fail(c, SFK_EINVAL, "tol must be finite >= 0");
+    if (p->method == SFK_FLSMR && p->noise_norm > 0.0 && p->resid != 2)
+      return fail(c, SFK_EINVAL, "FLSMR's projected residual is not ||b - A x||: for the "
+                  "discrepancy principle set resid = 2");
+    if (p->resid < 0 || p->resid > 2) return fail(c, SFK_EINVAL, "resid must be 0, 1 or 2");
+    if (p->copies != 0 && p->copies != 1) return fail(c, SFK_EINVAL, "copies must be 0 or 1");
+    if (p->copies && (p->perm || p->vw == 1)) return fail(c, SFK_EINVAL, "copies = 1 excludes perm and vw = 1");
+    if (p->perm) return fail(c, SFK_EINVAL, "FLSQR / FLSMR do not take perm");
+    if (p->driver < 0 || p->driver > 2) return fail(c, SFK_EINVAL, "unknown driver %d", p->driver);
+    if (p->reserved != 0) return fail(c, SFK_EINVAL, "reserved must be 0");
+    return SFK_OK;
+  }
   if (p->ell < 0 || p->ell > kMaxEll) return fail(c, SFK_EINVAL, "ell %d not in [0, %d]", p->ell, kMaxEll);
   if (p->s < 1 || p->s > kMaxS) return fail(c, SFK_EINVAL, "s %d not in [1, %d]", p->s, kMaxS);
   if (p->maxit < 1 || p->maxit >= p->s)
@@ -492,6 +536,7 @@ struct Plan {
   size_t o_W, o_P, o_Z, o_wraw, o_zraw, o_x, o_Apart, o_Bpart;
   size_t o_skcode, o_skent, o_skrp, o_chunk, o_srows, o_sd, o_spart, o_SK, o_skrhs;
   size_t o_V, o_tauv, o_R, o_c, o_y, o_ytmp, o_rtrue, o_xres;
+  size_t o_Wf, o_Pf, o_fscr, o_gc, o_gs, o_gR, o_gg;
   size_t o_brp, o_bci, o_bva, o_cursor;
   size_t total;
 };
@@ -582,6 +627,14 @@ static Plan make_plan(const sfk_csr *A, const sfk_csr *B, const sfk_params *p, i
   P.o_ytmp = L_.take<double>(mi);
   P.o_rtrue = L_.take<double>(p->resid ? mi : 1);
   P.o_xres = L_.take<double>(p->resid ? n : 1);
+  const bool full = p->method == SFK_FLSQR || p->method == SFK_FLSMR;
+  P.o_Wf = L_.take<double>(full ? (mi + 1) * m : 1);
+  P.o_Pf = L_.take<double>(full ? (mi + 1) * n : 1);
+  P.o_fscr = L_.take<double>(full ? full_scratch_doubles((int)mi) : 1);
+  P.o_gc = L_.take<double>(full ? mi : 1);
+  P.o_gs = L_.take<double>(full ? mi : 1);
+  P.o_gR = L_.take<double>(full ? mi * mi : 1);
+  P.o_gg = L_.take<double>(full ? mi + 1 : 1);
   if (P.transpose && !member) {
     P.o_brp = L_.take<int>(n + 1);
     P.o_bci = L_.take<int>(P.nnzB);
@@ -599,11 +652,27 @@ static int device_cus() {
   return cus;
 }
 
+static bool is_full(const sfk_params &p) { return p.method == SFK_FLSQR || p.method == SFK_FLSMR; }
+
+// The parameters the library works with: FLSQR / FLSMR draw no sketch (an
+// internal kind without arrays) and keep no window.
+static sfk_params internal_params(const sfk_params &p) {
+  sfk_params q = p;
+  if (is_full(p)) {
+    q.sketch = 3;
+    q.s = 1;
+    q.zeta = 1;
+    q.ell = 0;
+  }
+  return q;
+}
+
 extern "C" size_t sfk_workspace_bytes(const sfk_csr *A, const sfk_csr *B, const sfk_params *p) {
   if (validate(nullptr, A, B, p) != SFK_OK) return 0;
   int cus = device_cus();
   if (cus <= 0) cus = 256;
-  return make_plan(A, B, p, cus, default_nws(A, B, p, cus, 2)).total;
+  const sfk_params q = internal_params(*p);
+  return make_plan(A, B, &q, cus, default_nws(A, B, &q, cus, 2)).total;
 }
 
 // --------------------------------------------------------------------------
@@ -857,6 +926,13 @@ static sfk_status setup_instance(sfk_ctx *c, Inst &I, const sfk_csr *A, const sf
   D.y = at<double>(w, P.o_y);
   D.rtrue = at<double>(w, P.o_rtrue);
   D.xres = at<double>(w, P.o_xres);
+  D.Wf = at<double>(w, P.o_Wf);
+  D.Pf = at<double>(w, P.o_Pf);
+  D.fscr = at<double>(w, P.o_fscr);
+  D.gc = at<double>(w, P.o_gc);
+  D.gs = at<double>(w, P.o_gs);
+  D.gR = at<double>(w, P.o_gR);
+  D.gg = at<double>(w, P.o_gg);
   I.d_err = at<int>(w, P.o_err);
   I.d_scalar = at<double>(w, P.o_scalar);
   I.d_ytmp = at<double>(w, P.o_ytmp);
@@ -1088,10 +1164,14 @@ static sfk_status init_common(sfk_ctx *c) {
   sfk_status s = build_launch(c);
   if (s != SFK_OK) return s;
   hipStream_t st = c->stream;
-  run_stage(c, kStageC, 0, st);
-  launch_sketch(c->L, 0, st);
-  for (auto &I : c->inst) launch_init_rhs(I.D, st);
-  run_stage(c, kStageD, 0, st);
+  if (c->full) {
+    launch_full_init(c->inst[0].D, c->inst[0].D.vwB, st);
+  } else {
+    run_stage(c, kStageC, 0, st);
+    launch_sketch(c->L, 0, st);
+    for (auto &I : c->inst) launch_init_rhs(I.D, st);
+    run_stage(c, kStageD, 0, st);
+  }
   HIPCHK(c, hipGetLastError());
   s = read_scal(c);
   if (s != SFK_OK) return s;
@@ -1147,8 +1227,9 @@ extern "C" sfk_status sfk_init(sfk_ctx **out, const sfk_csr *A, const sfk_csr *B
   sfk_ctx *c = new sfk_ctx();
   c->stream = static_cast<hipStream_t>(stream);
   c->inst.resize(1);
-  c->inst[0].p = *p;
+  c->inst[0].p = internal_params(*p);
   c->resid = p->resid;
+  c->full = is_full(*p);
   s = create_streams(c, 1);
   if (s == SFK_OK)
     s = setup_instance(c, c->inst[0], A, B, b, workspace, workspace_bytes, cus,
@@ -1175,6 +1256,8 @@ extern "C" sfk_status sfk_init_batch(sfk_ctx **out, int32_t nb, const sfk_csr *A
     sfk_status s = validate(nullptr, &A[i], Bi, &p[i]);
     if (s == SFK_OK && p[i].resid != 0)
       s = fail(nullptr, SFK_EINVAL, "resid must be 0 in a batch (single-instance contexts only)");
+    if (s == SFK_OK && is_full(p[i]))
+      s = fail(nullptr, SFK_EINVAL, "FLSQR / FLSMR run in single-instance contexts");
     if (s != SFK_OK) {
       prefix_err(g_err, "instance", i);
       return s;
@@ -1584,14 +1667,15 @@ extern "C" sfk_status sfk_iterate(sfk_ctx *c, int32_t k, int32_t *iters_done_hos
   // halted, so a run that stops early does not pay for the rest of k.
   const int k0 = c->k_iter;
   // graphs are not used while the stages are timed (events between kernels)
-  const bool graph = c->graph && !c->timing;
+  const bool graph = c->graph && !c->timing && !c->full;
   const int kBatch = graph ? 8 : 4;
-  hipStream_t chk = graph ? c->stream : c->side;
+  hipStream_t chk = (graph || c->full) ? c->stream : c->side;
   int enq = 0, nbatch = 0;
   bool all_done = false;
   while (enq < k && !all_done) {
     const int n = std::min(kBatch, k - enq);
     if (graph) HIPCHK(c, enqueue_graph_batch(c, k0 + enq + 1, n));
+    else if (c->full) for (int i = 1; i <= n; ++i) enqueue_full_iteration(c, k0 + enq + i);
     else for (int i = 1; i <= n; ++i) enqueue_iteration(c, k0 + enq + i);
     enq += n;
     const int slot = nbatch % sfk_ctx::kChkSlots;
@@ -1611,7 +1695,7 @@ extern "C" sfk_status sfk_iterate(sfk_ctx *c, int32_t k, int32_t *iters_done_hos
     }
     ++nbatch;
   }
-  if (!graph) {
+  if (!graph && !c->full) {
     flush_side(c);
     if (enq > 0 && k0 + enq >= c->ev_from)
       HIPCHK(c, hipStreamWaitEvent(c->stream, c->ev_ls[(k0 + enq) % sfk_ctx::kRing], 0));
@@ -1641,7 +1725,8 @@ static sfk_status solution_impl(sfk_ctx *c, Inst &I, int j, double *x) {
   if (j == 0) {
     HIPCHK(c, hipMemsetAsync(x, 0, sizeof(double) * I.D.n, c->stream));
   } else {
-    launch_backsub(I.D, j, I.d_ytmp, c->stream);
+    if (c->full) launch_full_backsub(I.D, j, I.d_ytmp, c->stream);
+    else launch_backsub(I.D, j, I.d_ytmp, c->stream);
     launch_solution(I.D, j, I.d_ytmp, x, c->stream);
   }
   HIPCHK(c, hipGetLastError());
@@ -1694,7 +1779,8 @@ static sfk_status norms_impl(sfk_ctx *c, Inst &I, int kind, double *out_host, in
     if (n > 0)
       HIPCHK(c, hipMemcpy(H.data(), I.D.H, sizeof(double) * (size_t)ldh * n, hipMemcpyDeviceToHost));
     for (int j = 1; j <= n; ++j) {
-      launch_backsub(I.D, j, I.d_ytmp, c->stream);
+      if (c->full) launch_full_backsub(I.D, j, I.d_ytmp, c->stream);
+      else launch_backsub(I.D, j, I.d_ytmp, c->stream);
       HIPCHK(c, hipGetLastError());
       HIPCHK(c, hipMemcpyAsync(y.data(), I.d_ytmp, sizeof(double) * j, hipMemcpyDeviceToHost,
                                c->stream));
@@ -1880,16 +1966,20 @@ extern "C" sfk_status sfk_basis_vector(sfk_ctx *c, int32_t i, int32_t kind, int3
   const Dev &D = I->D;
   const int k = I->k_done;
   if (I->halted) return fail(c, SFK_ESTATE, "basis vectors are available while the run is live");
-  const int lo = kind == 0 ? std::max(1, k + 1 - (D.ell + 1))
+  const int lo = c->full ? 1 : kind == 0 ? std::max(1, k + 1 - (D.ell + 1))
                : (kind == 1 && D.tau == SFK_TAU_REWEIGHT_L1) ? std::max(1, k + 1 - D.ell) : 1;
   // the scale of p_{k+1} (and z_{k+1}) is formed by the next iteration's first stage
-  const int hi = kind == 0 ? k + 1 : k;
+  const int hi = (kind == 0 || c->full) ? k + 1 : k;
   if (j < lo || j > hi)
     return fail(c, SFK_ESTATE, "basis vector %d not kept (available %d..%d)", j, lo, hi);
   const double *src, *scale;
   int len;
   const int *pinv = nullptr;
-  if (kind == 0) {
+  if (c->full) {
+    src = (kind == 0 ? D.Wf : kind == 1 ? D.Pf : D.Z) + (size_t)(j - 1) * (kind == 0 ? D.m : D.n);
+    scale = (kind == 0 ? D.sigw : D.sigp) + j;    // 1: the stored vectors are unit
+    len = kind == 0 ? D.m : D.n;
+  } else if (kind == 0) {
     src = D.W + (size_t)(j % (D.ell + 2)) * D.m * D.vs;
     scale = D.sigw + j;
     len = D.m;

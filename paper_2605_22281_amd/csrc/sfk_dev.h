@@ -119,6 +119,14 @@ struct Dev {
   // per-iteration true residual (resid >= 1)
   double *rtrue;      // maxit: ||b - A x_k||
   double *xres;       // n: x_k in the library's order of the unknowns
+  // full orthogonalisation (FLSQR / FLSMR, method 2 / 3): the whole bases,
+  // orthonormal columns, and the Givens state of the projected problem
+  double *Wf;         // (maxit + 1) * m, w_j in column j - 1
+  double *Pf;         // (maxit + 1) * n, p_j in column j - 1
+  double *fscr;       // sweep partials and projections
+  double *gc, *gs;    // maxit rotations
+  double *gR;         // maxit * maxit, column-major upper triangular
+  double *gg;         // maxit + 1: Q^T (rhs)
 };
 
 // Launch geometry of a batch of instances: the device array of instance

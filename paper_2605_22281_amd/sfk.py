@@ -21,13 +21,13 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libsfk.so")
 
 OK, EINVAL, ENOMEM, EDEVICE, BREAKDOWN, ESTATE = range(6)
-SFLSQR, SFLSMR = 0, 1
+SFLSQR, SFLSMR, FLSQR, FLSMR = 0, 1, 2, 3
 SK_SPARSE_SIGN, SK_SRHT, SK_IDENTITY = 0, 1, 2
 TAU_IDENTITY, TAU_REWEIGHT_L1 = 0, 1
 DRIVER_AUTO, DRIVER_MULTI, DRIVER_GRAPH = 0, 1, 2
 RES_SKETCHED, RES_TRUE_RECURRENCE, RES_TRUE_EXPLICIT = 0, 1, 2
 
-_METHODS = {"sflsqr": SFLSQR, "sflsmr": SFLSMR}
+_METHODS = {"sflsqr": SFLSQR, "sflsmr": SFLSMR, "flsqr": FLSQR, "flsmr": FLSMR}
 _SKETCHES = {"sparse_sign": SK_SPARSE_SIGN, "countsketch": SK_SPARSE_SIGN, "srht": SK_SRHT,
              "identity": SK_IDENTITY}
 _TAUS = {"identity": TAU_IDENTITY, "reweight_l1": TAU_REWEIGHT_L1}

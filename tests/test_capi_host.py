@@ -99,6 +99,22 @@ def test_validation_rejects(kw, frag):
     assert frag in msg
 
 
+def test_validation_full_orthogonalisation_methods():
+    # sketch, s, zeta and ell do not apply to FLSQR / FLSMR
+    for m in ("flsqr", "flsmr"):
+        assert sfk.validate(_A(), None, sfk.params(m, maxit=300, s=5, ell=99))[0] == sfk.OK
+        assert sfk.validate(_A(), None, sfk.params(m, maxit=1025))[0] == sfk.EINVAL
+        assert sfk.validate(_A(), None, sfk.params(m, perm=None, tau="reweight_l1", eps=0))[0] \
+            == sfk.EINVAL
+    st, msg = sfk.validate(_A(), None, sfk.params("flsmr", noise_norm=1.0))
+    assert st == sfk.EINVAL and "resid = 2" in msg
+    assert sfk.validate(_A(), None, sfk.params("flsqr", noise_norm=1.0))[0] == sfk.OK
+    # workspace of FLSQR grows with maxit (whole bases), not with s
+    a = sfk.workspace_bytes(_A(), None, sfk.params("flsqr", maxit=10))
+    b = sfk.workspace_bytes(_A(), None, sfk.params("flsqr", maxit=40))
+    assert 0 < a < b
+
+
 def test_validation_accepts_new_options():
     for kw in (dict(resid=1), dict(resid=2), dict(copies=1), dict(vw=0, vw_b=64),
                dict(driver="graph"), dict(method="sflsmr", s=60, maxit=20, noise_norm=1.0, resid=2)):
