@@ -174,6 +174,80 @@ def multi_rhs_bench(P, cfg, A, B, R: int, K: int, order: str = "natural"):
             "stage_avg_ms": {k: (v[0] / v[1] if v[1] else 0.0) for k, v in times.items()}}
 
 
+def driver_compare(P, A, B, b, cfg, K, order):
+    """The same K iterations with the stream driver and with each batch of
+    iterations captured into a HIP graph (bit-identical results)."""
+    import numpy as np
+    import torch
+    from paper_2605_22281_amd import sfk
+    out = {}
+    xs = {}
+    for drv in ("multi", "graph"):
+        p = sfk.params(cfg["method"], ell=2, maxit=K, sketch=cfg["sketch"], s=cfg["s"],
+                       zeta=cfg["zeta"], seed=cfg["seed"], tau=cfg["tau"], eps=1e-3, driver=drv,
+                       perm=_order_tensor(order, P))
+        best = None
+        for rep_ in range(3):
+            ctx = sfk.init(A, B, b, p)
+            dt, done = _timed_iterate(sfk, torch, ctx, K)
+            xs[drv] = sfk.solution(ctx).cpu().numpy()
+            sfk.destroy(ctx)
+            best = dt if best is None else min(best, dt)
+        out[drv] = {"iterations_per_s": K / best, "ms_per_step": best * 1e3 / K}
+    out["bit_identical"] = bool(np.array_equal(xs["multi"], xs["graph"]))
+    out["note"] = "best of 3 runs of K iterations each, fresh context per run"
+    return out
+
+
+def full_vs_sketched(P, A, B, b, cfg, K, order):
+    """Per-iteration time of the full-orthogonalisation method (FLSQR / FLSMR,
+    Sec. 2.2) against the sketched one on the same operators, K iterations
+    each (the paper's comparison of Sec. 3.2)."""
+    import torch
+    from paper_2605_22281_amd import sfk
+    full = {"sflsqr": "flsqr", "sflsmr": "flsmr"}[cfg["method"]]
+    res = {}
+    for meth in (cfg["method"], full):
+        p = sfk.params(meth, ell=2, maxit=K, sketch=cfg["sketch"], s=cfg["s"], zeta=cfg["zeta"],
+                       seed=cfg["seed"], tau=cfg["tau"], eps=1e-3,
+                       perm=_order_tensor(order, P) if meth == cfg["method"] else None)
+        ctx = sfk.init(A, B, b, p)
+        dt, done = _timed_iterate(sfk, torch, ctx, K)
+        sfk.destroy(ctx)
+        res[meth] = {"iterations": done, "iterations_per_s": done / dt, "ms_per_step": dt * 1e3 / done}
+    res["sketched_speedup"] = res[cfg["method"]]["iterations_per_s"] / res[full]["iterations_per_s"]
+    return res
+
+
+def adjoint_bench(P, A, R=16, K=50, tape=10):
+    """Forward (K reweighted sFLSQR steps with checkpoints every `tape`) and
+    reverse sweep for R right-hand sides of the 256^2 operator with B = A^T
+    (the differentiation workload), through the autograd.Function."""
+    import numpy as np
+    import torch
+    from paper_2605_22281_amd import inputs
+    from paper_2605_22281_amd.autograd import SketchedFlexibleLSQR
+    bnp, xtnp, _ = inputs.multi_rhs(P, R, seed=31)
+    b = torch.from_numpy(np.ascontiguousarray(bnp)).cuda().requires_grad_(True)
+    eps = torch.tensor(1e-3, dtype=torch.float64, requires_grad=True)
+    xt = torch.from_numpy(np.ascontiguousarray(xtnp)).cuda()
+    opts = dict(sketch="srht", s=400, seed=3005, tape=tape)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    x = SketchedFlexibleLSQR.apply(b, eps, A, K, opts)
+    loss = 0.5 * ((x - xt) ** 2).sum()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    loss.backward()
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    return {"rhs": R, "iterations": K, "checkpoint_every": tape,
+            "forward_s": t1 - t0, "backward_s": t2 - t1,
+            "note": "forward includes each right-hand side's init (B = A^T built on the device); "
+                    "backward = reverse sweep with the basis regenerated between checkpoints",
+            "grad_eps": float(eps.grad)}
+
+
 def hetero_bench(count: int = 32, maxit: int = 100, order: str = "natural"):
     """Independent instances of uneven sizes in one context vs a plain loop."""
     import numpy as np
@@ -368,6 +442,7 @@ def main():
     ap.add_argument("--extras", default="all", choices=["all", "none"],
                     help="the other plain workloads beside the headline")
     ap.add_argument("--no-full-run", action="store_true")
+    ap.add_argument("--adjoint", type=int, default=1, help="time the derivative workload (0/1)")
     ap.add_argument("--rhs", type=int, default=32)
     ap.add_argument("--order", default="tiles4", choices=["natural", "tiles4", "tiles8"],
                     help="order of the unknowns passed to the library: the image's row-major "
@@ -432,8 +507,14 @@ def main():
         extras[q] = run_plain(q, Pq, Aq, Bq, bq, Kq, W, args)
         if q == "ct64":
             extras[q]["discrepancy_run"] = run_plain(q, Pq, Aq, Bq, bq, Kq, 0, args, noise=True)
+            extras[q]["drivers"] = driver_compare(Pq, Aq, Bq, bq, WORKLOADS[q], Kq, args.order)
         if q == "ct256_unmatched":
             keep = (Pq, Aq, Bq)
+            extras[q]["full_vs_sketched"] = full_vs_sketched(Pq, Aq, Bq, bq, WORKLOADS[q], Kq,
+                                                             args.order)
+            if args.adjoint:
+                log("bench: derivative workload (16 right-hand sides, 50 steps, forward + reverse)")
+                extras["adjoint_ct256"] = adjoint_bench(Pq, Aq)
         else:
             del Aq, Bq, bq
     if extras:

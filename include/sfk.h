@@ -150,7 +150,11 @@ typedef struct {
                           size); 1: it may not: CSR-stream or row kernels on the
                           caller's arrays (and the transpose in the workspace),
                           SFK_EINVAL with perm or vw = 1 */
-  int32_t reserved;    /* must be 0 */
+  int32_t tape;        /* derivative tape for sfk_adjoint: 0 = none; c >= 1 keeps a
+                          checkpoint of the w window every c iterations (the
+                          adjoint regenerates the basis between checkpoints).
+                          sFLSQR with B = A^T (B NULL), no perm, maxit <= 1024,
+                          single-instance contexts */
   const int32_t *perm; /* optional order of the n unknowns: a device array of n
                           distinct values in [0, n), or NULL (identity).  Unknown j
                           is stored at position perm[j] inside the library: columns
@@ -351,6 +355,19 @@ sfk_status sfk_basis_vector(sfk_ctx *ctx, int32_t i, int32_t kind, int32_t j, do
 sfk_status sfk_solve_noalloc(const sfk_csr *A, const sfk_csr *B, const double *b,
                              const sfk_params *p, int32_t k, double *x, double *rho_host,
                              int32_t *iters_done_host, int32_t *stopped_host, void *stream);
+
+/* ---- derivative ------------------------------------------------------------- */
+
+/* Reverse-mode derivative of x_K (K = iterations done) of a context created
+ * with sfk_params.tape = c >= 1 (sFLSQR, B = A^T): given xbar = dL/dx_K
+ * (device n-vector), writes bbar = dL/db (device m-vector) and *epsbar_host =
+ * dL/deps, eps the parameter of the l1 reweighting (0 with tau = identity).
+ * The derivative is that of the map b, eps -> x_K defined by K steps of eq.
+ * (FGK) and eq. (sFLSQR) with the sketch held fixed; the basis between the
+ * checkpoints is regenerated from eq. (FGK).  SFK_ESTATE if the context has no
+ * tape or its run stopped or broke down before K.  Allocates its own scratch
+ * (device), freed before returning; synchronous. */
+sfk_status sfk_adjoint(sfk_ctx *ctx, const double *xbar, double *bbar, double *epsbar_host);
 
 /* ---- timing ---------------------------------------------------------------- */
 

@@ -20,6 +20,7 @@
 #include "sfk.h"
 #include "sfk_dev.h"
 #include "sfk_units.h"
+#include "sfk_adjoint_layout.h"
 
 namespace sfk {
 void launch_stage_A(const Launch &L, int k, hipStream_t st);
@@ -54,6 +55,9 @@ void launch_full_init(const Dev &D, int vwB, hipStream_t st);
 void launch_full_iteration(const Dev &D, int k, int vwA, int vwB, hipStream_t st,
                            void (*mark)(void *, int, int), void *ctx);
 void launch_full_backsub(const Dev &D, int j, double *yout, hipStream_t st);
+void launch_checkpoint_w(const Dev &D, int k, double *ck, hipStream_t st);
+size_t adjoint_checkpoint_doubles(int maxit, int tape, int ell, int m);
+
 void launch_iota_map(int2 *map, int count, hipStream_t st);
 void launch_export_vec(const double *src, int vs, int len, const double *scale, const int *pinv,
                        double *out, hipStream_t st);
@@ -132,6 +136,7 @@ struct sfk_ctx {
   bool any_rew = false;
   int resid = 0;                    // per-iteration true residual (single instance)
   bool full = false;                // FLSQR / FLSMR (full orthogonalisation)
+  int tape = 0;                     // derivative tape: checkpoint interval (0: none)
   int open_stage[SFK_NUM_STAGES] = {-1, -1, -1, -1, -1, -1};
   size_t lib_bytes = 0;             // device memory allocated besides the workspaces
   int pending_side[2] = {-1, -1};   // iterations whose sketch/LS wait for the next flush point
@@ -293,6 +298,10 @@ static void enqueue_iteration(sfk_ctx *c, int k) {
   t = stage_begin(c, SFK_STAGE_SPMV_B, st);
   run_stage(c, kStageC, k, st);
   stage_end(c, t, st);
+  if (c->tape && k % c->tape == 0) {
+    const Dev &D0 = c->inst[0].D;
+    launch_checkpoint_w(D0, k, D0.ck + (size_t)(k / c->tape) * (D0.ell + 2) * D0.m, st);
+  }
   if (late) {
     defer_side(c, k);
     if (!c->sketch_after_C && k % 2 == 0) flush_side(c);
@@ -455,7 +464,7 @@ static sfk_status validate(sfk_ctx *c, const sfk_csr *A, const sfk_csr *B, const
     if (p->copies && (p->perm || p->vw == 1)) return fail(c, SFK_EINVAL, "copies = 1 excludes perm and vw = 1");
     if (p->perm) return fail(c, SFK_EINVAL, "FLSQR / FLSMR do not take perm");
     if (p->driver < 0 || p->driver > 2) return fail(c, SFK_EINVAL, "unknown driver %d", p->driver);
-    if (p->reserved != 0) return fail(c, SFK_EINVAL, "reserved must be 0");
+    if (p->tape != 0) return fail(c, SFK_EINVAL, "the derivative tape is for sFLSQR");
     return SFK_OK;
   }
   if (p->ell < 0 || p->ell > kMaxEll) return fail(c, SFK_EINVAL, "ell %d not in [0, %d]", p->ell, kMaxEll);
@@ -500,7 +509,10 @@ static sfk_status validate(sfk_ctx *c, const sfk_csr *A, const sfk_csr *B, const
   if (p->vw_split != 0 && p->vw_split != 1) return fail(c, SFK_EINVAL, "vw_split must be 0 or 1");
   if (p->resid < 0 || p->resid > 2) return fail(c, SFK_EINVAL, "resid must be 0, 1 or 2");
   if (p->copies != 0 && p->copies != 1) return fail(c, SFK_EINVAL, "copies must be 0 or 1");
-  if (p->reserved != 0) return fail(c, SFK_EINVAL, "reserved must be 0");
+  if (p->tape < 0 || p->tape > p->maxit) return fail(c, SFK_EINVAL, "tape must be in [0, maxit]");
+  if (p->tape > 0 && (p->method != SFK_SFLSQR || B != nullptr || p->perm || multi || p->maxit > 1024))
+    return fail(c, SFK_EINVAL, "the derivative tape (tape > 0) needs sFLSQR with B = A^T (B NULL), "
+                "no perm, maxit <= 1024, in a single-instance context");
   if (p->copies && (p->perm || p->vw == 1 || (p->vw_split && p->vw_b == 1)))
     return fail(c, SFK_EINVAL, "copies = 1 excludes perm and the SELL-64 kernel (vw = 1)");
   if (p->method == SFK_SFLSMR && p->noise_norm > 0.0 && p->resid != 2)
@@ -536,7 +548,7 @@ struct Plan {
   size_t o_W, o_P, o_Z, o_wraw, o_zraw, o_x, o_Apart, o_Bpart;
   size_t o_skcode, o_skent, o_skrp, o_chunk, o_srows, o_sd, o_spart, o_SK, o_skrhs;
   size_t o_V, o_tauv, o_R, o_c, o_y, o_ytmp, o_rtrue, o_xres;
-  size_t o_Wf, o_Pf, o_fscr, o_gc, o_gs, o_gR, o_gg;
+  size_t o_Wf, o_Pf, o_fscr, o_gc, o_gs, o_gR, o_gg, o_ck;
   size_t o_brp, o_bci, o_bva, o_cursor;
   size_t total;
 };
@@ -635,6 +647,7 @@ static Plan make_plan(const sfk_csr *A, const sfk_csr *B, const sfk_params *p, i
   P.o_gs = L_.take<double>(full ? mi : 1);
   P.o_gR = L_.take<double>(full ? mi * mi : 1);
   P.o_gg = L_.take<double>(full ? mi + 1 : 1);
+  P.o_ck = L_.take<double>(adjoint_checkpoint_doubles((int)mi, p->tape, (int)ell, (int)m));
   if (P.transpose && !member) {
     P.o_brp = L_.take<int>(n + 1);
     P.o_bci = L_.take<int>(P.nnzB);
@@ -933,6 +946,8 @@ static sfk_status setup_instance(sfk_ctx *c, Inst &I, const sfk_csr *A, const sf
   D.gs = at<double>(w, P.o_gs);
   D.gR = at<double>(w, P.o_gR);
   D.gg = at<double>(w, P.o_gg);
+  D.tape = p.tape;
+  D.ck = at<double>(w, P.o_ck);
   I.d_err = at<int>(w, P.o_err);
   I.d_scalar = at<double>(w, P.o_scalar);
   I.d_ytmp = at<double>(w, P.o_ytmp);
@@ -1168,6 +1183,7 @@ static sfk_status init_common(sfk_ctx *c) {
     launch_full_init(c->inst[0].D, c->inst[0].D.vwB, st);
   } else {
     run_stage(c, kStageC, 0, st);
+    if (c->tape) launch_checkpoint_w(c->inst[0].D, 0, c->inst[0].D.ck, st);
     launch_sketch(c->L, 0, st);
     for (auto &I : c->inst) launch_init_rhs(I.D, st);
     run_stage(c, kStageD, 0, st);
@@ -1230,6 +1246,7 @@ extern "C" sfk_status sfk_init(sfk_ctx **out, const sfk_csr *A, const sfk_csr *B
   c->inst[0].p = internal_params(*p);
   c->resid = p->resid;
   c->full = is_full(*p);
+  c->tape = p->tape;
   s = create_streams(c, 1);
   if (s == SFK_OK)
     s = setup_instance(c, c->inst[0], A, B, b, workspace, workspace_bytes, cus,
@@ -1996,6 +2013,44 @@ extern "C" sfk_status sfk_basis_vector(sfk_ctx *c, int32_t i, int32_t kind, int3
   return SFK_OK;
 }
 
+namespace sfk {
+void run_adjoint(const Dev &D, int K, int tape, const double *ck, const double *xbar_in,
+                 double *bbar, double *eacc_host, const AdjBufs &B, hipStream_t st);
+}  // namespace sfk
+
+extern "C" sfk_status sfk_adjoint(sfk_ctx *c, const double *xbar, double *bbar, double *epsbar_host) {
+  if (!c) return fail(nullptr, SFK_EINVAL, "NULL context");
+  if (!xbar || !bbar) return fail(c, SFK_EINVAL, "xbar and bbar must not be NULL");
+  if (!c->tape) return fail(c, SFK_ESTATE, "the context keeps no derivative tape (sfk_params.tape = 0)");
+  Inst &I = c->inst[0];
+  const Dev &D = I.D;
+  const int K = I.k_done;
+  if (K < 1 || I.stopped || I.breakdown || K != c->k_iter)
+    return fail(c, SFK_ESTATE, "the derivative needs a run of K >= 1 steps that neither stopped "
+                "nor broke down (done %d, launched %d)", K, c->k_iter);
+  AdjBufs B;
+  const size_t cnt = carve_adjoint(nullptr, D.m, D.n, D.s, K, D.maxit, c->tape, D.ell, B);
+  void *mem = nullptr;
+  if (hipMalloc(&mem, cnt * sizeof(double)) != hipSuccess)
+    return fail(c, SFK_ENOMEM, "hipMalloc of %zu bytes for the adjoint failed", cnt * sizeof(double));
+  const size_t used = carve_adjoint(static_cast<double *>(mem), D.m, D.n, D.s, K, D.maxit, c->tape,
+                                    D.ell, B);
+  if (used != cnt) {
+    hipFree(mem);
+    return fail(c, SFK_EDEVICE, "adjoint scratch layout mismatch");
+  }
+  std::vector<double> eacc(K);
+  run_adjoint(D, K, c->tape, D.ck, xbar, bbar, eacc.data(), B, c->stream);
+  hipError_t e = hipGetLastError();
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  hipFree(mem);
+  if (e != hipSuccess) return fail(c, SFK_EDEVICE, "adjoint failed: %s", hipGetErrorString(e));
+  double ebar = 0.0;
+  for (int k = 0; k < K; ++k) ebar += eacc[k];
+  if (epsbar_host) *epsbar_host = ebar;
+  return SFK_OK;
+}
+
 extern "C" sfk_status sfk_spmv_variant(const sfk_ctx *c, int32_t *vwA_host, int32_t *vwB_host) {
   if (!c) return fail(nullptr, SFK_EINVAL, "NULL context");
   const Grp &G = c->grp;
@@ -2034,6 +2089,7 @@ extern "C" sfk_status sfk_solve_noalloc(const sfk_csr *A, const sfk_csr *B, cons
   // no copies of the operators and no autotuning (the tuner's events are
   // allocations): CSR-stream unless a row kernel is asked for
   if (p.perm) return fail(nullptr, SFK_EINVAL, "sfk_solve_noalloc does not take perm");
+  if (p.tape) return fail(nullptr, SFK_EINVAL, "sfk_solve_noalloc keeps no derivative tape");
   if (p.vw == 1 || (p.vw_split && p.vw_b == 1))
     return fail(nullptr, SFK_EINVAL, "sfk_solve_noalloc does not take the SELL-64 kernel (vw = 1)");
   p.copies = 1;

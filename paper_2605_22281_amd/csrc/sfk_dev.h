@@ -127,6 +127,9 @@ struct Dev {
   double *gc, *gs;    // maxit rotations
   double *gR;         // maxit * maxit, column-major upper triangular
   double *gg;         // maxit + 1: Q^T (rhs)
+  // derivative tape: checkpoints of the w window every `tape` iterations
+  int tape;
+  double *ck;         // (maxit / tape + 1) * (ell + 2) * m
 };
 
 // Launch geometry of a batch of instances: the device array of instance

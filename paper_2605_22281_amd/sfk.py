@@ -55,7 +55,7 @@ class Params(ctypes.Structure):
                 ("tol", ctypes.c_double), ("driver", ctypes.c_int32), ("vw", ctypes.c_int32),
                 ("vw_b", ctypes.c_int32), ("vw_split", ctypes.c_int32),
                 ("wg_per_cu", ctypes.c_int32), ("resid", ctypes.c_int32),
-                ("copies", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("copies", ctypes.c_int32), ("tape", ctypes.c_int32),
                 ("perm", ctypes.c_void_p)]
 
 
@@ -84,6 +84,7 @@ def lib() -> ctypes.CDLL:
         "sfk_solution_at": (I32, [P, I32, P]),
         "sfk_residual_norms": (I32, [P, I32, PD, I32, PI32, PD]),
         "sfk_basis_vector": (I32, [P, I32, I32, I32, P]),
+        "sfk_adjoint": (I32, [P, P, P, PD]),
         "sfk_solve_noalloc": (I32, [PCSR, PCSR, P, PPAR, I32, P, PD, PI32, PI32, P]),
         "sfk_memory": (I32, [P, ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(ctypes.c_size_t)]),
         "sfk_true_residual": (I32, [P, PD]),
@@ -121,7 +122,7 @@ def exported_symbols() -> list[str]:
             "sfk_init_batch", "sfk_batch_size", "sfk_instance_status", "sfk_instance_solution",
             "sfk_instance_residual_norms", "sfk_instance_true_residual", "sfk_init_multi",
             "sfk_instance_solution_at", "sfk_spmv_variant", "sfk_memory", "sfk_basis_vector",
-            "sfk_solve_noalloc"]
+            "sfk_solve_noalloc", "sfk_adjoint"]
 
 
 def _check(status: int, ctx=None):
@@ -132,7 +133,7 @@ def _check(status: int, ctx=None):
 
 def params(method="sflsqr", *, ell=2, maxit=50, sketch="sparse_sign", s=101, zeta=8, seed=0,
            instance=0, tau="identity", eps=1e-3, eta=1.01, noise_norm=0.0, tol=0.0,
-           driver="auto", vw=-2, vw_b=None, wg_per_cu=0, resid=0, copies=0,
+           driver="auto", vw=-2, vw_b=None, wg_per_cu=0, resid=0, copies=0, tape=0,
            perm=None) -> Params:
     """perm: optional order of the unknowns, a torch.int32 device tensor of n
     distinct values in [0, n) (unknown j stored at position perm[j] inside the
@@ -160,7 +161,7 @@ def params(method="sflsqr", *, ell=2, maxit=50, sketch="sparse_sign", s=101, zet
     p.vw, p.wg_per_cu = vw, wg_per_cu
     if vw_b is not None:
         p.vw_b, p.vw_split = int(vw_b), 1
-    p.resid, p.copies = int(resid), int(copies)
+    p.resid, p.copies, p.tape = int(resid), int(copies), int(tape)
     if perm is not None:
         import torch
         if perm.dtype != torch.int32 or not perm.is_cuda or not perm.is_contiguous():
@@ -505,6 +506,18 @@ def basis_vector(ctx, kind: str, j: int, i: int = 0):
     _check(lib().sfk_basis_vector(inst_ctx.handle, int(i), BASIS[kind], int(j), x.data_ptr()),
            inst_ctx.handle)
     return x
+
+
+def adjoint(ctx: Context, xbar):
+    """sfk_adjoint: (dL/db as a CUDA float64 m-vector, dL/deps) for xbar = dL/dx_K."""
+    import torch
+    xb = xbar.contiguous()
+    if not (xb.is_cuda and xb.dtype == torch.float64 and xb.numel() == ctx.n):
+        raise ValueError("xbar must be a CUDA float64 n-vector")
+    bb = torch.empty(ctx.m, dtype=torch.float64, device=xb.device)
+    eb = ctypes.c_double()
+    _check(lib().sfk_adjoint(ctx.handle, xb.data_ptr(), bb.data_ptr(), ctypes.byref(eb)), ctx.handle)
+    return bb, eb.value
 
 
 def spmv_variant(ctx) -> tuple[int, int]:

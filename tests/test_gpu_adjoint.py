@@ -1,0 +1,134 @@
+"""The reverse-mode derivative of x_K (sfk_adjoint, and the autograd.Function
+over it) against the oracle's forward-mode derivative (oracle/derivative.py,
+itself pinned to central differences on the CPU) and against central
+differences of the GPU forward run."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import derivative, sketches
+from paper_2605_22281_amd import inputs
+
+from gpu_cases import say
+
+pytestmark = pytest.mark.gpu
+
+
+def _gpu_grad(P, K, *, kind="sparse_sign", s=50, eps=1e-2, tape=4, tau="reweight_l1", seed=5):
+    from paper_2605_22281_amd import sfk
+    A = sfk.to_device_csr(P.A)
+    b = torch.from_numpy(np.ascontiguousarray(P.b)).cuda()
+    p = sfk.params("sflsqr", maxit=K, sketch=kind, s=s, seed=seed, tau=tau, eps=eps, tape=tape)
+    ctx = sfk.init(A, None, b, p)
+    done, stopped, _ = sfk.iterate(ctx, K)
+    assert done == K and not stopped
+    x = sfk.solution(ctx)
+    xt = torch.from_numpy(P.x_true).cuda()
+    bb, eb = sfk.adjoint(ctx, (x - xt).contiguous())
+    return x.cpu().numpy(), bb.cpu().numpy(), eb
+
+
+@pytest.mark.parametrize("kind,tau", [("sparse_sign", "reweight_l1"), ("srht", "reweight_l1"),
+                                      ("sparse_sign", "identity")])
+def test_adjoint_matches_oracle_tangents(kind, tau):
+    P = inputs.small_ct(16, 12, noise=0.02, phantom="sparse", seed_offset=71)
+    K, eps = 12, 1e-2
+    say(f"case: adjoint small {kind} {tau}")
+    x, bb, eb = _gpu_grad(P, K, kind=kind, tau=tau, eps=eps)
+    S = sketches.make(kind, P.m, 50, 5)
+    rng = np.random.default_rng(11)
+    nb = np.linalg.norm(P.b)
+    worst = 0.0
+    for t in range(20):
+        db = rng.standard_normal(P.m)
+        db *= nb / np.linalg.norm(db)
+        deps = eps * rng.standard_normal() if tau == "reweight_l1" else 0.0
+        _, dl = derivative.loss_tangent(P.A, P.b, S, P.x_true, db, deps, method="sflsqr", maxit=K,
+                                        ell=2, tau=tau, eps=eps)
+        g = float(bb @ db) + eb * deps
+        worst = max(worst, abs(g - dl) / abs(dl))
+        assert abs(g - dl) <= 1e-8 * abs(dl), (t, g, dl)
+    if tau == "identity":
+        assert eb == 0.0
+    say(f"adjoint vs oracle tangents, 20 directions: worst rel {worst:.1e}")
+
+
+def test_checkpoint_interval_does_not_change_the_gradient():
+    P = inputs.small_ct(16, 12, noise=0.02, phantom="sparse", seed_offset=72)
+    say("case: adjoint tape 1 / 5 / 12")
+    out = {c: _gpu_grad(P, 12, tape=c) for c in (1, 5, 12)}
+    for c in (5, 12):
+        assert np.allclose(out[c][1], out[1][1], rtol=0, atol=1e-10 * np.abs(out[1][1]).max())
+        assert abs(out[c][2] - out[1][2]) <= 1e-10 * abs(out[1][2])
+
+
+def test_ct256_batch16_fd_and_oracle():
+    """256^2 CT (180 x 363), B = A^T, 16 ellipse phantoms, sFLSQR with the l1
+    reweighting eps = 1e-3, SRHT s = 400 on m, 50 steps, checkpoint every 10:
+    gradient of 0.5 sum ||x_50 - x_true||^2 in (b, eps) through the
+    autograd.Function, against central differences of the GPU run on 20
+    random directions (step h = 1e-6 relative), and against the oracle's
+    tangent for the first phantom.
+
+    The map is strongly curved along some directions (the h^2 term of a
+    central difference reaches 1e-7 relative at h = 1e-6), so each central
+    difference D(h) is compared within its own truncation estimate
+    |D(2h) - D(h)| / 3 (plus 1e-9), and the Richardson value (4 D(h) - D(2h)) / 3,
+    whose error is O(h^4), to 1e-7."""
+    from paper_2605_22281_amd import sfk
+    from paper_2605_22281_amd.autograd import SketchedFlexibleLSQR
+    P = inputs.workload("ct256_unmatched")
+    R, K, eps0 = 16, 50, 1e-3
+    b_np, xt_np, _ = inputs.multi_rhs(P, R, seed=31)
+    say(f"case: ct256 adjoint batch {R}, K = {K}")
+    A = sfk.to_device_csr(P.A)
+    b = torch.from_numpy(np.ascontiguousarray(b_np)).cuda().requires_grad_(True)
+    eps = torch.tensor(eps0, dtype=torch.float64, requires_grad=True)
+    xt = torch.from_numpy(np.ascontiguousarray(xt_np)).cuda()
+    opts = dict(sketch="srht", s=400, seed=3005, tape=10, vw=0)
+    x = SketchedFlexibleLSQR.apply(b, eps, A, K, opts)
+    loss = 0.5 * ((x - xt) ** 2).sum()
+    loss.backward()
+    gb = b.grad.detach().cpu().numpy()
+    ge = float(eps.grad.detach())
+
+    def L(bp, ep):
+        with torch.no_grad():
+            xx = SketchedFlexibleLSQR.apply(bp, torch.tensor(ep, dtype=torch.float64), A, K, opts)
+            return float(0.5 * ((xx - xt) ** 2).sum())
+
+    rng = np.random.default_rng(13)
+    h = 1e-6
+    bn = b.detach()
+    worst_fd = worst_rich = 0.0
+    dirs = []
+    for t in range(20):
+        db = rng.standard_normal(b_np.shape)
+        db *= np.linalg.norm(b_np) / np.linalg.norm(db)
+        deps = eps0 * rng.standard_normal()
+        dirs.append((db, deps))
+        dbt = torch.from_numpy(db).cuda()
+
+        def D(hh):
+            return (L(bn + hh * dbt, eps0 + hh * deps) - L(bn - hh * dbt, eps0 - hh * deps)) / (2 * hh)
+
+        d1, d2 = D(h), D(2 * h)
+        g = float((gb * db).sum()) + ge * deps
+        rich = (4 * d1 - d2) / 3
+        trunc = abs(d2 - d1) / 3
+        worst_fd = max(worst_fd, abs(d1 - g) / abs(g))
+        worst_rich = max(worst_rich, abs(rich - g) / abs(g))
+        assert abs(d1 - g) <= 2 * trunc + 1e-9 * abs(g), (t, d1, d2, g)
+        assert abs(rich - g) <= 1e-7 * abs(g), (t, rich, g)
+    say(f"ct256 batch: adjoint vs central differences (h = 1e-6), 20 directions: worst rel "
+        f"{worst_fd:.1e}; vs the extrapolated differences {worst_rich:.1e}")
+    # the oracle's forward-mode derivative for phantom 0 (its loss term
+    # depends on b_0 only; the eps derivative is the batch sum, checked above)
+    S = sketches.SRHT(P.m, 400, 3005)
+    for t in range(4):
+        db = dirs[t][0]
+        _, dl = derivative.loss_tangent(P.A, b_np[0], S, xt_np[0], db[0], 0.0, method="sflsqr",
+                                        maxit=K, ell=2, tau="reweight_l1", eps=eps0)
+        g0 = float(gb[0] @ db[0])
+        assert abs(g0 - dl) <= 1e-8 * abs(dl), (t, g0, dl)
+    say("ct256 batch: phantom 0 against the oracle tangent, 4 directions")
