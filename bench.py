@@ -248,6 +248,35 @@ def adjoint_bench(P, A, R=16, K=50, tape=10):
             "grad_eps": float(eps.grad)}
 
 
+def matrix_free_bench(P, name, K, W):
+    """The workload with the operators computed on the fly (sfk_init_beam:
+    exact Siddon projector and its exact transpose, or the interpolating
+    back-projector when the workload's B is unmatched) instead of the stored
+    matrices: K timed iterations, then the same with stage events."""
+    import torch
+    from paper_2605_22281_amd import sfk
+    cfg = WORKLOADS[name]
+    geo = sfk.BeamGeometry(P.N, P.n_angles, P.n_det, back=1 if P.B is not None else 0)
+    b = torch.from_numpy(P.b).cuda()
+    p = sfk.params(cfg["method"], ell=2, maxit=max(K, W, 1), sketch=cfg["sketch"], s=cfg["s"],
+                   zeta=cfg["zeta"], seed=cfg["seed"], tau=cfg["tau"], eps=1e-3)
+    if W > 0:
+        c = sfk.init_beam(geo, b, p)
+        sfk.iterate(c, W)
+        sfk.destroy(c)
+    c = sfk.init_beam(geo, b, p)
+    dt, done = _timed_iterate(sfk, torch, c, K)
+    sfk.destroy(c)
+    c = sfk.init_beam(geo, b, p)
+    sfk.set_timing(c, True)
+    sfk.iterate(c, K)
+    times = sfk.stage_times(c)
+    sfk.destroy(c)
+    return {"iterations": done, "iterations_per_s": done / dt, "ms_per_step": dt * 1e3 / done,
+            "back_projector": "exact transpose" if geo.back == 0 else "pixel-driven interpolation",
+            "stage_avg_ms": {k: (v[0] / v[1] if v[1] else 0.0) for k, v in times.items()}}
+
+
 def hetero_bench(count: int = 32, maxit: int = 100, order: str = "natural"):
     """Independent instances of uneven sizes in one context vs a plain loop."""
     import numpy as np
@@ -492,6 +521,9 @@ def main():
     }
     if "full_run" in head:
         out["full_run"] = head["full_run"]
+    if args.extras == "all":
+        log("bench: matrix-free operators on the headline workload")
+        out["matrix_free"] = matrix_free_bench(P, name, K, W)
     if not args.no_cpu_baseline:
         si = args.cpu_sample_iters or (12 if name == "ct512_sparse" else 40)
         log(f"bench: oracle baseline, {si} iterations")

@@ -103,6 +103,24 @@ typedef struct {
   const double *val;
 } sfk_csr;
 
+/* Matrix-free parallel-beam operators (computed on the fly, nothing stored).
+ * An N x N image of unit pixels on [-N/2, N/2]^2, row-major (row = y index);
+ * nz slices (parallel beam rotating about z, detector row z sees slice z; 1
+ * for 2D); n_angles directions u_a = (cos_a[a], sin_a[a]) (device arrays);
+ * n_det unit bins centred at t_d = d - (n_det - 1)/2.  Ray (z, a, d), index
+ * (z n_angles + a) n_det + d, is the line t_d u_a + lambda (-sin_a, cos_a).
+ * A: exact intersection lengths (Siddon: the ray's interval in the image cut
+ * at every grid-line crossing, each piece to the pixel holding its midpoint,
+ * pieces <= 1e-9 dropped).  B: back = 0 the exact transpose of A; back = 1
+ * pixel-driven linear interpolation between the two bins nearest to the
+ * pixel centre's projection (an unmatched back-projector). */
+typedef struct {
+  int32_t N, nz, n_angles, n_det;
+  const double *cos_a, *sin_a;
+  int32_t back;
+  int32_t reserved;
+} sfk_beam;
+
 typedef struct {
   int32_t method;      /* sfk_method */
   int32_t ell;         /* orthogonalisation window, 0..8; the paper uses 2 (Sec. 3) */
@@ -196,6 +214,18 @@ size_t sfk_workspace_bytes(const sfk_csr *A, const sfk_csr *B, const sfk_params 
  * stream before returning. */
 sfk_status sfk_init(sfk_ctx **out, const sfk_csr *A, const sfk_csr *B, const double *b,
                     const sfk_params *p, void *workspace, size_t workspace_bytes, void *stream);
+
+/* As sfk_init, with the matrix-free operators of geo (m = nz n_angles n_det,
+ * n = nz N^2) instead of stored matrices: the products compute the
+ * intersection lengths on the fly (SpMV kernel code 3).  Single instance;
+ * perm, tape and vw = 1 are not taken (SFK_EINVAL). */
+sfk_status sfk_init_beam(sfk_ctx **out, const sfk_beam *geo, const double *b, const sfk_params *p,
+                         void *workspace, size_t workspace_bytes, void *stream);
+
+/* y = A x (op 0, y an m-vector) or y = B x (op 1, y an n-vector) with the
+ * context's operators and SpMV kernels (device vectors; contexts without perm,
+ * single instance).  Synchronous. */
+sfk_status sfk_apply(sfk_ctx *ctx, int32_t op, const double *x, double *y);
 
 /* Runs up to k more iterations (Algorithm 1 / 2 loop body), stopping early on
  * the stop test or a breakdown.  Synchronous: returns after the device

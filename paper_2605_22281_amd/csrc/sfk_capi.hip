@@ -50,6 +50,8 @@ void launch_solution(const Dev &D, int kk, const double *yv, double *x, hipStrea
 void launch_true_residual(const Dev &D, const double *x, double *out, hipStream_t st);
 void launch_true_iter(const Dev &D, int k, hipStream_t st);
 void launch_zero_bytes(void *p, size_t n, hipStream_t st);
+void launch_beam_rays(const Dev &D, hipStream_t st);
+void launch_uniform_part(int rows, int nw, int *part, hipStream_t st);
 size_t full_scratch_doubles(int maxit);
 void launch_full_init(const Dev &D, int vwB, hipStream_t st);
 void launch_full_iteration(const Dev &D, int k, int vwA, int vwB, hipStream_t st,
@@ -548,7 +550,7 @@ struct Plan {
   size_t o_W, o_P, o_Z, o_wraw, o_zraw, o_x, o_Apart, o_Bpart;
   size_t o_skcode, o_skent, o_skrp, o_chunk, o_srows, o_sd, o_spart, o_SK, o_skrhs;
   size_t o_V, o_tauv, o_R, o_c, o_y, o_ytmp, o_rtrue, o_xres;
-  size_t o_Wf, o_Pf, o_fscr, o_gc, o_gs, o_gR, o_gg, o_ck;
+  size_t o_Wf, o_Pf, o_fscr, o_gc, o_gs, o_gR, o_gg, o_ck, o_brl, o_mscr;
   size_t o_brp, o_bci, o_bva, o_cursor;
   size_t total;
 };
@@ -579,7 +581,7 @@ static int default_nws(const sfk_csr *A, const sfk_csr *B, const sfk_params *p, 
 // vectors, row partitions and transposed B live in the group's workspace; its
 // own x (n) is then contiguous scratch for the true residual.
 static Plan make_plan(const sfk_csr *A, const sfk_csr *B, const sfk_params *p, int cus, int nws,
-                      bool member = false) {
+                      bool member = false, bool beam = false) {
   Plan P{};
   P.m = A->rows;
   P.n = A->cols;
@@ -648,6 +650,8 @@ static Plan make_plan(const sfk_csr *A, const sfk_csr *B, const sfk_params *p, i
   P.o_gR = L_.take<double>(full ? mi * mi : 1);
   P.o_gg = L_.take<double>(full ? mi + 1 : 1);
   P.o_ck = L_.take<double>(adjoint_checkpoint_doubles((int)mi, p->tape, (int)ell, (int)m));
+  P.o_brl = L_.take<double>(beam ? 2 * m : 1);
+  P.o_mscr = L_.take<double>(beam ? m : 1);
   if (P.transpose && !member) {
     P.o_brp = L_.take<int>(n + 1);
     P.o_bci = L_.take<int>(P.nnzB);
@@ -854,13 +858,15 @@ static sfk_status relabel(sfk_ctx *c, const int *perm, const sfk_csr *A, const s
 
 static sfk_status setup_instance(sfk_ctx *c, Inst &I, const sfk_csr *A, const sfk_csr *B,
                                  const double *b, void *workspace, size_t ws_bytes, int cus,
-                                 int nws, const Grp *grp = nullptr, int r = 0) {
+                                 int nws, const Grp *grp = nullptr, int r = 0,
+                                 const sfk_beam *beam = nullptr) {
   const sfk_params &p = I.p;
-  if ((A->nnz > 0 && (!A->rowptr || !A->colind || !A->val)) || !A->rowptr || !b)
-    return fail(c, SFK_EINVAL, "A arrays and b must be device pointers");
-  if (B && ((B->nnz > 0 && (!B->colind || !B->val)) || !B->rowptr))
+  if (!beam && ((A->nnz > 0 && (!A->rowptr || !A->colind || !A->val)) || !A->rowptr))
+    return fail(c, SFK_EINVAL, "A arrays must be device pointers");
+  if (!b) return fail(c, SFK_EINVAL, "b must be a device pointer");
+  if (!beam && B && ((B->nnz > 0 && (!B->colind || !B->val)) || !B->rowptr))
     return fail(c, SFK_EINVAL, "B arrays must be device pointers");
-  const Plan P = make_plan(A, B, &p, cus, nws, grp != nullptr);
+  const Plan P = make_plan(A, B, &p, cus, nws, grp != nullptr, beam != nullptr);
   if (workspace) {
     if (ws_bytes < P.total)
       return fail(c, SFK_ENOMEM, "workspace of %zu bytes is smaller than the %zu required",
@@ -948,6 +954,8 @@ static sfk_status setup_instance(sfk_ctx *c, Inst &I, const sfk_csr *A, const sf
   D.gg = at<double>(w, P.o_gg);
   D.tape = p.tape;
   D.ck = at<double>(w, P.o_ck);
+  D.brl = at<double>(w, P.o_brl);
+  D.mscr = at<double>(w, P.o_mscr);
   I.d_err = at<int>(w, P.o_err);
   I.d_scalar = at<double>(w, P.o_scalar);
   I.d_ytmp = at<double>(w, P.o_ytmp);
@@ -968,6 +976,18 @@ static sfk_status setup_instance(sfk_ctx *c, Inst &I, const sfk_csr *A, const sf
     return setup_sketch_and_b(c, I, st);
   }
 
+  if (beam) {
+    // matrix-free operators: directions, per-ray intervals, even row ranges
+    D.bN = beam->N; D.bNz = beam->nz; D.bNa = beam->n_angles; D.bNd = beam->n_det;
+    D.bBack = beam->back; D.bCos = beam->cos_a; D.bSin = beam->sin_a;
+    D.Arp = nullptr; D.Aci = nullptr; D.Ava = nullptr;
+    D.vwA = D.vwB = 3;
+    launch_beam_rays(D, st);
+    launch_uniform_part(D.m, D.nws, at<int>(w, P.o_Apart), st);
+    launch_uniform_part(D.n, D.nws, at<int>(w, P.o_Bpart), st);
+    HIPCHK(c, hipGetLastError());
+    return setup_sketch_and_b(c, I, st);
+  }
   // structure checks
   launch_csr_check(A->rowptr, A->colind, D.m, D.n, A->nnz, I.d_err, st);
   if (B) {
@@ -1251,6 +1271,54 @@ extern "C" sfk_status sfk_init(sfk_ctx **out, const sfk_csr *A, const sfk_csr *B
   if (s == SFK_OK)
     s = setup_instance(c, c->inst[0], A, B, b, workspace, workspace_bytes, cus,
                        default_nws(A, B, p, cus, spmv_blocks_per_cu()));
+  if (s == SFK_OK) s = init_common(c);
+  if (s != SFK_OK) {
+    set_err(g_err, c->err);
+    release(c);
+    return s;
+  }
+  *out = c;
+  return SFK_OK;
+}
+
+extern "C" sfk_status sfk_init_beam(sfk_ctx **out, const sfk_beam *geo, const double *b,
+                                    const sfk_params *p, void *workspace, size_t workspace_bytes,
+                                    void *stream) {
+  if (!out) return fail(nullptr, SFK_EINVAL, "out must not be NULL");
+  *out = nullptr;
+  if (!geo || !p) return fail(nullptr, SFK_EINVAL, "geometry and params must not be NULL");
+  if (geo->N < 1 || geo->nz < 1 || geo->n_angles < 1 || geo->n_det < 1 || !geo->cos_a || !geo->sin_a)
+    return fail(nullptr, SFK_EINVAL, "beam geometry: N, nz, n_angles, n_det >= 1 and device "
+                "direction arrays required");
+  if (geo->back != 0 && geo->back != 1) return fail(nullptr, SFK_EINVAL, "back must be 0 or 1");
+  const int64_t m = (int64_t)geo->nz * geo->n_angles * geo->n_det;
+  const int64_t n = (int64_t)geo->nz * geo->N * geo->N;
+  if (m >= (1ll << 31) || n >= (1ll << 31)) return fail(nullptr, SFK_EINVAL, "beam geometry too large");
+  if (p->perm || p->tape || p->vw == 1)
+    return fail(nullptr, SFK_EINVAL, "matrix-free operators take no perm, tape or SELL kernel");
+  // descriptors of the operators for the size checks and the work split: the
+  // number of pieces per ray is at most 2 N + 2
+  const int64_t nnz_est = std::min<int64_t>(m * (2 * (int64_t)geo->N + 2), (1ll << 31) - 1);
+  const sfk_csr Ad{m, n, nnz_est, nullptr, nullptr, nullptr};
+  const sfk_csr Bd{n, m, nnz_est, nullptr, nullptr, nullptr};
+  sfk_params q = *p;
+  q.vw = 3;
+  q.vw_split = 0;
+  q.copies = 1;
+  sfk_status s = validate(nullptr, &Ad, &Bd, p);
+  if (s != SFK_OK) return s;
+  const int cus = device_cus();
+  if (cus <= 0) return fail(nullptr, SFK_EDEVICE, "no HIP device available");
+  sfk_ctx *c = new sfk_ctx();
+  c->stream = static_cast<hipStream_t>(stream);
+  c->inst.resize(1);
+  c->inst[0].p = internal_params(q);
+  c->resid = p->resid;
+  c->full = is_full(*p);
+  s = create_streams(c, 1);
+  if (s == SFK_OK)
+    s = setup_instance(c, c->inst[0], &Ad, &Bd, b, workspace, workspace_bytes, cus,
+                       default_nws(&Ad, &Bd, &q, cus, spmv_blocks_per_cu()), nullptr, 0, geo);
   if (s == SFK_OK) s = init_common(c);
   if (s != SFK_OK) {
     set_err(g_err, c->err);
@@ -2048,6 +2116,18 @@ extern "C" sfk_status sfk_adjoint(sfk_ctx *c, const double *xbar, double *bbar, 
   double ebar = 0.0;
   for (int k = 0; k < K; ++k) ebar += eacc[k];
   if (epsbar_host) *epsbar_host = ebar;
+  return SFK_OK;
+}
+
+extern "C" sfk_status sfk_apply(sfk_ctx *c, int32_t op, const double *x, double *y) {
+  if (!c) return fail(nullptr, SFK_EINVAL, "NULL context");
+  if (!x || !y || (op != 0 && op != 1)) return fail(c, SFK_EINVAL, "op must be 0 (A) or 1 (B)");
+  if (c->multi || c->inst.size() != 1 || c->inst[0].p.perm)
+    return fail(c, SFK_EINVAL, "sfk_apply takes single-instance contexts without perm");
+  const Dev &D = c->inst[0].D;
+  launch_spmv_core(D, op == 0, op == 0 ? D.vwA : D.vwB, x, y, c->stream);
+  HIPCHK(c, hipGetLastError());
+  HIPCHK(c, hipStreamSynchronize(c->stream));
   return SFK_OK;
 }
 

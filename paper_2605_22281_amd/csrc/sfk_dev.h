@@ -130,6 +130,14 @@ struct Dev {
   // derivative tape: checkpoints of the w window every `tape` iterations
   int tape;
   double *ck;         // (maxit / tape + 1) * (ell + 2) * m
+  // matrix-free parallel-beam operators (SpMV variant 3; the CSR pointers
+  // are then NULL): image side, slices, angles, bins, back-projector (0
+  // exact transpose, 1 linear interpolation), directions, and per ray its
+  // parameter interval inside the image (lmin, lmax; lmin > lmax: misses it)
+  int bN, bNz, bNa, bNd, bBack;
+  const double *bCos, *bSin;
+  double *brl;        // 2 m
+  double *mscr;       // m: scratch of the explicit residual
 };
 
 // Launch geometry of a batch of instances: the device array of instance

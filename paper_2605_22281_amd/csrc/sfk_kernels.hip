@@ -23,6 +23,7 @@
 // interleaved stage kernels of sfk_multi.hip.  Sketch, least-squares, solution
 // and initialisation kernels here serve both.
 
+#include "sfk_beam.h"
 #include "sfk_common.h"
 
 namespace sfk {
@@ -304,6 +305,10 @@ __global__ void __launch_bounds__(kSpmvWG, 8) k_spmv(const Dev *__restrict__ dev
     r1 = part[wid + 1];
   }
   if (VW == 1) {
+  } else if (VW == 3) {
+    // matrix-free parallel-beam operators
+    if (ISA) beam_forward_rows(D, (const double *)xin, (double *)yout, ybuf, r0, r1, scale, NT);
+    else beam_back_rows(D, (const double *)xin, (double *)yout, ybuf, r0, r1, scale, NT);
   } else if (VW == 0) {
     spmv_stream(rp, ci, gmem(ISA ? D.Aci16 : D.Bci16), va, xin, yout, ybuf, r0, r1, scale);
   } else if (VW == 64) {
@@ -392,6 +397,9 @@ __global__ void __launch_bounds__(kSpmvWG, 8) k_spmv_core(Dev D, const double *_
               gmem(ISA ? D.Asval : D.Bsval), xg, yg, ybuf, s0, s1, rows, 1.0, lds_part);
   } else if (VW == 64) {
     spmv_rows64(rp, ci, va, xg, yg, ybuf, part[wid], part[wid + 1], 1.0);
+  } else if (VW == 3) {
+    if (ISA) beam_forward_rows(D, xin, yout, ybuf, part[wid], part[wid + 1], 1.0, kSpmvWG);
+    else beam_back_rows(D, xin, yout, ybuf, part[wid], part[wid + 1], 1.0, kSpmvWG);
   } else {
     spmv_stream(rp, ci, gmem(ISA ? D.Aci16 : D.Bci16), va, xg, yg, ybuf, part[wid], part[wid + 1], 1.0);
   }
@@ -978,6 +986,23 @@ __global__ void __launch_bounds__(kWG) k_true_res_iter(Dev D, int k) {
   produce<kWG>(D, kStageTrue, blockIdx.x, 1, acc, lds_w, blk);
 }
 
+// ||b - A x||^2 partials from a computed A x (matrix-free operators), over
+// the row ranges of the SpMV workgroups, into the partial buffer of `stage`
+__global__ void __launch_bounds__(kWG) k_resid_ax(Dev D, const double *ax, int stage, int k) {
+  if (stage == kStageTrue && true_iter_off(D, k)) return;
+  __shared__ double lds_w[kMaxQ * (kWG / 64)];
+  __shared__ double blk[kMaxQ];
+  double acc[kMaxQ];
+#pragma unroll
+  for (int q = 0; q < kMaxQ; ++q) acc[q] = 0.0;
+  const int r0 = D.Apart[blockIdx.x], r1 = D.Apart[blockIdx.x + 1];
+  for (int r = r0 + threadIdx.x; r < r1; r += kWG) {
+    const double rr = D.b[r] - ax[r];
+    acc[0] += rr * rr;
+  }
+  produce<kWG>(D, stage, blockIdx.x, 1, acc, lds_w, blk);
+}
+
 // rtrue[k-1] = ||b - A x_k||; with resid = 2 the discrepancy principle stops
 // the run at the first k with ||b - A x_k|| <= ttol
 __global__ void __launch_bounds__(kWG) k_true_stop(Dev D, int k) {
@@ -1321,6 +1346,7 @@ static void launch_spmv_vw(const Launch &L, int k, int vw, hipStream_t st) {
     case 32: hipLaunchKernelGGL((k_spmv<32, ISA>), g, b, 0, st, L.devs, map, k); break;
     case 64: hipLaunchKernelGGL((k_spmv<64, ISA>), g, b, 0, st, L.devs, map, k); break;
     case 1: hipLaunchKernelGGL((k_spmv<1, ISA>), g, b, 0, st, L.devs, map, k); break;
+    case 3: hipLaunchKernelGGL((k_spmv<3, ISA>), g, b, 0, st, L.devs, map, k); break;
     default: hipLaunchKernelGGL((k_spmv<0, ISA>), g, b, 0, st, L.devs, map, k); break;
   }
 }
@@ -1395,6 +1421,11 @@ void launch_collect_halt(const Launch &L, int k, int *out, hipStream_t st) {
 // one launch of the core of SpMV kernel vw (0, 1 or 64) for A (isa) or B
 void launch_spmv_core(const Dev &D, bool isa, int vw, const double *x, double *y, hipStream_t st) {
   const dim3 g(D.nws), b(kSpmvWG);
+  if (vw == 3) {
+    if (isa) hipLaunchKernelGGL((k_spmv_core<3, true>), g, b, 0, st, D, x, y);
+    else hipLaunchKernelGGL((k_spmv_core<3, false>), g, b, 0, st, D, x, y);
+    return;
+  }
   if (isa) {
     if (vw == 1) hipLaunchKernelGGL((k_spmv_core<1, true>), g, b, 0, st, D, x, y);
     else if (vw == 64) hipLaunchKernelGGL((k_spmv_core<64, true>), g, b, 0, st, D, x, y);
@@ -1490,6 +1521,30 @@ void launch_solution(const Dev &D, int kk, const double *yv, double *x, hipStrea
   hipLaunchKernelGGL(k_solution, dim3((D.n + kWG - 1) / kWG), dim3(kWG),
                      sizeof(double) * (size_t)max(1, kk), st, D, kk, yv, x);
 }
+// per-ray parameter interval inside the image (lmin, lmax; a ray that misses
+// the image gets lmin = 1, lmax = 0)
+__global__ void k_beam_rays(Dev D) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= D.m) return;
+  const int per_slice = D.bNa * D.bNd;
+  const int rem = r % per_slice, a = rem / D.bNd, d = rem % D.bNd;
+  const BeamRay R = beam_ray(D, a, d);
+  D.brl[2 * (size_t)r] = R.valid ? R.lmin : 1.0;
+  D.brl[2 * (size_t)r + 1] = R.valid ? R.lmax : 0.0;
+}
+void launch_beam_rays(const Dev &D, hipStream_t st) {
+  hipLaunchKernelGGL(k_beam_rays, dim3((D.m + 255) / 256), dim3(256), 0, st, D);
+}
+
+// rows split evenly over nw workgroups
+__global__ void k_uniform_part(int rows, int nw, int *part) {
+  const int w = blockIdx.x * blockDim.x + threadIdx.x;
+  if (w <= nw) part[w] = (int)((long long)rows * w / nw);
+}
+void launch_uniform_part(int rows, int nw, int *part, hipStream_t st) {
+  hipLaunchKernelGGL(k_uniform_part, dim3((nw + 1 + 255) / 256), dim3(256), 0, st, rows, nw, part);
+}
+
 // byte fill with zero (16-byte stores; the tail byte by byte)
 __global__ void k_zero_bytes(unsigned char *p, size_t n) {
   const size_t n16 = n / 16;
@@ -1533,11 +1588,23 @@ void launch_export_vec(const double *src, int vs, int len, const double *scale, 
 void launch_true_iter(const Dev &D, int k, hipStream_t st) {
   const int nb = std::max(1, std::min((D.n + kWG - 1) / kWG, 2048));
   hipLaunchKernelGGL(k_xres, dim3(nb), dim3(kWG), sizeof(double) * (size_t)max(1, k), st, D, k);
-  hipLaunchKernelGGL(k_true_res_iter, dim3(D.nws), dim3(kWG), 0, st, D, k);
+  if (D.vwA == 3) {
+    launch_spmv_core(D, true, 3, D.xres, D.mscr, st);
+    hipLaunchKernelGGL(k_resid_ax, dim3(D.nws), dim3(kWG), 0, st, D, (const double *)D.mscr,
+                       (int)kStageTrue, k);
+  } else {
+    hipLaunchKernelGGL(k_true_res_iter, dim3(D.nws), dim3(kWG), 0, st, D, k);
+  }
   hipLaunchKernelGGL(k_true_stop, dim3(1), dim3(kWG), 0, st, D, k);
 }
 void launch_true_residual(const Dev &D, const double *x, double *out, hipStream_t st) {
-  hipLaunchKernelGGL(k_true_residual, dim3(D.nws), dim3(kWG), 0, st, D, x);
+  if (D.vwA == 3) {
+    launch_spmv_core(D, true, 3, x, D.mscr, st);
+    hipLaunchKernelGGL(k_resid_ax, dim3(D.nws), dim3(kWG), 0, st, D, (const double *)D.mscr,
+                       (int)kStageMisc, 0);
+  } else {
+    hipLaunchKernelGGL(k_true_residual, dim3(D.nws), dim3(kWG), 0, st, D, x);
+  }
   hipLaunchKernelGGL(k_finish_misc, dim3(1), dim3(kWG), 0, st, D, out);
 }
 

@@ -59,6 +59,12 @@ class Params(ctypes.Structure):
                 ("perm", ctypes.c_void_p)]
 
 
+class Beam(ctypes.Structure):
+    _fields_ = [("N", ctypes.c_int32), ("nz", ctypes.c_int32), ("n_angles", ctypes.c_int32),
+                ("n_det", ctypes.c_int32), ("cos_a", ctypes.c_void_p), ("sin_a", ctypes.c_void_p),
+                ("back", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
 _lib = None
 
 
@@ -85,6 +91,8 @@ def lib() -> ctypes.CDLL:
         "sfk_residual_norms": (I32, [P, I32, PD, I32, PI32, PD]),
         "sfk_basis_vector": (I32, [P, I32, I32, I32, P]),
         "sfk_adjoint": (I32, [P, P, P, PD]),
+        "sfk_init_beam": (I32, [ctypes.POINTER(P), ctypes.POINTER(Beam), P, PPAR, P, ctypes.c_size_t, P]),
+        "sfk_apply": (I32, [P, I32, P, P]),
         "sfk_solve_noalloc": (I32, [PCSR, PCSR, P, PPAR, I32, P, PD, PI32, PI32, P]),
         "sfk_memory": (I32, [P, ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(ctypes.c_size_t)]),
         "sfk_true_residual": (I32, [P, PD]),
@@ -122,7 +130,7 @@ def exported_symbols() -> list[str]:
             "sfk_init_batch", "sfk_batch_size", "sfk_instance_status", "sfk_instance_solution",
             "sfk_instance_residual_norms", "sfk_instance_true_residual", "sfk_init_multi",
             "sfk_instance_solution_at", "sfk_spmv_variant", "sfk_memory", "sfk_basis_vector",
-            "sfk_solve_noalloc", "sfk_adjoint"]
+            "sfk_solve_noalloc", "sfk_adjoint", "sfk_init_beam", "sfk_apply"]
 
 
 def _check(status: int, ctx=None):
@@ -288,6 +296,53 @@ def solve_noalloc(A: DeviceCSR, B: DeviceCSR | None, b, p: Params, k: int, *, x=
     if st not in (OK, BREAKDOWN):
         _check(st)
     return x, np.array(rho[: done.value]), done.value, bool(stopped.value), st
+
+
+class BeamGeometry:
+    """Parallel-beam geometry for the matrix-free operators (sfk_beam): the
+    direction tables live on the device as long as this object."""
+
+    def __init__(self, N, n_angles, n_det, *, nz=1, back=0, cos_a=None, sin_a=None, device="cuda"):
+        import math
+        import torch
+        theta = np.arange(n_angles, dtype=np.float64) * (math.pi / n_angles)
+        ca = np.cos(theta) if cos_a is None else np.asarray(cos_a, dtype=np.float64)
+        sa = np.sin(theta) if sin_a is None else np.asarray(sin_a, dtype=np.float64)
+        self.cos = torch.from_numpy(np.ascontiguousarray(ca)).to(device)
+        self.sin = torch.from_numpy(np.ascontiguousarray(sa)).to(device)
+        self.N, self.nz, self.n_angles, self.n_det, self.back = N, nz, n_angles, n_det, back
+        self.m = nz * n_angles * n_det
+        self.n = nz * N * N
+
+    def c(self) -> Beam:
+        return Beam(self.N, self.nz, self.n_angles, self.n_det, self.cos.data_ptr(),
+                    self.sin.data_ptr(), self.back, 0)
+
+
+def init_beam(geo: BeamGeometry, b, p: Params, *, stream=None) -> Context:
+    """sfk_init_beam: matrix-free operators of the parallel-beam geometry."""
+    import torch
+    if not (b.is_cuda and b.dtype == torch.float64 and b.is_contiguous() and b.numel() == geo.m):
+        raise ValueError("b must be a contiguous float64 CUDA tensor of length m")
+    st_obj = stream if stream is not None else torch.cuda.current_stream(b.device)
+    h = ctypes.c_void_p()
+    g = geo.c()
+    st = lib().sfk_init_beam(ctypes.byref(h), ctypes.byref(g), b.data_ptr(), ctypes.byref(p), None, 0,
+                             st_obj.cuda_stream)
+    _check(st)
+    A = DeviceCSR(geo.m, geo.n, None, None, None)
+    ctx = Context(h, A, None, b, p, None, st_obj)
+    ctx.geo = geo
+    return ctx
+
+
+def apply(ctx: Context, op: str, x):
+    """sfk_apply: y = A x (op "A") or y = B x (op "B")."""
+    import torch
+    y = torch.empty(ctx.m if op == "A" else ctx.n, dtype=torch.float64, device=x.device)
+    _check(lib().sfk_apply(ctx.handle, 0 if op == "A" else 1, x.contiguous().data_ptr(), y.data_ptr()),
+           ctx.handle)
+    return y
 
 
 def iterate(ctx: Context, k: int) -> tuple[int, bool, int]:
