@@ -12,6 +12,10 @@ Modules
   fgk        partially orthogonalised flexible Golub-Kahan; sFLSQR (Alg. 1),
              sFLSMR (Alg. 2), and full-orthogonalisation FLSQR / FLSMR
              (Sec. 2.2) for comparison
+  lowrank    rank-r truncation tau_r of eq. (def:lowr-trc) (full SVD) and its
+             randomized-SVD variant (Halko-Martinsson-Tropp), as flexible
+             operators
+  derivative forward-mode derivative of x_k in b and eps
   dense      definitional dense forms x_k = Z_k (S A Z_k)^+ S b, bounds of
              Theorem 1 and the expectation of Corollary 1
 """

@@ -77,8 +77,12 @@ def lstsq_qr(M: np.ndarray, rhs: np.ndarray) -> np.ndarray:
     return sla.solve_triangular(R, Q.T @ rhs, lower=False)
 
 
-def tau_apply(tau: str, p: np.ndarray, x_prev: np.ndarray, eps: float) -> np.ndarray:
-    """Flexible operator: identity, or diagonal l1 reweighting (x^2 + eps^2)^(1/4)."""
+def tau_apply(tau, p: np.ndarray, x_prev: np.ndarray, eps: float, k: int = 0) -> np.ndarray:
+    """Flexible operator for z_k = tau(p_k): identity, diagonal l1 reweighting
+    (x_{k-1}^2 + eps^2)^(1/4), or a callable tau(p, x_prev, k) (the low-rank
+    truncations of oracle.lowrank)."""
+    if callable(tau):
+        return np.asarray(tau(p, x_prev, k), dtype=np.float64)
     if tau == "identity":
         return p.copy()
     if tau == "reweight_l1":
@@ -155,7 +159,7 @@ def sketched_flexible(A, b, sketch, *, method: str = "sflsqr", B=None, maxit: in
         T[k - 1, k - 1] = tkk
         p = z / tkk
         P.append(p)
-        zk = tau_apply(tau, p, x_prev, eps)
+        zk = tau_apply(tau, p, x_prev, eps, k)
         Z.append(zk)
 
         w = Av(zk)
@@ -263,7 +267,7 @@ def flexible_full(A, b, *, method: str = "flsqr", B=None, maxit: int = 20,
     p = orth_z(z, 1)
     for k in range(1, maxit + 1):
         P.append(p)
-        zk = tau_apply(tau, p, x_prev, eps)
+        zk = tau_apply(tau, p, x_prev, eps, k)
         Z.append(zk)
         w = Av(zk)
         for j in range(1, k + 1):

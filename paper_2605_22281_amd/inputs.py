@@ -1,8 +1,9 @@
 """Seeded synthetic inputs for the sketched flexible LSQR/LSMR solvers.
 
 This module builds test problems only: phantoms, 2D parallel-beam projection
-matrices, an unmatched pixel-driven back-projector, noise, and the artificial
-ill-posed matrices of the paper's synthetic experiment.  It contains none of the
+matrices, an unmatched pixel-driven back-projector, noise, the artificial
+ill-posed matrices of the paper's synthetic experiment, and the Gaussian
+blur + subsampling operator of its deblurring and inpainting example.  It contains none of the
 solver's arithmetic and serves both the CPU oracle and the GPU path, which each
 receive the same arrays.
 
@@ -272,8 +273,70 @@ WORKLOADS = {
 
 
 def workload(name: str) -> Problem:
+    if name in DEBLUR_WORKLOADS:
+        return deblur_problem(name=name, **DEBLUR_WORKLOADS[name])
     kw = dict(WORKLOADS[name])
     return ct_problem(name=name, **kw)
+
+
+# ----------------------------------------------------------------------------
+# Deblurring and inpainting (paper, Sec. 1.2 motivating example and Sec. 3.1)
+# ----------------------------------------------------------------------------
+
+def house_phantom(N: int) -> np.ndarray:
+    """A synthetic stand-in for the paper's 'house' photograph (not available):
+    a sky with a vertical gradient, a wall, two windows and a door (axis-aligned
+    blocks: each is a rank-one image) and a triangular roof, so that the
+    singular values decay quickly but the image is not exactly low rank.
+    Row-major, values in [0, 1]."""
+    y = (np.arange(N) + 0.5) / N
+    img = np.repeat((0.3 + 0.4 * y)[:, None], N, axis=1)
+
+    def block(r0, r1, c0, c1, v):
+        img[int(r0 * N):int(r1 * N), int(c0 * N):int(c1 * N)] = v
+
+    block(0.45, 0.95, 0.15, 0.85, 0.8)          # wall
+    block(0.55, 0.70, 0.25, 0.40, 0.2)          # windows
+    block(0.55, 0.70, 0.60, 0.75, 0.2)
+    block(0.72, 0.95, 0.45, 0.57, 0.35)         # door
+    xc = (np.arange(N) + 0.5) / N
+    for i in range(N):
+        if 0.15 <= y[i] < 0.45:                 # roof: half-width grows downwards
+            h = (y[i] - 0.15) / 0.30 * 0.40
+            img[i, np.abs(xc - 0.5) < h] = 0.55
+    return img.ravel()
+
+
+def gaussian_blur_matrix(N: int, variance: float = 0.25, radius: int = 2) -> sp.csr_matrix:
+    """Blur by a Gaussian point-spread function of the given variance (pixels^2),
+    truncated to a (2 radius + 1)^2 stencil and normalised to unit sum; zero
+    boundary conditions.  Separable: K = K1 (x) K1 on the row-major image."""
+    off = np.arange(-radius, radius + 1)
+    k1 = np.exp(-off.astype(np.float64) ** 2 / (2.0 * variance))
+    k1 /= k1.sum()
+    K1 = sp.diags([np.full(N - abs(d), k1[d + radius]) for d in off], off, shape=(N, N))
+    return sp.kron(K1, K1, format="csr")
+
+
+def deblur_problem(N: int, *, variance: float = 0.25, keep: float = 0.7, noise: float = 0.05,
+                   seed_offset: int = 0, name: str = "") -> Problem:
+    """b = M K x + e: Gaussian blur K, then subsampling M that keeps a random
+    fraction of the pixels (rows of K; the others are missing), then white noise
+    at the relative level 'noise'."""
+    rng = np.random.default_rng(SEED_PHANTOM + seed_offset)
+    kept = np.sort(rng.choice(N * N, size=int(round(keep * N * N)), replace=False))
+    A = _as_int32_csr(gaussian_blur_matrix(N, variance)[kept].tocsr())
+    x = house_phantom(N)
+    b, dn = add_noise(A @ x, noise, SEED_NOISE + seed_offset)
+    return Problem(A=A, B=None, b=b, x_true=x, noise_norm=dn, N=N, name=name)
+
+
+# The deblurring workloads: 512^2 as in the paper's example (variance 0.25,
+# 5% noise); 64^2 for quick tests.
+DEBLUR_WORKLOADS = {
+    "deblur512": dict(N=512, variance=0.25, keep=0.7, noise=0.05, seed_offset=8),
+    "deblur64": dict(N=64, variance=0.25, keep=0.7, noise=0.05, seed_offset=9),
+}
 
 
 def tile_order(N: int, tile: int = 4) -> np.ndarray:

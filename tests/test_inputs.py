@@ -2,6 +2,7 @@
 import math
 
 import numpy as np
+import pytest
 import scipy.sparse as sp
 
 from paper_2605_22281_amd import inputs
@@ -111,3 +112,20 @@ def test_tile_order_is_a_permutation_grouping_blocks():
     xp[perm] = x
     Ap = sp.csr_matrix((P.A.data, perm[P.A.indices], P.A.indptr), shape=P.A.shape)
     assert np.allclose(Ap @ xp, P.A @ x, rtol=1e-14, atol=1e-14)
+
+
+def test_deblur_operator():
+    P = inputs.workload("deblur64")
+    N = 64
+    K = inputs.gaussian_blur_matrix(N, 0.25)
+    # unit sum away from the boundary, symmetric, separable 5 x 5 stencil
+    rs = np.asarray(K.sum(axis=1)).ravel().reshape(N, N)
+    np.testing.assert_allclose(rs[2:-2, 2:-2], 1.0, rtol=1e-14)
+    assert abs(K - K.T).max() < 1e-16 and K.getnnz(axis=1).max() == 25
+    w = np.exp(-1.0 / 0.5)
+    assert K[N * 10 + 10, N * 10 + 11] / K[N * 10 + 10, N * 10 + 10] == pytest.approx(w, rel=1e-13)
+    assert P.m == round(0.7 * N * N) and P.n == N * N
+    e = P.b - P.A @ P.x_true
+    assert np.linalg.norm(e) == pytest.approx(0.05 * np.linalg.norm(P.A @ P.x_true), rel=1e-12)
+    s = np.linalg.svd(P.x_true.reshape(N, N), compute_uv=False)
+    assert s[10] < 0.05 * s[0]                 # quickly decaying spectrum
