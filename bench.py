@@ -28,6 +28,11 @@ Beside the headline, in the same JSON line:
     B = A^T built on the device, sparse-sign s = 201, zeta = 8, up to 100
     iterations with the discrepancy principle per instance, against a plain
     loop over the same 32;
+  * `deblur512`: the deblurring and inpainting workload (512^2 image, Gaussian
+    blur of variance 0.25, 30% missing pixels, 5% noise, CountSketch s = 101,
+    50 iterations) with the rank-30 truncation of every basis vector: FLSQR,
+    sFLSQR, sFLSMR with the truncated SVD and the -RND variants with the
+    randomized SVD, against plain sFLSQR;
   * `cpu_baseline`: the oracle on the headline workload, first iterations.
 
 Prints one JSON line.  --gpus N with N > 1 is refused: this build runs on one
@@ -68,10 +73,15 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+# The sources of the single-instance SpMV kernels (k_spmv and what it includes):
+# counter-derived traffic is only reported while these are unchanged.
+SPMV_SOURCES = ("sfk_kernels.hip", "sfk_common.h", "sfk_dev.h", "sfk_sell.h", "sfk_beam.h")
+
+
 def source_hash() -> str:
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2605_22281_amd", "csrc")
-    for f in sorted(os.listdir(csrc)):
+    for f in SPMV_SOURCES:
         with open(os.path.join(csrc, f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -277,6 +287,64 @@ def matrix_free_bench(P, name, K, W):
             "stage_avg_ms": {k: (v[0] / v[1] if v[1] else 0.0) for k, v in times.items()}}
 
 
+DEBLUR_METHODS = [
+    # (label, method, tau, power iterations of the randomized SVD)
+    ("sFLSQR (tau = I)", "sflsqr", "identity", 1),
+    ("FLSQR tau_r", "flsqr", "lowrank", 1),
+    ("sFLSQR tau_r", "sflsqr", "lowrank", 1),
+    ("sFLSMR tau_r", "sflsmr", "lowrank", 1),
+    ("sFLSQR-RND", "sflsqr", "lowrank_rnd", 1),
+    ("sFLSMR-RND", "sflsmr", "lowrank_rnd", 1),
+]
+
+
+def deblur_bench(K: int = 50, r: int = 30, W: int = 2):
+    """The deblurring and inpainting workload of the paper's timing comparison:
+    512^2 image, Gaussian blur of variance 0.25 then 30% of the pixels missing,
+    5% noise, CountSketch s = 101, rank r = 30 truncation of every basis vector
+    (truncated SVD to a Ritz-residual tolerance of 1e-13, or the randomized SVD
+    with 10 oversampling vectors and one power iteration), K = 50 iterations.
+    Each method: W untimed warm-up iterations on a throw-away context, then K
+    timed iterations of a fresh one, then the same K with stage events; and
+    the relative error of x_K to the true image."""
+    import numpy as np
+    import torch
+    from paper_2605_22281_amd import inputs, sfk
+    P = inputs.workload("deblur512")
+    A = sfk.to_device_csr(P.A)
+    b = torch.from_numpy(P.b).cuda()
+    xt = P.x_true
+    out = {"workload": "512^2 Gaussian blur (variance 0.25) + 30% missing pixels + 5% noise, "
+                       f"CountSketch s=101, rank {r}, {K} iterations",
+           "m": P.m, "n": P.n, "nnz_A": int(P.A.nnz), "methods": {}}
+    for label, method, tau, q in DEBLUR_METHODS:
+        kw = dict(ell=2, maxit=K, sketch="sparse_sign", s=101, zeta=1, seed=3008, tau=tau,
+                  lr_rows=P.N, lr_rank=r, lr_q=q)
+        if W > 0:
+            c = sfk.init(A, None, b, sfk.params(method, **{**kw, "maxit": max(W, 1)}))
+            sfk.iterate(c, W)
+            sfk.destroy(c)
+        c = sfk.init(A, None, b, sfk.params(method, **kw))
+        dt, done = _timed_iterate(sfk, torch, c, K)
+        x = sfk.solution(c).cpu().numpy()
+        stats = sfk.tau_stats(c) if tau.startswith("lowrank") else None
+        sfk.destroy(c)
+        c = sfk.init(A, None, b, sfk.params(method, **kw))
+        sfk.set_timing(c, True)
+        sfk.iterate(c, K)
+        times = sfk.stage_times(c)
+        sfk.destroy(c)
+        res = {"iterations": done, "ms_total": dt * 1e3, "iterations_per_s": done / dt,
+               "rel_error": float(np.linalg.norm(x - xt) / np.linalg.norm(xt)),
+               "stage_ms_total": {k: v[0] for k, v in times.items() if v[1]}}
+        if stats is not None:
+            res["tau_last_call"] = stats
+        out["methods"][label] = res
+        log(f"bench: deblur512 {label}: {done} its in {dt * 1e3:.1f} ms, "
+            f"error {res['rel_error']:.4f}")
+    return out
+
+
 def hetero_bench(count: int = 32, maxit: int = 100, order: str = "natural"):
     """Independent instances of uneven sizes in one context vs a plain loop."""
     import numpy as np
@@ -473,6 +541,8 @@ def main():
     ap.add_argument("--no-full-run", action="store_true")
     ap.add_argument("--adjoint", type=int, default=1, help="time the derivative workload (0/1)")
     ap.add_argument("--rhs", type=int, default=32)
+    ap.add_argument("--deblur", type=int, default=1,
+                    help="time the deblurring workload with the low-rank operators (0/1)")
     ap.add_argument("--order", default="tiles4", choices=["natural", "tiles4", "tiles8"],
                     help="order of the unknowns passed to the library: the image's row-major "
                          "pixels, or 4x4 / 8x8 pixel tiles (results are in row-major order "
@@ -563,6 +633,9 @@ def main():
         out["batched_multi_rhs"] = mr
         out["batched_plain_speedup"] = mr["speedup"]
         log(f"bench: shared operator speedup {mr['speedup']:.2f}x")
+    if args.extras == "all" and args.deblur:
+        log("bench: deblurring workload with the low-rank operators")
+        out["deblur512"] = deblur_bench()
     if args.batched in ("all", "hetero"):
         log("bench: heterogeneous batch of 32 instances, and plain loop")
         hb = hetero_bench(order=args.order)

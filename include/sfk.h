@@ -68,8 +68,27 @@ typedef enum { SFK_SK_SPARSE_SIGN = 0, SFK_SK_SRHT = 1, SFK_SK_IDENTITY = 2 } sf
 
 /* Flexible operator tau (paper eq. (modbasis); the l1 reweighting follows the
  * IRLS interpretation of Sec. 1.2): IDENTITY, or
- * REWEIGHT_L1: z_k = (x_{k-1}^2 + eps^2)^(1/4) * p_k elementwise, x_0 = 0. */
-typedef enum { SFK_TAU_IDENTITY = 0, SFK_TAU_REWEIGHT_L1 = 1 } sfk_tau;
+ * REWEIGHT_L1: z_k = (x_{k-1}^2 + eps^2)^(1/4) * p_k elementwise, x_0 = 0;
+ * LOWRANK: z_k = tau_r(p_k), the rank-r truncated SVD of p_k viewed as an
+ *   lr_rows x (n / lr_rows) image in row-major order (eq. (def:lowr-trc), the
+ *   operator of the deblurring experiments of Sec. 3.1).  Computed by
+ *   randomized subspace iteration with l = r + p vectors (re-based by a
+ *   shifted Cholesky QR after every product, orthonormalised by two more
+ *   passes before each Rayleigh-Ritz step) and a Rayleigh-Ritz step,
+ *   iterated until the Ritz residuals ||C v_i - theta_i x_i||, i < r, are at
+ *   most lr_tol * theta_1 (theta_i the squared singular values): the full
+ *   SVD's truncation to within that residual over the gap at r;
+ * LOWRANK_RND: the randomized SVD (Halko, Martinsson, Tropp, Algorithms 4.4
+ *   and 5.1) truncated to rank r, the paper's "-RND" solvers: lr_q power
+ *   iterations, then the SVD of B = Q^T C.  The Gaussian test matrix of basis
+ *   vector k (nc x l, column-major, entry e = j nc + i) is normal e mod 4 of
+ *   the Philox4x64-10 block (k, e >> 2, 0, 0) keyed (seed, 2 + (instance << 32)),
+ *   by Box-Muller: u1 = ((w_even >> 11) + 1/2) 2^-53, u2 = (w_odd >> 11) 2^-53,
+ *   sqrt(-2 ln u1) (cos 2 pi u2, sin 2 pi u2) from words (w0, w1) and (w2, w3).
+ * Both low-rank operators: single-instance contexts, no perm, driver MULTI
+ * (LOWRANK reads its convergence flag on the host every 4 power iterations). */
+typedef enum { SFK_TAU_IDENTITY = 0, SFK_TAU_REWEIGHT_L1 = 1, SFK_TAU_LOWRANK = 2,
+               SFK_TAU_LOWRANK_RND = 3 } sfk_tau;
 
 /* Iteration driver.  MULTI: every stage kernel of every iteration is launched
  * on the context's stream (and a second stream for the sketch and the small
@@ -187,11 +206,20 @@ typedef struct {
                           touch fewer cache lines.  With perm, rows of A must have at
                           most 4096 entries (SFK_EINVAL otherwise).  Must stay valid
                           until sfk_init returns. */
+  /* low-rank operators (tau LOWRANK / LOWRANK_RND) */
+  int32_t lr_rows;     /* image rows nr; n must be a multiple (nc = n / nr) */
+  int32_t lr_rank;     /* r, 1 <= r < min(nr, nc) */
+  int32_t lr_over;     /* oversampling p, l = min(r + p, nr, nc) <= 64; 0 = automatic:
+                          LOWRANK l = min(max(2 r, r + 16), 64), LOWRANK_RND p = 10 */
+  int32_t lr_q;        /* LOWRANK_RND power iterations, 0..16 (default 1) */
+  int32_t lr_maxit;    /* LOWRANK power-iteration limit per call; 0 = 300 */
+  int32_t lr_reserved;
+  double lr_tol;       /* LOWRANK Ritz-residual tolerance relative to theta_1; 0 = 1e-13 */
 } sfk_params;
 
 /* Fills *p with defaults: sFLSQR, ell = 2, maxit = 50, sparse-sign s = 101, zeta = 8,
  * seed 0, tau identity, eps 1e-3, eta 1.01, no discrepancy stop, tol 0, AUTO,
- * vw -2 (automatic SpMV kernel). */
+ * vw -2 (automatic SpMV kernel), lr_q = 1, the other lr_ fields 0. */
 void sfk_params_default(sfk_params *p);
 
 /* Host-only check of dimensions and parameters (no device access).  A and B
@@ -226,6 +254,20 @@ sfk_status sfk_init_beam(sfk_ctx **out, const sfk_beam *geo, const double *b, co
  * context's operators and SpMV kernels (device vectors; contexts without perm,
  * single instance).  Synchronous. */
 sfk_status sfk_apply(sfk_ctx *ctx, int32_t op, const double *x, double *y);
+
+/* y = tau(x): the context's low-rank operator (tau LOWRANK or LOWRANK_RND,
+ * eq. (def:lowr-trc)) applied to the n-vector x (device), into y (device; may
+ * not alias x), as the solver applies it to basis vector `call` (>= 1: the
+ * randomized variant's test matrix is that of call).  Uses the context's
+ * low-rank scratch: do not overlap with sfk_iterate.  Synchronous.
+ * SFK_EINVAL for other tau. */
+sfk_status sfk_tau_apply(sfk_ctx *ctx, const double *x, double *y, int32_t call);
+
+/* Counters of the low-rank operator's last application: out_host[0] power
+ * iterations, out_host[1] 1 if its residual test passed (LOWRANK), out_host[2]
+ * applications so far that reached lr_maxit unconverged; *resmax_host the last
+ * max_i ||C v_i - theta_i x_i|| / theta_1 (LOWRANK).  SFK_EINVAL for other tau. */
+sfk_status sfk_tau_stats(sfk_ctx *ctx, int32_t *out_host, double *resmax_host);
 
 /* Runs up to k more iterations (Algorithm 1 / 2 loop body), stopping early on
  * the stop test or a breakdown.  Synchronous: returns after the device
@@ -409,7 +451,8 @@ typedef enum {
   SFK_STAGE_LS = 3,        /* Householder update of the sketched least squares    */
   SFK_STAGE_SPMV_B = 4,    /* z = B w_{k+1} with the window dot products          */
   SFK_STAGE_P_UPDATE = 5,  /* truncated Gram-Schmidt of z, tau, ||p||             */
-  SFK_NUM_STAGES = 6
+  SFK_STAGE_TAU = 6,       /* the low-rank operators' z = tau_r(p) (LOWRANK*)    */
+  SFK_NUM_STAGES = 7
 } sfk_stage;
 
 /* Enables (on != 0) or disables timing of every stage kernel with HIP events

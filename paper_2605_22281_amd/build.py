@@ -11,7 +11,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libsfk.so")
-SOURCES = ["sfk_kernels.hip", "sfk_multi.hip", "sfk_full.hip", "sfk_adjoint.hip", "sfk_capi.hip"]
+SOURCES = ["sfk_kernels.hip", "sfk_multi.hip", "sfk_full.hip", "sfk_adjoint.hip", "sfk_lowrank.hip", "sfk_capi.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",

@@ -21,6 +21,7 @@
 #include "sfk_dev.h"
 #include "sfk_units.h"
 #include "sfk_adjoint_layout.h"
+#include "sfk_lowrank.h"
 
 namespace sfk {
 void launch_stage_A(const Launch &L, int k, hipStream_t st);
@@ -105,6 +106,8 @@ struct Inst {
   const double *user_ava = nullptr;  // run on a renumbered copy (true residual)
   int k_done = 0, stopped = 0, breakdown = 0, halted = 0;
   double rhsnorm = 0.0;
+  bool lowrank = false;           // tau LOWRANK / LOWRANK_RND: z = tau_r(p) stage
+  LrBufs lr{};
 };
 
 struct sfk_ctx {
@@ -139,7 +142,7 @@ struct sfk_ctx {
   int resid = 0;                    // per-iteration true residual (single instance)
   bool full = false;                // FLSQR / FLSMR (full orthogonalisation)
   int tape = 0;                     // derivative tape: checkpoint interval (0: none)
-  int open_stage[SFK_NUM_STAGES] = {-1, -1, -1, -1, -1, -1};
+  int open_stage[SFK_NUM_STAGES] = {-1, -1, -1, -1, -1, -1, -1};
   size_t lib_bytes = 0;             // device memory allocated besides the workspaces
   int pending_side[2] = {-1, -1};   // iterations whose sketch/LS wait for the next flush point
   bool multi = false;               // right-hand sides sharing A and B (stages via grp)
@@ -272,6 +275,18 @@ static void defer_side(sfk_ctx *c, int k) {
   else c->pending_side[1] = k;
 }
 
+// z~_{k+1} = tau_r(p~_{k+1}) of the low-rank operators, after D(k) (or after the
+// full path's p_{k+1}); k = 0 is the initial basis vector.
+static void enqueue_tau(sfk_ctx *c, int k) {
+  Inst &I = c->inst[0];
+  const Dev &D = I.D;
+  const double *pin = c->full ? D.Pf + (size_t)k * D.n
+                              : D.P + (size_t)((k + 1) % (D.ell + 1)) * D.n;
+  const int t = stage_begin(c, SFK_STAGE_TAU, c->stream);
+  lr_apply(I.lr, D.sc, D.maxit, c->full ? 1 : 0, k, pin, D.Z + (size_t)k * D.n, c->stream);
+  stage_end(c, t, c->stream);
+}
+
 // One iteration.  The sketch of iteration k reads raw product slot
 // k % kRawSlots, rewritten by iteration k + kRawSlots; the main stream waits
 // for the side stream once every four iterations (before A(k), k = 0 mod 4:
@@ -314,6 +329,7 @@ static void enqueue_iteration(sfk_ctx *c, int k) {
   t = stage_begin(c, SFK_STAGE_P_UPDATE, st);
   run_stage(c, kStageD, k, st);
   stage_end(c, t, st);
+  if (c->inst[0].lowrank) enqueue_tau(c, k);
 }
 
 // Stage timing of the full-orthogonalisation iteration (begin = 1 / 0).
@@ -326,6 +342,7 @@ static void full_mark(void *ctx, int stage, int begin) {
 static void enqueue_full_iteration(sfk_ctx *c, int k) {
   const Dev &D = c->inst[0].D;
   launch_full_iteration(D, k, D.vwA, D.vwB, c->stream, c->timing ? full_mark : nullptr, c);
+  if (c->inst[0].lowrank) enqueue_tau(c, k);
   if (c->resid) launch_true_iter(D, k, c->stream);
 }
 
@@ -420,6 +437,48 @@ extern "C" void sfk_params_default(sfk_params *p) {
   p->tol = 0.0;
   p->driver = SFK_DRIVER_AUTO;
   p->vw = -2;
+  p->lr_q = 1;
+}
+
+static bool is_lowrank(const sfk_params *p) {
+  return p->tau == SFK_TAU_LOWRANK || p->tau == SFK_TAU_LOWRANK_RND;
+}
+
+// test vectors l of the low-rank operators (0 when the sizes are invalid)
+static int lr_block(const sfk_params *p, int64_t n) {
+  if (p->lr_rows < 1 || n % p->lr_rows) return 0;
+  const int64_t nr = p->lr_rows, nc = n / nr, mn = std::min(nr, nc);
+  int64_t l;
+  if (p->lr_over > 0) l = (int64_t)p->lr_rank + p->lr_over;
+  else if (p->tau == SFK_TAU_LOWRANK)
+    l = std::min<int64_t>(std::max<int64_t>(2 * (int64_t)p->lr_rank, (int64_t)p->lr_rank + 16), kLrMaxL);
+  else l = (int64_t)p->lr_rank + 10;
+  return (int)std::min(l, mn);
+}
+
+// checks of the low-rank operators' parameters (n unknowns)
+static sfk_status validate_lowrank(sfk_ctx *c, const sfk_params *p, int64_t n, bool multi) {
+  if (multi) return fail(c, SFK_EINVAL, "the low-rank tau runs in single-instance contexts");
+  if (p->perm) return fail(c, SFK_EINVAL, "the low-rank tau needs the image order (no perm)");
+  if (p->driver == SFK_DRIVER_GRAPH)
+    return fail(c, SFK_EINVAL, "the low-rank tau runs with the MULTI driver");
+  if (p->tape != 0) return fail(c, SFK_EINVAL, "no derivative tape with the low-rank tau");
+  if (p->lr_rows < 1 || n % p->lr_rows != 0)
+    return fail(c, SFK_EINVAL, "lr_rows %d must divide n = %lld", p->lr_rows, (long long)n);
+  const int64_t nr = p->lr_rows, nc = n / nr, mn = std::min(nr, nc);
+  if (p->lr_rank < 1 || p->lr_rank >= mn)
+    return fail(c, SFK_EINVAL, "lr_rank %d not in [1, min(nr, nc) = %lld) (rank >= min(nr, nc) "
+                "is the identity)", p->lr_rank, (long long)mn);
+  if (p->lr_over < 0) return fail(c, SFK_EINVAL, "lr_over must be >= 0");
+  const int l = lr_block(p, n);
+  if (l > kLrMaxL || l < p->lr_rank)
+    return fail(c, SFK_EINVAL, "lr_rank + lr_over = %d test vectors exceed %d", l, kLrMaxL);
+  if (p->lr_q < 0 || p->lr_q > 16) return fail(c, SFK_EINVAL, "lr_q %d not in [0, 16]", p->lr_q);
+  if (p->lr_maxit < 0 || p->lr_maxit > 100000)
+    return fail(c, SFK_EINVAL, "lr_maxit %d not in [0, 100000]", p->lr_maxit);
+  if (!(p->lr_tol >= 0.0) || !std::isfinite(p->lr_tol))
+    return fail(c, SFK_EINVAL, "lr_tol must be finite >= 0");
+  return SFK_OK;
 }
 
 static int64_t next_pow2(int64_t d) {
@@ -450,10 +509,14 @@ static sfk_status validate(sfk_ctx *c, const sfk_csr *A, const sfk_csr *B, const
     if (multi) return fail(c, SFK_EINVAL, "FLSQR / FLSMR run in single-instance contexts");
     if (p->maxit < 1 || p->maxit > 1024)
       return fail(c, SFK_EINVAL, "maxit %d not in [1, 1024] for FLSQR / FLSMR", p->maxit);
-    if (p->tau != SFK_TAU_IDENTITY && p->tau != SFK_TAU_REWEIGHT_L1)
+    if (p->tau < SFK_TAU_IDENTITY || p->tau > SFK_TAU_LOWRANK_RND)
       return fail(c, SFK_EINVAL, "unknown tau %d", p->tau);
     if (p->tau == SFK_TAU_REWEIGHT_L1 && !(p->eps > 0.0 && std::isfinite(p->eps)))
       return fail(c, SFK_EINVAL, "reweighting needs finite eps > 0");
+    if (is_lowrank(p)) {
+      sfk_status s = validate_lowrank(c, p, n, multi);
+      if (s != SFK_OK) return s;
+    }
     if (!(p->eta >= 0.0) || !std::isfinite(p->eta)) return fail(c, SFK_EINVAL, "eta must be finite >= 0");
     if (!(p->noise_norm >= 0.0) || !std::isfinite(p->noise_norm))
       return fail(c, SFK_EINVAL, "noise_norm must be finite >= 0");
@@ -491,10 +554,14 @@ static sfk_status validate(sfk_ctx *c, const sfk_csr *A, const sfk_csr *B, const
     default:
       return fail(c, SFK_EINVAL, "unknown sketch kind %d", p->sketch);
   }
-  if (p->tau != SFK_TAU_IDENTITY && p->tau != SFK_TAU_REWEIGHT_L1)
+  if (p->tau < SFK_TAU_IDENTITY || p->tau > SFK_TAU_LOWRANK_RND)
     return fail(c, SFK_EINVAL, "unknown tau %d", p->tau);
   if (p->tau == SFK_TAU_REWEIGHT_L1 && !(p->eps > 0.0 && std::isfinite(p->eps)))
     return fail(c, SFK_EINVAL, "reweighting needs finite eps > 0");
+  if (is_lowrank(p)) {
+    sfk_status s = validate_lowrank(c, p, n, multi);
+    if (s != SFK_OK) return s;
+  }
   if (!(p->eta >= 0.0) || !std::isfinite(p->eta)) return fail(c, SFK_EINVAL, "eta must be finite >= 0");
   if (!(p->noise_norm >= 0.0) || !std::isfinite(p->noise_norm))
     return fail(c, SFK_EINVAL, "noise_norm must be finite >= 0");
@@ -551,7 +618,7 @@ struct Plan {
   size_t o_skcode, o_skent, o_skrp, o_chunk, o_srows, o_sd, o_spart, o_SK, o_skrhs;
   size_t o_V, o_tauv, o_R, o_c, o_y, o_ytmp, o_rtrue, o_xres;
   size_t o_Wf, o_Pf, o_fscr, o_gc, o_gs, o_gR, o_gg, o_ck, o_brl, o_mscr;
-  size_t o_brp, o_bci, o_bva, o_cursor;
+  size_t o_brp, o_bci, o_bva, o_cursor, o_lr;
   size_t total;
 };
 
@@ -615,7 +682,7 @@ static Plan make_plan(const sfk_csr *A, const sfk_csr *B, const sfk_params *p, i
   P.o_rho = L_.take<double>(mi);
   const int64_t vm = member ? 0 : 1;
   P.o_W = L_.take<double>(vm * (ell + 2) * m + 1);
-  P.o_P = L_.take<double>(p->tau == SFK_TAU_REWEIGHT_L1 ? vm * (ell + 1) * n + 1 : 1);
+  P.o_P = L_.take<double>(p->tau != SFK_TAU_IDENTITY ? vm * (ell + 1) * n + 1 : 1);
   P.o_Z = L_.take<double>(vm * (mi + 1) * n + 1);      // z~_1 .. z~_{maxit+1}
   P.o_wraw = L_.take<double>(vm * kRawSlots * m + 1);
   P.o_zraw = L_.take<double>(vm * kRawSlots * std::max<int64_t>(n, (P.N + 1) / 2 + 1) + 1);
@@ -652,6 +719,8 @@ static Plan make_plan(const sfk_csr *A, const sfk_csr *B, const sfk_params *p, i
   P.o_ck = L_.take<double>(adjoint_checkpoint_doubles((int)mi, p->tape, (int)ell, (int)m));
   P.o_brl = L_.take<double>(beam ? 2 * m : 1);
   P.o_mscr = L_.take<double>(beam ? m : 1);
+  P.o_lr = L_.take<double>(is_lowrank(p) ? lr_doubles(p->lr_rows, (int)(n / p->lr_rows), p->lr_rank,
+                                                      lr_block(p, n)) : 1);
   if (P.transpose && !member) {
     P.o_brp = L_.take<int>(n + 1);
     P.o_bci = L_.take<int>(P.nnzB);
@@ -960,6 +1029,22 @@ static sfk_status setup_instance(sfk_ctx *c, Inst &I, const sfk_csr *A, const sf
   I.d_scalar = at<double>(w, P.o_scalar);
   I.d_ytmp = at<double>(w, P.o_ytmp);
   I.chunk_scratch = at<int>(w, P.o_chunk);
+  if (is_lowrank(&p)) {
+    LrBufs &L = I.lr;
+    L.nr = p.lr_rows;
+    L.nc = (int)(P.n / p.lr_rows);
+    L.r = p.lr_rank;
+    L.l = lr_block(&p, P.n);
+    L.rnd = p.tau == SFK_TAU_LOWRANK_RND ? 1 : 0;
+    L.q = p.lr_q;
+    L.maxit = p.lr_maxit > 0 ? p.lr_maxit : 300;
+    L.check = 4;
+    L.tol = p.lr_tol > 0.0 ? p.lr_tol : 1e-13;
+    L.seed = p.seed;
+    L.instance = p.instance;
+    lr_carve(L, at<double>(w, P.o_lr));
+    I.lowrank = true;
+  }
 
   if (grp) {
     D.skperm = p.method == SFK_SFLSMR ? c->gperm : nullptr;
@@ -1208,6 +1293,7 @@ static sfk_status init_common(sfk_ctx *c) {
     for (auto &I : c->inst) launch_init_rhs(I.D, st);
     run_stage(c, kStageD, 0, st);
   }
+  if (c->inst[0].lowrank) enqueue_tau(c, 0);
   HIPCHK(c, hipGetLastError());
   s = read_scal(c);
   if (s != SFK_OK) return s;
@@ -1343,6 +1429,8 @@ extern "C" sfk_status sfk_init_batch(sfk_ctx **out, int32_t nb, const sfk_csr *A
       s = fail(nullptr, SFK_EINVAL, "resid must be 0 in a batch (single-instance contexts only)");
     if (s == SFK_OK && is_full(p[i]))
       s = fail(nullptr, SFK_EINVAL, "FLSQR / FLSMR run in single-instance contexts");
+    if (s == SFK_OK && is_lowrank(&p[i]) && nb > 1)
+      s = fail(nullptr, SFK_EINVAL, "the low-rank tau runs in single-instance contexts");
     if (s != SFK_OK) {
       prefix_err(g_err, "instance", i);
       return s;
@@ -2052,7 +2140,7 @@ extern "C" sfk_status sfk_basis_vector(sfk_ctx *c, int32_t i, int32_t kind, int3
   const int k = I->k_done;
   if (I->halted) return fail(c, SFK_ESTATE, "basis vectors are available while the run is live");
   const int lo = c->full ? 1 : kind == 0 ? std::max(1, k + 1 - (D.ell + 1))
-               : (kind == 1 && D.tau == SFK_TAU_REWEIGHT_L1) ? std::max(1, k + 1 - D.ell) : 1;
+               : (kind == 1 && D.tau != SFK_TAU_IDENTITY) ? std::max(1, k + 1 - D.ell) : 1;
   // the scale of p_{k+1} (and z_{k+1}) is formed by the next iteration's first stage
   const int hi = (kind == 0 || c->full) ? k + 1 : k;
   if (j < lo || j > hi)
@@ -2069,8 +2157,8 @@ extern "C" sfk_status sfk_basis_vector(sfk_ctx *c, int32_t i, int32_t kind, int3
     scale = D.sigw + j;
     len = D.m;
   } else {
-    src = (kind == 2 || D.tau != SFK_TAU_REWEIGHT_L1) ? D.Z + (size_t)(j - 1) * D.n * D.vs
-                                                      : D.P + (size_t)(j % (D.ell + 1)) * D.n * D.vs;
+    src = (kind == 2 || D.tau == SFK_TAU_IDENTITY) ? D.Z + (size_t)(j - 1) * D.n * D.vs
+                                                   : D.P + (size_t)(j % (D.ell + 1)) * D.n * D.vs;
     scale = D.sigp + j;
     len = D.n;
     pinv = D.pinv;
@@ -2128,6 +2216,33 @@ extern "C" sfk_status sfk_apply(sfk_ctx *c, int32_t op, const double *x, double 
   launch_spmv_core(D, op == 0, op == 0 ? D.vwA : D.vwB, x, y, c->stream);
   HIPCHK(c, hipGetLastError());
   HIPCHK(c, hipStreamSynchronize(c->stream));
+  return SFK_OK;
+}
+
+extern "C" sfk_status sfk_tau_apply(sfk_ctx *c, const double *x, double *y, int32_t call) {
+  if (!c) return fail(nullptr, SFK_EINVAL, "NULL context");
+  if (c->inst.size() != 1 || !c->inst[0].lowrank)
+    return fail(c, SFK_EINVAL, "sfk_tau_apply needs a single-instance context with a low-rank tau");
+  if (!x || !y || x == y) return fail(c, SFK_EINVAL, "x and y must be distinct device vectors");
+  if (call < 1) return fail(c, SFK_EINVAL, "call must be >= 1");
+  Inst &I = c->inst[0];
+  HIPCHK(c, lr_apply(I.lr, I.D.sc, I.D.maxit, 2, call - 1, x, y, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  return SFK_OK;
+}
+
+extern "C" sfk_status sfk_tau_stats(sfk_ctx *c, int32_t *out_host, double *resmax_host) {
+  if (!c) return fail(nullptr, SFK_EINVAL, "NULL context");
+  if (c->inst.size() != 1 || !c->inst[0].lowrank)
+    return fail(c, SFK_EINVAL, "sfk_tau_stats needs a single-instance context with a low-rank tau");
+  const LrBufs &L = c->inst[0].lr;
+  int st[4] = {0, 0, 0, 0};
+  double rm = 0.0;
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  HIPCHK(c, hipMemcpy(st, L.stat, sizeof st, hipMemcpyDeviceToHost));
+  HIPCHK(c, hipMemcpy(&rm, L.rb, sizeof rm, hipMemcpyDeviceToHost));
+  if (out_host) { out_host[0] = st[2]; out_host[1] = st[1]; out_host[2] = st[3]; }
+  if (resmax_host) *resmax_host = rm;
   return SFK_OK;
 }
 

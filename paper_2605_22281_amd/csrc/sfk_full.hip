@@ -220,6 +220,7 @@ __global__ void __launch_bounds__(64) k_f_backsub(Dev D, int jj, const double *g
 // z_{k+1} = tau(p_{k+1}) into Z column k: identity, or the l1 reweighting with
 // x_k = Z_k y_k assembled here (also kept in D.x)
 __global__ void __launch_bounds__(kFullWG) k_f_tau(Dev D, int k, const double *Pf) {
+  if (D.tau >= 2) return;   // the low-rank operators run as a stage of their own
   Scal *sc = D.sc;
   if (k > 0 && (ld_flag(&sc->halt) != 0 || k > ld_flag(&sc->klimit) || ld_flag(&sc->k_done) != k))
     return;

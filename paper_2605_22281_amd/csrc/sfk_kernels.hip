@@ -29,23 +29,6 @@
 namespace sfk {
 
 // ---------------------------------------------------------------------------
-// Philox4x64-10 (Salmon et al., SC'11), from the published definition.
-// ---------------------------------------------------------------------------
-__device__ __forceinline__ void philox4x64_10(uint64_t c[4], uint64_t k0, uint64_t k1) {
-  const uint64_t M0 = 0xD2E7470EE14C6C93ull, M1 = 0xCA5A826395121157ull;
-  const uint64_t W0 = 0x9E3779B97F4A7C15ull, W1 = 0xBB67AE8584CAA73Bull;
-#pragma unroll
-  for (int r = 0; r < 10; ++r) {
-    if (r) { k0 += W0; k1 += W1; }
-    const uint64_t hi0 = __umul64hi(M0, c[0]), lo0 = M0 * c[0];
-    const uint64_t hi1 = __umul64hi(M1, c[2]), lo1 = M1 * c[2];
-    const uint64_t n0 = hi1 ^ c[1] ^ k0;
-    const uint64_t n2 = hi0 ^ c[3] ^ k1;
-    c[0] = n0; c[1] = lo1; c[2] = n2; c[3] = lo0;
-  }
-}
-
-// ---------------------------------------------------------------------------
 // CSR-stream product of one workgroup's rows [r0, r1) (whole rows, contiguous
 // nonzeros).  The nonzeros are streamed in chunks of kChunk: every thread loads
 // kPerThread (value, column) pairs at once, gathers x, and leaves the products
@@ -453,7 +436,7 @@ __global__ void __launch_bounds__(kWG) k_wupdate(const Dev *__restrict__ devs,
 
 // ---------------------------------------------------------------------------
 // D(k): consumes C(k) (dots, ||z||) -> t_j,k+1; p~_{k+1} = z - sum t_j p_j;
-// z~_{k+1} = tau(p~_{k+1}).  k = 0 is the initial step (empty window, x_0 = 0).
+// z~_{k+1} = tau(p~_{k+1}) for the identity and the reweighting.  k = 0 is the initial step (empty window, x_0 = 0).
 // The reweighting assembles x_k = Z_k y_k on the fly (y_k from LS(k)).
 // ---------------------------------------------------------------------------
 __global__ void __launch_bounds__(kWG) k_pupdate(const Dev *__restrict__ devs,
@@ -484,7 +467,9 @@ __global__ void __launch_bounds__(kWG) k_pupdate(const Dev *__restrict__ devs,
   }
   const gptr<const double> zr = gmem(zrawk(D, k));
   const gptr<double> zout = gmem(D.Z + (size_t)k * D.n);
-  const gptr<double> pout = rew ? gmem(D.P + (size_t)pslot(D, k + 1) * D.n) : zout;
+  // tau = I: p~ is stored as the basis column itself; otherwise in the P ring
+  // (the low-rank operators then write z~ in a stage of their own)
+  const gptr<double> pout = D.tau != 0 ? gmem(D.P + (size_t)pslot(D, k + 1) * D.n) : zout;
   const gptr<const double> Zg = gmem(D.Z);
   const gptr<double> xg = gmem(D.x);
   const double eps2 = D.eps * D.eps;

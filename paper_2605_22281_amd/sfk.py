@@ -23,14 +23,15 @@ LIB_PATH = os.path.join(_HERE, "libsfk.so")
 OK, EINVAL, ENOMEM, EDEVICE, BREAKDOWN, ESTATE = range(6)
 SFLSQR, SFLSMR, FLSQR, FLSMR = 0, 1, 2, 3
 SK_SPARSE_SIGN, SK_SRHT, SK_IDENTITY = 0, 1, 2
-TAU_IDENTITY, TAU_REWEIGHT_L1 = 0, 1
+TAU_IDENTITY, TAU_REWEIGHT_L1, TAU_LOWRANK, TAU_LOWRANK_RND = 0, 1, 2, 3
 DRIVER_AUTO, DRIVER_MULTI, DRIVER_GRAPH = 0, 1, 2
 RES_SKETCHED, RES_TRUE_RECURRENCE, RES_TRUE_EXPLICIT = 0, 1, 2
 
 _METHODS = {"sflsqr": SFLSQR, "sflsmr": SFLSMR, "flsqr": FLSQR, "flsmr": FLSMR}
 _SKETCHES = {"sparse_sign": SK_SPARSE_SIGN, "countsketch": SK_SPARSE_SIGN, "srht": SK_SRHT,
              "identity": SK_IDENTITY}
-_TAUS = {"identity": TAU_IDENTITY, "reweight_l1": TAU_REWEIGHT_L1}
+_TAUS = {"identity": TAU_IDENTITY, "reweight_l1": TAU_REWEIGHT_L1, "lowrank": TAU_LOWRANK,
+         "lowrank_rnd": TAU_LOWRANK_RND}
 _DRIVERS = {"auto": DRIVER_AUTO, "multi": DRIVER_MULTI, "graph": DRIVER_GRAPH}
 _RES = {"sketched": RES_SKETCHED, "true_recurrence": RES_TRUE_RECURRENCE,
         "true_explicit": RES_TRUE_EXPLICIT}
@@ -56,7 +57,11 @@ class Params(ctypes.Structure):
                 ("vw_b", ctypes.c_int32), ("vw_split", ctypes.c_int32),
                 ("wg_per_cu", ctypes.c_int32), ("resid", ctypes.c_int32),
                 ("copies", ctypes.c_int32), ("tape", ctypes.c_int32),
-                ("perm", ctypes.c_void_p)]
+                ("perm", ctypes.c_void_p),
+                ("lr_rows", ctypes.c_int32), ("lr_rank", ctypes.c_int32),
+                ("lr_over", ctypes.c_int32), ("lr_q", ctypes.c_int32),
+                ("lr_maxit", ctypes.c_int32), ("lr_reserved", ctypes.c_int32),
+                ("lr_tol", ctypes.c_double)]
 
 
 class Beam(ctypes.Structure):
@@ -93,6 +98,8 @@ def lib() -> ctypes.CDLL:
         "sfk_adjoint": (I32, [P, P, P, PD]),
         "sfk_init_beam": (I32, [ctypes.POINTER(P), ctypes.POINTER(Beam), P, PPAR, P, ctypes.c_size_t, P]),
         "sfk_apply": (I32, [P, I32, P, P]),
+        "sfk_tau_apply": (I32, [P, P, P, I32]),
+        "sfk_tau_stats": (I32, [P, PI32, PD]),
         "sfk_solve_noalloc": (I32, [PCSR, PCSR, P, PPAR, I32, P, PD, PI32, PI32, P]),
         "sfk_memory": (I32, [P, ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(ctypes.c_size_t)]),
         "sfk_true_residual": (I32, [P, PD]),
@@ -130,7 +137,8 @@ def exported_symbols() -> list[str]:
             "sfk_init_batch", "sfk_batch_size", "sfk_instance_status", "sfk_instance_solution",
             "sfk_instance_residual_norms", "sfk_instance_true_residual", "sfk_init_multi",
             "sfk_instance_solution_at", "sfk_spmv_variant", "sfk_memory", "sfk_basis_vector",
-            "sfk_solve_noalloc", "sfk_adjoint", "sfk_init_beam", "sfk_apply"]
+            "sfk_solve_noalloc", "sfk_adjoint", "sfk_init_beam", "sfk_apply", "sfk_tau_apply",
+            "sfk_tau_stats"]
 
 
 def _check(status: int, ctx=None):
@@ -142,7 +150,8 @@ def _check(status: int, ctx=None):
 def params(method="sflsqr", *, ell=2, maxit=50, sketch="sparse_sign", s=101, zeta=8, seed=0,
            instance=0, tau="identity", eps=1e-3, eta=1.01, noise_norm=0.0, tol=0.0,
            driver="auto", vw=-2, vw_b=None, wg_per_cu=0, resid=0, copies=0, tape=0,
-           perm=None) -> Params:
+           perm=None, lr_rows=0, lr_rank=0, lr_over=0, lr_q=1, lr_maxit=0,
+           lr_tol=0.0) -> Params:
     """perm: optional order of the unknowns, a torch.int32 device tensor of n
     distinct values in [0, n) (unknown j stored at position perm[j] inside the
     library; results come back in the caller's order).
@@ -154,7 +163,11 @@ def params(method="sflsqr", *, ell=2, maxit=50, sketch="sparse_sign", s=101, zet
     vw_b: SpMV kernel of B (coded as vw) when it differs from A's (sets
     vw_split); resid: 0, 1 (record ||b - A x_k|| every iteration) or 2 (record
     it and stop on it); copies: 1 forbids device copies of the operators
-    beyond the workspace."""
+    beyond the workspace.
+    tau "lowrank" / "lowrank_rnd": rank-lr_rank truncation of each basis vector
+    viewed as an lr_rows x (n / lr_rows) image (truncated SVD to a Ritz-residual
+    tolerance lr_tol, or the randomized SVD with lr_q power iterations), with
+    l = lr_rank + lr_over test vectors (0: automatic)."""
     p = Params()
     lib().sfk_params_default(ctypes.byref(p))
     p.method = _METHODS[method] if isinstance(method, str) else int(method)
@@ -170,6 +183,8 @@ def params(method="sflsqr", *, ell=2, maxit=50, sketch="sparse_sign", s=101, zet
     if vw_b is not None:
         p.vw_b, p.vw_split = int(vw_b), 1
     p.resid, p.copies, p.tape = int(resid), int(copies), int(tape)
+    p.lr_rows, p.lr_rank, p.lr_over = int(lr_rows), int(lr_rank), int(lr_over)
+    p.lr_q, p.lr_maxit, p.lr_tol = int(lr_q), int(lr_maxit), float(lr_tol)
     if perm is not None:
         import torch
         if perm.dtype != torch.int32 or not perm.is_cuda or not perm.is_contiguous():
@@ -345,6 +360,26 @@ def apply(ctx: Context, op: str, x):
     return y
 
 
+def tau_apply(ctx: Context, x, call: int = 1):
+    """sfk_tau_apply: the context's low-rank operator applied to x (as to basis
+    vector `call`)."""
+    import torch
+    xc = x.contiguous()
+    y = torch.empty_like(xc)
+    _check(lib().sfk_tau_apply(ctx.handle, xc.data_ptr(), y.data_ptr(), int(call)), ctx.handle)
+    return y
+
+
+def tau_stats(ctx: Context) -> dict:
+    """sfk_tau_stats: power iterations and residual test of the last application,
+    unconverged applications so far, last relative Ritz residual."""
+    out = (ctypes.c_int32 * 3)()
+    rm = ctypes.c_double()
+    _check(lib().sfk_tau_stats(ctx.handle, out, ctypes.byref(rm)), ctx.handle)
+    return {"iterations": out[0], "converged": bool(out[1]), "unconverged_calls": out[2],
+            "resmax": rm.value}
+
+
 def iterate(ctx: Context, k: int) -> tuple[int, bool, int]:
     """sfk_iterate: returns (iterations done, stopped, status); BREAKDOWN is not raised."""
     done, stopped = ctypes.c_int32(), ctypes.c_int32()
@@ -439,7 +474,7 @@ def coefficients(ctx: Context, k: int) -> tuple[np.ndarray, np.ndarray]:
     return H.T.copy(), T.T.copy()
 
 
-STAGES = ("spmv_A", "w_update", "sketch", "ls", "spmv_B", "p_update")
+STAGES = ("spmv_A", "w_update", "sketch", "ls", "spmv_B", "p_update", "tau")
 
 
 def set_timing(ctx: Context, on: bool = True):

@@ -24,9 +24,10 @@ def rel(a, b):
 
 def gpu_run(P, method, kind, s, maxit, *, ell=2, tau="identity", eps=1e-3, zeta=8, seed=3001,
             tol=0.0, noise=0.0, eta=1.01, stepwise=True, driver="auto", vw=-2, perm=None,
-            resid=0, copies=0):
+            resid=0, copies=0, **extra):
     """Runs the GPU solver; returns (ctx, X (n x k), rho, rhs_norm, status).
-    perm: optional order of the unknowns (numpy int32, n entries)."""
+    perm: optional order of the unknowns (numpy int32, n entries); extra: more
+    sfk.params keywords (the low-rank operator's lr_*)."""
     import torch
     from paper_2605_22281_amd import sfk
     A = sfk.to_device_csr(P.A)
@@ -35,7 +36,7 @@ def gpu_run(P, method, kind, s, maxit, *, ell=2, tau="identity", eps=1e-3, zeta=
     pt = torch.from_numpy(np.ascontiguousarray(perm, dtype=np.int32)).cuda() if perm is not None else None
     p = sfk.params(method, ell=ell, maxit=maxit, sketch=kind, s=s, zeta=zeta, seed=seed, tau=tau,
                    eps=eps, tol=tol, noise_norm=noise, eta=eta, driver=driver, vw=vw, perm=pt,
-                   resid=resid, copies=copies)
+                   resid=resid, copies=copies, **extra)
     ctx = sfk.init(A, B, b, p)
     X = []
     st = sfk.OK

@@ -36,9 +36,10 @@ def test_every_declared_symbol_is_exported():
 
 
 def test_params_layout_matches_header(tmp_path):
-    # sfk_params: 6 int32, uint64 seed, 2 int32, 4 double, 8 int32, perm pointer
-    assert ctypes.sizeof(sfk.Params) == 112
-    assert sfk.Params.perm.offset == 104
+    # sfk_params: 6 int32, uint64 seed, 2 int32, 4 double, 8 int32, perm pointer,
+    # 6 int32 and a double of the low-rank operators
+    assert ctypes.sizeof(sfk.Params) == 144
+    assert sfk.Params.perm.offset == 104 and sfk.Params.lr_tol.offset == 136
     assert sfk.Params.seed.offset == 24 and sfk.Params.eps.offset == 40
     assert ctypes.sizeof(sfk.CSR) == 48
     # the C compiler's layout of the header agrees field by field
@@ -147,3 +148,31 @@ def test_workspace_bytes_is_zero_for_invalid_and_grows_with_maxit():
 def test_last_error_never_null():
     assert isinstance(sfk.lib().sfk_last_error(None), bytes)
     assert "gfx950" in sfk.version()
+
+
+def test_validation_lowrank_tau():
+    A = sfk.host_csr_descriptor(300, 16 * 12, 900)          # unknowns form a 16 x 12 image
+    ok = dict(s=60, maxit=20, tau="lowrank", lr_rows=16, lr_rank=4)
+    assert sfk.validate(A, None, sfk.params(**ok))[0] == sfk.OK
+    assert sfk.validate(A, None, sfk.params(**{**ok, "tau": "lowrank_rnd", "lr_q": 3}))[0] == sfk.OK
+    assert sfk.validate(A, None, sfk.params("flsqr", maxit=20, tau="lowrank", lr_rows=16,
+                                            lr_rank=4))[0] == sfk.OK
+    for kw, frag in [(dict(lr_rows=7), "lr_rows"), (dict(lr_rows=0), "lr_rows"),
+                     (dict(lr_rank=12), "lr_rank"), (dict(lr_rank=0), "lr_rank"),
+                     (dict(lr_q=17, tau="lowrank_rnd"), "lr_q"), (dict(lr_over=-1), "lr_over"),
+                     (dict(lr_tol=float("nan")), "lr_tol"), (dict(driver="graph"), "MULTI"),
+                     (dict(lr_maxit=-2), "lr_maxit")]:
+        st, msg = sfk.validate(A, None, sfk.params(**{**ok, **kw}))
+        assert st == sfk.EINVAL and frag in msg, (kw, msg)
+    big = sfk.host_csr_descriptor(300, 200 * 200, 900)
+    st, msg = sfk.validate(big, None, sfk.params(**{**ok, "lr_rows": 200, "lr_rank": 50,
+                                                     "lr_over": 20}))
+    assert st == sfk.EINVAL and "exceed" in msg            # l = 70 > 64 test vectors
+    # automatic oversampling is capped at 64 test vectors
+    assert sfk.validate(big, None, sfk.params(**{**ok, "lr_rows": 200, "lr_rank": 50}))[0] == sfk.OK
+    assert sfk.validate(big, None, sfk.params(**{**ok, "lr_rows": 200, "lr_rank": 40,
+                                                 "lr_over": 24}))[0] == sfk.OK
+    assert sfk.validate(A, None, sfk.params(**{**ok, "tau": 4}))[0] == sfk.EINVAL
+    # the workspace grows by the operator's buffers
+    assert sfk.workspace_bytes(A, None, sfk.params(**ok)) > sfk.workspace_bytes(
+        A, None, sfk.params(s=60, maxit=20))
