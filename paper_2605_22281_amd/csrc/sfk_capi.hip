@@ -976,6 +976,13 @@ static sfk_status setup_instance(sfk_ctx *c, Inst &I, const sfk_csr *A, const sf
   D.vs = 1;
   D.vwA = P.vwA;
   D.vwB = P.vwB;
+  // non-temporal operator loads in CSR-stream once the nonzeros exceed the
+  // 256 MB last-level cache (they cannot stay there; the gathered vector can)
+  {
+    const int64_t llc = 256ll << 20;
+    D.ntA = P.nnzA * (8 + (P.n <= 65536 ? 2 : 4)) > llc ? 1 : 0;
+    D.ntB = P.nnzB * (8 + (P.m <= 65536 ? 2 : 4)) > llc ? 1 : 0;
+  }
   D.nwmax = P.nwmax;
   D.nsg = p.sketch == SFK_SK_SPARSE_SIGN ? p.s                       // a workgroup per sketch row
         : p.sketch == SFK_SK_IDENTITY ? (p.s + kWG - 1) / kWG : 0;

@@ -62,6 +62,8 @@ struct Dev {
   int nwmax;          // stride of the per-stage partial-sum buffers
   int nsg;            // sparse-sign sketch gather workgroups of this instance
   int vwA, vwB;       // SpMV lanes per row
+  int ntA, ntB;       // 1: CSR-stream reads the operator with non-temporal loads (it
+                      // exceeds the last-level cache)
   int vs;             // element stride of W, P, Z, wraw, zraw, x: 1, or the
                       // interleave width when right-hand sides share A and B
   double eps;

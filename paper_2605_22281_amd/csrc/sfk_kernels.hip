@@ -35,23 +35,44 @@ namespace sfk {
 // in LDS; then one wave per row sums the row's segment of the chunk.  A row
 // that continues into the next chunk carries its partial sum.  The next
 // chunk's values and columns are loaded while the current one is reduced,
-// with ordinary (temporal) loads: an operator of up to ~200 MB of nonzeros can
-// then stay in the 256 MB last-level cache between iterations (measured on
-// the 256^2 projector: 70 us per product against 77 us with non-temporal
-// loads, while the larger back-projector keeps streaming through SELL-64).
+// with ordinary (temporal) loads when the operator's nonzeros fit the 256 MB
+// last-level cache, so that they stay there between iterations (the 256^2
+// projector, 150 MB: 48 us per product against 57 us with non-temporal
+// loads), and with non-temporal loads (nt) when they do not, so that the
+// stream does not evict the gathered vector (the 512^2 projector, 1.4 GB:
+// 407 us against 426 us).
 // y[r] = scale * sum_e val[e] x[col[e]]; also kept in ybuf for rows < kRowsLDS.
 // ---------------------------------------------------------------------------
 constexpr int kPerThread = 4;
 constexpr int kChunk = kSpmvWG * kPerThread;
 constexpr int kRowWin = 1024;   // row pointers staged per pass
 
+template <bool NTL, class T>
+__device__ __forceinline__ T stream_load(gptr<const T> p) {
+  if constexpr (NTL) return __builtin_nontemporal_load(p);
+  else return *p;
+}
+
+// LDS of spmv_stream, one allocation for both of its instantiations
+struct StreamLds {
+  double prod[kChunk];
+  int rps[kRowWin + 1];
+  double carry;
+};
+__device__ __forceinline__ StreamLds &stream_lds() {
+  __shared__ StreamLds s;
+  return s;
+}
+
+template <bool NTL>
 __device__ void spmv_stream(gptr<const int> rp, gptr<const int> ci, gptr<const uint16_t> c16,
                             gptr<const double> va, gptr<const double> xin, gptr<double> yout,
                             double *ybuf, int r0, int r1, double scale) {
   constexpr int NT = kSpmvWG;
-  __shared__ double prod[kChunk];
-  __shared__ int rps[kRowWin + 1];
-  __shared__ double s_carry;
+  StreamLds &L = stream_lds();
+  double *prod = L.prod;
+  int *rps = L.rps;
+  double &s_carry = L.carry;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   if (r0 >= r1) return;
   const int E0 = rp[r0], E1 = rp[r1];
@@ -62,8 +83,10 @@ __device__ void spmv_stream(gptr<const int> rp, gptr<const int> ci, gptr<const u
 #pragma unroll
   for (int j = 0; j < kPerThread; ++j) {
     const int e = E0 + j * NT + tid;
-    if (e < E1) { vv[j] = va[e]; cc[j] = c16 ? (int)c16[e] : ci[e]; }
-    else { vv[j] = 0.0; cc[j] = -1; }
+    if (e < E1) {
+      vv[j] = stream_load<NTL>(va + e);
+      cc[j] = c16 ? (int)stream_load<NTL>(c16 + e) : stream_load<NTL>(ci + e);
+    } else { vv[j] = 0.0; cc[j] = -1; }
   }
   for (int cs = E0; cs < E1; cs += kChunk) {
     const int ce = min(cs + kChunk, E1);
@@ -73,8 +96,10 @@ __device__ void spmv_stream(gptr<const int> rp, gptr<const int> ci, gptr<const u
 #pragma unroll
     for (int j = 0; j < kPerThread; ++j) {
       const int e = cs + kChunk + j * NT + tid;
-      if (e < E1) { vv[j] = va[e]; cc[j] = c16 ? (int)c16[e] : ci[e]; }
-      else { vv[j] = 0.0; cc[j] = -1; }
+      if (e < E1) {
+        vv[j] = stream_load<NTL>(va + e);
+        cc[j] = c16 ? (int)stream_load<NTL>(c16 + e) : stream_load<NTL>(ci + e);
+      } else { vv[j] = 0.0; cc[j] = -1; }
     }
     for (;;) {
       __syncthreads();
@@ -293,7 +318,10 @@ __global__ void __launch_bounds__(kSpmvWG, 8) k_spmv(const Dev *__restrict__ dev
     if (ISA) beam_forward_rows(D, (const double *)xin, (double *)yout, ybuf, r0, r1, scale, NT);
     else beam_back_rows(D, (const double *)xin, (double *)yout, ybuf, r0, r1, scale, NT);
   } else if (VW == 0) {
-    spmv_stream(rp, ci, gmem(ISA ? D.Aci16 : D.Bci16), va, xin, yout, ybuf, r0, r1, scale);
+    if (ISA ? D.ntA : D.ntB)
+      spmv_stream<true>(rp, ci, gmem(ISA ? D.Aci16 : D.Bci16), va, xin, yout, ybuf, r0, r1, scale);
+    else
+      spmv_stream<false>(rp, ci, gmem(ISA ? D.Aci16 : D.Bci16), va, xin, yout, ybuf, r0, r1, scale);
   } else if (VW == 64) {
     spmv_rows64(rp, ci, va, xin, yout, ybuf, r0, r1, scale);
   } else {
@@ -384,7 +412,12 @@ __global__ void __launch_bounds__(kSpmvWG, 8) k_spmv_core(Dev D, const double *_
     if (ISA) beam_forward_rows(D, xin, yout, ybuf, part[wid], part[wid + 1], 1.0, kSpmvWG);
     else beam_back_rows(D, xin, yout, ybuf, part[wid], part[wid + 1], 1.0, kSpmvWG);
   } else {
-    spmv_stream(rp, ci, gmem(ISA ? D.Aci16 : D.Bci16), va, xg, yg, ybuf, part[wid], part[wid + 1], 1.0);
+    if (ISA ? D.ntA : D.ntB)
+      spmv_stream<true>(rp, ci, gmem(ISA ? D.Aci16 : D.Bci16), va, xg, yg, ybuf, part[wid],
+                        part[wid + 1], 1.0);
+    else
+      spmv_stream<false>(rp, ci, gmem(ISA ? D.Aci16 : D.Bci16), va, xg, yg, ybuf, part[wid],
+                         part[wid + 1], 1.0);
   }
 }
 
