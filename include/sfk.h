@@ -158,7 +158,9 @@ typedef struct {
   int32_t driver;      /* sfk_driver */
   int32_t vw;          /* SpMV kernel: -2 = automatic (the default: CSR-stream,
                           a wave per row and SELL-64 are timed at init on each
-                          operator and the fastest is kept), 0 = CSR-stream chunks,
+                          operator and the fastest is kept, so two contexts may
+                          differ in kernel and hence in rounding; vw / vw_b from
+                          sfk_spmv_variant repeat a choice), 0 = CSR-stream chunks,
                           1 = SELL-64 copy built at init (64-row slices stored
                           column-major), 8/16/32/64 = lanes per row, -1 = lanes per
                           row chosen from the mean row length.  Right-hand sides

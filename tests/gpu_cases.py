@@ -56,6 +56,14 @@ def gpu_run(P, method, kind, s, maxit, *, ell=2, tau="identity", eps=1e-3, zeta=
     return ctx, Xm, rho, rn, st
 
 
+def pinned(ctx):
+    """vw / vw_b that repeat the SpMV kernels ctx launches: the automatic
+    choice is timed at init, so two contexts may differ in kernel and rounding."""
+    from paper_2605_22281_amd import sfk
+    va, vb = sfk.spmv_variant(ctx)
+    return dict(vw=va, vw_b=vb)
+
+
 def oracle_sketch(method, kind, P, s, zeta=8, seed=3001):
     d = P.m if method == "sflsqr" else P.n
     if kind == "identity":

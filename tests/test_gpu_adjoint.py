@@ -73,8 +73,12 @@ def test_ct256_batch16_fd_and_oracle():
     The map is strongly curved along some directions (the h^2 term of a
     central difference reaches 1e-7 relative at h = 1e-6), so each central
     difference D(h) is compared within its own truncation estimate
-    |D(2h) - D(h)| / 3 (plus 1e-9), and the Richardson value (4 D(h) - D(2h)) / 3,
-    whose error is O(h^4), to 1e-7."""
+    |D(2h) - D(h)| / 3 plus a rounding floor of 1e-7 relative, and the
+    Richardson value (4 D(h) - D(2h)) / 3, whose truncation error is O(h^4), to
+    the same 1e-7.  The floor is the rounding of the loss differences: the 50
+    reweighted iterations leave a relative rounding of ~1e-13 in each loss,
+    which a difference quotient at h = 1e-6 turns into a few 1e-8 of the
+    derivative, and its sign and size change with the SpMV summation order."""
     from paper_2605_22281_amd import sfk
     from paper_2605_22281_amd.autograd import SketchedFlexibleLSQR
     P = inputs.workload("ct256_unmatched")
@@ -118,7 +122,7 @@ def test_ct256_batch16_fd_and_oracle():
         trunc = abs(d2 - d1) / 3
         worst_fd = max(worst_fd, abs(d1 - g) / abs(g))
         worst_rich = max(worst_rich, abs(rich - g) / abs(g))
-        assert abs(d1 - g) <= 2 * trunc + 1e-9 * abs(g), (t, d1, d2, g)
+        assert abs(d1 - g) <= 2 * trunc + 1e-7 * abs(g), (t, d1, d2, g)
         assert abs(rich - g) <= 1e-7 * abs(g), (t, rich, g)
     say(f"ct256 batch: adjoint vs central differences (h = 1e-6), 20 directions: worst rel "
         f"{worst_fd:.1e}; vs the extrapolated differences {worst_rich:.1e}")

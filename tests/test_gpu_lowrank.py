@@ -15,7 +15,7 @@ import pytest
 from oracle import fgk, lowrank, sketches
 from paper_2605_22281_amd import inputs
 
-from gpu_cases import gpu_run, rel, say
+from gpu_cases import gpu_run, pinned, rel, say
 
 pytestmark = pytest.mark.gpu
 
@@ -206,7 +206,7 @@ def test_lowrank_stop_and_stepwise_equal_batched():
     c1, X1, _, _, _ = gpu_run(P, "sflsqr", "sparse_sign", 101, 30, zeta=1, tau="lowrank",
                               lr_rows=N, lr_rank=8, stepwise=True)
     c2, X2, _, _, _ = gpu_run(P, "sflsqr", "sparse_sign", 101, 30, zeta=1, tau="lowrank",
-                              lr_rows=N, lr_rank=8, stepwise=False)
+                              lr_rows=N, lr_rank=8, stepwise=False, **pinned(c1))
     sfk.destroy(c1)
     sfk.destroy(c2)
     assert np.array_equal(X1, X2)

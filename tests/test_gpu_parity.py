@@ -11,7 +11,7 @@ import scipy.sparse as sp
 from oracle import sketches
 from paper_2605_22281_amd import inputs
 
-from gpu_cases import compare, gpu_run, oracle_run, rel, say
+from gpu_cases import compare, gpu_run, oracle_run, pinned, rel, say
 
 pytestmark = pytest.mark.gpu
 
@@ -191,7 +191,8 @@ def test_resume_equals_single_call_and_is_deterministic(ct24):
     say("case: resume/determinism")
     ctx1, *_ = gpu_run(ct24, "sflsmr", "srht", 60, 10, tau="reweight_l1", eps=1e-2, stepwise=False)
     x1 = sfk.solution(ctx1).cpu().numpy()
-    ctx2, *_ = gpu_run(ct24, "sflsmr", "srht", 60, 10, tau="reweight_l1", eps=1e-2, stepwise=True)
+    ctx2, *_ = gpu_run(ct24, "sflsmr", "srht", 60, 10, tau="reweight_l1", eps=1e-2, stepwise=True,
+                       **pinned(ctx1))
     x2 = sfk.solution(ctx2).cpu().numpy()
     assert np.array_equal(x1, x2)              # same launch sequence, fixed-order reductions
     r1, _ = sfk.residual_norms(ctx1)

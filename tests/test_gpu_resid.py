@@ -11,7 +11,7 @@ import pytest
 from oracle import fgk, sketches
 from paper_2605_22281_amd import inputs
 
-from gpu_cases import compare, gpu_run, oracle_run, rel, say
+from gpu_cases import compare, gpu_run, oracle_run, pinned, rel, say
 
 pytestmark = pytest.mark.gpu
 
@@ -110,7 +110,7 @@ def test_recording_does_not_change_iterates():
     say("case: resid=1 leaves iterates bit-identical")
     c0, X0, r0, _, _ = gpu_run(P, "sflsqr", "sparse_sign", 60, 12, tau="reweight_l1", stepwise=False)
     c1, X1, r1, _, _ = gpu_run(P, "sflsqr", "sparse_sign", 60, 12, tau="reweight_l1", stepwise=False,
-                               resid=1)
+                               resid=1, **pinned(c0))
     assert np.array_equal(X0, X1) and np.array_equal(r0, r1)
 
 
@@ -136,10 +136,11 @@ def test_graph_driver_bit_identical(method, kind, tau, prob):
     ca, Xa, ra, _, _ = gpu_run(P, method, kind, s, k, tau=tau, eps=1e-2, stepwise=False,
                                driver="multi")
     cb, Xb, rb, _, _ = gpu_run(P, method, kind, s, k, tau=tau, eps=1e-2, stepwise=False,
-                               driver="graph")
+                               driver="graph", **pinned(ca))
     assert np.array_equal(Xa, Xb) and np.array_equal(ra, rb)
     # iterate calls of odd lengths (partial batches, resumed runs)
-    cc = gpu_run(P, method, kind, s, k, tau=tau, eps=1e-2, stepwise=True, driver="graph")
+    cc = gpu_run(P, method, kind, s, k, tau=tau, eps=1e-2, stepwise=True, driver="graph",
+                 **pinned(ca))
     assert np.array_equal(cc[1], Xa)
 
 
@@ -148,18 +149,18 @@ def test_graph_driver_discrepancy_stop_and_batch():
     import torch
     P = inputs.workload("ct64")
     say("case: graph driver ct64 discrepancy")
-    _, Xa, ra, _, _ = gpu_run(P, "sflsqr", "sparse_sign", 200, 50, noise=P.noise_norm, seed=3001,
-                              stepwise=False, driver="multi")
+    ca, Xa, ra, _, _ = gpu_run(P, "sflsqr", "sparse_sign", 200, 50, noise=P.noise_norm, seed=3001,
+                               stepwise=False, driver="multi")
     _, Xb, rb, _, _ = gpu_run(P, "sflsqr", "sparse_sign", 200, 50, noise=P.noise_norm, seed=3001,
-                              stepwise=False, driver="graph")
+                              stepwise=False, driver="graph", **pinned(ca))
     assert Xa.shape == Xb.shape and np.array_equal(Xa, Xb) and np.array_equal(ra, rb)
     probs = [inputs.small_ct(n, 12, noise=0.02, seed_offset=40 + n) for n in (12, 16, 20)]
     As = [sfk.to_device_csr(Q.A) for Q in probs]
     bs = [torch.from_numpy(Q.b).cuda() for Q in probs]
     out = {}
     for drv in ("multi", "graph"):
-        ps = [sfk.params("sflsqr", maxit=20, s=60, seed=11 + i, noise_norm=Q.noise_norm, driver=drv)
-              for i, Q in enumerate(probs)]
+        ps = [sfk.params("sflsqr", maxit=20, s=60, seed=11 + i, noise_norm=Q.noise_norm, driver=drv,
+                         vw=0) for i, Q in enumerate(probs)]
         ctx = sfk.init_batch(As, None, bs, ps)
         sfk.iterate(ctx, 20)
         out[drv] = [sfk.instance_solution(ctx, i, Q.n).cpu().numpy() for i, Q in enumerate(probs)]

@@ -15,7 +15,11 @@ the arithmetic; test_rounding_sensitivity_horizon pins that on the CPU).
     matrix has condition ~1e15 and |y_k| ~1e13, so forming x_k = Z_k y_k loses
     digits: the oracle itself misses both identities by up to ~1e-2 relative
     there.  The GPU must be as consistent as the oracle: within 10 times the
-    oracle's own deviation at the same k (and 1e-9 where that is smaller).
+    larger deviation of two oracle runs that differ only in the summation
+    order of the sparse products (each row's nonzeros in stored and in reversed
+    order), up to the same k (and 1e-9 where that is smaller).  One order alone
+    is no yardstick: on the 64^2 workload the two orders miss the minimum by
+    5e-9 and 1.3e-6 at k = 26, by 2e-6 and 3e-4 at k = 28.
 """
 import numpy as np
 import pytest
@@ -67,6 +71,17 @@ def _ls_consistency(P, S, method, Z, X, rho, K):
     return np.array(res), np.array(mn)
 
 
+def _reversed_rows(M):
+    """The same matrix with each row's nonzeros stored in reverse order."""
+    R = M.tocsr().copy()
+    for r in range(R.shape[0]):
+        a, b = R.indptr[r], R.indptr[r + 1]
+        R.indices[a:b] = R.indices[a:b][::-1].copy()
+        R.data[a:b] = R.data[a:b][::-1].copy()
+    R.has_sorted_indices = False
+    return R
+
+
 def _check(P, method, kind, s, K, seed, label, perm=None, basis_parity=0):
     g = _gpu_basis(P, method, kind, s, K, seed, perm)
     Bm = P.backprojector()
@@ -100,9 +115,14 @@ def _check(P, method, kind, s, K, seed, label, perm=None, basis_parity=0):
     assert np.all(rho[1:] <= rho[:-1] * (1 + 1e-12))
     gres, gmin = _ls_consistency(P, S, method, g["Z"], g["X"], rho, K)
     ores, omin = _ls_consistency(P, S, method, orc.Z, orc.X, orc.rho, K)
-    # yardstick: the oracle's own deviation up to k (running maximum)
+    orv = fgk.sketched_flexible(_reversed_rows(P.A), P.b, S, method=method,
+                                B=_reversed_rows(P.B) if P.B is not None else None, maxit=K, ell=2)
+    ores2, omin2 = _ls_consistency(P, S, method, orv.Z, orv.X, orv.rho, K)
+    ores = np.maximum(ores, ores2)
+    omin = np.maximum(np.abs(omin), np.abs(omin2))
+    # yardstick: the oracle's deviation up to k (running maximum over both orders)
     yres = np.maximum(1e-9, 10 * np.maximum.accumulate(ores))
-    ymin = np.maximum(1e-9, 10 * np.maximum.accumulate(np.abs(omin)))
+    ymin = np.maximum(1e-9, 10 * np.maximum.accumulate(omin))
     say(f"{label}: rho vs ||S(A x - b)||: GPU worst {gres.max():.1e}, oracle worst {ores.max():.1e}; "
         f"rho above the minimum: GPU worst {gmin.max():.1e}, oracle {omin.max():.1e}")
     for k in range(K):
