@@ -30,7 +30,7 @@ void launch_stage_C(const Launch &L, int k, hipStream_t st);
 void launch_stage_D(const Launch &L, int k, hipStream_t st);
 void launch_sketch(const Launch &L, int k, hipStream_t st);
 void launch_ls(const Launch &L, int k, hipStream_t st);
-int spmv_blocks_per_cu(int vw);
+int spmv_blocks_per_cu();
 void launch_backsub(const Dev &D, int j, double *yout, hipStream_t st);
 void launch_init_b(const Dev &D, double eta, double noise, double tol_user, int use_disc,
                    hipStream_t st);
@@ -634,23 +634,14 @@ static int pick_vw(int64_t nnz, int64_t rows, int user) {
   return 8;
 }
 
-// Workgroups of a stage grid: one per 8192 nonzeros and per 2048 rows at
-// least, at most one wave of resident workgroups (blocks_per_cu per CU, or the
-// caller's wg_per_cu).
-static int grid_size(int64_t nnzmax, int64_t rows, int wg_per_cu, int cus, int blocks_per_cu) {
-  const int cap = cus * (wg_per_cu ? wg_per_cu : std::max(1, blocks_per_cu));
-  int64_t nw = (nnzmax + 8191) / 8192;
-  nw = std::max<int64_t>(nw, (rows + 2047) / 2048);
-  nw = std::min<int64_t>(std::max<int64_t>(nw, 1), cap);
-  return (int)nw;
-}
-
-// The vector stages' workgroups, also the partial-sum stride's lower bound
-// (sized for the 1024-thread SpMV kernels).
 static int default_nws(const sfk_csr *A, const sfk_csr *B, const sfk_params *p, int cus,
                        int blocks_per_cu) {
-  return grid_size(std::max(A->nnz, B ? B->nnz : A->nnz), std::max(A->rows, A->cols),
-                   p->wg_per_cu, cus, blocks_per_cu);
+  const int64_t nnzmax = std::max(A->nnz, B ? B->nnz : A->nnz);
+  const int cap = cus * (p->wg_per_cu ? p->wg_per_cu : std::max(1, blocks_per_cu));
+  int64_t nw = (nnzmax + 8191) / 8192;
+  nw = std::max<int64_t>(nw, (std::max(A->rows, A->cols) + 2047) / 2048);
+  nw = std::min<int64_t>(std::max<int64_t>(nw, 1), cap);
+  return (int)nw;
 }
 
 // member = true: a right-hand side of a shared-operator group, whose long
@@ -980,8 +971,7 @@ static sfk_status setup_instance(sfk_ctx *c, Inst &I, const sfk_csr *A, const sf
   D.N = P.N;
   D.log2L = P.log2L;
   D.nblk = P.nblk;
-  D.nwsA = P.nw;
-  D.nwsB = P.nw;
+  D.nws = P.nw;
   D.nwv = P.nw;
   D.vs = 1;
   D.vwA = P.vwA;
@@ -1085,8 +1075,8 @@ static sfk_status setup_instance(sfk_ctx *c, Inst &I, const sfk_csr *A, const sf
     D.Arp = nullptr; D.Aci = nullptr; D.Ava = nullptr;
     D.vwA = D.vwB = 3;
     launch_beam_rays(D, st);
-    launch_uniform_part(D.m, D.nwsA, at<int>(w, P.o_Apart), st);
-    launch_uniform_part(D.n, D.nwsB, at<int>(w, P.o_Bpart), st);
+    launch_uniform_part(D.m, D.nws, at<int>(w, P.o_Apart), st);
+    launch_uniform_part(D.n, D.nws, at<int>(w, P.o_Bpart), st);
     HIPCHK(c, hipGetLastError());
     return setup_sketch_and_b(c, I, st);
   }
@@ -1122,17 +1112,8 @@ static sfk_status setup_instance(sfk_ctx *c, Inst &I, const sfk_csr *A, const sf
                      I.d_err, st);
     D.Brp = brp; D.Bci = bci; D.Bva = bva;
   }
-  // row ranges of a product for SpMV kernel vw: as many nnz-balanced ranges as
-  // that kernel has resident workgroups (CSR-stream: 512-thread workgroups)
-  auto set_part = [&](bool isa, int vw) {
-    const int nw = std::min(P.nwmax, grid_size(std::max(P.nnzA, P.nnzB), std::max(P.m, P.n),
-                                               p.wg_per_cu, cus, spmv_blocks_per_cu(vw)));
-    (isa ? D.nwsA : D.nwsB) = nw;
-    if (isa) launch_partition(D.Arp, D.m, P.nnzA, nw, at<int>(w, P.o_Apart), st);
-    else launch_partition(D.Brp, D.n, P.nnzB, nw, at<int>(w, P.o_Bpart), st);
-  };
-  set_part(true, D.vwA);
-  set_part(false, D.vwB);
+  launch_partition(D.Arp, D.m, P.nnzA, D.nws, at<int>(w, P.o_Apart), st);
+  launch_partition(D.Brp, D.n, P.nnzB, D.nws, at<int>(w, P.o_Bpart), st);
   // 16-bit column indices for an operator with at most 65536 columns: the
   // CSR-stream and SELL-64 products read 10 bytes per stored nonzero instead of 12
   for (int op = 0; op < 2; ++op) {
@@ -1164,7 +1145,6 @@ static sfk_status setup_instance(sfk_ctx *c, Inst &I, const sfk_csr *A, const sf
     if (e != SFK_OK) return e;
     if (!tune) {
       vw = ok ? 1 : 0;
-      set_part(isa, vw);
       continue;
     }
     // scratch (all zeros at this point): A reads Z ((maxit + 1) n >= n entries)
@@ -1180,7 +1160,6 @@ static sfk_status setup_instance(sfk_ctx *c, Inst &I, const sfk_csr *A, const sf
     HIPCHK(c, hipEventCreate(&e1));
     for (int q = 0; q < 3; ++q) {
       if (cand[q] == 1 && !ok) continue;
-      set_part(isa, cand[q]);
       launch_spmv_core(D, isa, cand[q], x, y, st);          // warm-up
       HIPCHK(c, hipEventRecord(e0, st));
       for (int rep = 0; rep < 4; ++rep) launch_spmv_core(D, isa, cand[q], x, y, st);
@@ -1194,7 +1173,6 @@ static sfk_status setup_instance(sfk_ctx *c, Inst &I, const sfk_csr *A, const sf
     hipEventDestroy(e1);
     HIPCHK(c, hipGetLastError());
     vw = pick;
-    set_part(isa, pick);
     if (pick != 1) {          // the SELL copy lost (or was refused): release it
       HIPCHK(c, hipStreamSynchronize(st));
       while (c->xmem.size() > mark) lib_pop(c);
@@ -1206,7 +1184,7 @@ static sfk_status setup_instance(sfk_ctx *c, Inst &I, const sfk_csr *A, const sf
 // Uploads the instance descriptors and the block maps of every stage type.
 static sfk_status build_launch(sfk_ctx *c) {
   const int nb = (int)c->inst.size();
-  std::vector<int2> msa, msb, mv, mg, mb, mc;
+  std::vector<int2> ms, mv, mg, mb, mc;
   int smax = 0, maxitmax = 0;
   if (c->multi) {
     // right-hand sides of one group have identical sketch shapes; ordering the
@@ -1225,8 +1203,7 @@ static sfk_status build_launch(sfk_ctx *c) {
   for (int i = 0; i < nb; ++i) {
     const Dev &D = c->inst[i].D;
     if (!c->multi) {
-      for (int w = 0; w < D.nwsA; ++w) msa.push_back(make_int2(i, w));
-      for (int w = 0; w < D.nwsB; ++w) msb.push_back(make_int2(i, w));
+      for (int w = 0; w < D.nws; ++w) ms.push_back(make_int2(i, w));
       for (int w = 0; w < D.nwv; ++w) mv.push_back(make_int2(i, w));
       for (int w = 0; w < D.nsg; ++w) mg.push_back(make_int2(i, w));
       if (D.sketch == SFK_SK_SRHT) {
@@ -1242,9 +1219,8 @@ static sfk_status build_launch(sfk_ctx *c) {
   }
   auto al = [](size_t v) { return (v + 255) / 256 * 256; };
   const size_t o_dev = 0;
-  const size_t o_msa = al(o_dev + sizeof(Dev) * nb);
-  const size_t o_msb = al(o_msa + sizeof(int2) * msa.size());
-  const size_t o_mv = al(o_msb + sizeof(int2) * msb.size());
+  const size_t o_ms = al(o_dev + sizeof(Dev) * nb);
+  const size_t o_mv = al(o_ms + sizeof(int2) * ms.size());
   const size_t o_mg = al(o_mv + sizeof(int2) * mv.size());
   const size_t o_mb = al(o_mg + sizeof(int2) * mg.size());
   const size_t o_mc = al(o_mb + sizeof(int2) * mb.size());
@@ -1256,20 +1232,18 @@ static sfk_status build_launch(sfk_ctx *c) {
   auto put = [&](size_t off, const std::vector<int2> &v) {
     if (!v.empty()) std::memcpy(h.data() + off, v.data(), sizeof(int2) * v.size());
   };
-  put(o_msa, msa); put(o_msb, msb); put(o_mv, mv); put(o_mg, mg); put(o_mb, mb); put(o_mc, mc);
+  put(o_ms, ms); put(o_mv, mv); put(o_mg, mg); put(o_mb, mb); put(o_mc, mc);
   HIPCHK(c, hipMemcpyAsync(c->hdr, h.data(), total, hipMemcpyHostToDevice, c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
   Launch &L = c->L;
   char *base = static_cast<char *>(c->hdr);
   L.devs = reinterpret_cast<const Dev *>(base + o_dev);
-  L.map_spmvA = reinterpret_cast<const int2 *>(base + o_msa);
-  L.map_spmvB = reinterpret_cast<const int2 *>(base + o_msb);
+  L.map_spmv = reinterpret_cast<const int2 *>(base + o_ms);
   L.map_vec = reinterpret_cast<const int2 *>(base + o_mv);
   L.map_sg = reinterpret_cast<const int2 *>(base + o_mg);
   L.map_sb = reinterpret_cast<const int2 *>(base + o_mb);
   L.map_sc = reinterpret_cast<const int2 *>(base + o_mc);
-  L.nspmvA = (int)msa.size();
-  L.nspmvB = (int)msb.size();
+  L.nspmv = (int)ms.size();
   L.nvec = (int)mv.size();
   L.nsg = (int)mg.size();
   L.nsb = (int)mb.size();
@@ -1389,7 +1363,7 @@ extern "C" sfk_status sfk_init(sfk_ctx **out, const sfk_csr *A, const sfk_csr *B
   s = create_streams(c, 1);
   if (s == SFK_OK)
     s = setup_instance(c, c->inst[0], A, B, b, workspace, workspace_bytes, cus,
-                       default_nws(A, B, p, cus, spmv_blocks_per_cu(-1)));
+                       default_nws(A, B, p, cus, spmv_blocks_per_cu()));
   if (s == SFK_OK) s = init_common(c);
   if (s != SFK_OK) {
     set_err(g_err, c->err);
@@ -1437,7 +1411,7 @@ extern "C" sfk_status sfk_init_beam(sfk_ctx **out, const sfk_beam *geo, const do
   s = create_streams(c, 1);
   if (s == SFK_OK)
     s = setup_instance(c, c->inst[0], &Ad, &Bd, b, workspace, workspace_bytes, cus,
-                       default_nws(&Ad, &Bd, &q, cus, spmv_blocks_per_cu(-1)), nullptr, 0, geo);
+                       default_nws(&Ad, &Bd, &q, cus, spmv_blocks_per_cu()), nullptr, 0, geo);
   if (s == SFK_OK) s = init_common(c);
   if (s != SFK_OK) {
     set_err(g_err, c->err);
@@ -1475,7 +1449,7 @@ extern "C" sfk_status sfk_init_batch(sfk_ctx **out, int32_t nb, const sfk_csr *A
   // instances are live the grid is oversubscribed and the hardware balances
   // it; once some have stopped (their workgroups exit at once), the ones still
   // running keep the whole device.
-  const int bpc = spmv_blocks_per_cu(-1);
+  const int bpc = spmv_blocks_per_cu();
   sfk_ctx *c = new sfk_ctx();
   c->stream = static_cast<hipStream_t>(stream);
   c->inst.resize(nb);
@@ -2331,7 +2305,7 @@ extern "C" sfk_status sfk_solve_noalloc(const sfk_csr *A, const sfk_csr *B, cons
     return fail(nullptr, SFK_EDEVICE, "no usable HIP device");
   const int cus = device_cus();
   if (cus <= 0) return fail(nullptr, SFK_EDEVICE, "no HIP device available");
-  const int nws = default_nws(A, B, &p, cus, spmv_blocks_per_cu(-1));
+  const int nws = default_nws(A, B, &p, cus, spmv_blocks_per_cu());
   const Plan P = make_plan(A, B, &p, cus, nws);
   // descriptor and block maps after the instance's workspace
   const int nsg = p.sketch == SFK_SK_SPARSE_SIGN ? p.s
@@ -2341,7 +2315,7 @@ extern "C" sfk_status sfk_solve_noalloc(const sfk_csr *A, const sfk_csr *B, cons
   Layout L_;
   L_.off = P.total;
   const size_t o_dev = L_.take<Dev>(1);
-  const size_t o_ms = L_.take<int2>(P.nwmax);   // any product's grid (at most nwmax)
+  const size_t o_ms = L_.take<int2>(nws);
   const size_t o_mv = L_.take<int2>(nws);
   const size_t o_mg = L_.take<int2>(std::max(nsg, 1));
   const size_t o_mb = L_.take<int2>(std::max(nsb, 1));
@@ -2379,14 +2353,12 @@ extern "C" sfk_status sfk_solve_noalloc(const sfk_csr *A, const sfk_csr *B, cons
   char *hb = static_cast<char *>(base);
   Launch &L = c.L;
   L.devs = reinterpret_cast<const Dev *>(hb + o_dev);
-  L.map_spmvA = reinterpret_cast<const int2 *>(hb + o_ms);
-  L.map_spmvB = L.map_spmvA;
+  L.map_spmv = reinterpret_cast<const int2 *>(hb + o_ms);
   L.map_vec = reinterpret_cast<const int2 *>(hb + o_mv);
   L.map_sg = reinterpret_cast<const int2 *>(hb + o_mg);
   L.map_sb = reinterpret_cast<const int2 *>(hb + o_mb);
   L.map_sc = reinterpret_cast<const int2 *>(hb + o_mc);
-  L.nspmvA = D.nwsA;
-  L.nspmvB = D.nwsB;
+  L.nspmv = D.nws;
   L.nvec = D.nwv;
   L.nsg = D.nsg;
   L.nsb = nsb;
@@ -2398,7 +2370,7 @@ extern "C" sfk_status sfk_solve_noalloc(const sfk_csr *A, const sfk_csr *B, cons
   L.vwA = D.vwA;
   L.vwB = D.vwB;
   HIPCHK(nullptr, hipMemcpyAsync(hb + o_dev, &D, sizeof(Dev), hipMemcpyHostToDevice, st));
-  launch_iota_map(reinterpret_cast<int2 *>(hb + o_ms), std::max(D.nwsA, D.nwsB), st);
+  launch_iota_map(reinterpret_cast<int2 *>(hb + o_ms), D.nws, st);
   launch_iota_map(reinterpret_cast<int2 *>(hb + o_mv), D.nwv, st);
   launch_iota_map(reinterpret_cast<int2 *>(hb + o_mg), D.nsg, st);
   launch_iota_map(reinterpret_cast<int2 *>(hb + o_mb), nsb, st);

@@ -111,7 +111,7 @@ __device__ __forceinline__ double *part_of(const Dev &D, int stage) {
 
 // workgroups that produced a stage's partial sums
 __device__ __forceinline__ int producers(const Dev &D, int stage) {
-  return (stage == kStageB || stage == kStageD) ? D.nwv : stage == kStageC ? D.nwsB : D.nwsA;
+  return (stage == kStageB || stage == kStageD) ? D.nwv : D.nws;
 }
 
 // Totals of the Q partial sums that the previous stage left, in a fixed order

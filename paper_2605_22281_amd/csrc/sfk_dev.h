@@ -13,10 +13,7 @@ namespace sfk {
 constexpr int kMaxEll = 8;                 // orthogonalisation window limit
 constexpr int kMaxS = 2048;                // sketch rows limit (LS kept in one wave)
 constexpr int kWG = 256;                   // threads per vector-stage workgroup
-constexpr int kSpmvWG = 1024;              // threads per SpMV workgroup (SELL-64, row kernels)
-constexpr int kStreamWG = 512;             // threads per CSR-stream SpMV workgroup
-// threads per workgroup of the SpMV kernel vw (0: CSR-stream, else 1024)
-constexpr int spmv_threads(int vw) { return vw == 0 ? kStreamWG : kSpmvWG; }
+constexpr int kSpmvWG = 1024;              // threads per SpMV workgroup
 constexpr int kRowsLDS = 2048;             // SpMV results kept in LDS for the epilogue
 constexpr int kMaxQ = kMaxEll + 2;         // partial sums per workgroup and stage
 constexpr int kRawSlots = 8;   // raw products kept (the sketch of iteration k reads
@@ -60,7 +57,7 @@ struct Dev {
   int N;              // SRHT padded length
   int log2L;          // SRHT block length log2
   int nblk;           // SRHT blocks
-  int nwsA, nwsB;     // SpMV workgroups (row ranges) of the A and B products
+  int nws;            // SpMV workgroups of this instance (row ranges)
   int nwv;            // vector-stage workgroups of this instance
   int nwmax;          // stride of the per-stage partial-sum buffers
   int nsg;            // sparse-sign sketch gather workgroups of this instance
@@ -75,7 +72,7 @@ struct Dev {
   const int *Arp, *Aci; const double *Ava;
   const int *Brp, *Bci; const double *Bva;
   const double *b;
-  const int *Apart, *Bpart;    // nnz-balanced row ranges, nwsA + 1 and nwsB + 1 entries
+  const int *Apart, *Bpart;    // nnz-balanced row ranges, nws + 1 entries each
   // caller's order of the unknowns (sfk_params.perm): unknown j at position
   // perm[j]; skperm = perm when the sketched vectors are n-vectors (sFLSMR),
   // pinv the inverse (solutions are written back in the caller's order); both
@@ -149,8 +146,8 @@ struct Dev {
 // descriptors and, per stage type, a block -> (instance, workgroup) map.
 struct Launch {
   const Dev *devs;
-  const int2 *map_spmvA, *map_spmvB, *map_vec, *map_sg, *map_sb, *map_sc;
-  int nspmvA, nspmvB, nvec, nsg, nsb, nsc;   // grid sizes
+  const int2 *map_spmv, *map_vec, *map_sg, *map_sb, *map_sc;
+  int nspmv, nvec, nsg, nsb, nsc;   // grid sizes
   int ninst, smax, maxitmax, tau, vwA, vwB;
 };
 

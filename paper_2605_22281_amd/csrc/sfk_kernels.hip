@@ -30,26 +30,22 @@ namespace sfk {
 
 // ---------------------------------------------------------------------------
 // CSR-stream product of one workgroup's rows [r0, r1) (whole rows, contiguous
-// nonzeros).  The nonzeros are streamed in chunks of kChunk: every thread
-// holds kPerThread (value, column) pairs, gathers x for all of them at once,
-// and leaves the products in LDS; then one wave per row sums the row's
-// segment of the chunk.  A row that continues into the next chunk carries its
-// partial sum.  Per chunk, the row pointers from the current row on, the
-// chunk's gathers and the next chunk's values and columns are issued together
-// (every load unconditional: indices past the end are clamped to the last
-// nonzero or row, and the reduction never reads the products they give), so a
-// chunk costs one memory round trip and two barriers.  The operator is read
-// with ordinary (temporal) loads when its nonzeros fit the 256 MB last-level
-// cache, so that they stay there between iterations (the 256^2 projector,
-// 150 MB: 48 us per product against 57 us with non-temporal loads), and with
-// non-temporal loads (NTL) when they do not, so that the stream does not
-// evict the gathered vector (the 512^2 projector, 1.4 GB).  C16: 16-bit
-// column indices.
+// nonzeros).  The nonzeros are streamed in chunks of kChunk: every thread loads
+// kPerThread (value, column) pairs at once, gathers x, and leaves the products
+// in LDS; then one wave per row sums the row's segment of the chunk.  A row
+// that continues into the next chunk carries its partial sum.  The next
+// chunk's values and columns are loaded while the current one is reduced,
+// with ordinary (temporal) loads when the operator's nonzeros fit the 256 MB
+// last-level cache, so that they stay there between iterations (the 256^2
+// projector, 150 MB: 48 us per product against 57 us with non-temporal
+// loads), and with non-temporal loads (nt) when they do not, so that the
+// stream does not evict the gathered vector (the 512^2 projector, 1.4 GB:
+// 407 us against 426 us).
 // y[r] = scale * sum_e val[e] x[col[e]]; also kept in ybuf for rows < kRowsLDS.
 // ---------------------------------------------------------------------------
-constexpr int kPerThread = 8;
-constexpr int kChunk = kStreamWG * kPerThread;
-constexpr int kRowWin = kStreamWG;   // row pointers staged per pass (one per thread): kRowWin - 1 rows
+constexpr int kPerThread = 4;
+constexpr int kChunk = kSpmvWG * kPerThread;
+constexpr int kRowWin = 1024;   // row pointers staged per pass
 
 template <bool NTL, class T>
 __device__ __forceinline__ T stream_load(gptr<const T> p) {
@@ -57,10 +53,10 @@ __device__ __forceinline__ T stream_load(gptr<const T> p) {
   else return *p;
 }
 
-// LDS of spmv_stream, one allocation for all of its instantiations
+// LDS of spmv_stream, one allocation for both of its instantiations
 struct StreamLds {
   double prod[kChunk];
-  int rps[kRowWin];
+  int rps[kRowWin + 1];
   double carry;
 };
 __device__ __forceinline__ StreamLds &stream_lds() {
@@ -68,12 +64,11 @@ __device__ __forceinline__ StreamLds &stream_lds() {
   return s;
 }
 
-template <bool NTL, bool C16>
+template <bool NTL>
 __device__ void spmv_stream(gptr<const int> rp, gptr<const int> ci, gptr<const uint16_t> c16,
                             gptr<const double> va, gptr<const double> xin, gptr<double> yout,
                             double *ybuf, int r0, int r1, double scale) {
-  constexpr int NT = kStreamWG;
-  constexpr int kPast = 0x7fffffff;   // row pointer of a row past r1
+  constexpr int NT = kSpmvWG;
   StreamLds &L = stream_lds();
   double *prod = L.prod;
   int *rps = L.rps;
@@ -82,98 +77,69 @@ __device__ void spmv_stream(gptr<const int> rp, gptr<const int> ci, gptr<const u
   if (r0 >= r1) return;
   const int E0 = rp[r0], E1 = rp[r1];
   int rcur = r0;
-  if (E0 < E1) {
-    const int elast = E1 - 1;
-    auto col = [&](int e) -> int {
-      if constexpr (C16) return (int)stream_load<NTL>(c16 + e);
-      else return stream_load<NTL>(ci + e);
-    };
-    double carry = 0.0;
-    double vv[kPerThread];
-    int cc[kPerThread];
+  double carry = 0.0;
+  double vv[kPerThread];
+  int cc[kPerThread];
+#pragma unroll
+  for (int j = 0; j < kPerThread; ++j) {
+    const int e = E0 + j * NT + tid;
+    if (e < E1) {
+      vv[j] = stream_load<NTL>(va + e);
+      cc[j] = c16 ? (int)stream_load<NTL>(c16 + e) : stream_load<NTL>(ci + e);
+    } else { vv[j] = 0.0; cc[j] = -1; }
+  }
+  for (int cs = E0; cs < E1; cs += kChunk) {
+    const int ce = min(cs + kChunk, E1);
+#pragma unroll
+    for (int j = 0; j < kPerThread; ++j) prod[j * NT + tid] = cc[j] >= 0 ? vv[j] * xin[cc[j]] : 0.0;
+    // prefetch the next chunk while this one is reduced
 #pragma unroll
     for (int j = 0; j < kPerThread; ++j) {
-      const int e = min(E0 + j * NT + tid, elast);
-      vv[j] = stream_load<NTL>(va + e);
-      cc[j] = col(e);
-    }
-    for (int cs = E0; cs < E1; cs += kChunk) {
-      const int ce = min(cs + kChunk, E1);
-      // the row pointers of rows rcur .. rcur + kRowWin - 1 and this chunk's
-      // gathers in flight together; the next chunk's entries are requested
-      // once the gathers have returned (issued earlier, the operator stream
-      // delays them: 440 us against 396 us per 512^2 product)
-      int rpv = rp[min(rcur + tid, r1)];
-      double xv[kPerThread];
-#pragma unroll
-      for (int j = 0; j < kPerThread; ++j) xv[j] = xin[cc[j]];
-      if (rcur + tid > r1) rpv = kPast;
-#pragma unroll
-      for (int j = 0; j < kPerThread; ++j) prod[j * NT + tid] = vv[j] * xv[j];
-      rps[tid] = rpv;
-      __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-      for (int j = 0; j < kPerThread; ++j) {
-        const int e = min(cs + kChunk + j * NT + tid, elast);
+      const int e = cs + kChunk + j * NT + tid;
+      if (e < E1) {
         vv[j] = stream_load<NTL>(va + e);
-        cc[j] = col(e);
-      }
-      for (bool first = true;; first = false) {
-        if (!first) {   // kRowWin - 1 rows or more start in this chunk: next window
-          __syncthreads();
-          rps[tid] = (rcur + tid <= r1) ? rp[rcur + tid] : kPast;
-        }
-        const int nr = __syncthreads_count(tid < kRowWin - 1 && rcur + tid < r1 && rps[tid] < ce);
-        if (nr == 0) break;
-        for (int i = wv; i < nr; i += NT / 64) {
-          const int a = max(rps[i], cs) - cs, b = min(rps[i + 1], ce) - cs;
-          double sum = 0.0;
-          for (int q = a + lane; q < b; q += 64) sum += prod[q];
-          sum = wave_sum(sum);
-          if (lane == 0) {
-            if (i == 0) sum += carry;
-            if (rps[i + 1] <= ce) {
-              const int r = rcur + i;
-              const double yr = sum * scale;
-              yout[r] = yr;
-              if (r - r0 < kRowsLDS) ybuf[r - r0] = yr;
-            } else {
-              s_carry = sum;
-            }
+        cc[j] = c16 ? (int)stream_load<NTL>(c16 + e) : stream_load<NTL>(ci + e);
+      } else { vv[j] = 0.0; cc[j] = -1; }
+    }
+    for (;;) {
+      __syncthreads();
+      rps[tid] = (rcur + tid <= r1) ? rp[rcur + tid] : 0x7fffffff;
+      if (tid == 0) rps[kRowWin] = (rcur + kRowWin <= r1) ? rp[rcur + kRowWin] : 0x7fffffff;
+      __syncthreads();
+      const int nr = __syncthreads_count(rcur + tid < r1 && rps[tid] < ce);
+      if (nr == 0) break;
+      for (int i = wv; i < nr; i += NT / 64) {
+        const int a = max(rps[i], cs) - cs, b = min(rps[i + 1], ce) - cs;
+        double sum = 0.0;
+        for (int q = a + lane; q < b; q += 64) sum += prod[q];
+        sum = wave_sum(sum);
+        if (lane == 0) {
+          if (i == 0) sum += carry;
+          if (rps[i + 1] <= ce) {
+            const int r = rcur + i;
+            const double yr = sum * scale;
+            yout[r] = yr;
+            if (r - r0 < kRowsLDS) ybuf[r - r0] = yr;
+          } else {
+            s_carry = sum;
           }
         }
-        // read before the barrier: past it, the next chunk rewrites rps
-        const bool cont = rps[nr] > ce;   // the last row continues into the next chunk
-        __syncthreads();
-        if (cont) {
-          carry = s_carry;
-          rcur += nr - 1;
-          break;
-        }
-        carry = 0.0;
-        rcur += nr;
-        if (nr < kRowWin - 1) break;
       }
+      __syncthreads();
+      if (rps[nr] > ce) {             // the last row continues into the next chunk
+        carry = s_carry;
+        rcur += nr - 1;
+        break;
+      }
+      carry = 0.0;
+      rcur += nr;
+      if (nr < kRowWin) break;
     }
   }
   // rows after the last nonzero are empty
   for (int r = rcur + tid; r < r1; r += NT) {
     yout[r] = 0.0;
     if (r - r0 < kRowsLDS) ybuf[r - r0] = 0.0;
-  }
-}
-
-// One of the four instantiations of spmv_stream (the choice is uniform).
-__device__ __forceinline__ void spmv_stream_any(bool ntl, gptr<const int> rp, gptr<const int> ci,
-                                                gptr<const uint16_t> c16, gptr<const double> va,
-                                                gptr<const double> xin, gptr<double> yout,
-                                                double *ybuf, int r0, int r1, double scale) {
-  if (c16) {
-    if (ntl) spmv_stream<true, true>(rp, ci, c16, va, xin, yout, ybuf, r0, r1, scale);
-    else spmv_stream<false, true>(rp, ci, c16, va, xin, yout, ybuf, r0, r1, scale);
-  } else {
-    if (ntl) spmv_stream<true, false>(rp, ci, c16, va, xin, yout, ybuf, r0, r1, scale);
-    else spmv_stream<false, false>(rp, ci, c16, va, xin, yout, ybuf, r0, r1, scale);
   }
 }
 
@@ -196,22 +162,20 @@ __device__ void spmv_rows64(gptr<const int> __restrict__ rp, gptr<const int> __r
     for (int base = e0; base < e1; base += 64 * kRowSlots) {
       double v[kRowSlots];
       int c[kRowSlots];
-      // unconditional loads (indices clamped to the row's last nonzero), so
-      // that all of them are in flight at once; the clamped slots are dropped
 #pragma unroll
       for (int u = 0; u < kRowSlots; ++u) {
-        const int e = min(base + u * 64 + lane, e1 - 1);
-        v[u] = __builtin_nontemporal_load(va + e);
-        c[u] = __builtin_nontemporal_load(ci + e);
+        const int e = base + u * 64 + lane;
+        const bool ok = e < e1;
+        v[u] = ok ? __builtin_nontemporal_load(va + e) : 0.0;
+        c[u] = ok ? __builtin_nontemporal_load(ci + e) : 0;
       }
       double xv[kRowSlots];
 #pragma unroll
-      for (int u = 0; u < kRowSlots; ++u) xv[u] = xin[c[u]];
+      for (int u = 0; u < kRowSlots; ++u) xv[u] = (base + u * 64 < e1) ? xin[c[u]] : 0.0;
 #pragma unroll
       for (int u = 0; u < kRowSlots; u += 2) {
-        const int e = base + u * 64 + lane;
-        a0 += e < e1 ? v[u] * xv[u] : 0.0;
-        a1 += e + 64 < e1 ? v[u + 1] * xv[u + 1] : 0.0;
+        a0 += v[u] * xv[u];
+        a1 += v[u + 1] * xv[u + 1];
       }
     }
     double sum = wave_sum(a0 + a1);
@@ -290,9 +254,9 @@ __device__ void spmv_sell(gptr<const int> __restrict__ soff, gptr<const int> __r
 // cooperate on a row, four independent loads per lane in flight.
 // ---------------------------------------------------------------------------
 template <int VW, bool ISA>
-__global__ void __launch_bounds__(spmv_threads(VW), 8) k_spmv(const Dev *__restrict__ devs,
-                                                               const int2 *__restrict__ map, int k) {
-  constexpr int NT = spmv_threads(VW);
+__global__ void __launch_bounds__(kSpmvWG, 8) k_spmv(const Dev *__restrict__ devs,
+                                                      const int2 *__restrict__ map, int k) {
+  constexpr int NT = kSpmvWG;
   const int2 bm = map[blockIdx.x];
   const Dev &D = devs[bm.x];
   if (skip_iter(D, k)) return;
@@ -337,8 +301,7 @@ __global__ void __launch_bounds__(spmv_threads(VW), 8) k_spmv(const Dev *__restr
     // SELL-64: the workgroup's rows are its slice range
     const int nsl = ISA ? D.Ansl : D.Bnsl;
     const int rows = ISA ? D.m : D.n;
-    const int nw = ISA ? D.nwsA : D.nwsB;
-    const int s0 = (int)((long long)wid * nsl / nw), s1 = (int)((long long)(wid + 1) * nsl / nw);
+    const int s0 = (int)((long long)wid * nsl / D.nws), s1 = (int)((long long)(wid + 1) * nsl / D.nws);
     r0 = min(rows, s0 * kSellC);
     r1 = min(rows, s1 * kSellC);
     __shared__ double lds_part[(kSpmvWG / 64) * kSellC];
@@ -355,8 +318,10 @@ __global__ void __launch_bounds__(spmv_threads(VW), 8) k_spmv(const Dev *__restr
     if (ISA) beam_forward_rows(D, (const double *)xin, (double *)yout, ybuf, r0, r1, scale, NT);
     else beam_back_rows(D, (const double *)xin, (double *)yout, ybuf, r0, r1, scale, NT);
   } else if (VW == 0) {
-    spmv_stream_any(ISA ? D.ntA : D.ntB, rp, ci, gmem(ISA ? D.Aci16 : D.Bci16), va, xin, yout,
-                    ybuf, r0, r1, scale);
+    if (ISA ? D.ntA : D.ntB)
+      spmv_stream<true>(rp, ci, gmem(ISA ? D.Aci16 : D.Bci16), va, xin, yout, ybuf, r0, r1, scale);
+    else
+      spmv_stream<false>(rp, ci, gmem(ISA ? D.Aci16 : D.Bci16), va, xin, yout, ybuf, r0, r1, scale);
   } else if (VW == 64) {
     spmv_rows64(rp, ci, va, xin, yout, ybuf, r0, r1, scale);
   } else {
@@ -423,8 +388,8 @@ __global__ void __launch_bounds__(spmv_threads(VW), 8) k_spmv(const Dev *__restr
 // epilogue): what the initialisation times to choose the kernel per operator.
 // ---------------------------------------------------------------------------
 template <int VW, bool ISA>
-__global__ void __launch_bounds__(spmv_threads(VW), 8) k_spmv_core(Dev D, const double *__restrict__ xin,
-                                                                  double *yout) {
+__global__ void __launch_bounds__(kSpmvWG, 8) k_spmv_core(Dev D, const double *__restrict__ xin,
+                                                         double *yout) {
   __shared__ double ybuf[kRowsLDS];
   const int wid = blockIdx.x;
   const gptr<const int> rp = gmem(ISA ? D.Arp : D.Brp);
@@ -436,8 +401,7 @@ __global__ void __launch_bounds__(spmv_threads(VW), 8) k_spmv_core(Dev D, const 
   if (VW == 1) {
     const int nsl = ISA ? D.Ansl : D.Bnsl;
     const int rows = ISA ? D.m : D.n;
-    const int nw = ISA ? D.nwsA : D.nwsB;
-    const int s0 = (int)((long long)wid * nsl / nw), s1 = (int)((long long)(wid + 1) * nsl / nw);
+    const int s0 = (int)((long long)wid * nsl / D.nws), s1 = (int)((long long)(wid + 1) * nsl / D.nws);
     __shared__ double lds_part[(kSpmvWG / 64) * kSellC];
     spmv_sell(gmem(ISA ? D.Asoff : D.Bsoff), gmem(ISA ? D.Aslen : D.Bslen),
               gmem(ISA ? D.Ascol : D.Bscol), gmem(ISA ? D.Ascol16 : D.Bscol16),
@@ -448,8 +412,12 @@ __global__ void __launch_bounds__(spmv_threads(VW), 8) k_spmv_core(Dev D, const 
     if (ISA) beam_forward_rows(D, xin, yout, ybuf, part[wid], part[wid + 1], 1.0, kSpmvWG);
     else beam_back_rows(D, xin, yout, ybuf, part[wid], part[wid + 1], 1.0, kSpmvWG);
   } else {
-    spmv_stream_any(ISA ? D.ntA : D.ntB, rp, ci, gmem(ISA ? D.Aci16 : D.Bci16), va, xg, yg, ybuf,
-                    part[wid], part[wid + 1], 1.0);
+    if (ISA ? D.ntA : D.ntB)
+      spmv_stream<true>(rp, ci, gmem(ISA ? D.Aci16 : D.Bci16), va, xg, yg, ybuf, part[wid],
+                        part[wid + 1], 1.0);
+    else
+      spmv_stream<false>(rp, ci, gmem(ISA ? D.Aci16 : D.Bci16), va, xg, yg, ybuf, part[wid],
+                         part[wid + 1], 1.0);
   }
 }
 
@@ -1059,12 +1027,12 @@ __global__ void __launch_bounds__(kWG) k_true_stop(Dev D, int k) {
   if (true_iter_off(D, k)) return;
   __shared__ double lds_w[kMaxQ * (kWG / 64)];
   __shared__ double tot[kMaxQ];
-  // the producers of kStageTrue are the nwsA row ranges of the A products
+  // the producers of kStageTrue are the nws SpMV row ranges
   const gptr<const double> p = gmem(part_of(D, kStageTrue));
   double acc[kMaxQ];
 #pragma unroll
   for (int q = 0; q < kMaxQ; ++q) acc[q] = 0.0;
-  for (int i = threadIdx.x; i < D.nwsA; i += kWG) acc[0] += p[i];
+  for (int i = threadIdx.x; i < D.nws; i += kWG) acc[0] += p[i];
   block_sum<kWG>(acc, 1, lds_w, tot);
   if (threadIdx.x != 0) return;
   const double r = sqrt(tot[0]);
@@ -1388,8 +1356,8 @@ __global__ void k_collect_halt(const Dev *__restrict__ devs, int n, int k, int *
 // Launch geometry of one batch of instances (device arrays built by the host).
 template <bool ISA>
 static void launch_spmv_vw(const Launch &L, int k, int vw, hipStream_t st) {
-  const dim3 g(ISA ? L.nspmvA : L.nspmvB), b(spmv_threads(vw));
-  const int2 *map = ISA ? L.map_spmvA : L.map_spmvB;
+  const dim3 g(L.nspmv), b(kSpmvWG);
+  const int2 *map = L.map_spmv;
   switch (vw) {
     case 8: hipLaunchKernelGGL((k_spmv<8, ISA>), g, b, 0, st, L.devs, map, k); break;
     case 16: hipLaunchKernelGGL((k_spmv<16, ISA>), g, b, 0, st, L.devs, map, k); break;
@@ -1401,14 +1369,11 @@ static void launch_spmv_vw(const Launch &L, int k, int vw, hipStream_t st) {
   }
 }
 
-// resident workgroups per CU of the SpMV kernel vw (the grid of a product is
-// sized to one wave of workgroups); vw < 0: the 1024-thread kernels
-int spmv_blocks_per_cu(int vw) {
+// resident SpMV workgroups per CU (the grid is sized to one wave of workgroups)
+int spmv_blocks_per_cu() {
   int nb = 0;
-  hipError_t e = vw == 0
-      ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_spmv<0, true>, spmv_threads(0), 0)
-      : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_spmv<1, true>, spmv_threads(1), 0);
-  if (e != hipSuccess) return 1;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_spmv<0, true>, kSpmvWG, 0) != hipSuccess)
+    return 1;
   return nb > 0 ? nb : 1;
 }
 
@@ -1473,7 +1438,7 @@ void launch_collect_halt(const Launch &L, int k, int *out, hipStream_t st) {
 }
 // one launch of the core of SpMV kernel vw (0, 1 or 64) for A (isa) or B
 void launch_spmv_core(const Dev &D, bool isa, int vw, const double *x, double *y, hipStream_t st) {
-  const dim3 g(isa ? D.nwsA : D.nwsB), b(spmv_threads(vw));
+  const dim3 g(D.nws), b(kSpmvWG);
   if (vw == 3) {
     if (isa) hipLaunchKernelGGL((k_spmv_core<3, true>), g, b, 0, st, D, x, y);
     else hipLaunchKernelGGL((k_spmv_core<3, false>), g, b, 0, st, D, x, y);
@@ -1643,20 +1608,20 @@ void launch_true_iter(const Dev &D, int k, hipStream_t st) {
   hipLaunchKernelGGL(k_xres, dim3(nb), dim3(kWG), sizeof(double) * (size_t)max(1, k), st, D, k);
   if (D.vwA == 3) {
     launch_spmv_core(D, true, 3, D.xres, D.mscr, st);
-    hipLaunchKernelGGL(k_resid_ax, dim3(D.nwsA), dim3(kWG), 0, st, D, (const double *)D.mscr,
+    hipLaunchKernelGGL(k_resid_ax, dim3(D.nws), dim3(kWG), 0, st, D, (const double *)D.mscr,
                        (int)kStageTrue, k);
   } else {
-    hipLaunchKernelGGL(k_true_res_iter, dim3(D.nwsA), dim3(kWG), 0, st, D, k);
+    hipLaunchKernelGGL(k_true_res_iter, dim3(D.nws), dim3(kWG), 0, st, D, k);
   }
   hipLaunchKernelGGL(k_true_stop, dim3(1), dim3(kWG), 0, st, D, k);
 }
 void launch_true_residual(const Dev &D, const double *x, double *out, hipStream_t st) {
   if (D.vwA == 3) {
     launch_spmv_core(D, true, 3, x, D.mscr, st);
-    hipLaunchKernelGGL(k_resid_ax, dim3(D.nwsA), dim3(kWG), 0, st, D, (const double *)D.mscr,
+    hipLaunchKernelGGL(k_resid_ax, dim3(D.nws), dim3(kWG), 0, st, D, (const double *)D.mscr,
                        (int)kStageMisc, 0);
   } else {
-    hipLaunchKernelGGL(k_true_residual, dim3(D.nwsA), dim3(kWG), 0, st, D, x);
+    hipLaunchKernelGGL(k_true_residual, dim3(D.nws), dim3(kWG), 0, st, D, x);
   }
   hipLaunchKernelGGL(k_finish_misc, dim3(1), dim3(kWG), 0, st, D, out);
 }
