@@ -352,17 +352,28 @@ def tile_order(N: int, tile: int = 4) -> np.ndarray:
     return perm
 
 
-def batch_instances(count: int = 32, sides=(128, 192, 256, 384), seed: int = 4,
-                    max_side: int | None = None) -> list[Problem]:
-    """Heterogeneous batch: sides drawn uniformly, own phantom, noise U[0.5%, 3%].
-    Instances of equal side share the (cached, read-only) projection matrix."""
+def batch_instance_sides(count: int = 32, sides=(128, 192, 256, 384), seed: int = 4,
+                         max_side: int | None = None) -> list[tuple[int, float]]:
+    """(side, noise level) of each instance of batch_instances, without building them."""
     rng = np.random.default_rng(SEED_PHANTOM + seed)
     out = []
-    for i in range(count):
+    for _ in range(count):
         side = int(rng.choice(sides))
         if max_side is not None:
             side = min(side, max_side)
-        level = float(rng.uniform(0.005, 0.03))
+        out.append((side, float(rng.uniform(0.005, 0.03))))
+    return out
+
+
+def batch_instances(count: int = 32, sides=(128, 192, 256, 384), seed: int = 4,
+                    max_side: int | None = None, select=None) -> list[Problem]:
+    """Heterogeneous batch: sides drawn uniformly, own phantom, noise U[0.5%, 3%].
+    Instances of equal side share the (cached, read-only) projection matrix.
+    select: indices of the instances to build (default: all), in that order."""
+    drawn = batch_instance_sides(count, sides, seed, max_side)
+    out = []
+    for i in (range(count) if select is None else select):
+        side, level = drawn[i]
         na, nd = geometry_for_side(side)
         out.append(ct_problem(side, na, nd, phantom="ellipses", noise=level,
                               seed_offset=seed + INSTANCE_STRIDE * (i + 1),

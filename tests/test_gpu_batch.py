@@ -97,3 +97,45 @@ def test_batch_resume_and_per_instance_capacity():
         assert rel(x, orc.x) <= 1e-8
     with pytest.raises(sfk.SfkError):
         sfk.iterate(ctx, 1)            # largest capacity (9) exhausted
+
+
+def test_heterogeneous_batch_at_benchmark_sizes():
+    """The heterogeneous benchmark's batch at its own sizes: its first four
+    instances (one of each side 256, 128, 384, 192; 1.9e6 to 5.1e7 nonzeros),
+    4 x 4 tile order, sFLSQR, sparse-sign s = 201, discrepancy stop eta = 1.01.
+    Each instance's stopping iteration, x at the stop and rho_k against the
+    oracle (1e-8; the stops come before the reproducibility horizon), and
+    against the same instance solved on its own."""
+    from paper_2605_22281_amd import sfk
+    count, sel = 32, [0, 1, 2, 3]
+    drawn = inputs.batch_instance_sides(count)
+    assert sorted(drawn[i][0] for i in sel) == [128, 192, 256, 384]
+    probs = inputs.batch_instances(count, select=sel)
+    say("case: heterogeneous batch at the benchmark sizes, sides", [P.N for P in probs])
+    perms = [inputs.tile_order(P.N, 4) for P in probs]
+    As = [sfk.to_device_csr(P.A) for P in probs]
+    bs = [torch.from_numpy(np.ascontiguousarray(P.b)).cuda() for P in probs]
+    pts = [torch.from_numpy(pm).cuda() for pm in perms]
+    maxit, s = 100, 201
+    ps = [sfk.params("sflsqr", ell=2, maxit=maxit, sketch="sparse_sign", s=s, zeta=8, seed=5000 + i,
+                     noise_norm=P.noise_norm, eta=1.01, perm=pts[j])
+          for j, (i, P) in enumerate(zip(sel, probs))]
+    ctx = sfk.init_batch(As, None, bs, ps)
+    sfk.iterate(ctx, maxit)
+    for j, (i, P) in enumerate(zip(sel, probs)):
+        k_i, stopped_i, brk = sfk.instance_status(ctx, j)
+        S = sketches.SparseSign(P.m, s, 8, 5000 + i)
+        tol = fgk.discrepancy_tol(1.01, P.noise_norm, np.linalg.norm(P.b))
+        orc = fgk.sketched_flexible(P.A, P.b, S, maxit=maxit, ell=2, tol=tol)
+        assert stopped_i and not brk and k_i == orc.k, (j, k_i, orc.k)
+        x = sfk.instance_solution(ctx, j, P.n).cpu().numpy()
+        rho, _ = sfk.instance_residual_norms(ctx, j, k_i)
+        assert rel(x, orc.x) <= 1e-8, (j, rel(x, orc.x))
+        assert np.all(np.abs(rho[:k_i] - orc.rho[:k_i]) <= 1e-8 * orc.rho[:k_i]), j
+        _, Xp, _, _, _ = gpu_run(P, "sflsqr", "sparse_sign", s, maxit, seed=5000 + i,
+                                 noise=P.noise_norm, eta=1.01, perm=perms[j], stepwise=False)
+        assert Xp.shape[1] == k_i
+        assert rel(x, Xp[:, -1]) <= 1e-10
+        say(f"instance {i} side {P.N} nnz {P.A.nnz}: stop k = {k_i} (oracle {orc.k}), "
+            f"rel err vs oracle {rel(x, orc.x):.1e}")
+    sfk.destroy(ctx)

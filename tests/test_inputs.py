@@ -86,6 +86,13 @@ def test_batch_instances_uneven():
         assert p.A.shape == (na * nd, p.N * p.N)
         lvl = p.noise_norm / np.linalg.norm(p.A @ p.x_true)
         assert 0.005 <= lvl <= 0.03
+    # a selection builds the same instances as the whole batch
+    drawn = inputs.batch_instance_sides(count=6, sides=(16, 24, 32), seed=4)
+    assert [d[0] for d in drawn] == [p.N for p in insts]
+    sub = inputs.batch_instances(count=6, sides=(16, 24, 32), seed=4, select=[4, 1])
+    for q, i in zip(sub, (4, 1)):
+        assert q.N == insts[i].N and np.array_equal(q.b, insts[i].b)
+        assert np.array_equal(q.x_true, insts[i].x_true)
 
 
 def test_random_sparse_problem_has_empty_rows():
