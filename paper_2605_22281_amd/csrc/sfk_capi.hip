@@ -634,11 +634,17 @@ static int pick_vw(int64_t nnz, int64_t rows, int user) {
   return 8;
 }
 
+// Workgroups of the data-parallel stages: one per 8192 nonzeros, and at least
+// one per CU while each still gets 2048 nonzeros (a small operator's product
+// is a chain of chunk latencies per workgroup: on the 64^2 workload 230
+// workgroups instead of 58 take it from 18.9k to 23.8k iterations/s), one per
+// 2048 rows at least; at most one wave of resident workgroups.
 static int default_nws(const sfk_csr *A, const sfk_csr *B, const sfk_params *p, int cus,
                        int blocks_per_cu) {
   const int64_t nnzmax = std::max(A->nnz, B ? B->nnz : A->nnz);
   const int cap = cus * (p->wg_per_cu ? p->wg_per_cu : std::max(1, blocks_per_cu));
   int64_t nw = (nnzmax + 8191) / 8192;
+  nw = std::max<int64_t>(nw, std::min<int64_t>(cus, (nnzmax + 2047) / 2048));
   nw = std::max<int64_t>(nw, (std::max(A->rows, A->cols) + 2047) / 2048);
   nw = std::min<int64_t>(std::max<int64_t>(nw, 1), cap);
   return (int)nw;
