@@ -206,10 +206,10 @@ static void collect_stage_times(sfk_ctx *c) {
 // One lockstep iteration k of Algorithm 1 (sFLSQR) / Algorithm 2 (sFLSMR) for
 // every instance.  The data-parallel stages A, B, C, D run on the context's
 // stream; the sketch of the new vector and the least-squares update run on the
-// side stream as soon as their input exists.  The raw products are
-// double-buffered by iteration parity, so iteration k + 2 waits for the sketch
-// of iteration k only.  The reweighting needs y_k before D(k), so it waits for
-// LS(k).
+// side stream as soon as their input exists.  The raw products are kept in a
+// ring of kRawSlots slots, so the main stream waits for the side stream only
+// every few iterations (enqueue_iteration).  The reweighting needs y_k before
+// D(k), so it waits for LS(k).
 static void run_stage(sfk_ctx *c, int stage, int k, hipStream_t st) {
   if (c->multi) {
     launch_group_stage(c->grp, stage, k, st);
