@@ -1258,6 +1258,8 @@ static sfk_status build_launch(sfk_ctx *c) {
   L.smax = smax;
   L.maxitmax = maxitmax;
   L.tau = c->any_rew ? 1 : 0;
+  L.ellmax = 0;
+  for (int i = 0; i < nb; ++i) L.ellmax = std::max(L.ellmax, c->inst[i].D.ell);
   // one launch serves every instance, so all run one SpMV kernel: instance 0's
   // when every instance has its data, else CSR-stream (valid for all)
   L.vwA = c->inst[0].D.vwA;
@@ -2373,6 +2375,7 @@ extern "C" sfk_status sfk_solve_noalloc(const sfk_csr *A, const sfk_csr *B, cons
   L.smax = D.s;
   L.maxitmax = D.maxit;
   L.tau = D.tau;
+  L.ellmax = D.ell;
   L.vwA = D.vwA;
   L.vwB = D.vwB;
   HIPCHK(nullptr, hipMemcpyAsync(hb + o_dev, &D, sizeof(Dev), hipMemcpyHostToDevice, st));

@@ -149,6 +149,7 @@ struct Launch {
   const int2 *map_spmv, *map_vec, *map_sg, *map_sb, *map_sc;
   int nspmv, nvec, nsg, nsb, nsc;   // grid sizes
   int ninst, smax, maxitmax, tau, vwA, vwB;
+  int ellmax;         // largest orthogonalisation window of the instances
 };
 
 // Right-hand sides that share one operator pair A, B (a group): the long

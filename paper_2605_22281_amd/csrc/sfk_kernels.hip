@@ -423,7 +423,13 @@ __global__ void __launch_bounds__(kSpmvWG, 8) k_spmv_core(Dev D, const double *_
 
 // ---------------------------------------------------------------------------
 // B(k): consumes A(k) (dots, ||w||) -> h_jk; w~_{k+1} = w - sum h_jk w_j
+// E: window slots compiled in (3 serves ell <= 2, kMaxEll + 1 any ell).  Every
+// load of an element is issued before its arithmetic: the slots past the
+// window read the raw product instead (a valid vector of the same length, the
+// value unused), so that no load sits in a branch of its own, where the
+// compiler waits for each before issuing the next.
 // ---------------------------------------------------------------------------
+template <int E>
 __global__ void __launch_bounds__(kWG) k_wupdate(const Dev *__restrict__ devs,
                                                 const int2 *__restrict__ map, int k) {
   const int2 bm = map[blockIdx.x];
@@ -438,15 +444,15 @@ __global__ void __launch_bounds__(kWG) k_wupdate(const Dev *__restrict__ devs,
   consume<kWG>(D, kStageA, nwin + 1, lds_w, tot);
   if (threadIdx.x == 0) finish_w_coeffs(D, k, tot, s_cf, wid == 0);
   __syncthreads();
-  gptr<const double> win[kMaxEll + 1];
-  double cf[kMaxEll + 1];
-#pragma unroll
-  for (int q = 0; q < kMaxEll + 1; ++q) {
-    win[q] = (q < nwin) ? gmem(wvec(D, j0 + q)) : nullptr;
-    cf[q] = (q < nwin) ? s_cf[q] : 0.0;
-  }
   const gptr<const double> wr = gmem(wrawk(D, k));
   const gptr<double> out = gmem(wvec(D, k + 1));
+  gptr<const double> win[E];
+  double cf[E];
+#pragma unroll
+  for (int q = 0; q < E; ++q) {
+    win[q] = (q < nwin) ? gmem(wvec(D, j0 + q)) : wr;
+    cf[q] = (q < nwin) ? s_cf[q] : 0.0;
+  }
   int i0, i1;
   chunk_range(D.m, D.nwv, wid, i0, i1);
   double acc[kMaxQ];
@@ -454,14 +460,16 @@ __global__ void __launch_bounds__(kWG) k_wupdate(const Dev *__restrict__ devs,
   for (int q = 0; q < kMaxQ; ++q) acc[q] = 0.0;
   for (int i = i0 + threadIdx.x; i < i1; i += kWG) {
     double v = wr[i];
-    double wj[kMaxEll + 1];
+    double wj[E];
 #pragma unroll
-    for (int q = 0; q < kMaxEll + 1; ++q)
-      if (q < nwin) { wj[q] = win[q][i]; v -= cf[q] * wj[q]; }
+    for (int q = 0; q < E; ++q) wj[q] = win[q][i];
+#pragma unroll
+    for (int q = 0; q < E; ++q)
+      if (q < nwin) v -= cf[q] * wj[q];
     out[i] = v;
     acc[0] += v * v;
 #pragma unroll
-    for (int q = 0; q < kMaxEll + 1; ++q)
+    for (int q = 0; q < E; ++q)
       if (q < nwin) acc[1 + q] += v * wj[q];
   }
   produce<kWG>(D, kStageB, wid, nwin + 1, acc, lds_w, blk);
@@ -472,6 +480,7 @@ __global__ void __launch_bounds__(kWG) k_wupdate(const Dev *__restrict__ devs,
 // z~_{k+1} = tau(p~_{k+1}) for the identity and the reweighting.  k = 0 is the initial step (empty window, x_0 = 0).
 // The reweighting assembles x_k = Z_k y_k on the fly (y_k from LS(k)).
 // ---------------------------------------------------------------------------
+template <int E>
 __global__ void __launch_bounds__(kWG) k_pupdate(const Dev *__restrict__ devs,
                                                 const int2 *__restrict__ map, int k) {
   const int2 bm = map[blockIdx.x];
@@ -491,14 +500,14 @@ __global__ void __launch_bounds__(kWG) k_pupdate(const Dev *__restrict__ devs,
   if (rew)
     for (int j = threadIdx.x; j < k; j += kWG) coefx[j] = D.sigp[j + 1] * D.y[j];
   __syncthreads();
-  gptr<const double> win[kMaxEll + 1];
-  double cf[kMaxEll + 1];
+  const gptr<const double> zr = gmem(zrawk(D, k));
+  gptr<const double> win[E];     // past the window: the raw product (see k_wupdate)
+  double cf[E];
 #pragma unroll
-  for (int q = 0; q < kMaxEll + 1; ++q) {
-    win[q] = (q < nwin) ? gmem(pvec(D, j0 + q)) : nullptr;
+  for (int q = 0; q < E; ++q) {
+    win[q] = (q < nwin) ? gmem(pvec(D, j0 + q)) : zr;
     cf[q] = (q < nwin) ? s_cf[q] : 0.0;
   }
-  const gptr<const double> zr = gmem(zrawk(D, k));
   const gptr<double> zout = gmem(D.Z + (size_t)k * D.n);
   // tau = I: p~ is stored as the basis column itself; otherwise in the P ring
   // (the low-rank operators then write z~ in a stage of their own)
@@ -513,10 +522,12 @@ __global__ void __launch_bounds__(kWG) k_pupdate(const Dev *__restrict__ devs,
   for (int q = 0; q < kMaxQ; ++q) acc[q] = 0.0;
   for (int i = i0 + threadIdx.x; i < i1; i += kWG) {
     double v = zr[i];
-    double pj[kMaxEll + 1];
+    double pj[E];
 #pragma unroll
-    for (int q = 0; q < kMaxEll + 1; ++q)
-      if (q < nwin) { pj[q] = win[q][i]; v -= cf[q] * pj[q]; }
+    for (int q = 0; q < E; ++q) pj[q] = win[q][i];
+#pragma unroll
+    for (int q = 0; q < E; ++q)
+      if (q < nwin) v -= cf[q] * pj[q];
     pout[i] = v;
     if (rew) {
       double xi = 0.0;
@@ -526,7 +537,7 @@ __global__ void __launch_bounds__(kWG) k_pupdate(const Dev *__restrict__ devs,
     }
     acc[0] += v * v;
 #pragma unroll
-    for (int q = 0; q < kMaxEll + 1; ++q)
+    for (int q = 0; q < E; ++q)
       if (q < nwin) acc[1 + q] += v * pj[q];
   }
   produce<kWG>(D, kStageD, wid, nwin + 1, acc, lds_w, blk);
@@ -1380,11 +1391,13 @@ int spmv_blocks_per_cu() {
 void launch_stage_A(const Launch &L, int k, hipStream_t st) { launch_spmv_vw<true>(L, k, L.vwA, st); }
 void launch_stage_C(const Launch &L, int k, hipStream_t st) { launch_spmv_vw<false>(L, k, L.vwB, st); }
 void launch_stage_B(const Launch &L, int k, hipStream_t st) {
-  hipLaunchKernelGGL(k_wupdate, dim3(L.nvec), dim3(kWG), 0, st, L.devs, L.map_vec, k);
+  if (L.ellmax <= 2) hipLaunchKernelGGL((k_wupdate<3>), dim3(L.nvec), dim3(kWG), 0, st, L.devs, L.map_vec, k);
+  else hipLaunchKernelGGL((k_wupdate<kMaxEll + 1>), dim3(L.nvec), dim3(kWG), 0, st, L.devs, L.map_vec, k);
 }
 void launch_stage_D(const Launch &L, int k, hipStream_t st) {
   const size_t sh = L.tau == 1 ? sizeof(double) * (size_t)max(1, k) : 0;
-  hipLaunchKernelGGL(k_pupdate, dim3(L.nvec), dim3(kWG), sh, st, L.devs, L.map_vec, k);
+  if (L.ellmax <= 2) hipLaunchKernelGGL((k_pupdate<3>), dim3(L.nvec), dim3(kWG), sh, st, L.devs, L.map_vec, k);
+  else hipLaunchKernelGGL((k_pupdate<kMaxEll + 1>), dim3(L.nvec), dim3(kWG), sh, st, L.devs, L.map_vec, k);
 }
 
 // sketch of iteration k (k = 0: the initial sketch) for every instance
