@@ -116,17 +116,24 @@ __device__ __forceinline__ int producers(const Dev &D, int stage) {
 
 // Totals of the Q partial sums that the previous stage left, in a fixed order
 // (every workgroup obtains identical values).
+// Every row is read unconditionally (rows from Q on re-read row Q - 1, cached,
+// their values unused), so that the loads of a producer are in flight
+// together instead of one branch and one wait each.
 template <int NT>
 __device__ __forceinline__ void consume(const Dev &D, int stage, int Q, double *lds_w, double *tot) {
   const gptr<const double> p = gmem(part_of(D, stage));
   const int np = producers(D, stage);
+  const int qlast = Q > 0 ? Q - 1 : 0;
   double acc[kMaxQ];
 #pragma unroll
   for (int q = 0; q < kMaxQ; ++q) acc[q] = 0.0;
   for (int i = threadIdx.x; i < np; i += NT) {
+    double v[kMaxQ];
+#pragma unroll
+    for (int q = 0; q < kMaxQ; ++q) v[q] = p[(size_t)min(q, qlast) * D.nwmax + i];
 #pragma unroll
     for (int q = 0; q < kMaxQ; ++q)
-      if (q < Q) acc[q] += p[(size_t)q * D.nwmax + i];
+      if (q < Q) acc[q] += v[q];
   }
   block_sum<NT>(acc, Q, lds_w, tot);
 }
