@@ -152,7 +152,8 @@ __device__ __forceinline__ int ld_flag(const int *p) {
 // stages of iteration k run only while the instance is live, within its
 // capacity, and while its basis reaches k
 __device__ __forceinline__ bool skip_iter(const Dev &D, int k) {
-  return k > D.maxit || ld_flag(&D.sc->halt) != 0 || k > ld_flag(&D.sc->klimit);
+  const int halt = ld_flag(&D.sc->halt), klimit = ld_flag(&D.sc->klimit);   // both in flight
+  return k > D.maxit || halt != 0 || k > klimit;
 }
 
 __device__ __forceinline__ void chunk_range(int d, int nw, int wid, int &i0, int &i1) {
@@ -205,19 +206,47 @@ __device__ inline double finish_p_norm(const Dev &D, int k, const double *tot, b
 
 // after A(k): h_jk by modified Gram-Schmidt over the window j = max(1,k-ell)..k,
 // h_q = <w_jq, w> - sum_{i<q} h_i <w_jq, w_ji>.  cf[q] = h_q * sigw_jq multiplies w~_jq.
+// E: window slots of the caller (nwin <= E).  With a small E every input is
+// loaded first, all at once (indices past the window clamped to its last
+// entry, values unused), then combined in the same order as the loop form.
+template <int E>
 __device__ inline void finish_w_coeffs(const Dev &D, int k, const double *tot, double *cf,
                                        bool store) {
   Scal *sc = D.sc;
   const int j0 = wwin0(D, k), nwin = k - j0 + 1;
   const int ns = D.ell + 2, ldh = D.maxit + 1;
-  double h[kMaxEll + 1];
-  for (int q = 0; q < nwin; ++q) {
-    const int jq = j0 + q;
-    double t = D.sigw[jq] * tot[q];
-    for (int i = 0; i < q; ++i) t -= h[i] * sc->Gw[wslot(D, jq) * ns + wslot(D, j0 + i)];
-    h[q] = t;
-    cf[q] = t * D.sigw[jq];
-    if (store) D.H[(size_t)(k - 1) * ldh + (jq - 1)] = t;
+  if constexpr (E <= 3) {
+    double sg[E], G[E][E];
+#pragma unroll
+    for (int q = 0; q < E; ++q) {
+      const int jq = j0 + max(0, min(q, nwin - 1));
+      sg[q] = D.sigw[jq];
+#pragma unroll
+      for (int i = 0; i < q; ++i)
+        G[q][i] = sc->Gw[wslot(D, jq) * ns + wslot(D, j0 + max(0, min(i, nwin - 1)))];
+    }
+    double h[E];
+#pragma unroll
+    for (int q = 0; q < E; ++q) {
+      if (q < nwin) {
+        double t = sg[q] * tot[q];
+#pragma unroll
+        for (int i = 0; i < q; ++i) t -= h[i] * G[q][i];
+        h[q] = t;
+        cf[q] = t * sg[q];
+        if (store) D.H[(size_t)(k - 1) * ldh + (j0 + q - 1)] = t;
+      }
+    }
+  } else {
+    double h[kMaxEll + 1];
+    for (int q = 0; q < nwin; ++q) {
+      const int jq = j0 + q;
+      double t = D.sigw[jq] * tot[q];
+      for (int i = 0; i < q; ++i) t -= h[i] * sc->Gw[wslot(D, jq) * ns + wslot(D, j0 + i)];
+      h[q] = t;
+      cf[q] = t * D.sigw[jq];
+      if (store) D.H[(size_t)(k - 1) * ldh + (jq - 1)] = t;
+    }
   }
   if (store) sc->wpre = sqrt(tot[nwin]);
 }
@@ -253,21 +282,46 @@ __device__ inline double finish_w_norm(const Dev &D, int k, const double *tot, b
 }
 
 // after C(k): t_{j,k+1} by modified Gram-Schmidt over j = max(1,k+1-ell)..k;
-// cf[q] multiplies p~_jq.
+// cf[q] multiplies p~_jq.  E as in finish_w_coeffs (the window may be empty).
+template <int E>
 __device__ inline void finish_p_coeffs(const Dev &D, int k, const double *tot, double *cf,
                                        bool store) {
   Scal *sc = D.sc;
   const int j0 = pwin0(D, k);
   const int nwin = k >= j0 ? k - j0 + 1 : 0;
   const int ns = D.ell + 1, ldh = D.maxit + 1;
-  double t[kMaxEll + 1];
-  for (int q = 0; q < nwin; ++q) {
-    const int jq = j0 + q;
-    double v = D.sigp[jq] * tot[q];
-    for (int i = 0; i < q; ++i) v -= t[i] * sc->Gp[pslot(D, jq) * ns + pslot(D, j0 + i)];
-    t[q] = v;
-    cf[q] = v * D.sigp[jq];
-    if (store) D.T[(size_t)k * ldh + (jq - 1)] = v;
+  if constexpr (E <= 3) {
+    double sg[E], G[E][E];
+#pragma unroll
+    for (int q = 0; q < E; ++q) {
+      const int jq = j0 + max(0, min(q, nwin - 1));
+      sg[q] = D.sigp[jq];
+#pragma unroll
+      for (int i = 0; i < q; ++i)
+        G[q][i] = sc->Gp[pslot(D, jq) * ns + pslot(D, j0 + max(0, min(i, nwin - 1)))];
+    }
+    double t[E];
+#pragma unroll
+    for (int q = 0; q < E; ++q) {
+      if (q < nwin) {
+        double v = sg[q] * tot[q];
+#pragma unroll
+        for (int i = 0; i < q; ++i) v -= t[i] * G[q][i];
+        t[q] = v;
+        cf[q] = v * sg[q];
+        if (store) D.T[(size_t)k * ldh + (j0 + q - 1)] = v;
+      }
+    }
+  } else {
+    double t[kMaxEll + 1];
+    for (int q = 0; q < nwin; ++q) {
+      const int jq = j0 + q;
+      double v = D.sigp[jq] * tot[q];
+      for (int i = 0; i < q; ++i) v -= t[i] * sc->Gp[pslot(D, jq) * ns + pslot(D, j0 + i)];
+      t[q] = v;
+      cf[q] = v * D.sigp[jq];
+      if (store) D.T[(size_t)k * ldh + (jq - 1)] = v;
+    }
   }
   if (store) sc->zpre = sqrt(tot[nwin]);
 }

@@ -442,7 +442,7 @@ __global__ void __launch_bounds__(kWG) k_wupdate(const Dev *__restrict__ devs,
   __shared__ double s_cf[kMaxEll + 1];
   const int j0 = wwin0(D, k), nwin = k - j0 + 1;
   consume<kWG>(D, kStageA, nwin + 1, lds_w, tot);
-  if (threadIdx.x == 0) finish_w_coeffs(D, k, tot, s_cf, wid == 0);
+  if (threadIdx.x == 0) finish_w_coeffs<E>(D, k, tot, s_cf, wid == 0);
   __syncthreads();
   const gptr<const double> wr = gmem(wrawk(D, k));
   const gptr<double> out = gmem(wvec(D, k + 1));
@@ -495,7 +495,7 @@ __global__ void __launch_bounds__(kWG) k_pupdate(const Dev *__restrict__ devs,
   const int j0 = pwin0(D, k);
   const int nwin = k >= j0 ? k - j0 + 1 : 0;
   consume<kWG>(D, kStageC, nwin + 1, lds_w, tot);
-  if (threadIdx.x == 0) finish_p_coeffs(D, k, tot, s_cf, wid == 0);
+  if (threadIdx.x == 0) finish_p_coeffs<E>(D, k, tot, s_cf, wid == 0);
   const bool rew = D.tau == 1;
   if (rew)
     for (int j = threadIdx.x; j < k; j += kWG) coefx[j] = D.sigp[j + 1] * D.y[j];

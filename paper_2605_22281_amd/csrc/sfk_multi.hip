@@ -65,7 +65,7 @@ __global__ void __launch_bounds__(kWG) k_gfinish(Grp G, int k) {
     // before B(k): h_jk from the dots of A(k)
     consume<kWG>(D, kStageA, k - wwin0(D, k) + 2, lds_w, tot);
     if (threadIdx.x == 0) {
-      finish_w_coeffs(D, k, tot, cf, true);
+      finish_w_coeffs<kMaxEll + 1>(D, k, tot, cf, true);
       G.act[r] = 1;
     }
   } else if (ST == kStageC) {
@@ -82,7 +82,7 @@ __global__ void __launch_bounds__(kWG) k_gfinish(Grp G, int k) {
     const int nwin = k >= j0 ? k - j0 + 1 : 0;
     consume<kWG>(D, kStageC, nwin + 1, lds_w, tot);
     if (threadIdx.x == 0) {
-      finish_p_coeffs(D, k, tot, cf, true);
+      finish_p_coeffs<kMaxEll + 1>(D, k, tot, cf, true);
       G.act[r] = 1;
     }
     if (D.tau == 1)
