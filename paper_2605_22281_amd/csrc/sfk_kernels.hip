@@ -195,6 +195,7 @@ __device__ void spmv_rows64(gptr<const int> __restrict__ rp, gptr<const int> __r
 // on few cache lines.  The 16 partial sums of a row are added in LDS in wave
 // order.  Rows [r0, r1) of the workgroup are returned for the epilogue.
 // ---------------------------------------------------------------------------
+template <bool C16>
 __device__ void spmv_sell(gptr<const int> __restrict__ soff, gptr<const int> __restrict__ slen,
                           gptr<const int> __restrict__ scol, gptr<const uint16_t> __restrict__ scol16,
                           gptr<const double> __restrict__ sval, gptr<const double> __restrict__ xin,
@@ -217,7 +218,8 @@ __device__ void spmv_sell(gptr<const int> __restrict__ soff, gptr<const int> __r
       for (int u = 0; u < kSellPad; ++u) {
         const size_t e = sell_at(base, j + u, lane);
         v[u] = __builtin_nontemporal_load(sval + e);
-        c[u] = scol16 ? (int)__builtin_nontemporal_load(scol16 + e) : __builtin_nontemporal_load(scol + e);
+        if constexpr (C16) c[u] = (int)__builtin_nontemporal_load(scol16 + e);
+        else c[u] = __builtin_nontemporal_load(scol + e);
       }
       double xv[kSellPad];
 #pragma unroll
@@ -242,6 +244,20 @@ __device__ void spmv_sell(gptr<const int> __restrict__ soff, gptr<const int> __r
     }
     __syncthreads();
   }
+}
+
+// spmv_sell with 16-bit or 32-bit column indices (a uniform choice: with the
+// choice inside the unrolled loop, the 32-bit path waited for every load of a
+// step group before issuing its last column load)
+__device__ __forceinline__ void spmv_sell_any(gptr<const int> soff, gptr<const int> slen,
+                                              gptr<const int> scol, gptr<const uint16_t> scol16,
+                                              gptr<const double> sval, gptr<const double> xin,
+                                              gptr<double> yout, double *ybuf, int s0, int s1,
+                                              int rows, double scale, double *lds_part) {
+  if (scol16)
+    spmv_sell<true>(soff, slen, scol, scol16, sval, xin, yout, ybuf, s0, s1, rows, scale, lds_part);
+  else
+    spmv_sell<false>(soff, slen, scol, scol16, sval, xin, yout, ybuf, s0, s1, rows, scale, lds_part);
 }
 
 // ---------------------------------------------------------------------------
@@ -305,7 +321,7 @@ __global__ void __launch_bounds__(kSpmvWG, 8) k_spmv(const Dev *__restrict__ dev
     r0 = min(rows, s0 * kSellC);
     r1 = min(rows, s1 * kSellC);
     __shared__ double lds_part[(kSpmvWG / 64) * kSellC];
-    spmv_sell(gmem(ISA ? D.Asoff : D.Bsoff), gmem(ISA ? D.Aslen : D.Bslen),
+    spmv_sell_any(gmem(ISA ? D.Asoff : D.Bsoff), gmem(ISA ? D.Aslen : D.Bslen),
               gmem(ISA ? D.Ascol : D.Bscol), gmem(ISA ? D.Ascol16 : D.Bscol16),
               gmem(ISA ? D.Asval : D.Bsval), xin, yout, ybuf, s0, s1, rows, scale, lds_part);
   } else {
@@ -365,16 +381,31 @@ __global__ void __launch_bounds__(kSpmvWG, 8) k_spmv(const Dev *__restrict__ dev
   gptr<const double> win[kMaxEll + 1];
 #pragma unroll
   for (int q = 0; q < kMaxEll + 1; ++q)
-    win[q] = (q < nwin) ? gmem(ISA ? wvec(D, j0 + q) : pvec(D, j0 + q)) : nullptr;
+    win[q] = (q < nwin) ? gmem(ISA ? wvec(D, j0 + q) : pvec(D, j0 + q)) : yout;
   double acc[kMaxQ];
 #pragma unroll
   for (int q = 0; q < kMaxQ; ++q) acc[q] = 0.0;
-  for (int r = r0 + threadIdx.x; r < r1; r += NT) {
-    const double yr = (r - r0 < kRowsLDS) ? ybuf[r - r0] : yout[r];
+  if (nwin <= 3) {
+    // the window's three loads of a row issued together (slots past the window
+    // read this product's own output, same length, value unused)
+    for (int r = r0 + threadIdx.x; r < r1; r += NT) {
+      const double yr = (r - r0 < kRowsLDS) ? ybuf[r - r0] : yout[r];
+      double wq[3];
 #pragma unroll
-    for (int q = 0; q < kMaxEll + 1; ++q)
-      if (q < nwin) acc[q] += win[q][r] * yr;
-    acc[kMaxEll + 1] += yr * yr;
+      for (int q = 0; q < 3; ++q) wq[q] = win[q][r];
+#pragma unroll
+      for (int q = 0; q < 3; ++q)
+        if (q < nwin) acc[q] += wq[q] * yr;
+      acc[kMaxEll + 1] += yr * yr;
+    }
+  } else {
+    for (int r = r0 + threadIdx.x; r < r1; r += NT) {
+      const double yr = (r - r0 < kRowsLDS) ? ybuf[r - r0] : yout[r];
+#pragma unroll
+      for (int q = 0; q < kMaxEll + 1; ++q)
+        if (q < nwin) acc[q] += win[q][r] * yr;
+      acc[kMaxEll + 1] += yr * yr;
+    }
   }
   double v[kMaxQ];
 #pragma unroll
@@ -403,7 +434,7 @@ __global__ void __launch_bounds__(kSpmvWG, 8) k_spmv_core(Dev D, const double *_
     const int rows = ISA ? D.m : D.n;
     const int s0 = (int)((long long)wid * nsl / D.nws), s1 = (int)((long long)(wid + 1) * nsl / D.nws);
     __shared__ double lds_part[(kSpmvWG / 64) * kSellC];
-    spmv_sell(gmem(ISA ? D.Asoff : D.Bsoff), gmem(ISA ? D.Aslen : D.Bslen),
+    spmv_sell_any(gmem(ISA ? D.Asoff : D.Bsoff), gmem(ISA ? D.Aslen : D.Bslen),
               gmem(ISA ? D.Ascol : D.Bscol), gmem(ISA ? D.Ascol16 : D.Bscol16),
               gmem(ISA ? D.Asval : D.Bsval), xg, yg, ybuf, s0, s1, rows, 1.0, lds_part);
   } else if (VW == 64) {
