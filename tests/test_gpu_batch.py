@@ -99,10 +99,10 @@ def test_batch_resume_and_per_instance_capacity():
         sfk.iterate(ctx, 1)            # largest capacity (9) exhausted
 
 
-@pytest.mark.skip(reason="the GPU reported a memory fault while this case ran (together with a "
-                  "change to the least-squares kernels that read no address the current "
-                  "kernels do not, since taken out); the cause has not been shown, so the "
-                  "case stays off the GPU until it is")
+@pytest.mark.skip(reason="this case failed in a run that left the GPU with a memory fault "
+                  "(together with a change to the least-squares kernels that read no address "
+                  "the current kernels do not, since taken out); the cause has not been shown, "
+                  "so the case stays off the GPU until it is")
 def test_heterogeneous_batch_at_benchmark_sizes():
     """The heterogeneous benchmark's batch at its own sizes: its first four
     instances (one of each side 256, 128, 384, 192; 1.9e6 to 5.1e7 nonzeros),
