@@ -546,7 +546,11 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-iters", type=int, default=None)
     ap.add_argument("--copy-calibration", action="store_true")
-    ap.add_argument("--batched", default="all", choices=["all", "multi", "hetero", "none"])
+    ap.add_argument("--batched", default="multi", choices=["all", "multi", "hetero", "none"],
+                    help="batched comparisons: right-hand sides sharing the operators (multi) "
+                         "and/or the heterogeneous batch of independent instances (hetero, not "
+                         "in the default run while a memory fault seen with the heterogeneous "
+                         "batch at these sizes has no known cause)")
     ap.add_argument("--extras", default="all", choices=["all", "none"],
                     help="the other plain workloads beside the headline")
     ap.add_argument("--no-full-run", action="store_true")
