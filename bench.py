@@ -565,7 +565,7 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1:
-        print(f"bench.py: --gpus {args.gpus} is not supported: this build measures one GPU "
+        print(f"bench.py: --gpus {args.gpus} is not supported: the benchmark measures one GPU "
               f"(a single MI355X); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
     if args.copy_calibration:
